@@ -1,0 +1,531 @@
+/*
+ * pd_oracle.c -- plain, slow FP64 CPU oracle for the bond-based PMB peridynamics step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline of the benchmark may load this library.  It shares no code, header,
+ * table or constant with the HIP library; the two meet only through the seeded
+ * input generators (module pd_inputs).
+ *
+ * Built with gcc -O2 -ffp-contract=off (no FMA contraction, no fast-math) so the
+ * rounding sequence of every expression below is the one written.  Parallel loops
+ * run over rows only; each row's arithmetic and summation order is fixed, so any
+ * thread count gives bitwise the same result.
+ *
+ * What it computes (paper: "PeriPy - a high performance OpenCL peridynamics package"):
+ *   family          H_i = { j != i : |x_j - x_i| <= delta }            (Eq. family; self excluded)
+ *   kinematics      xi = x_j - x_i, eta = u_j - u_i                    (Sec. 2.1)
+ *   stretch         s = (|eta + xi| - |xi|) / |xi|                     (Eq. microelastic)
+ *   PMB force       f = c s mu (eta + xi)/|eta + xi|, c = 18K/(pi d^4) (Eq. simpleBond, Sec. 2.2)
+ *   breaking        mu = 0 for ever once s >= s_c                      (Eq. mu; the paper's bond
+ *                   kernel keeps a bond only while s < s0, and a bond that breaks contributes
+ *                   nothing in the pass that breaks it: Algorithm 2)
+ *   node force      F_i = sum_j f(eta_ij, xi_ij) V_j + b_i             (Eq. discrete EOM, beta = 1)
+ *   damage          phi_i = 1 - sum_j mu_ij V_j / sum_j V_j            (Sec. 2.2, local damage)
+ *   integrators     velocity Verlet (Eqs. Velocity_Verlet1-3), Euler-Cromer and forward Euler
+ *                   (the integrator classes listed in Sec. 3.6; their update rules are not printed).
+ *   adjoint         reverse-mode derivative of an Euler-Cromer run with the break schedule
+ *                   frozen, w.r.t. per-slot stiffness and body-force magnitude.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PDO_EC 0
+#define PDO_VV 1
+#define PDO_FE 2
+
+#define PDO_FREE 0
+#define PDO_DISP 1
+#define PDO_VEL 2
+
+typedef struct pdo_problem {
+    int64_t n;
+    const double *x;         /* n*3 reference coordinates (row-major) */
+    const double *vol;       /* n   lumped node volumes */
+    const int64_t *row_ptr;  /* n+1 CSR row starts */
+    const int32_t *col;      /* nnz neighbour ids, ascending within each row */
+    const double *kslot;     /* nnz per-slot micromodulus, or NULL: every slot uses c */
+    double c;                /* constant micromodulus */
+    double s0;               /* critical stretch */
+    double rho;              /* density */
+    double eta;              /* dynamic-relaxation damping coefficient */
+    double dt;               /* time step */
+    const double *bhat;      /* n*3 body-force direction field, or NULL */
+    double bmag;             /* body-force magnitude: b_i = bmag * bhat_i */
+    const uint8_t *bc_kind;  /* n*3: PDO_FREE / PDO_DISP / PDO_VEL, or NULL (no constraints) */
+    const uint8_t *bc_sched; /* n*3: 0 -> g(t) = 1, 1 -> g(t) = t */
+    const double *bc_val;    /* n*3 amplitudes A */
+    int32_t scheme;          /* PDO_EC / PDO_VV / PDO_FE */
+    int32_t nthreads;        /* <= 0: library default */
+} pdo_problem;
+
+typedef struct pdo_state {
+    double *u;               /* n*3 displacement */
+    double *v;               /* n*3 velocity */
+    double *a;               /* n*3 acceleration (velocity Verlet) */
+    uint8_t *broken;         /* nnz: 1 once the slot's bond is broken */
+    int32_t *break_step;     /* nnz or NULL: pass index at which a slot broke */
+    const int32_t *frozen;   /* nnz or NULL: replay, slot alive in pass k iff k < frozen[b] */
+    int64_t step;            /* number of completed time steps */
+    int32_t a_valid;         /* velocity Verlet: a holds the acceleration of the current u */
+    int32_t pad_;
+} pdo_state;
+
+static void set_threads(const pdo_problem *P)
+{
+#ifdef _OPENMP
+    if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
+#else
+    (void)P;
+#endif
+}
+
+/* ------------------------------------------------------------------ family (Eq. family) */
+
+static int within_horizon(const double *x, int64_t i, int64_t j, double d2max)
+{
+    double a = x[3 * j + 0] - x[3 * i + 0];
+    double b = x[3 * j + 1] - x[3 * i + 1];
+    double c = x[3 * j + 2] - x[3 * i + 2];
+    double d2 = a * a + b * b;
+    d2 = d2 + c * c;
+    return d2 <= d2max;
+}
+
+/* Brute force O(n^2).  With col == NULL only row_ptr is filled; returns nnz. */
+int64_t pdo_family_brute(int64_t n, const double *x, double delta, int64_t *row_ptr, int32_t *col)
+{
+    double d2max = delta * delta;
+    if (col == NULL) {
+        row_ptr[0] = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t cnt = 0;
+            for (int64_t j = 0; j < n; ++j)
+                if (j != i && within_horizon(x, i, j, d2max)) ++cnt;
+            row_ptr[i + 1] = row_ptr[i] + cnt;
+        }
+        return row_ptr[n];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t w = row_ptr[i];
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i && within_horizon(x, i, j, d2max)) col[w++] = (int32_t)j;
+    }
+    return row_ptr[n];
+}
+
+/* Cell list with cells at least delta wide; rows sorted ascending.  Same contract. */
+typedef struct cellgrid {
+    double lo[3];
+    double h;
+    int64_t dim[3];
+    int64_t *start;  /* ncell+1 */
+    int64_t *items;  /* n, node ids grouped by cell, ascending within a cell */
+} cellgrid;
+
+static int64_t cell_coord(const cellgrid *g, double v, int d)
+{
+    int64_t c = (int64_t)floor((v - g->lo[d]) / g->h);
+    if (c < 0) c = 0;
+    if (c >= g->dim[d]) c = g->dim[d] - 1;
+    return c;
+}
+
+static void grid_build(cellgrid *g, int64_t n, const double *x, double delta)
+{
+    double hi[3];
+    for (int d = 0; d < 3; ++d) { g->lo[d] = x[d]; hi[d] = x[d]; }
+    for (int64_t i = 1; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            if (x[3 * i + d] < g->lo[d]) g->lo[d] = x[3 * i + d];
+            if (x[3 * i + d] > hi[d]) hi[d] = x[3 * i + d];
+        }
+    /* cells a hair wider than delta, so that rounding in the cell coordinate can
+     * never put two nodes within delta of each other two cells apart */
+    g->h = delta > 0 ? delta * (1.0 + 1e-9) : 1.0;
+    int64_t ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        g->dim[d] = (int64_t)floor((hi[d] - g->lo[d]) / g->h) + 1;
+        ncell *= g->dim[d];
+    }
+    g->start = calloc((size_t)ncell + 1, sizeof(int64_t));
+    g->items = malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *cid = malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t cx = cell_coord(g, x[3 * i], 0), cy = cell_coord(g, x[3 * i + 1], 1),
+                cz = cell_coord(g, x[3 * i + 2], 2);
+        cid[i] = (cz * g->dim[1] + cy) * g->dim[0] + cx;
+        g->start[cid[i] + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) g->start[c + 1] += g->start[c];
+    int64_t *fill = malloc((size_t)ncell * sizeof(int64_t) + 1);
+    memcpy(fill, g->start, (size_t)ncell * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) g->items[fill[cid[i]]++] = i;
+    free(fill);
+    free(cid);
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+int64_t pdo_family_cells(int64_t n, const double *x, double delta, int64_t *row_ptr, int32_t *col)
+{
+    cellgrid g;
+    double d2max = delta * delta;
+    grid_build(&g, n, x, delta);
+    if (col == NULL) row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t cx = cell_coord(&g, x[3 * i], 0), cy = cell_coord(&g, x[3 * i + 1], 1),
+                cz = cell_coord(&g, x[3 * i + 2], 2);
+        int64_t w = col ? row_ptr[i] : 0;
+        for (int64_t z = cz - 1; z <= cz + 1; ++z) {
+            if (z < 0 || z >= g.dim[2]) continue;
+            for (int64_t y = cy - 1; y <= cy + 1; ++y) {
+                if (y < 0 || y >= g.dim[1]) continue;
+                for (int64_t xx = cx - 1; xx <= cx + 1; ++xx) {
+                    if (xx < 0 || xx >= g.dim[0]) continue;
+                    int64_t c = (z * g.dim[1] + y) * g.dim[0] + xx;
+                    for (int64_t p = g.start[c]; p < g.start[c + 1]; ++p) {
+                        int64_t j = g.items[p];
+                        if (j == i || !within_horizon(x, i, j, d2max)) continue;
+                        if (col) col[w] = (int32_t)j;
+                        ++w;
+                    }
+                }
+            }
+        }
+        if (col)
+            qsort(col + row_ptr[i], (size_t)(w - row_ptr[i]), sizeof(int32_t), cmp_i32);
+        else
+            row_ptr[i + 1] = row_ptr[i] + w;
+    }
+    free(g.start);
+    free(g.items);
+    return row_ptr[n];
+}
+
+/* ------------------------------------------------------------------ bond forces */
+
+/* Force density of every node for displacement u, in pass k (the index of the time
+ * level u belongs to).  Without a frozen schedule, a slot whose stretch reaches s0
+ * is marked broken (and its pass recorded) and contributes nothing; with a frozen
+ * schedule, the slot is alive in pass k iff k < frozen[b]. */
+void pdo_force(const pdo_problem *P, pdo_state *S, const double *u, int64_t k, double *F)
+{
+    const double *x = P->x;
+    set_threads(P);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < P->n; ++i) {
+        double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+        for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
+            if (S->frozen) {
+                if (!(k < (int64_t)S->frozen[b])) continue;
+            } else if (S->broken[b]) {
+                continue;
+            }
+            int64_t j = P->col[b];
+            double xi0 = x[3 * j + 0] - x[3 * i + 0];
+            double xi1 = x[3 * j + 1] - x[3 * i + 1];
+            double xi2 = x[3 * j + 2] - x[3 * i + 2];
+            double y0 = xi0 + (u[3 * j + 0] - u[3 * i + 0]);
+            double y1 = xi1 + (u[3 * j + 1] - u[3 * i + 1]);
+            double y2 = xi2 + (u[3 * j + 2] - u[3 * i + 2]);
+            double r = sqrt((y0 * y0 + y1 * y1) + y2 * y2);
+            double L = sqrt((xi0 * xi0 + xi1 * xi1) + xi2 * xi2);
+            double s = (r - L) / L;
+            if (!S->frozen && s >= P->s0) {
+                S->broken[b] = 1;
+                if (S->break_step) S->break_step[b] = (int32_t)k;
+                continue;
+            }
+            double kb = P->kslot ? P->kslot[b] : P->c;
+            double scal = ((kb * s) * P->vol[j]) / r;
+            f0 += scal * y0;
+            f1 += scal * y1;
+            f2 += scal * y2;
+        }
+        if (P->bhat) {
+            f0 += P->bmag * P->bhat[3 * i + 0];
+            f1 += P->bmag * P->bhat[3 * i + 1];
+            f2 += P->bmag * P->bhat[3 * i + 2];
+        }
+        F[3 * i + 0] = f0;
+        F[3 * i + 1] = f1;
+        F[3 * i + 2] = f2;
+    }
+}
+
+/* ------------------------------------------------------------------ boundary conditions */
+
+static int bc_kind(const pdo_problem *P, int64_t i, int d)
+{
+    return P->bc_kind ? P->bc_kind[3 * i + d] : PDO_FREE;
+}
+
+static double sched_g(int sched, double t) { return sched == 1 ? t : 1.0; }
+static double sched_dg(int sched) { return sched == 1 ? 1.0 : 0.0; }
+
+/* Prescribed velocity of a constrained component at time t. */
+static double bc_velocity(const pdo_problem *P, int64_t i, int d, double t)
+{
+    double A = P->bc_val[3 * i + d];
+    int sc = P->bc_sched[3 * i + d];
+    if (P->bc_kind[3 * i + d] == PDO_DISP) return A * sched_dg(sc);
+    return A * sched_g(sc, t);
+}
+
+/* Prescribed displacement at time t; uprev is the component's displacement one step earlier. */
+static double bc_displacement(const pdo_problem *P, int64_t i, int d, double t, double uprev)
+{
+    double A = P->bc_val[3 * i + d];
+    int sc = P->bc_sched[3 * i + d];
+    if (P->bc_kind[3 * i + d] == PDO_DISP) return A * sched_g(sc, t);
+    return uprev + P->dt * (A * sched_g(sc, t));
+}
+
+/* ------------------------------------------------------------------ time integration */
+
+static int64_t nnz_of(const pdo_problem *P) { return P->row_ptr[P->n]; }
+
+/* One step k -> k+1.  Returns 0. */
+static int step_once(const pdo_problem *P, pdo_state *S, double *F, double *unew)
+{
+    const int64_t n = P->n;
+    const int64_t k = S->step;
+    const double dt = P->dt;
+    const double t1 = (double)(k + 1) * dt;
+
+    if (P->scheme == PDO_EC || P->scheme == PDO_FE) {
+        pdo_force(P, S, S->u, k, F);
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d) {
+                int64_t q = 3 * i + d;
+                double a = (F[q] - P->eta * S->v[q]) / P->rho;
+                double u0 = S->u[q];
+                double un, vn;
+                if (P->scheme == PDO_EC) {
+                    vn = S->v[q] + dt * a;
+                    un = u0 + dt * vn;
+                } else {
+                    un = u0 + dt * S->v[q];
+                    vn = S->v[q] + dt * a;
+                }
+                if (bc_kind(P, i, d) != PDO_FREE) {
+                    vn = bc_velocity(P, i, d, t1);
+                    un = bc_displacement(P, i, d, t1, u0);
+                }
+                S->u[q] = un;
+                S->v[q] = vn;
+            }
+        S->step = k + 1;
+        return 0;
+    }
+
+    /* velocity Verlet (Eqs. Velocity_Verlet1-3): position, force at the new position, velocity */
+    if (!S->a_valid) {
+        pdo_force(P, S, S->u, k, F);
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d) {
+                int64_t q = 3 * i + d;
+                S->a[q] = bc_kind(P, i, d) != PDO_FREE ? 0.0 : (F[q] - P->eta * S->v[q]) / P->rho;
+            }
+        S->a_valid = 1;
+    }
+    const double half_dt = 0.5 * dt;
+    const double half_dt2 = 0.5 * dt * dt;
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            int64_t q = 3 * i + d;
+            double un = (S->u[q] + dt * S->v[q]) + half_dt2 * S->a[q];
+            if (bc_kind(P, i, d) != PDO_FREE) un = bc_displacement(P, i, d, t1, S->u[q]);
+            unew[q] = un;
+        }
+    pdo_force(P, S, unew, k + 1, F);
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            int64_t q = 3 * i + d;
+            double vhalf = S->v[q] + half_dt * S->a[q];
+            double an = (F[q] - P->eta * vhalf) / P->rho;
+            double vn = S->v[q] + half_dt * (S->a[q] + an);
+            if (bc_kind(P, i, d) != PDO_FREE) {
+                vn = bc_velocity(P, i, d, t1);
+                an = 0.0;
+            }
+            S->u[q] = unew[q];
+            S->v[q] = vn;
+            S->a[q] = an;
+        }
+    S->step = k + 1;
+    return 0;
+}
+
+/* Advance nsteps steps.  Returns 0, or -1 if the state became non-finite (the
+ * step index is left at the first non-finite step). */
+int pdo_run(const pdo_problem *P, pdo_state *S, int64_t nsteps)
+{
+    const int64_t n3 = 3 * P->n;
+    double *F = malloc((size_t)(n3 > 0 ? n3 : 1) * sizeof(double));
+    double *unew = malloc((size_t)(n3 > 0 ? n3 : 1) * sizeof(double));
+    int rc = 0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        step_once(P, S, F, unew);
+        for (int64_t q = 0; q < n3; ++q)
+            if (!isfinite(S->u[q]) || !isfinite(S->v[q])) { rc = -1; break; }
+        if (rc) break;
+    }
+    free(F);
+    free(unew);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ damage */
+
+void pdo_damage(const pdo_problem *P, const uint8_t *broken, double *phi)
+{
+    for (int64_t i = 0; i < P->n; ++i) {
+        double num = 0.0, den = 0.0;
+        for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
+            double vj = P->vol[P->col[b]];
+            den += vj;
+            if (!broken[b]) num += vj;
+        }
+        phi[i] = den > 0.0 ? 1.0 - num / den : 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------ adjoint (Euler-Cromer) */
+
+/* out = J_F(u)^T nu in pass k with the frozen schedule, written as the literal
+ * transpose of the Jacobian: every slot b = (i, j) has dF_i/du_j = k_b V_j K_b and
+ * dF_i/du_i -= k_b V_j K_b, K_b = (1/L - 1/r) I + y y^T / r^3 (the derivative of
+ * y/L - y/r with respect to y).  Single-threaded scatter. */
+void pdo_apply_jt(const pdo_problem *P, const int32_t *frozen, const double *u, int64_t k,
+                  const double *nu, double *out)
+{
+    const double *x = P->x;
+    memset(out, 0, (size_t)(3 * P->n) * sizeof(double));
+    for (int64_t i = 0; i < P->n; ++i) {
+        for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
+            if (!(k < (int64_t)frozen[b])) continue;
+            int64_t j = P->col[b];
+            double xi[3], y[3];
+            for (int d = 0; d < 3; ++d) {
+                xi[d] = x[3 * j + d] - x[3 * i + d];
+                y[d] = xi[d] + (u[3 * j + d] - u[3 * i + d]);
+            }
+            double r = sqrt((y[0] * y[0] + y[1] * y[1]) + y[2] * y[2]);
+            double L = sqrt((xi[0] * xi[0] + xi[1] * xi[1]) + xi[2] * xi[2]);
+            double kb = P->kslot ? P->kslot[b] : P->c;
+            double w = kb * P->vol[j];
+            double diag = 1.0 / L - 1.0 / r;
+            double r3 = r * r * r;
+            /* (K_b nu_i) */
+            double yn = y[0] * nu[3 * i + 0] + y[1] * nu[3 * i + 1] + y[2] * nu[3 * i + 2];
+            for (int d = 0; d < 3; ++d) {
+                double kn = diag * nu[3 * i + d] + y[d] * yn / r3;
+                out[3 * j + d] += w * kn;   /* (dF_i/du_j)^T nu_i */
+                out[3 * i + d] -= w * kn;   /* (dF_i/du_i)^T nu_i */
+            }
+        }
+    }
+}
+
+/* Gradient of L = sum over sensors of |u^T - target|^2 after nsteps Euler-Cromer
+ * steps from (u0, v0) at step index step0, with the break schedule frozen.  The
+ * caller passes dL/du^T for the m sensor nodes (m*3).  Outputs the gradient with
+ * respect to every slot's stiffness (grad_k, nnz; the problem must carry kslot)
+ * and with respect to the body-force magnitude (grad_A).  The whole trajectory is
+ * stored.  Returns 0, or -1 on allocation failure. */
+int pdo_adjoint_ec(const pdo_problem *P, const int32_t *frozen, int64_t nsteps,
+                   const double *u0, const double *v0, int64_t step0,
+                   int64_t m, const int64_t *sensors, const double *dLdu,
+                   double *grad_k, double *grad_A)
+{
+    const int64_t n = P->n, n3 = 3 * n, nnz = nnz_of(P);
+    const double dt = P->dt;
+    double *traj = malloc((size_t)(nsteps > 0 ? nsteps : 1) * (size_t)n3 * sizeof(double));
+    double *F = malloc((size_t)(n3 > 0 ? n3 : 1) * sizeof(double));
+    double *unew = malloc((size_t)(n3 > 0 ? n3 : 1) * sizeof(double));
+    double *lu = calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    double *lv = calloc((size_t)(n3 > 0 ? n3 : 1), sizeof(double));
+    double *nu = malloc((size_t)(n3 > 0 ? n3 : 1) * sizeof(double));
+    double *jt = malloc((size_t)(n3 > 0 ? n3 : 1) * sizeof(double));
+    if (!traj || !F || !unew || !lu || !lv || !nu || !jt) {
+        free(traj); free(F); free(unew); free(lu); free(lv); free(nu); free(jt);
+        return -1;
+    }
+    pdo_problem Q = *P;
+    Q.scheme = PDO_EC;
+    pdo_state S;
+    memset(&S, 0, sizeof S);
+    S.u = malloc((size_t)(n3 > 0 ? n3 : 1) * sizeof(double));
+    S.v = malloc((size_t)(n3 > 0 ? n3 : 1) * sizeof(double));
+    S.frozen = frozen;
+    S.step = step0;
+    memcpy(S.u, u0, (size_t)n3 * sizeof(double));
+    memcpy(S.v, v0, (size_t)n3 * sizeof(double));
+    for (int64_t s = 0; s < nsteps; ++s) {
+        memcpy(traj + (size_t)s * n3, S.u, (size_t)n3 * sizeof(double));
+        step_once(&Q, &S, F, unew);
+    }
+    for (int64_t p = 0; p < m; ++p)
+        for (int d = 0; d < 3; ++d) lu[3 * sensors[p] + d] += dLdu[3 * p + d];
+    memset(grad_k, 0, (size_t)nnz * sizeof(double));
+    double gA = 0.0;
+    const double h = dt / P->rho;
+    const double damp = 1.0 - dt * P->eta / P->rho;
+    for (int64_t s = nsteps - 1; s >= 0; --s) {
+        const int64_t k = step0 + s;
+        const double *u = traj + (size_t)s * n3;
+        /* nu = adjoint of the unconstrained new velocity.  A prescribed component
+         * passes nothing to the new velocity; a displacement-controlled one passes
+         * nothing back to u^k either, a velocity-controlled one (u' = u + dt V) does. */
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d) {
+                int64_t q = 3 * i + d;
+                int kind = bc_kind(P, i, d);
+                if (kind == PDO_FREE) {
+                    nu[q] = lv[q] + dt * lu[q];
+                } else {
+                    nu[q] = 0.0;
+                    if (kind == PDO_DISP) lu[q] = 0.0;
+                }
+            }
+        /* parameter gradients: dF_i/dk_b = V_j s y / r, dF_i/dA = bhat_i */
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
+                if (!(k < (int64_t)frozen[b])) continue;
+                int64_t j = P->col[b];
+                double xi[3], y[3];
+                for (int d = 0; d < 3; ++d) {
+                    xi[d] = P->x[3 * j + d] - P->x[3 * i + d];
+                    y[d] = xi[d] + (u[3 * j + d] - u[3 * i + d]);
+                }
+                double r = sqrt((y[0] * y[0] + y[1] * y[1]) + y[2] * y[2]);
+                double L = sqrt((xi[0] * xi[0] + xi[1] * xi[1]) + xi[2] * xi[2]);
+                double sv = ((r - L) / L) * P->vol[j] / r;
+                grad_k[b] += h * sv * (y[0] * nu[3 * i] + y[1] * nu[3 * i + 1] + y[2] * nu[3 * i + 2]);
+            }
+            if (P->bhat)
+                gA += h * (P->bhat[3 * i] * nu[3 * i] + P->bhat[3 * i + 1] * nu[3 * i + 1] +
+                           P->bhat[3 * i + 2] * nu[3 * i + 2]);
+        }
+        pdo_apply_jt(P, frozen, u, k, nu, jt);
+        for (int64_t q = 0; q < n3; ++q) {
+            lu[q] = lu[q] + h * jt[q];
+            lv[q] = damp * nu[q];
+        }
+    }
+    *grad_A = gA;
+    free(traj); free(F); free(unew); free(lu); free(lv); free(nu); free(jt);
+    free(S.u); free(S.v);
+    return 0;
+}
