@@ -1,0 +1,230 @@
+/*
+ * pdmi.h -- C ABI of the MI355X (gfx950) bond-based peridynamics library.
+ *
+ * The library advances the explicit bond-based peridynamic equation of motion
+ * (paper: "PeriPy - a high performance OpenCL peridynamics package", Sec. 2):
+ *
+ *   rho u''_i = sum_{j in H_i} f(eta_ij, xi_ij) V_j + b_i             (Eq. discrete EOM)
+ *   f = c s mu (eta + xi) / |eta + xi|,  s = (|eta + xi| - |xi|)/|xi| (Eqs. microelastic, simpleBond)
+ *   mu = 0 for ever once s >= s0 (irreversible brittle breaking)       (Eq. mu)
+ *   H_i = { j != i : |x_j - x_i| <= delta }                           (Eq. family)
+ *
+ * with an explicit time integrator (Sec. 2.4) and per-node local damage (Sec. 2.2).
+ * Every time step runs in hand-written HIP kernels on one GPU.
+ *
+ * Conventions (all entry points):
+ *  - Return value: PD_OK (0) or a negative PD_E* code; pd_last_error() gives a
+ *    message.  No C++ exception crosses this boundary.
+ *  - Setters are all-or-nothing: on error the context is unchanged.
+ *  - Host pointers are read during the call only; the caller keeps ownership.
+ *  - Node ids, slot ids and every per-node / per-slot array are in the caller's
+ *    ("user") order: node ids as passed to pd_build_family, slots in the CSR order
+ *    returned by pd_get_family.  Any internal renumbering is invisible.
+ *  - A context serves one HIP stream; work is stream-ordered and asynchronous
+ *    unless a call says it synchronises.  A context is not thread-safe.
+ *  - Instances: a context holds one or more independent problems ("instances",
+ *    numbered from 0) that pd_step advances together in the same kernel launches.
+ *    Single-problem callers use instance 0.
+ */
+#ifndef PDMI_H
+#define PDMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+#define PD_OK 0
+#define PD_EINVAL (-1)      /* bad argument: NULL pointer, size or enum out of range */
+#define PD_ENOMEM (-2)      /* host or device allocation failed */
+#define PD_EHIP (-3)        /* a HIP runtime call failed */
+#define PD_ESTATE (-4)      /* call out of order (e.g. pd_step before pd_build_family) */
+#define PD_ENONFINITE (-5)  /* a displacement or velocity became non-finite */
+#define PD_ERANGE (-6)      /* problem exceeds the index types (2^31-1 nodes or slots) */
+
+/* ---------------------------------------------------------------- enumerations */
+#define PD_FP64 0           /* state and arithmetic in double precision */
+#define PD_FP32 1           /* state (u, v, a) and bond arithmetic in single precision */
+
+#define PD_ORDER_NATURAL 0  /* keep the caller's node order in device memory */
+#define PD_ORDER_MORTON 1   /* renumber nodes internally along a Morton (Z-order) curve */
+
+#define PD_EULER_CROMER 0     /* v += dt (F - eta v)/rho; u += dt v_new */
+#define PD_VELOCITY_VERLET 1  /* Eqs. Velocity_Verlet1-3 */
+#define PD_EULER_FORWARD 2    /* u += dt v; v += dt (F - eta v)/rho (unstable; tests only) */
+
+#define PD_BC_DISP 1        /* prescribed displacement: u_c = A_c g(t), v_c = A_c g'(t) */
+#define PD_BC_VEL 2         /* prescribed velocity: v_c = A_c g(t), u_c += dt v_c */
+
+#define PD_SCHED_CONST 0    /* g(t) = 1 */
+#define PD_SCHED_LINEAR 1   /* g(t) = t */
+
+typedef struct pd_ctx pd_ctx;
+
+/* Material of one instance (Sec. 2.2-2.3). */
+typedef struct pd_material {
+    double rho;             /* mass density (kg/m^3), > 0 */
+    double c;               /* micromodulus (N/m^6), e.g. 18 K / (pi delta^4); used by every
+                               bond that has no per-slot stiffness (pd_set_bond_stiffness) */
+    double s0;              /* critical stretch, > 0 */
+    double eta;             /* dynamic-relaxation damping coefficient (Eq. damped EOM), >= 0 */
+    double volume;          /* uniform node volume V (m^3) when volumes == NULL, > 0 */
+    const double *volumes;  /* host array of n per-node volumes (user order), or NULL */
+} pd_material;
+
+/* Sizes of the device problem (informational; see pd_get_info). */
+typedef struct pd_info {
+    int64_t n_nodes;        /* user nodes, all instances */
+    int64_t n_slots;        /* directed family slots, all instances (bond updates per step) */
+    int64_t n_nodes_dev;    /* device node records incl. slice padding */
+    int64_t n_slots_dev;    /* device slot entries incl. slice padding */
+    int32_t n_instances;
+    int32_t lanes_per_node; /* work-items cooperating on one node's bonds */
+    int32_t precision;      /* PD_FP64 / PD_FP32 */
+    int32_t scheme;         /* integrator */
+    double model_bytes_per_step; /* algorithmic HBM bytes of one step (see the design notes) */
+} pd_info;
+
+/* ---------------------------------------------------------------- lifetime */
+
+/* Create a context on HIP device `device` computing in `precision`.  `hip_stream` is
+ * the caller's hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or NULL,
+ * in which case the library creates its own stream.  *out receives the handle. */
+int pd_create(pd_ctx **out, int device, int precision, void *hip_stream);
+
+/* Free every device and host resource of the context.  NULL is accepted. */
+int pd_destroy(pd_ctx *ctx);
+
+/* Message describing the last failure on this context ("" if none).  With ctx ==
+ * NULL, the message of the last failed pd_create in this process. */
+const char *pd_last_error(const pd_ctx *ctx);
+
+/* ---------------------------------------------------------------- problem setup */
+
+/* Build the family of a single-instance problem (Eq. family: every j != i with
+ * |x_j - x_i| <= horizon, tested as ((dx^2 + dy^2) + dz^2) <= horizon^2 without
+ * fused multiply-add) from `coords` (host, n x 3 row-major doubles, metres), sorted
+ * ascending per row, and upload it.  `order` picks the device node order.  Resets
+ * the state: u = v = a = 0, no broken bonds, no BCs, no body force, step 0.
+ * Errors: PD_EINVAL (n < 1, NULL coords, horizon <= 0 or not finite, bad order),
+ * PD_ERANGE (n or nnz >= 2^31), PD_ENOMEM, PD_EHIP. */
+int pd_build_family(pd_ctx *ctx, int64_t n, const double *coords, double horizon, int order);
+
+/* Same for `ninst` independent instances advanced together: instance b has n[b]
+ * nodes at coords[b] (host, n[b] x 3) and horizon horizon[b].  Errors as above. */
+int pd_build_family_batch(pd_ctx *ctx, int32_t ninst, const int64_t *n,
+                          const double *const *coords, const double *horizon, int order);
+
+/* Number of instances of the current problem. */
+int pd_num_instances(const pd_ctx *ctx, int32_t *ninst);
+
+/* Node and slot counts of instance `inst` (either pointer may be NULL). */
+int pd_instance_size(const pd_ctx *ctx, int32_t inst, int64_t *n, int64_t *nnz);
+
+/* Export the family of instance `inst` in CSR form: row_ptr (n+1 int64) and col
+ * (nnz int32), user order, rows ascending.  Either array may be NULL to query
+ * sizes only; *nnz (if not NULL) receives the slot count.  Synchronising. */
+int pd_get_family(pd_ctx *ctx, int32_t inst, int64_t *row_ptr, int32_t *col, int64_t *nnz);
+
+/* Set the material of instance `inst` (Sec. 2.2).  Default after a family build:
+ * rho = 1, c = 1, s0 = +inf (nothing breaks), eta = 0, V = 1. */
+int pd_set_material(pd_ctx *ctx, int32_t inst, const pd_material *m);
+
+/* Per-slot micromodulus k[nnz] (host, user CSR order) replacing c for instance
+ * `inst` (bond classes / stiffness fields, Sec. 2.2 remark).  The two slots of a
+ * bond must carry the same value for Newton's third law to hold; the library does
+ * not enforce it.  k == NULL removes the field. */
+int pd_set_bond_stiffness(pd_ctx *ctx, int32_t inst, const double *k);
+
+/* Mark slots broken before or between steps (e.g. a notch pre-broken as an initial
+ * condition).  broken[nnz] (host, user CSR order): nonzero = break.  Breaking is
+ * irreversible; zero entries leave a slot unchanged.  Breaking one slot of a bond
+ * does not break the other; pass both. */
+int pd_break_bonds(pd_ctx *ctx, int32_t inst, const uint8_t *broken);
+
+/* Boundary conditions (Sec. 3.6: directions fixed, magnitudes time-varying).  For
+ * each of the m nodes (host ids, user order) and each component d with bit d of
+ * comp_mask set, prescribe kind PD_BC_DISP or PD_BC_VEL with amplitude value[d] and
+ * schedule `sched`.  After every step, at t = step * dt, a displacement-controlled
+ * component gets u = A g(t), v = A g'(t); a velocity-controlled one gets v = A g(t)
+ * and u = u_previous + dt v.  Later calls override earlier ones per component.
+ * Errors: PD_EINVAL (node id out of range, empty mask, bad kind or schedule). */
+int pd_set_bcs(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes, int comp_mask,
+               int kind, const double value[3], int sched);
+
+/* Remove every boundary condition of instance `inst`. */
+int pd_clear_bcs(pd_ctx *ctx, int32_t inst);
+
+/* Body force density b_i = magnitude * b_hat_i (N/m^3) of instance `inst`;
+ * b_hat: host n x 3, user order; NULL removes it. */
+int pd_set_body_force(pd_ctx *ctx, int32_t inst, const double *b_hat, double magnitude);
+
+/* Choose the integrator (PD_EULER_CROMER, PD_VELOCITY_VERLET, PD_EULER_FORWARD) and
+ * time step dt > 0 for all instances.  Default: Euler-Cromer, dt = 1e-7 s. */
+int pd_set_integrator(pd_ctx *ctx, int scheme, double dt);
+
+/* ---------------------------------------------------------------- stepping */
+
+/* Advance every instance by nsteps >= 0 steps.  Each step reads the current
+ * displacement snapshot, gathers neighbours over the family, computes stretches,
+ * breaks bonds with s >= s0 (they contribute nothing from that step on), sums the
+ * PMB bond forces per node, then integrates and applies the BCs.  Asynchronous: a
+ * non-finite state is reported by the next synchronising call (PD_ENONFINITE). */
+int pd_step(pd_ctx *ctx, int64_t nsteps);
+
+/* Wait for the stream; returns PD_ENONFINITE if any step produced a non-finite
+ * displacement or velocity since the state was last set. */
+int pd_sync(pd_ctx *ctx);
+
+/* Number of completed steps. */
+int pd_get_step(const pd_ctx *ctx, int64_t *step);
+
+/* ---------------------------------------------------------------- readout (synchronising) */
+
+/* Copy the displacement / velocity / acceleration (velocity Verlet; zeros otherwise)
+ * of instance `inst` into out (host, n x 3 doubles, user order). */
+int pd_get_u(pd_ctx *ctx, int32_t inst, double *out);
+int pd_get_v(pd_ctx *ctx, int32_t inst, double *out);
+int pd_get_a(pd_ctx *ctx, int32_t inst, double *out);
+
+/* Local damage phi_i = 1 - sum_j mu_ij V_j / sum_j V_j over the initial family
+ * (Sec. 2.2), as of the last completed step; 0 for a node without bonds.
+ * out: host, n doubles, user order. */
+int pd_get_damage(pd_ctx *ctx, int32_t inst, double *out);
+
+/* Broken flags of every slot: out[nnz] (host, user CSR order), 1 = broken. */
+int pd_get_broken(pd_ctx *ctx, int32_t inst, uint8_t *out);
+
+/* Overwrite the state of instance `inst` (checkpoint / restart, Sec. 3.6 "initiating
+ * a simulation from an intermediate state").  Any of u, v, a (host n x 3) or broken
+ * (host nnz; replaces the broken set exactly, un-breaking included) may be NULL to
+ * keep the current value.  pd_set_step sets the step counter of all instances. */
+int pd_set_state(pd_ctx *ctx, int32_t inst, const double *u, const double *v, const double *a,
+                 const uint8_t *broken);
+int pd_set_step(pd_ctx *ctx, int64_t step);
+
+/* ---------------------------------------------------------------- tuning and introspection */
+
+/* Lanes (work-items) cooperating on one node's bonds: 1, 2, 4, 8, 16, 32 or 64
+ * (0 = library default).  Rebuilds the device layout; state is preserved. */
+int pd_set_lanes_per_node(pd_ctx *ctx, int lanes);
+
+/* Time `trial_steps` steps for each candidate lanes-per-node on the current problem
+ * and keep the fastest.  Requires the state to be untouched since the family build
+ * (step 0); leaves it so.  *chosen (may be NULL) receives the choice. */
+int pd_autotune(pd_ctx *ctx, int64_t trial_steps, int32_t *chosen);
+
+/* Problem and layout sizes. */
+int pd_get_info(const pd_ctx *ctx, pd_info *info);
+
+/* Device time of the last pd_step call in milliseconds (HIP events recorded on the
+ * context's stream around that call's kernels); synchronising. */
+int pd_last_step_ms(pd_ctx *ctx, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDMI_H */

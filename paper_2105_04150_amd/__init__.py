@@ -1,0 +1,157 @@
+"""MI355X-native bond-based PMB peridynamics (HIP kernels behind a C ABI).
+
+``_binding`` exposes every C entry point of ``include/pdmi.h`` under its own name;
+``Simulation`` is a small owner of one context.  Importing the package does not need
+a GPU; creating a context does, and fails loudly if ``libpdmi.so`` is missing.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+from . import _binding as B
+from ._binding import (PD_BC_DISP, PD_BC_VEL, PD_EULER_CROMER, PD_EULER_FORWARD, PD_FP32,  # noqa: F401
+                       PD_FP64, PD_ORDER_MORTON, PD_ORDER_NATURAL, PD_SCHED_CONST, PD_SCHED_LINEAR,
+                       PD_VELOCITY_VERLET, PdmiError)
+
+SCHEMES = {"euler_cromer": PD_EULER_CROMER, "velocity_verlet": PD_VELOCITY_VERLET,
+           "forward_euler": PD_EULER_FORWARD}
+ORDERS = {"natural": PD_ORDER_NATURAL, "morton": PD_ORDER_MORTON}
+
+
+class Simulation:
+    """Owns one library context (one HIP stream, one or more instances)."""
+
+    def __init__(self, device: int = 0, precision: int = PD_FP64, stream: Optional[int] = None):
+        self.ctx = B.pd_create(device, precision, stream)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            B.pd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # setup
+    def build_family(self, coords, horizon, order="natural"):
+        B.pd_build_family(self.ctx, coords, horizon, ORDERS.get(order, order))
+
+    def build_family_batch(self, coords_list, horizons, order="natural"):
+        B.pd_build_family_batch(self.ctx, coords_list, horizons, ORDERS.get(order, order))
+
+    def family(self, inst=0):
+        return B.pd_get_family(self.ctx, inst)
+
+    def size(self, inst=0):
+        return B.pd_instance_size(self.ctx, inst)
+
+    def set_material(self, rho, c, s0, eta=0.0, volume=1.0, volumes=None, inst=0):
+        B.pd_set_material(self.ctx, inst, rho, c, s0, eta, volume, volumes)
+
+    def set_bond_stiffness(self, k, inst=0):
+        B.pd_set_bond_stiffness(self.ctx, inst, k)
+
+    def break_bonds(self, broken, inst=0):
+        B.pd_break_bonds(self.ctx, inst, broken)
+
+    def set_bcs(self, nodes, comp_mask, kind, value, sched, inst=0):
+        B.pd_set_bcs(self.ctx, inst, nodes, comp_mask, kind, value, sched)
+
+    def clear_bcs(self, inst=0):
+        B.pd_clear_bcs(self.ctx, inst)
+
+    def set_body_force(self, b_hat, magnitude, inst=0):
+        B.pd_set_body_force(self.ctx, inst, b_hat, magnitude)
+
+    def set_integrator(self, scheme, dt):
+        B.pd_set_integrator(self.ctx, SCHEMES.get(scheme, scheme), dt)
+
+    def set_lanes_per_node(self, lanes):
+        B.pd_set_lanes_per_node(self.ctx, lanes)
+
+    def autotune(self, trial_steps=20):
+        return B.pd_autotune(self.ctx, trial_steps)
+
+    # stepping and readout
+    def step(self, nsteps):
+        B.pd_step(self.ctx, nsteps)
+
+    def sync(self):
+        B.pd_sync(self.ctx)
+
+    @property
+    def step_count(self):
+        return B.pd_get_step(self.ctx)
+
+    def u(self, inst=0):
+        return B.pd_get_u(self.ctx, inst)
+
+    def v(self, inst=0):
+        return B.pd_get_v(self.ctx, inst)
+
+    def a(self, inst=0):
+        return B.pd_get_a(self.ctx, inst)
+
+    def damage(self, inst=0):
+        return B.pd_get_damage(self.ctx, inst)
+
+    def broken(self, inst=0):
+        return B.pd_get_broken(self.ctx, inst)
+
+    def set_state(self, u=None, v=None, a=None, broken=None, inst=0):
+        B.pd_set_state(self.ctx, inst, u, v, a, broken)
+
+    def set_step(self, step):
+        B.pd_set_step(self.ctx, step)
+
+    def info(self):
+        return B.pd_get_info(self.ctx)
+
+    def last_step_ms(self):
+        return B.pd_last_step_ms(self.ctx)
+
+
+def apply_workload(sim: Simulation, w, inst: int = 0, row_ptr=None, col=None) -> None:
+    """Install a synthetic workload's material, BCs, notch, stiffness field and loads.
+
+    ``w`` is a ``pd_inputs.Workload``; its family must already be built on ``sim``.
+    The notch mask and stiffness field are input data generated from the library's own
+    family (pd_get_family).
+    """
+    import pd_inputs as pi
+    if row_ptr is None:
+        row_ptr, col = sim.family(inst)
+    sim.set_material(w.rho, w.c, w.s0, 0.0, w.volume, inst=inst)
+    for bc in w.bcs:
+        sim.set_bcs(bc.nodes, bc.comp_mask, bc.kind, bc.value, bc.sched, inst=inst)
+    if w.notch is not None:
+        sim.break_bonds(pi.notch_mask(w.ijk, row_ptr, col, *w.notch), inst=inst)
+    if w.stiffness_field is not None:
+        sig, ell, seed = w.stiffness_field
+        g = pi.gaussian_node_field(w.dims, sig, ell, seed)
+        sim.set_bond_stiffness(pi.slot_stiffness(w.c, g, row_ptr, col), inst=inst)
+    if w.body_force is not None:
+        bhat, bmag = w.body_force
+        sim.set_body_force(bhat, bmag, inst=inst)
+
+
+def simulation_for(w, precision: int = PD_FP64, lanes: int = 0, device: int = 0, order=None) -> Simulation:
+    """A single-instance Simulation set up for workload ``w`` (family built on the host)."""
+    sim = Simulation(device, precision)
+    if lanes:
+        sim.set_lanes_per_node(lanes)
+    sim.build_family(w.coords, w.horizon, order or w.order)
+    sim.set_integrator(w.scheme, w.dt)
+    apply_workload(sim, w)
+    return sim

@@ -1,0 +1,284 @@
+"""ctypes binding of libpdmi.so: the C ABI of include/pdmi.h, argument marshalling only.
+
+Every function here has the name of the C entry point it wraps, converts NumPy arrays
+to pointers, and raises ``PdmiError`` on a non-zero status.  All computation happens
+in the library's HIP kernels; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpdmi.so")
+
+PD_OK, PD_EINVAL, PD_ENOMEM, PD_EHIP, PD_ESTATE, PD_ENONFINITE, PD_ERANGE = 0, -1, -2, -3, -4, -5, -6
+PD_FP64, PD_FP32 = 0, 1
+PD_ORDER_NATURAL, PD_ORDER_MORTON = 0, 1
+PD_EULER_CROMER, PD_VELOCITY_VERLET, PD_EULER_FORWARD = 0, 1, 2
+PD_BC_DISP, PD_BC_VEL = 1, 2
+PD_SCHED_CONST, PD_SCHED_LINEAR = 0, 1
+
+SYMBOLS = [
+    "pd_create", "pd_destroy", "pd_last_error", "pd_build_family", "pd_build_family_batch",
+    "pd_num_instances", "pd_instance_size", "pd_get_family", "pd_set_material", "pd_set_bond_stiffness",
+    "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_body_force", "pd_set_integrator",
+    "pd_step", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
+    "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_lanes_per_node", "pd_autotune",
+    "pd_get_info", "pd_last_step_ms",
+]
+
+
+class PdmiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pdmi error {code}: {msg}")
+        self.code = code
+
+
+class pd_material(C.Structure):
+    _fields_ = [("rho", C.c_double), ("c", C.c_double), ("s0", C.c_double), ("eta", C.c_double),
+                ("volume", C.c_double), ("volumes", C.c_void_p)]
+
+
+class pd_info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_slots", C.c_int64), ("n_nodes_dev", C.c_int64),
+                ("n_slots_dev", C.c_int64), ("n_instances", C.c_int32), ("lanes_per_node", C.c_int32),
+                ("precision", C.c_int32), ("scheme", C.c_int32), ("model_bytes_per_step", C.c_double)]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the built library; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2105_04150_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "pd_create": [P, C.c_int, C.c_int, P],
+        "pd_destroy": [P],
+        "pd_build_family": [P, i64, P, d, C.c_int],
+        "pd_build_family_batch": [P, i32, P, P, P, C.c_int],
+        "pd_num_instances": [P, P],
+        "pd_instance_size": [P, i32, P, P],
+        "pd_get_family": [P, i32, P, P, P],
+        "pd_set_material": [P, i32, P],
+        "pd_set_bond_stiffness": [P, i32, P],
+        "pd_break_bonds": [P, i32, P],
+        "pd_set_bcs": [P, i32, i64, P, C.c_int, C.c_int, P, C.c_int],
+        "pd_clear_bcs": [P, i32],
+        "pd_set_body_force": [P, i32, P, d],
+        "pd_set_integrator": [P, C.c_int, d],
+        "pd_step": [P, i64],
+        "pd_sync": [P],
+        "pd_get_step": [P, P],
+        "pd_get_u": [P, i32, P], "pd_get_v": [P, i32, P], "pd_get_a": [P, i32, P],
+        "pd_get_damage": [P, i32, P],
+        "pd_get_broken": [P, i32, P],
+        "pd_set_state": [P, i32, P, P, P, P],
+        "pd_set_step": [P, i64],
+        "pd_set_lanes_per_node": [P, C.c_int],
+        "pd_autotune": [P, i64, P],
+        "pd_get_info": [P, P],
+        "pd_last_step_ms": [P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.pd_last_error.argtypes = [P]
+    lib.pd_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    out = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and out.size != int(np.prod(shape)):
+        raise ValueError(f"expected {shape} doubles, got {out.shape}")
+    return out
+
+
+def _check(ctx, rc: int):
+    if rc != PD_OK:
+        msg = load().pd_last_error(ctx)
+        raise PdmiError(rc, (msg or b"").decode())
+
+
+# ------------------------------------------------------------------ one function per entry point
+
+def pd_create(device: int = 0, precision: int = PD_FP64, stream: Optional[int] = None) -> C.c_void_p:
+    lib = load()
+    h = C.c_void_p()
+    rc = lib.pd_create(C.byref(h), int(device), int(precision), C.c_void_p(stream) if stream else None)
+    if rc != PD_OK:
+        raise PdmiError(rc, (lib.pd_last_error(None) or b"").decode())
+    return h
+
+
+def pd_destroy(ctx) -> None:
+    load().pd_destroy(ctx)
+
+
+def pd_build_family(ctx, coords, horizon: float, order: int = PD_ORDER_NATURAL) -> None:
+    x = _f64(coords)
+    _check(ctx, load().pd_build_family(ctx, x.shape[0], _p(x), float(horizon), int(order)))
+
+
+def pd_build_family_batch(ctx, coords_list, horizons, order: int = PD_ORDER_NATURAL) -> None:
+    xs = [_f64(x) for x in coords_list]
+    n = np.array([x.shape[0] for x in xs], dtype=np.int64)
+    ptrs = (C.c_void_p * len(xs))(*[x.ctypes.data for x in xs])
+    h = _f64(horizons)
+    _check(ctx, load().pd_build_family_batch(ctx, len(xs), _p(n), ptrs, _p(h), int(order)))
+
+
+def pd_num_instances(ctx) -> int:
+    v = C.c_int32()
+    _check(ctx, load().pd_num_instances(ctx, C.byref(v)))
+    return v.value
+
+
+def pd_instance_size(ctx, inst: int = 0):
+    n, nnz = C.c_int64(), C.c_int64()
+    _check(ctx, load().pd_instance_size(ctx, inst, C.byref(n), C.byref(nnz)))
+    return n.value, nnz.value
+
+
+def pd_get_family(ctx, inst: int = 0):
+    n, nnz = pd_instance_size(ctx, inst)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(max(nnz, 1), dtype=np.int32)
+    _check(ctx, load().pd_get_family(ctx, inst, _p(row_ptr), _p(col), None))
+    return row_ptr, col[:nnz]
+
+
+def _inst_n(ctx, inst: int) -> int:
+    return pd_instance_size(ctx, inst)[0]
+
+
+def pd_set_material(ctx, inst: int, rho: float, c: float, s0: float, eta: float = 0.0,
+                    volume: float = 1.0, volumes=None) -> None:
+    vols = _f64(volumes)
+    m = pd_material(float(rho), float(c), float(s0), float(eta), float(volume),
+                    None if vols is None else vols.ctypes.data)
+    _check(ctx, load().pd_set_material(ctx, inst, C.byref(m)))
+
+
+def pd_set_bond_stiffness(ctx, inst: int, k) -> None:
+    kk = _f64(k)
+    _check(ctx, load().pd_set_bond_stiffness(ctx, inst, _p(kk)))
+
+
+def pd_break_bonds(ctx, inst: int, broken) -> None:
+    b = np.ascontiguousarray(broken, dtype=np.uint8)
+    _check(ctx, load().pd_break_bonds(ctx, inst, _p(b)))
+
+
+def pd_set_bcs(ctx, inst: int, nodes, comp_mask: int, kind: int, value, sched: int) -> None:
+    nd = np.ascontiguousarray(nodes, dtype=np.int64)
+    val = _f64(value, (3,))
+    _check(ctx, load().pd_set_bcs(ctx, inst, nd.shape[0], _p(nd), int(comp_mask), int(kind), _p(val),
+                                  int(sched)))
+
+
+def pd_clear_bcs(ctx, inst: int = 0) -> None:
+    _check(ctx, load().pd_clear_bcs(ctx, inst))
+
+
+def pd_set_body_force(ctx, inst: int, b_hat, magnitude: float) -> None:
+    b = _f64(b_hat)
+    _check(ctx, load().pd_set_body_force(ctx, inst, _p(b), float(magnitude)))
+
+
+def pd_set_integrator(ctx, scheme: int, dt: float) -> None:
+    _check(ctx, load().pd_set_integrator(ctx, int(scheme), float(dt)))
+
+
+def pd_step(ctx, nsteps: int) -> None:
+    _check(ctx, load().pd_step(ctx, int(nsteps)))
+
+
+def pd_sync(ctx) -> None:
+    _check(ctx, load().pd_sync(ctx))
+
+
+def pd_get_step(ctx) -> int:
+    v = C.c_int64()
+    _check(ctx, load().pd_get_step(ctx, C.byref(v)))
+    return v.value
+
+
+def _get3(fn, ctx, inst):
+    out = np.zeros((_inst_n(ctx, inst), 3))
+    _check(ctx, fn(ctx, inst, _p(out)))
+    return out
+
+
+def pd_get_u(ctx, inst: int = 0) -> np.ndarray:
+    return _get3(load().pd_get_u, ctx, inst)
+
+
+def pd_get_v(ctx, inst: int = 0) -> np.ndarray:
+    return _get3(load().pd_get_v, ctx, inst)
+
+
+def pd_get_a(ctx, inst: int = 0) -> np.ndarray:
+    return _get3(load().pd_get_a, ctx, inst)
+
+
+def pd_get_damage(ctx, inst: int = 0) -> np.ndarray:
+    out = np.zeros(_inst_n(ctx, inst))
+    _check(ctx, load().pd_get_damage(ctx, inst, _p(out)))
+    return out
+
+
+def pd_get_broken(ctx, inst: int = 0) -> np.ndarray:
+    nnz = pd_instance_size(ctx, inst)[1]
+    out = np.zeros(max(nnz, 1), dtype=np.uint8)
+    _check(ctx, load().pd_get_broken(ctx, inst, _p(out)))
+    return out[:nnz]
+
+
+def pd_set_state(ctx, inst: int = 0, u=None, v=None, a=None, broken=None) -> None:
+    uu, vv, aa = _f64(u), _f64(v), _f64(a)
+    bb = None if broken is None else np.ascontiguousarray(broken, dtype=np.uint8)
+    _check(ctx, load().pd_set_state(ctx, inst, _p(uu), _p(vv), _p(aa), _p(bb)))
+
+
+def pd_set_step(ctx, step: int) -> None:
+    _check(ctx, load().pd_set_step(ctx, int(step)))
+
+
+def pd_set_lanes_per_node(ctx, lanes: int) -> None:
+    _check(ctx, load().pd_set_lanes_per_node(ctx, int(lanes)))
+
+
+def pd_autotune(ctx, trial_steps: int) -> int:
+    v = C.c_int32()
+    _check(ctx, load().pd_autotune(ctx, int(trial_steps), C.byref(v)))
+    return v.value
+
+
+def pd_get_info(ctx) -> dict:
+    info = pd_info()
+    _check(ctx, load().pd_get_info(ctx, C.byref(info)))
+    return {k: getattr(info, k) for k, _ in pd_info._fields_}
+
+
+def pd_last_step_ms(ctx) -> float:
+    v = C.c_double()
+    _check(ctx, load().pd_last_step_ms(ctx, C.byref(v)))
+    return v.value

@@ -1,0 +1,1430 @@
+// pdmi_host.cpp -- host runtime behind the C ABI of include/pdmi.h.
+//
+// Responsibilities: argument validation, the family search (cell list on the host;
+// the family is built once per model, paper Sec. 3), node renumbering, the sliced
+// device layout, boundary-condition tables, stream-ordered stepping with hipGraph
+// replay, and synchronising readout in the caller's node and slot order.
+//
+// Built with -ffp-contract=off: the family test ((dx^2 + dy^2) + dz^2) <= delta^2 is
+// evaluated exactly as written, without fused multiply-add.
+#include "pdmi.h"
+#include "pdmi_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <limits>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+using namespace pdmi;
+
+namespace {
+
+constexpr int kDefaultLanes = 1;
+constexpr int64_t kGraphChunk = 64;  // steps per captured graph (even: buffer parity repeats)
+
+struct PdError : std::exception {
+    int code;
+    std::string msg;
+    PdError(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw PdError(code, msg); }
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? PD_ENOMEM : PD_EHIP,
+                              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Owning device allocation.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t n)
+    {
+        release();
+        if (n == 0) n = 16;
+        hip_check(hipMalloc(&p, n), "hipMalloc");
+        bytes = n;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct Inst {
+    int64_t n = 0, nnz = 0;
+    double horizon = 0.0;
+    std::vector<double> x;           // user order, n*3
+    std::vector<int64_t> row_ptr;    // user CSR
+    std::vector<int32_t> col;
+    // material and loads
+    double rho = 1.0, c = 1.0, s0 = std::numeric_limits<double>::infinity(), eta = 0.0, volume = 1.0;
+    std::vector<double> vols;        // user order; empty = uniform
+    std::vector<double> kslot;       // user CSR order; empty = c
+    std::vector<double> bhat;        // user order n*3; empty = none
+    double bmag = 0.0;
+    std::vector<uint8_t> bc_kind, bc_sched;  // n*3
+    std::vector<double> bc_val;              // n*3
+    // device layout
+    std::vector<int64_t> perm;       // device-local node -> user node, -1 = padding
+    std::vector<int64_t> iperm;      // user node -> device-local node
+    std::vector<int32_t> dslot_user; // device slot (instance-local) -> user slot, -1 = padding
+    std::vector<int64_t> s_start;    // first device slot (instance-local) of every slice
+    std::vector<int64_t> s_T;        // 64-wide slot rows of every slice
+    int64_t node_off = 0, n_pad = 0, slice_off = 0, nslices = 0, dslot_off = 0, n_dslots = 0;
+};
+
+}  // namespace
+
+struct pd_ctx {
+    int device = 0;
+    int precision = PD_FP64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    std::vector<Inst> inst;
+    int order = PD_ORDER_NATURAL;
+    int lanes = kDefaultLanes;
+    int scheme = PD_EULER_CROMER;
+    double dt = 1.0e-7;
+    int64_t step = 0;
+    int cur = 0;                     // node-record buffer holding u of level `step`
+    bool a_valid = false;            // velocity Verlet: a holds the acceleration of level `step`
+    bool vv_ahead = false;           // velocity Verlet: buffer 1-cur holds u of level step+1
+    bool built = false;
+    bool use_graphs = true;
+
+    int64_t nn = 0, ns = 0, nslices = 0;
+    bool has_stiff = false, has_vol = false, has_body = false;
+    DevBuf rec[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc, step_base,
+        status, phi;
+
+    // graphs: [parity][mode] for chunks of kGraphChunk steps
+    hipGraphExec_t graph[2][4] = {{nullptr}};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+
+    ~pd_ctx()
+    {
+        drop_graphs();
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+    void drop_graphs()
+    {
+        for (auto& row : graph)
+            for (auto& g : row)
+                if (g) {
+                    (void)hipGraphExecDestroy(g);
+                    g = nullptr;
+                }
+    }
+};
+
+namespace {
+
+std::string g_create_error;
+
+template <typename F>
+int guarded(pd_ctx* ctx, F&& f)
+{
+    try {
+        f();
+        if (ctx) ctx->err.clear();
+        return PD_OK;
+    } catch (const PdError& e) {
+        if (ctx) ctx->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (ctx) ctx->err = "host allocation failed";
+        return PD_ENOMEM;
+    } catch (const std::exception& e) {
+        if (ctx) ctx->err = e.what();
+        return PD_EINVAL;
+    } catch (...) {
+        if (ctx) ctx->err = "unknown failure";
+        return PD_EINVAL;
+    }
+}
+
+void set_device(pd_ctx* ctx) { hip_check(hipSetDevice(ctx->device), "hipSetDevice"); }
+
+void require_built(const pd_ctx* ctx)
+{
+    if (!ctx->built) fail(PD_ESTATE, "no problem: call pd_build_family first");
+}
+
+Inst& instance(pd_ctx* ctx, int32_t inst)
+{
+    require_built(ctx);
+    if (inst < 0 || inst >= static_cast<int32_t>(ctx->inst.size()))
+        fail(PD_EINVAL, "instance index out of range");
+    return ctx->inst[inst];
+}
+
+unsigned n_threads()
+{
+    unsigned t = std::thread::hardware_concurrency();
+    return std::max(1u, std::min(t, 16u));
+}
+
+template <typename F>
+void parallel_for(int64_t n, F&& f)
+{
+    const unsigned nt = n_threads();
+    if (nt <= 1 || n < 4096) {
+        f(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        const int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+        if (lo >= hi) break;
+        th.emplace_back([&f, lo, hi] { f(lo, hi); });
+    }
+    for (auto& x : th) x.join();
+}
+
+// ------------------------------------------------------------------ family search
+
+// Family of every node (Eq. family, self excluded): bin nodes into cubic cells slightly
+// wider than delta, test the 27 surrounding cells, sort each row ascending.
+void family_search(int64_t n, const double* x, double delta, std::vector<int64_t>& row_ptr,
+                   std::vector<int32_t>& col)
+{
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = x[d];
+    for (int64_t i = 1; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], x[3 * i + d]);
+            hi[d] = std::max(hi[d], x[3 * i + d]);
+        }
+    const double h = delta * (1.0 + 1e-9);
+    int64_t dim[3];
+    for (int d = 0; d < 3; ++d) {
+        const double span = (hi[d] - lo[d]) / h;
+        if (!(span < 4.0e6)) fail(PD_ERANGE, "domain spans too many horizon cells");
+        dim[d] = static_cast<int64_t>(std::floor(span)) + 1;
+    }
+    const int64_t ncell = dim[0] * dim[1] * dim[2];
+    if (ncell > (int64_t(1) << 31)) fail(PD_ERANGE, "too many cells for the family search");
+    auto cell_of = [&](int64_t i, int64_t* c3) {
+        for (int d = 0; d < 3; ++d) {
+            int64_t c = static_cast<int64_t>(std::floor((x[3 * i + d] - lo[d]) / h));
+            c3[d] = std::min(std::max<int64_t>(c, 0), dim[d] - 1);
+        }
+    };
+    std::vector<int64_t> cstart(ncell + 1, 0), items(n);
+    std::vector<int64_t> cid(n);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c3[3];
+        cell_of(i, c3);
+        cid[i] = (c3[2] * dim[1] + c3[1]) * dim[0] + c3[0];
+        ++cstart[cid[i] + 1];
+    }
+    for (int64_t c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
+    {
+        std::vector<int64_t> fill(cstart.begin(), cstart.end() - 1);
+        for (int64_t i = 0; i < n; ++i) items[fill[cid[i]]++] = i;
+    }
+    const double d2max = delta * delta;
+    std::vector<int64_t> count(n, 0);
+    // pass 1: counts; pass 2: fill and sort
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            row_ptr.assign(n + 1, 0);
+            for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + count[i];
+            if (row_ptr[n] > std::numeric_limits<int32_t>::max())
+                fail(PD_ERANGE, "family has 2^31 or more slots");
+            col.assign(static_cast<size_t>(row_ptr[n]), 0);
+        }
+        parallel_for(n, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                int64_t c3[3];
+                cell_of(i, c3);
+                int64_t w = pass ? row_ptr[i] : 0;
+                for (int64_t z = std::max<int64_t>(c3[2] - 1, 0); z <= std::min(c3[2] + 1, dim[2] - 1); ++z)
+                    for (int64_t y = std::max<int64_t>(c3[1] - 1, 0); y <= std::min(c3[1] + 1, dim[1] - 1); ++y)
+                        for (int64_t xx = std::max<int64_t>(c3[0] - 1, 0); xx <= std::min(c3[0] + 1, dim[0] - 1);
+                             ++xx) {
+                            const int64_t c = (z * dim[1] + y) * dim[0] + xx;
+                            for (int64_t p = cstart[c]; p < cstart[c + 1]; ++p) {
+                                const int64_t j = items[p];
+                                if (j == i) continue;
+                                const double a = x[3 * j + 0] - x[3 * i + 0];
+                                const double b = x[3 * j + 1] - x[3 * i + 1];
+                                const double e = x[3 * j + 2] - x[3 * i + 2];
+                                double d2 = a * a + b * b;
+                                d2 = d2 + e * e;
+                                if (!(d2 <= d2max)) continue;
+                                if (pass) col[w] = static_cast<int32_t>(j);
+                                ++w;
+                            }
+                        }
+                if (pass)
+                    std::sort(col.begin() + row_ptr[i], col.begin() + w);
+                else
+                    count[i] = w;
+            }
+        });
+    }
+}
+
+// ------------------------------------------------------------------ device layout
+
+// Spacing estimate: the smallest bond length among the first rows.
+double spacing_estimate(const Inst& I)
+{
+    double best = std::numeric_limits<double>::infinity();
+    const int64_t rows = std::min<int64_t>(I.n, 4096);
+    for (int64_t i = 0; i < rows; ++i)
+        for (int64_t b = I.row_ptr[i]; b < I.row_ptr[i + 1]; ++b) {
+            const int64_t j = I.col[b];
+            double s = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double t = I.x[3 * j + d] - I.x[3 * i + d];
+                s += t * t;
+            }
+            best = std::min(best, std::sqrt(s));
+        }
+    if (!(best > 0.0) || !std::isfinite(best)) best = I.horizon > 0 ? I.horizon : 1.0;
+    return best;
+}
+
+uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+// Device-local node order of one instance.
+void node_order(Inst& I, int order, double h)
+{
+    I.iperm.assign(I.n, 0);
+    std::vector<int64_t> p(I.n);
+    std::iota(p.begin(), p.end(), 0);
+    if (order == PD_ORDER_MORTON && I.n > 1) {
+        double lo[3];
+        for (int d = 0; d < 3; ++d) lo[d] = I.x[d];
+        for (int64_t i = 1; i < I.n; ++i)
+            for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], I.x[3 * i + d]);
+        std::vector<uint64_t> key(I.n);
+        for (int64_t i = 0; i < I.n; ++i) {
+            uint64_t k = 0;
+            for (int d = 0; d < 3; ++d) {
+                double q = std::floor((I.x[3 * i + d] - lo[d]) / h + 0.5);
+                q = std::min(std::max(q, 0.0), 2097151.0);
+                k |= spread3(static_cast<uint64_t>(q)) << d;
+            }
+            key[i] = k;
+        }
+        std::stable_sort(p.begin(), p.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+    }
+    for (int64_t i = 0; i < I.n; ++i) I.iperm[p[i]] = i;
+    I.perm = std::move(p);
+}
+
+// Order of each row's slots on the device: by the bond offset rounded to the lattice
+// spacing (z, then y, then x), so lanes of neighbouring nodes visit neighbours at the
+// same relative position together.  On a natural-order lattice this is ascending j.
+std::vector<int32_t> slot_ranks(const Inst& I, double h)
+{
+    std::vector<int32_t> order(static_cast<size_t>(I.nnz));
+    parallel_for(I.n, [&](int64_t i0, int64_t i1) {
+        std::vector<std::pair<int64_t, int32_t>> tmp;
+        for (int64_t i = i0; i < i1; ++i) {
+            const int64_t b0 = I.row_ptr[i], b1 = I.row_ptr[i + 1];
+            tmp.clear();
+            for (int64_t b = b0; b < b1; ++b) {
+                const int64_t j = I.col[b];
+                int64_t q[3];
+                for (int d = 0; d < 3; ++d)
+                    q[d] = static_cast<int64_t>(std::llround((I.x[3 * j + d] - I.x[3 * i + d]) / h));
+                const int64_t key = ((q[2] + 4096) * 8192 + (q[1] + 4096)) * 8192 + (q[0] + 4096);
+                tmp.emplace_back(key, static_cast<int32_t>(b - b0));
+            }
+            std::sort(tmp.begin(), tmp.end());
+            for (int64_t r = 0; r < b1 - b0; ++r) order[b0 + r] = tmp[r].second;
+        }
+    });
+    return order;
+}
+
+InstParams make_params(const Inst& I)
+{
+    InstParams p{};
+    p.c = I.c;
+    p.q0 = I.s0 * (2.0 + I.s0);
+    p.rho = I.rho;
+    p.eta = I.eta;
+    p.volume = I.volume;
+    p.bmag = I.bmag;
+    p.has_body = I.bhat.empty() ? 0 : 1;
+    return p;
+}
+
+// Setup-path copy from pageable host memory; returns once the source may be freed.
+void upload(const DevBuf& b, const void* src, size_t bytes, size_t offset_bytes, hipStream_t s)
+{
+    if (bytes == 0) return;
+    if (offset_bytes + bytes > b.bytes) fail(PD_EINVAL, "internal: upload beyond buffer");
+    hip_check(hipMemcpyAsync(static_cast<char*>(b.p) + offset_bytes, src, bytes, hipMemcpyHostToDevice, s),
+              "hipMemcpyAsync H2D");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+void download(void* dst, const DevBuf& b, size_t bytes, size_t offset_bytes, hipStream_t s)
+{
+    if (bytes == 0) return;
+    if (offset_bytes + bytes > b.bytes) fail(PD_EINVAL, "internal: download beyond buffer");
+    hip_check(hipMemcpyAsync(dst, static_cast<const char*>(b.p) + offset_bytes, bytes, hipMemcpyDeviceToHost, s),
+              "hipMemcpyAsync D2H");
+}
+
+void sync(pd_ctx* ctx) { hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"); }
+
+size_t real_size(const pd_ctx* ctx) { return ctx->precision == PD_FP64 ? 8 : 4; }
+
+// (Re)build the whole device problem for the current lanes-per-node, keeping the state
+// given in user order (nullptr = zero / intact).
+struct HostState {
+    std::vector<std::vector<double>> u, v, a;   // per instance, n*3
+    std::vector<std::vector<uint8_t>> broken;   // per instance, nnz
+};
+
+void upload_params(pd_ctx* ctx)
+{
+    std::vector<InstParams> p;
+    for (auto& I : ctx->inst) p.push_back(make_params(I));
+    upload(ctx->params, p.data(), p.size() * sizeof(InstParams), 0, ctx->stream);
+}
+
+void upload_bcs(pd_ctx* ctx)
+{
+    std::vector<int32_t> id(static_cast<size_t>(ctx->nn), kNodePad);
+    std::vector<BCRec> recs;
+    for (auto& I : ctx->inst) {
+        for (int64_t l = 0; l < I.n_pad; ++l) {
+            const int64_t u = I.perm[l];
+            if (u < 0) continue;
+            int32_t code = 0;
+            BCRec r{};
+            for (int d = 0; d < 3; ++d) {
+                const int kind = I.bc_kind[3 * u + d];
+                if (!kind) continue;
+                code |= kind << (2 * d);
+                code |= (I.bc_sched[3 * u + d] & 1) << (8 + d);
+                r.A[d] = I.bc_val[3 * u + d];
+            }
+            if (code == 0) {
+                id[I.node_off + l] = kNodeFree;
+            } else {
+                r.code = code;
+                id[I.node_off + l] = static_cast<int32_t>(recs.size());
+                recs.push_back(r);
+            }
+        }
+    }
+    upload(ctx->bc_id, id.data(), id.size() * sizeof(int32_t), 0, ctx->stream);
+    ctx->bc.alloc(std::max<size_t>(recs.size(), 1) * sizeof(BCRec));
+    upload(ctx->bc, recs.data(), recs.size() * sizeof(BCRec), 0, ctx->stream);
+    sync(ctx);
+}
+
+void upload_stiffness(pd_ctx* ctx)
+{
+    ctx->has_stiff = false;
+    for (auto& I : ctx->inst) ctx->has_stiff |= !I.kslot.empty();
+    if (!ctx->has_stiff) {
+        ctx->kslot.release();
+        return;
+    }
+    ctx->kslot.alloc(static_cast<size_t>(ctx->ns) * sizeof(double));
+    for (auto& I : ctx->inst) {
+        std::vector<double> k(static_cast<size_t>(I.n_dslots), 0.0);
+        for (int64_t s = 0; s < I.n_dslots; ++s) {
+            const int32_t b = I.dslot_user[s];
+            if (b >= 0) k[s] = I.kslot.empty() ? I.c : I.kslot[b];
+        }
+        upload(ctx->kslot, k.data(), k.size() * sizeof(double), I.dslot_off * sizeof(double), ctx->stream);
+        sync(ctx);
+    }
+}
+
+void upload_volumes(pd_ctx* ctx)
+{
+    ctx->has_vol = false;
+    for (auto& I : ctx->inst) ctx->has_vol |= !I.vols.empty();
+    if (!ctx->has_vol) {
+        ctx->vol.release();
+        return;
+    }
+    std::vector<double> V(static_cast<size_t>(ctx->nn), 0.0);
+    for (auto& I : ctx->inst)
+        for (int64_t l = 0; l < I.n_pad; ++l) {
+            const int64_t u = I.perm[l];
+            V[I.node_off + l] = u < 0 ? I.volume : (I.vols.empty() ? I.volume : I.vols[u]);
+        }
+    ctx->vol.alloc(V.size() * sizeof(double));
+    upload(ctx->vol, V.data(), V.size() * sizeof(double), 0, ctx->stream);
+    sync(ctx);
+}
+
+void upload_body(pd_ctx* ctx)
+{
+    ctx->has_body = false;
+    for (auto& I : ctx->inst) ctx->has_body |= !I.bhat.empty();
+    if (!ctx->has_body) {
+        ctx->bhat.release();
+        return;
+    }
+    const int64_t nn = ctx->nn;
+    std::vector<double> B(static_cast<size_t>(3 * nn), 0.0);
+    for (auto& I : ctx->inst) {
+        if (I.bhat.empty()) continue;
+        for (int64_t l = 0; l < I.n_pad; ++l) {
+            const int64_t u = I.perm[l];
+            if (u < 0) continue;
+            for (int d = 0; d < 3; ++d) B[d * nn + I.node_off + l] = I.bhat[3 * u + d];
+        }
+    }
+    ctx->bhat.alloc(B.size() * sizeof(double));
+    upload(ctx->bhat, B.data(), B.size() * sizeof(double), 0, ctx->stream);
+    sync(ctx);
+}
+
+// Write one instance's state (user order) into the device buffers.
+void upload_state(pd_ctx* ctx, const Inst& I, const double* u, const double* v, const double* a)
+{
+    const int64_t nn = ctx->nn;
+    if (u) {
+        std::vector<double> rec(static_cast<size_t>(6 * I.n_pad), 0.0);
+        for (int64_t l = 0; l < I.n_pad; ++l) {
+            const int64_t p = I.perm[l];
+            if (p < 0) continue;
+            for (int d = 0; d < 3; ++d) rec[6 * l + d] = I.x[3 * p + d];
+            if (ctx->precision == PD_FP64) {
+                for (int d = 0; d < 3; ++d) rec[6 * l + 3 + d] = u[3 * p + d];
+            } else {
+                float f[3] = {float(u[3 * p]), float(u[3 * p + 1]), float(u[3 * p + 2])};
+                std::memcpy(&rec[6 * l + 3], f, sizeof f);
+            }
+        }
+        for (int b = 0; b < 2; ++b)
+            upload(ctx->rec[b], rec.data(), rec.size() * sizeof(double), I.node_off * 48, ctx->stream);
+        sync(ctx);
+    }
+    auto put_soa = [&](DevBuf& buf, const double* src) {
+        if (!src) return;
+        for (int d = 0; d < 3; ++d) {
+            if (ctx->precision == PD_FP64) {
+                std::vector<double> h(static_cast<size_t>(I.n_pad), 0.0);
+                for (int64_t l = 0; l < I.n_pad; ++l)
+                    if (I.perm[l] >= 0) h[l] = src[3 * I.perm[l] + d];
+                upload(buf, h.data(), h.size() * 8, (d * nn + I.node_off) * 8, ctx->stream);
+                sync(ctx);
+            } else {
+                std::vector<float> h(static_cast<size_t>(I.n_pad), 0.0f);
+                for (int64_t l = 0; l < I.n_pad; ++l)
+                    if (I.perm[l] >= 0) h[l] = float(src[3 * I.perm[l] + d]);
+                upload(buf, h.data(), h.size() * 4, (d * nn + I.node_off) * 4, ctx->stream);
+                sync(ctx);
+            }
+        }
+    };
+    put_soa(ctx->v, v);
+    put_soa(ctx->a, a);
+}
+
+void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
+{
+    std::vector<int32_t> colv(static_cast<size_t>(I.n_dslots));
+    const int G = ctx->lanes, W = kWave / G;
+    parallel_for(I.nslices, [&](int64_t s0, int64_t s1) {
+        for (int64_t s = s0; s < s1; ++s)
+            for (int64_t t = 0; t < I.s_T[s]; ++t)
+                for (int lane = 0; lane < kWave; ++lane) {
+                    const int64_t ds = I.s_start[s] + t * kWave + lane;
+                    const int32_t b = I.dslot_user[ds];
+                    if (b < 0) {
+                        // padding names the slot's own node, which is never its own neighbour
+                        colv[ds] = ~static_cast<int32_t>(I.node_off + s * W + lane / G);
+                    } else {
+                        const int32_t j = static_cast<int32_t>(I.node_off + I.iperm[I.col[b]]);
+                        colv[ds] = (broken && broken[b]) ? ~j : j;
+                    }
+                }
+    });
+    upload(ctx->col, colv.data(), colv.size() * sizeof(int32_t), I.dslot_off * sizeof(int32_t), ctx->stream);
+    sync(ctx);
+}
+
+// Download one instance's broken mask (user CSR order).
+std::vector<uint8_t> broken_of(pd_ctx* ctx, const Inst& I)
+{
+    std::vector<int32_t> colv(static_cast<size_t>(I.n_dslots));
+    download(colv.data(), ctx->col, colv.size() * sizeof(int32_t), I.dslot_off * sizeof(int32_t), ctx->stream);
+    sync(ctx);
+    std::vector<uint8_t> out(static_cast<size_t>(I.nnz), 0);
+    for (int64_t s = 0; s < I.n_dslots; ++s) {
+        const int32_t b = I.dslot_user[s];
+        if (b >= 0 && colv[s] < 0) out[b] = 1;
+    }
+    return out;
+}
+
+std::vector<double> soa_of(pd_ctx* ctx, const Inst& I, const DevBuf& buf)
+{
+    const int64_t nn = ctx->nn;
+    std::vector<double> out(static_cast<size_t>(3 * I.n), 0.0);
+    for (int d = 0; d < 3; ++d) {
+        if (ctx->precision == PD_FP64) {
+            std::vector<double> h(static_cast<size_t>(I.n_pad));
+            download(h.data(), buf, h.size() * 8, (d * nn + I.node_off) * 8, ctx->stream);
+            sync(ctx);
+            for (int64_t l = 0; l < I.n_pad; ++l)
+                if (I.perm[l] >= 0) out[3 * I.perm[l] + d] = h[l];
+        } else {
+            std::vector<float> h(static_cast<size_t>(I.n_pad));
+            download(h.data(), buf, h.size() * 4, (d * nn + I.node_off) * 4, ctx->stream);
+            sync(ctx);
+            for (int64_t l = 0; l < I.n_pad; ++l)
+                if (I.perm[l] >= 0) out[3 * I.perm[l] + d] = h[l];
+        }
+    }
+    return out;
+}
+
+std::vector<double> u_of(pd_ctx* ctx, const Inst& I)
+{
+    std::vector<double> rec(static_cast<size_t>(6 * I.n_pad));
+    download(rec.data(), ctx->rec[ctx->cur], rec.size() * 8, I.node_off * 48, ctx->stream);
+    sync(ctx);
+    std::vector<double> out(static_cast<size_t>(3 * I.n), 0.0);
+    for (int64_t l = 0; l < I.n_pad; ++l) {
+        const int64_t p = I.perm[l];
+        if (p < 0) continue;
+        if (ctx->precision == PD_FP64) {
+            for (int d = 0; d < 3; ++d) out[3 * p + d] = rec[6 * l + 3 + d];
+        } else {
+            float f[3];
+            std::memcpy(f, &rec[6 * l + 3], sizeof f);
+            for (int d = 0; d < 3; ++d) out[3 * p + d] = f[d];
+        }
+    }
+    return out;
+}
+
+HostState snapshot(pd_ctx* ctx)
+{
+    HostState S;
+    for (auto& I : ctx->inst) {
+        S.u.push_back(u_of(ctx, I));
+        S.v.push_back(soa_of(ctx, I, ctx->v));
+        S.a.push_back(soa_of(ctx, I, ctx->a));
+        S.broken.push_back(broken_of(ctx, I));
+    }
+    return S;
+}
+
+// Allocate and fill the device problem for ctx->lanes from the instances' user data.
+void build_layout(pd_ctx* ctx, const HostState* S)
+{
+    const int G = ctx->lanes, W = kWave / G;
+    ctx->drop_graphs();
+    int64_t nn = 0, nsl = 0, ns = 0;
+    std::vector<int64_t> sp;
+    std::vector<int32_t> sT, sI;
+    for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
+        Inst& I = ctx->inst[ii];
+        const double h = spacing_estimate(I);
+        node_order(I, ctx->order, h);
+        I.n_pad = (I.n + W - 1) / W * W;
+        I.perm.resize(static_cast<size_t>(I.n_pad), -1);
+        I.node_off = nn;
+        I.nslices = I.n_pad / W;
+        I.slice_off = nsl;
+        I.dslot_off = ns;
+        const std::vector<int32_t> ranks = slot_ranks(I, h);
+        // slice row counts
+        std::vector<int64_t> T(static_cast<size_t>(I.nslices), 0);
+        for (int64_t s = 0; s < I.nslices; ++s)
+            for (int w = 0; w < W; ++w) {
+                const int64_t p = I.perm[s * W + w];
+                if (p >= 0) T[s] = std::max<int64_t>(T[s], (I.row_ptr[p + 1] - I.row_ptr[p] + G - 1) / G);
+            }
+        int64_t nds = 0;
+        std::vector<int64_t> start(static_cast<size_t>(I.nslices));
+        for (int64_t s = 0; s < I.nslices; ++s) {
+            start[s] = nds;
+            nds += T[s] * kWave;
+        }
+        I.n_dslots = nds;
+        I.s_start = start;
+        I.s_T = T;
+        I.dslot_user.assign(static_cast<size_t>(nds), -1);
+        parallel_for(I.nslices, [&](int64_t s0, int64_t s1) {
+            for (int64_t s = s0; s < s1; ++s)
+                for (int w = 0; w < W; ++w) {
+                    const int64_t p = I.perm[s * W + w];
+                    if (p < 0) continue;
+                    const int64_t b0 = I.row_ptr[p], len = I.row_ptr[p + 1] - b0;
+                    for (int64_t r = 0; r < len; ++r) {
+                        const int64_t t = r / G, g = r % G;
+                        I.dslot_user[start[s] + t * kWave + w * G + g] = static_cast<int32_t>(b0 + ranks[b0 + r]);
+                    }
+                }
+        });
+        for (int64_t s = 0; s < I.nslices; ++s) {
+            sp.push_back(ns + start[s]);
+            if (T[s] > std::numeric_limits<int32_t>::max()) fail(PD_ERANGE, "row too long");
+            sT.push_back(static_cast<int32_t>(T[s]));
+            sI.push_back(static_cast<int32_t>(ii));
+        }
+        nn += I.n_pad;
+        nsl += I.nslices;
+        ns += nds;
+    }
+    if (nn >= std::numeric_limits<int32_t>::max() || ns >= std::numeric_limits<int32_t>::max())
+        fail(PD_ERANGE, "device problem needs 2^31 or more nodes or slots");
+    ctx->nn = nn;
+    ctx->nslices = nsl;
+    ctx->ns = ns;
+    const size_t rs = real_size(ctx);
+    for (int b = 0; b < 2; ++b) ctx->rec[b].alloc(static_cast<size_t>(nn) * 48);
+    ctx->v.alloc(static_cast<size_t>(3 * nn) * rs);
+    ctx->a.alloc(static_cast<size_t>(3 * nn) * rs);
+    ctx->col.alloc(static_cast<size_t>(ns) * sizeof(int32_t));
+    ctx->slice_ptr.alloc(sp.size() * sizeof(int64_t));
+    ctx->slice_T.alloc(sT.size() * sizeof(int32_t));
+    ctx->slice_inst.alloc(sI.size() * sizeof(int32_t));
+    ctx->params.alloc(ctx->inst.size() * sizeof(InstParams));
+    ctx->bc_id.alloc(static_cast<size_t>(nn) * sizeof(int32_t));
+    ctx->step_base.alloc(sizeof(int64_t));
+    ctx->status.alloc(sizeof(int32_t));
+    ctx->phi.alloc(static_cast<size_t>(nn) * sizeof(double));
+    hip_check(hipMemsetAsync(ctx->rec[0].p, 0, ctx->rec[0].bytes, ctx->stream), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(ctx->rec[1].p, 0, ctx->rec[1].bytes, ctx->stream), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(ctx->v.p, 0, ctx->v.bytes, ctx->stream), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(ctx->a.p, 0, ctx->a.bytes, ctx->stream), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(ctx->status.p, 0, sizeof(int32_t), ctx->stream), "hipMemsetAsync");
+    upload(ctx->slice_ptr, sp.data(), sp.size() * sizeof(int64_t), 0, ctx->stream);
+    upload(ctx->slice_T, sT.data(), sT.size() * sizeof(int32_t), 0, ctx->stream);
+    upload(ctx->slice_inst, sI.data(), sI.size() * sizeof(int32_t), 0, ctx->stream);
+    const int64_t st = ctx->step;
+    upload(ctx->step_base, &st, sizeof st, 0, ctx->stream);
+    sync(ctx);
+    upload_params(ctx);
+    upload_bcs(ctx);
+    upload_stiffness(ctx);
+    upload_volumes(ctx);
+    upload_body(ctx);
+    for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
+        const Inst& I = ctx->inst[ii];
+        std::vector<double> zeros(static_cast<size_t>(3 * I.n), 0.0);
+        upload_state(ctx, I, S ? S->u[ii].data() : zeros.data(), S ? S->v[ii].data() : nullptr,
+                     S ? S->a[ii].data() : nullptr);
+        upload_col(ctx, I, S ? S->broken[ii].data() : nullptr);
+    }
+    ctx->cur = 0;
+    ctx->vv_ahead = false;
+    ctx->built = true;
+}
+
+void validate_coords(int64_t n, const double* coords, double horizon)
+{
+    if (n < 1) fail(PD_EINVAL, "n must be >= 1");
+    if (n >= std::numeric_limits<int32_t>::max()) fail(PD_ERANGE, "n must be < 2^31 - 1");
+    if (!coords) fail(PD_EINVAL, "coords is NULL");
+    if (!(horizon > 0.0) || !std::isfinite(horizon)) fail(PD_EINVAL, "horizon must be positive and finite");
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(coords[i])) fail(PD_EINVAL, "coords must be finite");
+}
+
+void new_problem(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* const* coords, const double* horizon,
+                 int order)
+{
+    if (order != PD_ORDER_NATURAL && order != PD_ORDER_MORTON) fail(PD_EINVAL, "unknown node order");
+    if (ninst < 1) fail(PD_EINVAL, "need at least one instance");
+    std::vector<Inst> insts(static_cast<size_t>(ninst));
+    int64_t total = 0;
+    for (int32_t b = 0; b < ninst; ++b) {
+        validate_coords(n[b], coords[b], horizon[b]);
+        Inst& I = insts[b];
+        I.n = n[b];
+        I.horizon = horizon[b];
+        I.x.assign(coords[b], coords[b] + 3 * n[b]);
+        family_search(I.n, I.x.data(), I.horizon, I.row_ptr, I.col);
+        I.nnz = I.row_ptr[I.n];
+        I.bc_kind.assign(static_cast<size_t>(3 * I.n), 0);
+        I.bc_sched.assign(static_cast<size_t>(3 * I.n), 0);
+        I.bc_val.assign(static_cast<size_t>(3 * I.n), 0.0);
+        total += I.nnz;
+    }
+    (void)total;
+    set_device(ctx);
+    ctx->built = false;
+    ctx->inst = std::move(insts);
+    ctx->order = order;
+    ctx->step = 0;
+    ctx->a_valid = false;
+    ctx->vv_ahead = false;
+    build_layout(ctx, nullptr);
+}
+
+// ------------------------------------------------------------------ stepping
+
+template <typename Real>
+StepArgs<Real> step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
+{
+    StepArgs<Real> A{};
+    A.rec_in = ctx->rec[in].as<double>();
+    A.rec_out = ctx->rec[out].as<double>();
+    A.v = ctx->v.as<Real>();
+    A.a = ctx->a.as<Real>();
+    A.col = ctx->col.as<int32_t>();
+    A.kslot = ctx->has_stiff ? ctx->kslot.as<double>() : nullptr;
+    A.vol = ctx->has_vol ? ctx->vol.as<double>() : nullptr;
+    A.bhat = ctx->has_body ? ctx->bhat.as<double>() : nullptr;
+    A.slice_ptr = ctx->slice_ptr.as<int64_t>();
+    A.slice_T = ctx->slice_T.as<int32_t>();
+    A.slice_inst = ctx->slice_inst.as<int32_t>();
+    A.params = ctx->params.as<InstParams>();
+    A.bc_id = ctx->bc_id.as<int32_t>();
+    A.bc = ctx->bc.as<BCRec>();
+    A.step_base = ctx->step_base.as<int64_t>();
+    A.status = ctx->status.as<int32_t>();
+    A.nn = ctx->nn;
+    A.nslices = ctx->nslices;
+    A.step_local = step_local;
+    A.dt = ctx->dt;
+    return A;
+}
+
+int step_mode(int scheme)
+{
+    return scheme == PD_VELOCITY_VERLET ? kModeVV : scheme == PD_EULER_FORWARD ? kModeFE : kModeEC;
+}
+
+template <typename Real>
+void launch_one(pd_ctx* ctx, int mode, int in, int out, int64_t step_local)
+{
+    hip_check(launch_step<Real>(step_args<Real>(ctx, in, out, step_local), ctx->lanes, mode, ctx->has_stiff,
+                                ctx->stream),
+              "step kernel launch");
+}
+
+// Launch `count` consecutive steps starting at buffer parity `cur`, step_local offsets
+// 0..count-1 relative to the device step base, then advance the base.
+template <typename Real>
+void launch_steps(pd_ctx* ctx, int mode, int cur, int64_t count)
+{
+    for (int64_t i = 0; i < count; ++i) {
+        const int in = (mode == kModeVV) ? 1 - cur : cur;
+        const int out = 1 - in;
+        launch_one<Real>(ctx, mode, in, out, i);
+        cur ^= 1;
+    }
+    hip_check(launch_advance(ctx->step_base.as<int64_t>(), count, ctx->stream), "advance launch");
+}
+
+template <typename Real>
+hipGraphExec_t chunk_graph(pd_ctx* ctx, int mode, int parity)
+{
+    hipGraphExec_t& g = ctx->graph[parity][mode];
+    if (g) return g;
+    hipGraph_t graph = nullptr;
+    hip_check(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+        launch_steps<Real>(ctx, mode, parity, kGraphChunk);
+    } catch (...) {
+        (void)hipStreamEndCapture(ctx->stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    hip_check(hipStreamEndCapture(ctx->stream, &graph), "hipStreamEndCapture");
+    hipError_t e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    hip_check(e, "hipGraphInstantiate");
+    return g;
+}
+
+template <typename Real>
+void do_steps(pd_ctx* ctx, int64_t nsteps)
+{
+    const int mode = step_mode(ctx->scheme);
+    if (!ctx->ev0) {
+        hip_check(hipEventCreate(&ctx->ev0), "hipEventCreate");
+        hip_check(hipEventCreate(&ctx->ev1), "hipEventCreate");
+    }
+    hip_check(hipEventRecord(ctx->ev0, ctx->stream), "hipEventRecord");
+    if (mode == kModeVV && nsteps > 0) {
+        if (!ctx->a_valid) {
+            launch_one<Real>(ctx, kModeVVInit, ctx->cur, 1 - ctx->cur, 0);
+            ctx->a_valid = true;
+            ctx->vv_ahead = true;
+        } else if (!ctx->vv_ahead) {
+            hip_check(launch_drift<Real>(step_args<Real>(ctx, ctx->cur, 1 - ctx->cur, 0), ctx->lanes, ctx->stream),
+                      "drift launch");
+            ctx->vv_ahead = true;
+        }
+    }
+    int64_t left = nsteps;
+    if (ctx->use_graphs) {
+        while (left >= kGraphChunk) {
+            hip_check(hipGraphLaunch(chunk_graph<Real>(ctx, mode, ctx->cur), ctx->stream), "hipGraphLaunch");
+            left -= kGraphChunk;  // even chunk: parity unchanged
+        }
+    }
+    if (left > 0) {
+        launch_steps<Real>(ctx, mode, ctx->cur, left);
+        if (left & 1) ctx->cur ^= 1;
+    }
+    hip_check(hipEventRecord(ctx->ev1, ctx->stream), "hipEventRecord");
+    ctx->timed = true;
+    ctx->step += nsteps;
+}
+
+void check_status(pd_ctx* ctx)
+{
+    int32_t st = 0;
+    download(&st, ctx->status, sizeof st, 0, ctx->stream);
+    sync(ctx);
+    if (st & 1) fail(PD_ENONFINITE, "a displacement or velocity became non-finite");
+}
+
+void reset_flags_after_state_change(pd_ctx* ctx, bool a_given)
+{
+    ctx->a_valid = a_given;
+    ctx->vv_ahead = false;
+    const int32_t z = 0;
+    upload(ctx->status, &z, sizeof z, 0, ctx->stream);
+    sync(ctx);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+int pd_create(pd_ctx** out, int device, int precision, void* hip_stream)
+{
+    if (!out) {
+        g_create_error = "out is NULL";
+        return PD_EINVAL;
+    }
+    *out = nullptr;
+    if (precision != PD_FP64 && precision != PD_FP32) {
+        g_create_error = "unknown precision";
+        return PD_EINVAL;
+    }
+    std::unique_ptr<pd_ctx> ctx(new (std::nothrow) pd_ctx);
+    if (!ctx) {
+        g_create_error = "host allocation failed";
+        return PD_ENOMEM;
+    }
+    int rc = guarded(ctx.get(), [&] {
+        int count = 0;
+        hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
+        if (device < 0 || device >= count) fail(PD_EINVAL, "device index out of range");
+        ctx->device = device;
+        ctx->precision = precision;
+        set_device(ctx.get());
+        if (hip_stream) {
+            ctx->stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            hip_check(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking), "hipStreamCreate");
+            ctx->own_stream = true;
+        }
+    });
+    if (rc != PD_OK) {
+        g_create_error = ctx->err;
+        return rc;
+    }
+    *out = ctx.release();
+    return PD_OK;
+}
+
+int pd_destroy(pd_ctx* ctx)
+{
+    if (!ctx) return PD_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return PD_OK;
+}
+
+const char* pd_last_error(const pd_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+int pd_build_family(pd_ctx* ctx, int64_t n, const double* coords, double horizon, int order)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] { new_problem(ctx, 1, &n, &coords, &horizon, order); });
+}
+
+int pd_build_family_batch(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* const* coords,
+                          const double* horizon, int order)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        if (ninst < 1 || !n || !coords || !horizon) fail(PD_EINVAL, "bad batch arguments");
+        new_problem(ctx, ninst, n, coords, horizon, order);
+    });
+}
+
+int pd_num_instances(const pd_ctx* ctx, int32_t* ninst)
+{
+    if (!ctx || !ninst) return PD_EINVAL;
+    *ninst = ctx->built ? static_cast<int32_t>(ctx->inst.size()) : 0;
+    return PD_OK;
+}
+
+int pd_instance_size(const pd_ctx* ctx, int32_t inst, int64_t* n, int64_t* nnz)
+{
+    if (!ctx || !ctx->built || inst < 0 || inst >= static_cast<int32_t>(ctx->inst.size())) return PD_EINVAL;
+    if (n) *n = ctx->inst[inst].n;
+    if (nnz) *nnz = ctx->inst[inst].nnz;
+    return PD_OK;
+}
+
+int pd_get_family(pd_ctx* ctx, int32_t inst, int64_t* row_ptr, int32_t* col, int64_t* nnz)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (nnz) *nnz = I.nnz;
+        if (row_ptr) std::memcpy(row_ptr, I.row_ptr.data(), I.row_ptr.size() * sizeof(int64_t));
+        if (col) std::memcpy(col, I.col.data(), I.col.size() * sizeof(int32_t));
+    });
+}
+
+int pd_set_material(pd_ctx* ctx, int32_t inst, const pd_material* m)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (!m) fail(PD_EINVAL, "material is NULL");
+        if (!(m->rho > 0.0) || !std::isfinite(m->rho)) fail(PD_EINVAL, "rho must be positive and finite");
+        if (!std::isfinite(m->c)) fail(PD_EINVAL, "c must be finite");
+        if (!(m->s0 > 0.0)) fail(PD_EINVAL, "s0 must be positive");
+        if (!(m->eta >= 0.0) || !std::isfinite(m->eta)) fail(PD_EINVAL, "eta must be >= 0 and finite");
+        std::vector<double> vols;
+        if (m->volumes) {
+            vols.assign(m->volumes, m->volumes + I.n);
+            for (double x : vols)
+                if (!(x > 0.0) || !std::isfinite(x)) fail(PD_EINVAL, "volumes must be positive and finite");
+        } else if (!(m->volume > 0.0) || !std::isfinite(m->volume)) {
+            fail(PD_EINVAL, "volume must be positive and finite");
+        }
+        set_device(ctx);
+        I.rho = m->rho;
+        I.c = m->c;
+        I.s0 = m->s0;
+        I.eta = m->eta;
+        I.volume = m->volumes ? 1.0 : m->volume;
+        I.vols = std::move(vols);
+        upload_params(ctx);
+        upload_volumes(ctx);
+        if (ctx->has_stiff) upload_stiffness(ctx);
+        ctx->a_valid = false;
+        ctx->vv_ahead = false;
+        ctx->drop_graphs();
+        sync(ctx);
+    });
+}
+
+int pd_set_bond_stiffness(pd_ctx* ctx, int32_t inst, const double* k)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        std::vector<double> kv;
+        if (k) {
+            kv.assign(k, k + I.nnz);
+            for (double x : kv)
+                if (!std::isfinite(x)) fail(PD_EINVAL, "stiffness must be finite");
+        }
+        set_device(ctx);
+        I.kslot = std::move(kv);
+        upload_stiffness(ctx);
+        ctx->a_valid = false;
+        ctx->vv_ahead = false;
+        ctx->drop_graphs();
+    });
+}
+
+int pd_break_bonds(pd_ctx* ctx, int32_t inst, const uint8_t* broken)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (!broken) fail(PD_EINVAL, "broken is NULL");
+        set_device(ctx);
+        std::vector<uint8_t> cur = broken_of(ctx, I);
+        for (int64_t b = 0; b < I.nnz; ++b) cur[b] = cur[b] || broken[b];
+        upload_col(ctx, I, cur.data());
+        ctx->a_valid = false;
+        ctx->vv_ahead = false;
+    });
+}
+
+int pd_set_bcs(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t* nodes, int comp_mask, int kind,
+               const double value[3], int sched)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (m < 0 || (m > 0 && !nodes)) fail(PD_EINVAL, "bad node list");
+        if (comp_mask < 1 || comp_mask > 7) fail(PD_EINVAL, "comp_mask must be in 1..7");
+        if (kind != PD_BC_DISP && kind != PD_BC_VEL) fail(PD_EINVAL, "unknown BC kind");
+        if (sched != PD_SCHED_CONST && sched != PD_SCHED_LINEAR) fail(PD_EINVAL, "unknown schedule");
+        if (!value) fail(PD_EINVAL, "value is NULL");
+        for (int d = 0; d < 3; ++d)
+            if ((comp_mask >> d & 1) && !std::isfinite(value[d])) fail(PD_EINVAL, "BC value must be finite");
+        for (int64_t i = 0; i < m; ++i)
+            if (nodes[i] < 0 || nodes[i] >= I.n) fail(PD_EINVAL, "BC node id out of range");
+        set_device(ctx);
+        for (int64_t i = 0; i < m; ++i)
+            for (int d = 0; d < 3; ++d)
+                if (comp_mask >> d & 1) {
+                    I.bc_kind[3 * nodes[i] + d] = static_cast<uint8_t>(kind);
+                    I.bc_sched[3 * nodes[i] + d] = static_cast<uint8_t>(sched);
+                    I.bc_val[3 * nodes[i] + d] = value[d];
+                }
+        upload_bcs(ctx);
+        ctx->vv_ahead = false;
+        ctx->drop_graphs();
+    });
+}
+
+int pd_clear_bcs(pd_ctx* ctx, int32_t inst)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        set_device(ctx);
+        std::fill(I.bc_kind.begin(), I.bc_kind.end(), 0);
+        std::fill(I.bc_sched.begin(), I.bc_sched.end(), 0);
+        std::fill(I.bc_val.begin(), I.bc_val.end(), 0.0);
+        upload_bcs(ctx);
+        ctx->vv_ahead = false;
+        ctx->drop_graphs();
+    });
+}
+
+int pd_set_body_force(pd_ctx* ctx, int32_t inst, const double* b_hat, double magnitude)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (!std::isfinite(magnitude)) fail(PD_EINVAL, "magnitude must be finite");
+        std::vector<double> b;
+        if (b_hat) {
+            b.assign(b_hat, b_hat + 3 * I.n);
+            for (double x : b)
+                if (!std::isfinite(x)) fail(PD_EINVAL, "b_hat must be finite");
+        }
+        set_device(ctx);
+        I.bhat = std::move(b);
+        I.bmag = b_hat ? magnitude : 0.0;
+        upload_params(ctx);
+        upload_body(ctx);
+        ctx->a_valid = false;
+        ctx->vv_ahead = false;
+        ctx->drop_graphs();
+    });
+}
+
+int pd_set_integrator(pd_ctx* ctx, int scheme, double dt)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        if (scheme != PD_EULER_CROMER && scheme != PD_VELOCITY_VERLET && scheme != PD_EULER_FORWARD)
+            fail(PD_EINVAL, "unknown scheme");
+        if (!(dt > 0.0) || !std::isfinite(dt)) fail(PD_EINVAL, "dt must be positive and finite");
+        if (scheme != ctx->scheme || dt != ctx->dt) {
+            ctx->scheme = scheme;
+            ctx->dt = dt;
+            ctx->a_valid = false;
+            ctx->vv_ahead = false;
+            ctx->drop_graphs();
+        }
+    });
+}
+
+int pd_step(pd_ctx* ctx, int64_t nsteps)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        require_built(ctx);
+        if (nsteps < 0) fail(PD_EINVAL, "nsteps must be >= 0");
+        if (ctx->step + nsteps >= std::numeric_limits<int32_t>::max())
+            fail(PD_ERANGE, "step counter would exceed 2^31 - 1");
+        set_device(ctx);
+        if (ctx->precision == PD_FP64)
+            do_steps<double>(ctx, nsteps);
+        else
+            do_steps<float>(ctx, nsteps);
+    });
+}
+
+int pd_sync(pd_ctx* ctx)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        set_device(ctx);
+        sync(ctx);
+        if (ctx->built) check_status(ctx);
+    });
+}
+
+int pd_get_step(const pd_ctx* ctx, int64_t* step)
+{
+    if (!ctx || !step) return PD_EINVAL;
+    *step = ctx->step;
+    return PD_OK;
+}
+
+int pd_get_u(pd_ctx* ctx, int32_t inst, double* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        set_device(ctx);
+        auto u = u_of(ctx, I);
+        std::memcpy(out, u.data(), u.size() * sizeof(double));
+        check_status(ctx);
+    });
+}
+
+int pd_get_v(pd_ctx* ctx, int32_t inst, double* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        set_device(ctx);
+        auto v = soa_of(ctx, I, ctx->v);
+        std::memcpy(out, v.data(), v.size() * sizeof(double));
+        check_status(ctx);
+    });
+}
+
+int pd_get_a(pd_ctx* ctx, int32_t inst, double* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        set_device(ctx);
+        auto a = soa_of(ctx, I, ctx->a);
+        std::memcpy(out, a.data(), a.size() * sizeof(double));
+    });
+}
+
+int pd_get_damage(pd_ctx* ctx, int32_t inst, double* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        set_device(ctx);
+        DamageArgs D{};
+        D.col = ctx->col.as<int32_t>();
+        D.vol = ctx->has_vol ? ctx->vol.as<double>() : nullptr;
+        D.slice_ptr = ctx->slice_ptr.as<int64_t>();
+        D.slice_T = ctx->slice_T.as<int32_t>();
+        D.slice_inst = ctx->slice_inst.as<int32_t>();
+        D.params = ctx->params.as<InstParams>();
+        D.phi = ctx->phi.as<double>();
+        D.nslices = ctx->nslices;
+        hip_check(launch_damage(D, ctx->lanes, ctx->stream), "damage launch");
+        std::vector<double> h(static_cast<size_t>(I.n_pad));
+        download(h.data(), ctx->phi, h.size() * 8, I.node_off * 8, ctx->stream);
+        sync(ctx);
+        for (int64_t l = 0; l < I.n_pad; ++l)
+            if (I.perm[l] >= 0) out[I.perm[l]] = h[l];
+    });
+}
+
+int pd_get_broken(pd_ctx* ctx, int32_t inst, uint8_t* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        set_device(ctx);
+        auto b = broken_of(ctx, I);
+        std::memcpy(out, b.data(), b.size());
+    });
+}
+
+int pd_set_state(pd_ctx* ctx, int32_t inst, const double* u, const double* v, const double* a,
+                 const uint8_t* broken)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        for (const double* p : {u, v, a})
+            if (p)
+                for (int64_t q = 0; q < 3 * I.n; ++q)
+                    if (!std::isfinite(p[q])) fail(PD_EINVAL, "state must be finite");
+        set_device(ctx);
+        if (u) {
+            // both buffers: the current one and the one the next step writes
+            upload_state(ctx, I, u, nullptr, nullptr);
+        }
+        upload_state(ctx, I, nullptr, v, a);
+        if (broken) upload_col(ctx, I, broken);
+        reset_flags_after_state_change(ctx, a != nullptr);
+    });
+}
+
+int pd_set_step(pd_ctx* ctx, int64_t step)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        require_built(ctx);
+        if (step < 0 || step >= std::numeric_limits<int32_t>::max()) fail(PD_EINVAL, "step out of range");
+        set_device(ctx);
+        ctx->step = step;
+        upload(ctx->step_base, &step, sizeof step, 0, ctx->stream);
+        sync(ctx);
+        ctx->vv_ahead = false;
+    });
+}
+
+int pd_set_lanes_per_node(pd_ctx* ctx, int lanes)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        if (lanes == 0) lanes = kDefaultLanes;
+        if (!lanes_supported(lanes)) fail(PD_EINVAL, "unsupported lanes-per-node");
+        if (!ctx->built) {
+            ctx->lanes = lanes;
+            return;
+        }
+        if (lanes == ctx->lanes) return;
+        set_device(ctx);
+        HostState S = snapshot(ctx);
+        const bool av = ctx->a_valid;
+        ctx->lanes = lanes;
+        build_layout(ctx, &S);
+        ctx->a_valid = av;
+    });
+}
+
+int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        require_built(ctx);
+        if (trial_steps < 1) fail(PD_EINVAL, "trial_steps must be >= 1");
+        set_device(ctx);
+        HostState S = snapshot(ctx);
+        const int64_t step0 = ctx->step;
+        const bool av = ctx->a_valid;
+        const int cands[] = {1, 4, 16, 64};
+        int best = ctx->lanes;
+        double best_ms = std::numeric_limits<double>::infinity();
+        for (int L : cands) {
+            ctx->lanes = L;
+            build_layout(ctx, &S);
+            ctx->a_valid = av;
+            for (int rep = 0; rep < 2; ++rep) {  // first pass builds graphs and warms caches
+                if (ctx->precision == PD_FP64)
+                    do_steps<double>(ctx, trial_steps);
+                else
+                    do_steps<float>(ctx, trial_steps);
+            }
+            float ms = 0.f;
+            sync(ctx);
+            hip_check(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "hipEventElapsedTime");
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = L;
+            }
+            ctx->step = step0;
+        }
+        ctx->lanes = best;
+        build_layout(ctx, &S);
+        ctx->step = step0;
+        const int64_t st = step0;
+        upload(ctx->step_base, &st, sizeof st, 0, ctx->stream);
+        sync(ctx);
+        ctx->a_valid = av;
+        reset_flags_after_state_change(ctx, av);
+        if (chosen) *chosen = best;
+    });
+}
+
+int pd_get_info(const pd_ctx* ctx, pd_info* info)
+{
+    if (!ctx || !info) return PD_EINVAL;
+    std::memset(info, 0, sizeof *info);
+    if (!ctx->built) return PD_OK;
+    int64_t n = 0, nnz = 0;
+    for (auto& I : ctx->inst) {
+        n += I.n;
+        nnz += I.nnz;
+    }
+    info->n_nodes = n;
+    info->n_slots = nnz;
+    info->n_nodes_dev = ctx->nn;
+    info->n_slots_dev = ctx->ns;
+    info->n_instances = static_cast<int32_t>(ctx->inst.size());
+    info->lanes_per_node = ctx->lanes;
+    info->precision = ctx->precision;
+    info->scheme = ctx->scheme;
+    const double r = ctx->precision == PD_FP64 ? 8.0 : 4.0;
+    // algorithmic bytes: 4 per slot (+8 with a stiffness field); per node x (24 B) read,
+    // u read + write, v read + write, a read + write (velocity Verlet)
+    double per_node = 24.0 + 4.0 * 3.0 * r + (ctx->scheme == PD_VELOCITY_VERLET ? 2.0 * 3.0 * r : 0.0);
+    info->model_bytes_per_step = static_cast<double>(nnz) * (4.0 + (ctx->has_stiff ? 8.0 : 0.0)) +
+                                 static_cast<double>(n) * per_node;
+    return PD_OK;
+}
+
+int pd_last_step_ms(pd_ctx* ctx, double* ms)
+{
+    if (!ctx || !ms) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        if (!ctx->timed) fail(PD_ESTATE, "no pd_step has been timed yet");
+        set_device(ctx);
+        hip_check(hipEventSynchronize(ctx->ev1), "hipEventSynchronize");
+        float f = 0.f;
+        hip_check(hipEventElapsedTime(&f, ctx->ev0, ctx->ev1), "hipEventElapsedTime");
+        *ms = f;
+    });
+}
+
+}  // extern "C"

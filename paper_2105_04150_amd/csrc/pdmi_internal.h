@@ -1,0 +1,99 @@
+// pdmi_internal.h -- device data layout and kernel launchers of the peridynamics library.
+//
+// Device layout (one context, all instances concatenated):
+//   node records  rec[2][nn]      48 bytes per node: x (3 x f64) then u.  FP64: u as 3 x f64;
+//                                 FP32: u as 3 x f32 at byte 24, bytes 36..47 unused.  Two
+//                                 copies hold consecutive displacement levels (ping-pong);
+//                                 x is written once into both.
+//   velocity      v[3][nn]        structure of arrays, Real
+//   acceleration  a[3][nn]        structure of arrays, Real (velocity Verlet)
+//   slots         col[ns]         int32 per slot in "slices": a slice is the W = 64/G nodes one
+//                                 wavefront serves (G lanes per node); its slots are stored as
+//                                 T rows of 64 entries, entry (t, w*G + g) = slot t*G + g of the
+//                                 slice's node w.  col >= 0: intact bond to device node col;
+//                                 col < 0: ~col is the neighbour of a broken bond, or the node
+//                                 itself for padding (a node is never its own neighbour).
+//   stiffness     kslot[ns]       f64 per slot, same layout (only with a stiffness field)
+//   slices        slice_ptr/T/inst first entry, row count and instance of every slice
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pdmi {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;             // 4 wavefronts per workgroup, one slice each
+constexpr int32_t kNodeFree = -1;       // bc_id of an unconstrained node
+constexpr int32_t kNodePad = -2;        // bc_id of a padding node (never updated)
+
+struct InstParams {
+    double c;        // micromodulus without a stiffness field
+    double q0;       // break threshold on q = r^2/L^2 - 1: (1 + s0)^2 - 1
+    double rho;
+    double eta;
+    double volume;   // uniform node volume without a volume array
+    double bmag;     // body-force magnitude
+    int32_t has_body;
+    int32_t pad_;
+};
+
+// Constraint of one node: per component d, kind in bits 2d..2d+1 (0 free, 1 displacement,
+// 2 velocity) and schedule in bit 8+d (0 constant, 1 linear in t).
+struct BCRec {
+    double A[3];
+    int32_t code;
+    int32_t pad_;
+};
+
+enum StepMode : int { kModeEC = 0, kModeVV = 1, kModeVVInit = 2, kModeFE = 3 };
+
+template <typename Real>
+struct StepArgs {
+    const double* rec_in;       // 6 doubles per node
+    double* rec_out;
+    Real* v;                    // v + d*nn
+    Real* a;                    // a + d*nn
+    int32_t* col;
+    const double* kslot;        // nullptr unless STIFF
+    const double* vol;          // nullptr unless per-node volumes
+    const double* bhat;         // bhat + d*nn, nullptr without body forces
+    const int64_t* slice_ptr;
+    const int32_t* slice_T;
+    const int32_t* slice_inst;
+    const InstParams* params;
+    const int32_t* bc_id;
+    const BCRec* bc;
+    const int64_t* step_base;   // completed steps when the launch sequence started
+    int32_t* status;            // bit 0: a non-finite u or v was produced
+    int64_t nn;                 // device node count (SoA stride)
+    int64_t nslices;
+    int64_t step_local;         // this launch advances step *step_base + step_local
+    double dt;
+};
+
+struct DamageArgs {
+    const int32_t* col;
+    const double* vol;
+    const int64_t* slice_ptr;
+    const int32_t* slice_T;
+    const int32_t* slice_inst;
+    const InstParams* params;
+    double* phi;
+    int64_t nslices;
+};
+
+template <typename Real>
+hipError_t launch_step(const StepArgs<Real>& a, int lanes, int mode, bool stiff, hipStream_t s);
+
+template <typename Real>
+hipError_t launch_drift(const StepArgs<Real>& a, int lanes, hipStream_t s);
+
+hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s);
+
+hipError_t launch_advance(int64_t* step_base, int64_t by, hipStream_t s);
+
+// lanes-per-node values with compiled kernels
+bool lanes_supported(int lanes);
+
+}  // namespace pdmi

@@ -162,8 +162,13 @@ def gaussian_node_field(dims: Sequence[int], sigma: float, corr_len: float, seed
     lx, ly, lz = (int(d) for d in dims)
     w = normal(seed, lx * ly * lz).reshape(lz, ly, lx)
     k = _gauss_kernel(corr_len / math.sqrt(2.0))
+    r = (k.shape[0] - 1) // 2
+
+    def conv(a):  # zero-padded convolution cropped to the input length
+        return np.convolve(a, k, mode="full")[r:r + a.shape[0]]
+
     for ax in range(3):
-        w = np.apply_along_axis(lambda a: np.convolve(a, k, mode="same"), ax, w)
+        w = np.apply_along_axis(conv, ax, w)
     scale = math.sqrt(float(np.sum(k * k)) ** 3)
     return (sigma / scale) * w.ravel()
 
