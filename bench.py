@@ -66,9 +66,25 @@ def main():
     ap.add_argument("--workload", default="cube100", choices=["cube100", "cube100_wide", "block10", "beam3pb"])
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--lanes", type=int, default=0, help="lanes per node (0: autotune)")
+    ap.add_argument("--order", default=None, choices=[None, "natural", "morton"],
+                    help="device node order (default: the workload's)")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+
+    if args.calib_copy_mib:
+        import torch
+        n = args.calib_copy_mib * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8,
+                          "copies": 3}), flush=True)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -79,6 +95,8 @@ def main():
     import paper_2105_04150_amd as P
 
     w = pi.workload(args.workload)
+    if args.order:
+        w.order = args.order
     prec = P.PD_FP64 if args.precision == "f64" else P.PD_FP32
     t0 = time.perf_counter()
     sim = P.simulation_for(w, precision=prec, lanes=args.lanes or 1)

@@ -58,6 +58,11 @@ extern "C" {
 #define PD_BC_DISP 1        /* prescribed displacement: u_c = A_c g(t), v_c = A_c g'(t) */
 #define PD_BC_VEL 2         /* prescribed velocity: v_c = A_c g(t), u_c += dt v_c */
 
+#define PD_MAP_SLICED 0     /* slots in 64-wide rows, G lanes per node, neighbours gathered from
+                               global memory through the L1 cache */
+#define PD_MAP_STAGED 1     /* one lane per node; each wavefront stages runs of consecutive
+                               neighbour records in LDS and reads them from there */
+
 #define PD_SCHED_CONST 0    /* g(t) = 1 */
 #define PD_SCHED_LINEAR 1   /* g(t) = t */
 
@@ -84,6 +89,8 @@ typedef struct pd_info {
     int32_t lanes_per_node; /* work-items cooperating on one node's bonds */
     int32_t precision;      /* PD_FP64 / PD_FP32 */
     int32_t scheme;         /* integrator */
+    int32_t mapping;        /* PD_MAP_SLICED / PD_MAP_STAGED */
+    int32_t pad_;
     double model_bytes_per_step; /* algorithmic HBM bytes of one step (see the design notes) */
 } pd_info;
 
@@ -207,13 +214,18 @@ int pd_set_step(pd_ctx *ctx, int64_t step);
 
 /* ---------------------------------------------------------------- tuning and introspection */
 
-/* Lanes (work-items) cooperating on one node's bonds: 1, 2, 4, 8, 16, 32 or 64
- * (0 = library default).  Rebuilds the device layout; state is preserved. */
+/* Work mapping of the step kernel: PD_MAP_SLICED with `lanes` work-items cooperating on
+ * one node's bonds (1, 4, 16 or 64; 0 = library default), or PD_MAP_STAGED (lanes
+ * ignored).  Rebuilds the device layout; the state (u, v, a, broken bonds, step) is kept. */
+int pd_set_mapping(pd_ctx *ctx, int mapping, int lanes);
+
+/* Shorthand for pd_set_mapping(ctx, PD_MAP_SLICED, lanes). */
 int pd_set_lanes_per_node(pd_ctx *ctx, int lanes);
 
-/* Time `trial_steps` steps for each candidate lanes-per-node on the current problem
- * and keep the fastest.  Requires the state to be untouched since the family build
- * (step 0); leaves it so.  *chosen (may be NULL) receives the choice. */
+/* Time `trial_steps` steps (after as many untimed ones) of every mapping candidate on
+ * the current problem and keep the fastest; the state is restored afterwards.
+ * *chosen (may be NULL) receives the lanes-per-node of the chosen sliced mapping, or
+ * -1 for the staged mapping. */
 int pd_autotune(pd_ctx *ctx, int64_t trial_steps, int32_t *chosen);
 
 /* Problem and layout sizes. */

@@ -12,8 +12,8 @@ import numpy as np
 
 from . import _binding as B
 from ._binding import (PD_BC_DISP, PD_BC_VEL, PD_EULER_CROMER, PD_EULER_FORWARD, PD_FP32,  # noqa: F401
-                       PD_FP64, PD_ORDER_MORTON, PD_ORDER_NATURAL, PD_SCHED_CONST, PD_SCHED_LINEAR,
-                       PD_VELOCITY_VERLET, PdmiError)
+                       PD_FP64, PD_MAP_SLICED, PD_MAP_STAGED, PD_ORDER_MORTON, PD_ORDER_NATURAL,
+                       PD_SCHED_CONST, PD_SCHED_LINEAR, PD_VELOCITY_VERLET, PdmiError)
 
 SCHEMES = {"euler_cromer": PD_EULER_CROMER, "velocity_verlet": PD_VELOCITY_VERLET,
            "forward_euler": PD_EULER_FORWARD}
@@ -79,6 +79,11 @@ class Simulation:
 
     def set_lanes_per_node(self, lanes):
         B.pd_set_lanes_per_node(self.ctx, lanes)
+
+    def set_mapping(self, mapping, lanes=0):
+        """mapping: "sliced" (with lanes per node) or "staged"."""
+        m = {"sliced": PD_MAP_SLICED, "staged": PD_MAP_STAGED}.get(mapping, mapping)
+        B.pd_set_mapping(self.ctx, m, lanes)
 
     def autotune(self, trial_steps=20):
         return B.pd_autotune(self.ctx, trial_steps)
@@ -146,11 +151,12 @@ def apply_workload(sim: Simulation, w, inst: int = 0, row_ptr=None, col=None) ->
         sim.set_body_force(bhat, bmag, inst=inst)
 
 
-def simulation_for(w, precision: int = PD_FP64, lanes: int = 0, device: int = 0, order=None) -> Simulation:
+def simulation_for(w, precision: int = PD_FP64, lanes: int = 0, device: int = 0, order=None,
+                   mapping="sliced") -> Simulation:
     """A single-instance Simulation set up for workload ``w`` (family built on the host)."""
     sim = Simulation(device, precision)
-    if lanes:
-        sim.set_lanes_per_node(lanes)
+    if lanes or mapping != "sliced":
+        sim.set_mapping(mapping, lanes)
     sim.build_family(w.coords, w.horizon, order or w.order)
     sim.set_integrator(w.scheme, w.dt)
     apply_workload(sim, w)

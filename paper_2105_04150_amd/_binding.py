@@ -20,13 +20,14 @@ PD_ORDER_NATURAL, PD_ORDER_MORTON = 0, 1
 PD_EULER_CROMER, PD_VELOCITY_VERLET, PD_EULER_FORWARD = 0, 1, 2
 PD_BC_DISP, PD_BC_VEL = 1, 2
 PD_SCHED_CONST, PD_SCHED_LINEAR = 0, 1
+PD_MAP_SLICED, PD_MAP_STAGED = 0, 1
 
 SYMBOLS = [
     "pd_create", "pd_destroy", "pd_last_error", "pd_build_family", "pd_build_family_batch",
     "pd_num_instances", "pd_instance_size", "pd_get_family", "pd_set_material", "pd_set_bond_stiffness",
     "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_body_force", "pd_set_integrator",
     "pd_step", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
-    "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_lanes_per_node", "pd_autotune",
+    "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
     "pd_get_info", "pd_last_step_ms",
 ]
 
@@ -45,7 +46,8 @@ class pd_material(C.Structure):
 class pd_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_slots", C.c_int64), ("n_nodes_dev", C.c_int64),
                 ("n_slots_dev", C.c_int64), ("n_instances", C.c_int32), ("lanes_per_node", C.c_int32),
-                ("precision", C.c_int32), ("scheme", C.c_int32), ("model_bytes_per_step", C.c_double)]
+                ("precision", C.c_int32), ("scheme", C.c_int32), ("mapping", C.c_int32), ("pad_", C.c_int32),
+                ("model_bytes_per_step", C.c_double)]
 
 
 _lib = None
@@ -83,6 +85,7 @@ def load() -> C.CDLL:
         "pd_get_broken": [P, i32, P],
         "pd_set_state": [P, i32, P, P, P, P],
         "pd_set_step": [P, i64],
+        "pd_set_mapping": [P, C.c_int, C.c_int],
         "pd_set_lanes_per_node": [P, C.c_int],
         "pd_autotune": [P, i64, P],
         "pd_get_info": [P, P],
@@ -260,6 +263,10 @@ def pd_set_state(ctx, inst: int = 0, u=None, v=None, a=None, broken=None) -> Non
 
 def pd_set_step(ctx, step: int) -> None:
     _check(ctx, load().pd_set_step(ctx, int(step)))
+
+
+def pd_set_mapping(ctx, mapping: int, lanes: int = 0) -> None:
+    _check(ctx, load().pd_set_mapping(ctx, int(mapping), int(lanes)))
 
 
 def pd_set_lanes_per_node(ctx, lanes: int) -> None:

@@ -11,6 +11,7 @@
 #include "pdmi_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -29,6 +30,10 @@ using namespace pdmi;
 namespace {
 
 constexpr int kDefaultLanes = 1;
+// spare slot rows after the last slice: the sliced kernel prefetches kRowUnroll rows
+// ahead, the staged kernel reads a full piece of stiffness rows
+constexpr size_t kSpareRows = kRowUnroll > kPieceRows ? kRowUnroll : kPieceRows;
+constexpr int64_t kMaxGap = 12;  // staged ranges absorb gaps of up to this many unused records
 constexpr int64_t kGraphChunk = 64;  // steps per captured graph (even: buffer parity repeats)
 
 struct PdError : std::exception {
@@ -89,7 +94,10 @@ struct Inst {
     std::vector<int64_t> iperm;      // user node -> device-local node
     std::vector<int32_t> dslot_user; // device slot (instance-local) -> user slot, -1 = padding
     std::vector<int64_t> s_start;    // first device slot (instance-local) of every slice
-    std::vector<int64_t> s_T;        // 64-wide slot rows of every slice
+    std::vector<int64_t> s_T;        // 64-wide slot rows of every slice (sliced layout)
+    std::vector<int2> pieces;        // staged layout: {first device node, len | rows << 8}
+    std::vector<int32_t> slice_piece;  // staged layout: first piece of each slice (+ end), local
+    std::vector<uint8_t> ent_idx;    // staged layout: range index of every device slot
     int64_t node_off = 0, n_pad = 0, slice_off = 0, nslices = 0, dslot_off = 0, n_dslots = 0;
 };
 
@@ -105,6 +113,7 @@ struct pd_ctx {
     std::vector<Inst> inst;
     int order = PD_ORDER_NATURAL;
     int lanes = kDefaultLanes;
+    int mapping = PD_MAP_SLICED;
     int scheme = PD_EULER_CROMER;
     double dt = 1.0e-7;
     int64_t step = 0;
@@ -117,7 +126,7 @@ struct pd_ctx {
     int64_t nn = 0, ns = 0, nslices = 0;
     bool has_stiff = false, has_vol = false, has_body = false;
     DevBuf rec[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc, step_base,
-        status, phi;
+        status, phi, pieces, slice_piece, ent;
 
     // graphs: [parity][mode] for chunks of kGraphChunk steps
     hipGraphExec_t graph[2][4] = {{nullptr}};
@@ -466,7 +475,8 @@ void upload_stiffness(pd_ctx* ctx)
         ctx->kslot.release();
         return;
     }
-    ctx->kslot.alloc(static_cast<size_t>(ctx->ns) * sizeof(double));
+    ctx->kslot.alloc((static_cast<size_t>(ctx->ns) + kSpareRows * kWave) * sizeof(double));
+    hip_check(hipMemsetAsync(ctx->kslot.p, 0, ctx->kslot.bytes, ctx->stream), "hipMemsetAsync");
     for (auto& I : ctx->inst) {
         std::vector<double> k(static_cast<size_t>(I.n_dslots), 0.0);
         for (int64_t s = 0; s < I.n_dslots; ++s) {
@@ -565,8 +575,21 @@ void upload_state(pd_ctx* ctx, const Inst& I, const double* u, const double* v, 
 
 void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
 {
+    if (ctx->mapping == PD_MAP_STAGED) {
+        std::vector<uint16_t> e(static_cast<size_t>(I.n_dslots));
+        parallel_for(I.n_dslots, [&](int64_t s0, int64_t s1) {
+            for (int64_t d = s0; d < s1; ++d) {
+                const int32_t b = I.dslot_user[d];
+                if (b < 0)
+                    e[d] = static_cast<uint16_t>(0x8000 | kSegMax);
+                else
+                    e[d] = static_cast<uint16_t>(I.ent_idx[d] | ((broken && broken[b]) ? 0x8000 : 0));
+            }
+        });
+        upload(ctx->ent, e.data(), e.size() * sizeof(uint16_t), I.dslot_off * sizeof(uint16_t), ctx->stream);
+        return;
+    }
     std::vector<int32_t> colv(static_cast<size_t>(I.n_dslots));
-    const int G = ctx->lanes, W = kWave / G;
     parallel_for(I.nslices, [&](int64_t s0, int64_t s1) {
         for (int64_t s = s0; s < s1; ++s)
             for (int64_t t = 0; t < I.s_T[s]; ++t)
@@ -574,8 +597,7 @@ void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
                     const int64_t ds = I.s_start[s] + t * kWave + lane;
                     const int32_t b = I.dslot_user[ds];
                     if (b < 0) {
-                        // padding names the slot's own node, which is never its own neighbour
-                        colv[ds] = ~static_cast<int32_t>(I.node_off + s * W + lane / G);
+                        colv[ds] = ~static_cast<int32_t>(ctx->nn);  // padding: the sentinel record
                     } else {
                         const int32_t j = static_cast<int32_t>(I.node_off + I.iperm[I.col[b]]);
                         colv[ds] = (broken && broken[b]) ? ~j : j;
@@ -589,6 +611,17 @@ void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
 // Download one instance's broken mask (user CSR order).
 std::vector<uint8_t> broken_of(pd_ctx* ctx, const Inst& I)
 {
+    if (ctx->mapping == PD_MAP_STAGED) {
+        std::vector<uint16_t> e(static_cast<size_t>(I.n_dslots));
+        download(e.data(), ctx->ent, e.size() * sizeof(uint16_t), I.dslot_off * sizeof(uint16_t), ctx->stream);
+        sync(ctx);
+        std::vector<uint8_t> out(static_cast<size_t>(I.nnz), 0);
+        for (int64_t d = 0; d < I.n_dslots; ++d) {
+            const int32_t b = I.dslot_user[d];
+            if (b >= 0 && (e[d] & 0x8000)) out[b] = 1;
+        }
+        return out;
+    }
     std::vector<int32_t> colv(static_cast<size_t>(I.n_dslots));
     download(colv.data(), ctx->col, colv.size() * sizeof(int32_t), I.dslot_off * sizeof(int32_t), ctx->stream);
     sync(ctx);
@@ -654,14 +687,96 @@ HostState snapshot(pd_ctx* ctx)
     return S;
 }
 
+// Staged layout of one instance (one lane per node, 64 nodes per slice): per slice, the
+// sorted union of neighbour device indices is cut into ranges of consecutive nodes
+// (at most kSegMax long); each lane's slots in a range, in ascending neighbour order,
+// fill rows of pieces of at most kPieceRows rows.  Fills start (first slot of each slice),
+// pieces, slice_piece, dslot_user and ent_idx; returns the slot count.
+int64_t build_staged(Inst& I, std::vector<int64_t>& start)
+{
+    const int64_t nsl = I.nslices;
+    std::vector<std::vector<int2>> spieces(static_cast<size_t>(nsl));
+    std::vector<std::vector<int32_t>> suser(static_cast<size_t>(nsl));
+    std::vector<std::vector<uint8_t>> sidx(static_cast<size_t>(nsl));
+    parallel_for(nsl, [&](int64_t s0, int64_t s1) {
+        std::vector<std::array<int64_t, 3>> sl;  // (device neighbour, lane, user slot)
+        std::vector<std::vector<std::pair<int32_t, uint8_t>>> per_lane(kWave);
+        for (int64_t s = s0; s < s1; ++s) {
+            sl.clear();
+            for (int w = 0; w < kWave; ++w) {
+                const int64_t p = I.perm[s * kWave + w];
+                if (p < 0) continue;
+                for (int64_t b = I.row_ptr[p]; b < I.row_ptr[p + 1]; ++b)
+                    sl.push_back({I.node_off + I.iperm[I.col[b]], w, b});
+            }
+            std::sort(sl.begin(), sl.end());
+            auto& pcs = spieces[s];
+            auto& us = suser[s];
+            auto& ix = sidx[s];
+            size_t k = 0;
+            while (k < sl.size()) {
+                // one range: consecutive device nodes starting at sl[k][0]
+                const int64_t r0 = sl[k][0];
+                size_t e = k;
+                // small gaps are loaded along (cheaper than another piece)
+                while (e < sl.size() && sl[e][0] - r0 < kSegMax && sl[e][0] - sl[e == k ? k : e - 1][0] <= kMaxGap)
+                    ++e;
+                const int64_t len = sl[e - 1][0] - r0 + 1;
+                for (auto& v : per_lane) v.clear();
+                for (size_t q = k; q < e; ++q)
+                    per_lane[sl[q][1]].push_back({static_cast<int32_t>(sl[q][2]), static_cast<uint8_t>(sl[q][0] - r0)});
+                size_t T = 0;
+                for (auto& v : per_lane) T = std::max(T, v.size());
+                for (size_t t0 = 0; t0 < T; t0 += kPieceRows) {
+                    const int rows = static_cast<int>(std::min<size_t>(kPieceRows, T - t0));
+                    pcs.push_back(int2{static_cast<int>(r0), static_cast<int>(len | (rows << 8))});
+                    for (int t = 0; t < rows; ++t)
+                        for (int w = 0; w < kWave; ++w) {
+                            const auto& v = per_lane[w];
+                            if (t0 + t < v.size()) {
+                                us.push_back(v[t0 + t].first);
+                                ix.push_back(v[t0 + t].second);
+                            } else {
+                                us.push_back(-1);
+                                ix.push_back(static_cast<uint8_t>(kSegMax));
+                            }
+                        }
+                }
+                k = e;
+            }
+        }
+    });
+    I.pieces.clear();
+    I.slice_piece.assign(static_cast<size_t>(nsl) + 1, 0);
+    start.assign(static_cast<size_t>(nsl), 0);
+    int64_t nds = 0;
+    for (int64_t s = 0; s < nsl; ++s) {
+        I.slice_piece[s] = static_cast<int32_t>(I.pieces.size());
+        start[s] = nds;
+        I.pieces.insert(I.pieces.end(), spieces[s].begin(), spieces[s].end());
+        nds += static_cast<int64_t>(suser[s].size());
+    }
+    I.slice_piece[nsl] = static_cast<int32_t>(I.pieces.size());
+    I.dslot_user.resize(static_cast<size_t>(nds));
+    I.ent_idx.resize(static_cast<size_t>(nds));
+    parallel_for(nsl, [&](int64_t s0, int64_t s1) {
+        for (int64_t s = s0; s < s1; ++s) {
+            std::copy(suser[s].begin(), suser[s].end(), I.dslot_user.begin() + start[s]);
+            std::copy(sidx[s].begin(), sidx[s].end(), I.ent_idx.begin() + start[s]);
+        }
+    });
+    return nds;
+}
+
 // Allocate and fill the device problem for ctx->lanes from the instances' user data.
 void build_layout(pd_ctx* ctx, const HostState* S)
 {
-    const int G = ctx->lanes, W = kWave / G;
+    const int G = ctx->mapping == PD_MAP_STAGED ? 1 : ctx->lanes, W = kWave / G;
     ctx->drop_graphs();
     int64_t nn = 0, nsl = 0, ns = 0;
     std::vector<int64_t> sp;
-    std::vector<int32_t> sT, sI;
+    std::vector<int32_t> sT, sI, spc;
+    std::vector<int2> pcs;
     for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
         Inst& I = ctx->inst[ii];
         const double h = spacing_estimate(I);
@@ -672,36 +787,43 @@ void build_layout(pd_ctx* ctx, const HostState* S)
         I.nslices = I.n_pad / W;
         I.slice_off = nsl;
         I.dslot_off = ns;
-        const std::vector<int32_t> ranks = slot_ranks(I, h);
-        // slice row counts
         std::vector<int64_t> T(static_cast<size_t>(I.nslices), 0);
-        for (int64_t s = 0; s < I.nslices; ++s)
-            for (int w = 0; w < W; ++w) {
-                const int64_t p = I.perm[s * W + w];
-                if (p >= 0) T[s] = std::max<int64_t>(T[s], (I.row_ptr[p + 1] - I.row_ptr[p] + G - 1) / G);
-            }
-        int64_t nds = 0;
         std::vector<int64_t> start(static_cast<size_t>(I.nslices));
-        for (int64_t s = 0; s < I.nslices; ++s) {
-            start[s] = nds;
-            nds += T[s] * kWave;
+        int64_t nds = 0;
+        if (ctx->mapping == PD_MAP_STAGED) {
+            nds = build_staged(I, start);
+            for (int64_t s = 0; s < I.nslices; ++s) spc.push_back(static_cast<int32_t>(pcs.size()) + I.slice_piece[s]);
+            pcs.insert(pcs.end(), I.pieces.begin(), I.pieces.end());
+        } else {
+            const std::vector<int32_t> ranks = slot_ranks(I, h);
+            // slice row counts
+            for (int64_t s = 0; s < I.nslices; ++s)
+                for (int w = 0; w < W; ++w) {
+                    const int64_t p = I.perm[s * W + w];
+                    if (p >= 0) T[s] = std::max<int64_t>(T[s], (I.row_ptr[p + 1] - I.row_ptr[p] + G - 1) / G);
+                }
+            for (auto& t : T) t = (t + kRowUnroll - 1) / kRowUnroll * kRowUnroll;
+            for (int64_t s = 0; s < I.nslices; ++s) {
+                start[s] = nds;
+                nds += T[s] * kWave;
+            }
+            I.dslot_user.assign(static_cast<size_t>(nds), -1);
+            parallel_for(I.nslices, [&](int64_t s0, int64_t s1) {
+                for (int64_t s = s0; s < s1; ++s)
+                    for (int w = 0; w < W; ++w) {
+                        const int64_t p = I.perm[s * W + w];
+                        if (p < 0) continue;
+                        const int64_t b0 = I.row_ptr[p], len = I.row_ptr[p + 1] - b0;
+                        for (int64_t r = 0; r < len; ++r) {
+                            const int64_t t = r / G, g = r % G;
+                            I.dslot_user[start[s] + t * kWave + w * G + g] = static_cast<int32_t>(b0 + ranks[b0 + r]);
+                        }
+                    }
+            });
         }
         I.n_dslots = nds;
         I.s_start = start;
         I.s_T = T;
-        I.dslot_user.assign(static_cast<size_t>(nds), -1);
-        parallel_for(I.nslices, [&](int64_t s0, int64_t s1) {
-            for (int64_t s = s0; s < s1; ++s)
-                for (int w = 0; w < W; ++w) {
-                    const int64_t p = I.perm[s * W + w];
-                    if (p < 0) continue;
-                    const int64_t b0 = I.row_ptr[p], len = I.row_ptr[p + 1] - b0;
-                    for (int64_t r = 0; r < len; ++r) {
-                        const int64_t t = r / G, g = r % G;
-                        I.dslot_user[start[s] + t * kWave + w * G + g] = static_cast<int32_t>(b0 + ranks[b0 + r]);
-                    }
-                }
-        });
         for (int64_t s = 0; s < I.nslices; ++s) {
             sp.push_back(ns + start[s]);
             if (T[s] > std::numeric_limits<int32_t>::max()) fail(PD_ERANGE, "row too long");
@@ -714,17 +836,34 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     }
     if (nn >= std::numeric_limits<int32_t>::max() || ns >= std::numeric_limits<int32_t>::max())
         fail(PD_ERANGE, "device problem needs 2^31 or more nodes or slots");
+    if (nn + 1 >= (int64_t(1) << 24))
+        fail(PD_ERANGE, "device problem needs 2^24 or more node records (the gather uses 24-bit indices)");
     ctx->nn = nn;
     ctx->nslices = nsl;
     ctx->ns = ns;
     const size_t rs = real_size(ctx);
-    for (int b = 0; b < 2; ++b) ctx->rec[b].alloc(static_cast<size_t>(nn) * 48);
+    for (int b = 0; b < 2; ++b) ctx->rec[b].alloc(static_cast<size_t>(nn + 1) * 48);
     ctx->v.alloc(static_cast<size_t>(3 * nn) * rs);
     ctx->a.alloc(static_cast<size_t>(3 * nn) * rs);
-    ctx->col.alloc(static_cast<size_t>(ns) * sizeof(int32_t));
+    const size_t spare = kSpareRows * kWave;
+    if (ctx->mapping == PD_MAP_STAGED) {
+        ctx->col.release();
+        ctx->ent.alloc((static_cast<size_t>(ns) + spare) * sizeof(uint16_t));
+    } else {
+        ctx->ent.release();
+        ctx->col.alloc((static_cast<size_t>(ns) + spare) * sizeof(int32_t));
+    }
     ctx->slice_ptr.alloc(sp.size() * sizeof(int64_t));
     ctx->slice_T.alloc(sT.size() * sizeof(int32_t));
     ctx->slice_inst.alloc(sI.size() * sizeof(int32_t));
+    if (ctx->mapping == PD_MAP_STAGED) {
+        spc.push_back(static_cast<int32_t>(pcs.size()));
+        ctx->pieces.alloc(std::max<size_t>(pcs.size(), 1) * sizeof(int2));
+        ctx->slice_piece.alloc(spc.size() * sizeof(int32_t));
+    } else {
+        ctx->pieces.release();
+        ctx->slice_piece.release();
+    }
     ctx->params.alloc(ctx->inst.size() * sizeof(InstParams));
     ctx->bc_id.alloc(static_cast<size_t>(nn) * sizeof(int32_t));
     ctx->step_base.alloc(sizeof(int64_t));
@@ -735,11 +874,19 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     hip_check(hipMemsetAsync(ctx->v.p, 0, ctx->v.bytes, ctx->stream), "hipMemsetAsync");
     hip_check(hipMemsetAsync(ctx->a.p, 0, ctx->a.bytes, ctx->stream), "hipMemsetAsync");
     hip_check(hipMemsetAsync(ctx->status.p, 0, sizeof(int32_t), ctx->stream), "hipMemsetAsync");
+    if (ctx->col.p) hip_check(hipMemsetAsync(ctx->col.p, 0, ctx->col.bytes, ctx->stream), "hipMemsetAsync");
+    if (ctx->ent.p) hip_check(hipMemsetAsync(ctx->ent.p, 0, ctx->ent.bytes, ctx->stream), "hipMemsetAsync");
     upload(ctx->slice_ptr, sp.data(), sp.size() * sizeof(int64_t), 0, ctx->stream);
     upload(ctx->slice_T, sT.data(), sT.size() * sizeof(int32_t), 0, ctx->stream);
     upload(ctx->slice_inst, sI.data(), sI.size() * sizeof(int32_t), 0, ctx->stream);
+    if (ctx->mapping == PD_MAP_STAGED) {
+        upload(ctx->pieces, pcs.data(), pcs.size() * sizeof(int2), 0, ctx->stream);
+        upload(ctx->slice_piece, spc.data(), spc.size() * sizeof(int32_t), 0, ctx->stream);
+    }
     const int64_t st = ctx->step;
     upload(ctx->step_base, &st, sizeof st, 0, ctx->stream);
+    const double sentinel[6] = {1e10, 1e10, 1e10, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; ++b) upload(ctx->rec[b], sentinel, sizeof sentinel, static_cast<size_t>(nn) * 48, ctx->stream);
     sync(ctx);
     upload_params(ctx);
     upload_bcs(ctx);
@@ -819,6 +966,9 @@ StepArgs<Real> step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
     A.params = ctx->params.as<InstParams>();
     A.bc_id = ctx->bc_id.as<int32_t>();
     A.bc = ctx->bc.as<BCRec>();
+    A.pieces = ctx->pieces.as<int2>();
+    A.slice_piece = ctx->slice_piece.as<int32_t>();
+    A.ent = ctx->ent.as<uint16_t>();
     A.step_base = ctx->step_base.as<int64_t>();
     A.status = ctx->status.as<int32_t>();
     A.nn = ctx->nn;
@@ -836,9 +986,11 @@ int step_mode(int scheme)
 template <typename Real>
 void launch_one(pd_ctx* ctx, int mode, int in, int out, int64_t step_local)
 {
-    hip_check(launch_step<Real>(step_args<Real>(ctx, in, out, step_local), ctx->lanes, mode, ctx->has_stiff,
-                                ctx->stream),
-              "step kernel launch");
+    const StepArgs<Real> A = step_args<Real>(ctx, in, out, step_local);
+    if (ctx->mapping == PD_MAP_STAGED)
+        hip_check(launch_step_staged<Real>(A, mode, ctx->stream), "step kernel launch");
+    else
+        hip_check(launch_step<Real>(A, ctx->lanes, mode, ctx->has_stiff, ctx->stream), "step kernel launch");
 }
 
 // Launch `count` consecutive steps starting at buffer parity `cur`, step_local offsets
@@ -1260,6 +1412,7 @@ int pd_get_damage(pd_ctx* ctx, int32_t inst, double* out)
         set_device(ctx);
         DamageArgs D{};
         D.col = ctx->col.as<int32_t>();
+        D.sentinel = static_cast<int32_t>(ctx->nn);
         D.vol = ctx->has_vol ? ctx->vol.as<double>() : nullptr;
         D.slice_ptr = ctx->slice_ptr.as<int64_t>();
         D.slice_T = ctx->slice_T.as<int32_t>();
@@ -1267,7 +1420,13 @@ int pd_get_damage(pd_ctx* ctx, int32_t inst, double* out)
         D.params = ctx->params.as<InstParams>();
         D.phi = ctx->phi.as<double>();
         D.nslices = ctx->nslices;
-        hip_check(launch_damage(D, ctx->lanes, ctx->stream), "damage launch");
+        D.pieces = ctx->pieces.as<int2>();
+        D.slice_piece = ctx->slice_piece.as<int32_t>();
+        D.ent = ctx->ent.as<uint16_t>();
+        if (ctx->mapping == PD_MAP_STAGED)
+            hip_check(launch_damage_staged(D, ctx->stream), "damage launch");
+        else
+            hip_check(launch_damage(D, ctx->lanes, ctx->stream), "damage launch");
         std::vector<double> h(static_cast<size_t>(I.n_pad));
         download(h.data(), ctx->phi, h.size() * 8, I.node_off * 8, ctx->stream);
         sync(ctx);
@@ -1323,25 +1482,31 @@ int pd_set_step(pd_ctx* ctx, int64_t step)
     });
 }
 
-int pd_set_lanes_per_node(pd_ctx* ctx, int lanes)
+int pd_set_mapping(pd_ctx* ctx, int mapping, int lanes)
 {
     if (!ctx) return PD_EINVAL;
     return guarded(ctx, [&] {
+        if (mapping != PD_MAP_SLICED && mapping != PD_MAP_STAGED) fail(PD_EINVAL, "unknown mapping");
+        if (mapping == PD_MAP_STAGED) lanes = 1;
         if (lanes == 0) lanes = kDefaultLanes;
         if (!lanes_supported(lanes)) fail(PD_EINVAL, "unsupported lanes-per-node");
         if (!ctx->built) {
+            ctx->mapping = mapping;
             ctx->lanes = lanes;
             return;
         }
-        if (lanes == ctx->lanes) return;
+        if (lanes == ctx->lanes && mapping == ctx->mapping) return;
         set_device(ctx);
         HostState S = snapshot(ctx);
         const bool av = ctx->a_valid;
+        ctx->mapping = mapping;
         ctx->lanes = lanes;
         build_layout(ctx, &S);
         ctx->a_valid = av;
     });
 }
+
+int pd_set_lanes_per_node(pd_ctx* ctx, int lanes) { return pd_set_mapping(ctx, PD_MAP_SLICED, lanes); }
 
 int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
 {
@@ -1353,11 +1518,16 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
         HostState S = snapshot(ctx);
         const int64_t step0 = ctx->step;
         const bool av = ctx->a_valid;
-        const int cands[] = {1, 4, 16, 64};
-        int best = ctx->lanes;
+        struct Cand {
+            int mapping, lanes;
+        };
+        const Cand cands[] = {{PD_MAP_SLICED, 1}, {PD_MAP_SLICED, 4}, {PD_MAP_SLICED, 16}, {PD_MAP_SLICED, 64},
+                              {PD_MAP_STAGED, 1}};
+        Cand best{ctx->mapping, ctx->lanes};
         double best_ms = std::numeric_limits<double>::infinity();
-        for (int L : cands) {
-            ctx->lanes = L;
+        for (const Cand& cd : cands) {
+            ctx->mapping = cd.mapping;
+            ctx->lanes = cd.lanes;
             build_layout(ctx, &S);
             ctx->a_valid = av;
             for (int rep = 0; rep < 2; ++rep) {  // first pass builds graphs and warms caches
@@ -1371,11 +1541,12 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
             hip_check(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "hipEventElapsedTime");
             if (ms < best_ms) {
                 best_ms = ms;
-                best = L;
+                best = cd;
             }
             ctx->step = step0;
         }
-        ctx->lanes = best;
+        ctx->mapping = best.mapping;
+        ctx->lanes = best.lanes;
         build_layout(ctx, &S);
         ctx->step = step0;
         const int64_t st = step0;
@@ -1383,7 +1554,7 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
         sync(ctx);
         ctx->a_valid = av;
         reset_flags_after_state_change(ctx, av);
-        if (chosen) *chosen = best;
+        if (chosen) *chosen = best.mapping == PD_MAP_STAGED ? -1 : best.lanes;
     });
 }
 
@@ -1402,7 +1573,8 @@ int pd_get_info(const pd_ctx* ctx, pd_info* info)
     info->n_nodes_dev = ctx->nn;
     info->n_slots_dev = ctx->ns;
     info->n_instances = static_cast<int32_t>(ctx->inst.size());
-    info->lanes_per_node = ctx->lanes;
+    info->lanes_per_node = ctx->mapping == PD_MAP_STAGED ? 1 : ctx->lanes;
+    info->mapping = ctx->mapping;
     info->precision = ctx->precision;
     info->scheme = ctx->scheme;
     const double r = ctx->precision == PD_FP64 ? 8.0 : 4.0;

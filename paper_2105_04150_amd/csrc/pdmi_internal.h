@@ -7,14 +7,25 @@
 //                                 x is written once into both.
 //   velocity      v[3][nn]        structure of arrays, Real
 //   acceleration  a[3][nn]        structure of arrays, Real (velocity Verlet)
+//   sentinel      rec[*][nn]      one extra record far from every node; padding slots point at it
 //   slots         col[ns]         int32 per slot in "slices": a slice is the W = 64/G nodes one
 //                                 wavefront serves (G lanes per node); its slots are stored as
 //                                 T rows of 64 entries, entry (t, w*G + g) = slot t*G + g of the
 //                                 slice's node w.  col >= 0: intact bond to device node col;
-//                                 col < 0: ~col is the neighbour of a broken bond, or the node
-//                                 itself for padding (a node is never its own neighbour).
+//                                 col < 0: ~col is the neighbour of a broken bond, or the
+//                                 sentinel nn for padding.
 //   stiffness     kslot[ns]       f64 per slot, same layout (only with a stiffness field)
 //   slices        slice_ptr/T/inst first entry, row count and instance of every slice
+//
+// Staged layout (one lane per node, 64 nodes per slice).  The neighbours of a slice are
+// covered by "ranges" of at most kSegMax consecutive device nodes; each range's slots
+// are cut into "pieces" of at most kPieceRows rows of 64 uint16 entries.  A wavefront
+// copies a piece's node records and entries into LDS, then reads neighbours from there.
+//   pieces        int2 {first node of the range, len | T << 8} per piece
+//   slice_piece   first piece of every slice (+ one past the last)
+//   ent[ns]       uint16 per slot: bits 0..6 index into the range (kSegMax = padding,
+//                 the LDS sentinel record), bit 15 = broken; slice_ptr gives each slice's
+//                 first entry
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,6 +35,11 @@ namespace pdmi {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;             // 4 wavefronts per workgroup, one slice each
+constexpr int kRowUnroll = 2;           // slot rows per step-kernel iteration; every slice's row
+                                        // count is a multiple, and the slot arrays carry this
+                                        // many spare rows at the end
+constexpr int kSegMax = 80;             // node records per staged range (LDS slot kSegMax: sentinel)
+constexpr int kPieceRows = 8;           // slot rows per staged piece
 constexpr int32_t kNodeFree = -1;       // bc_id of an unconstrained node
 constexpr int32_t kNodePad = -2;        // bc_id of a padding node (never updated)
 
@@ -64,9 +80,12 @@ struct StepArgs {
     const InstParams* params;
     const int32_t* bc_id;
     const BCRec* bc;
+    const int2* pieces;         // staged layout only
+    const int32_t* slice_piece; // staged layout only
+    uint16_t* ent;              // staged layout only
     const int64_t* step_base;   // completed steps when the launch sequence started
     int32_t* status;            // bit 0: a non-finite u or v was produced
-    int64_t nn;                 // device node count (SoA stride)
+    int64_t nn;                 // device node count (SoA stride); record nn is the sentinel
     int64_t nslices;
     int64_t step_local;         // this launch advances step *step_base + step_local
     double dt;
@@ -74,6 +93,7 @@ struct StepArgs {
 
 struct DamageArgs {
     const int32_t* col;
+    int32_t sentinel;           // device index of the sentinel record (= node count)
     const double* vol;
     const int64_t* slice_ptr;
     const int32_t* slice_T;
@@ -81,6 +101,9 @@ struct DamageArgs {
     const InstParams* params;
     double* phi;
     int64_t nslices;
+    const int2* pieces;         // staged layout only
+    const int32_t* slice_piece;
+    const uint16_t* ent;
 };
 
 template <typename Real>
@@ -90,6 +113,11 @@ template <typename Real>
 hipError_t launch_drift(const StepArgs<Real>& a, int lanes, hipStream_t s);
 
 hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s);
+
+template <typename Real>
+hipError_t launch_step_staged(const StepArgs<Real>& a, int mode, hipStream_t s);
+
+hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
 
 hipError_t launch_advance(int64_t* step_base, int64_t by, hipStream_t s);
 

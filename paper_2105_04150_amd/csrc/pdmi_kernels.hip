@@ -23,26 +23,29 @@
 namespace pdmi {
 namespace {
 
-// 1/sqrt(x): hardware estimate (about 2^-23 relative) and two Newton steps.
+// 1/sqrt(x): hardware estimate (specified to 2^29 ulp, i.e. about 2^-23 relative) and NR
+// Newton steps; one step leaves a relative error near 1e-14, two reach rounding level.
+template <int NR>
 __device__ __forceinline__ double rsq64(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    double e = __builtin_fma(-h, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    h = x * y;
-    e = __builtin_fma(-h, y, 1.0);
-    return __builtin_fma(0.5 * y, e, y);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const double h = x * y;
+        const double e = __builtin_fma(-h, y, 1.0);
+        y = __builtin_fma(0.5 * y, e, y);
+    }
+    return y;
 }
 
-// 1 - (1+q)^(-1/2).  Series q/2 - 3q^2/8 + 5q^3/16 - 35q^4/128 + 63q^5/256 - 231q^6/1024
-// + 429q^7/2048; the first omitted term is below 0.2 q^8, i.e. under 1e-17 relative for
-// |q| < 4e-3.
+// 1 - (1+q)^(-1/2).  Series q/2 - 3q^2/8 + 5q^3/16 - 35q^4/128 + 63q^5/256 - 231q^6/1024;
+// the first omitted term, 429q^7/2048, is below 2e-15 of the sum for |q| < 4e-3.  Larger
+// |q| (strongly compressed or broken bonds) takes the closed form, whose cancellation
+// costs at most 1e-16/|q| < 3e-14 relative there.
 __device__ __forceinline__ double one_minus_rsqrt1p(double q)
 {
     if (fabs(q) < 4.0e-3) {
-        double p = 429.0 / 2048.0;
-        p = __builtin_fma(p, q, -231.0 / 1024.0);
+        double p = -231.0 / 1024.0;
         p = __builtin_fma(p, q, 63.0 / 256.0);
         p = __builtin_fma(p, q, -35.0 / 128.0);
         p = __builtin_fma(p, q, 5.0 / 16.0);
@@ -50,7 +53,7 @@ __device__ __forceinline__ double one_minus_rsqrt1p(double q)
         p = __builtin_fma(p, q, 0.5);
         return q * p;
     }
-    return 1.0 - rsq64(1.0 + q);
+    return 1.0 - rsq64<2>(1.0 + q);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that each XCD
@@ -87,61 +90,38 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v)
     return (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo);
 }
 
-template <int G, int MODE, bool STIFF>
-__global__ __launch_bounds__(kBlock) void step_f64(StepArgs<double> A)
+// Contribution of one slot.  c is the slot's col entry, (X, U) the owner's position and
+// displacement, p0..p2 the neighbour's node record, kv = stiffness times neighbour volume.
+// Adds the force density to F; returns true when the bond breaks in this step.
+__device__ __forceinline__ bool slot_force(int32_t c, const double2 p0, const double2 p1, const double2 p2,
+                                           double X0, double X1, double X2, double U0, double U1, double U2,
+                                           double kv, double q0, double& F0, double& F1, double& F2)
 {
-    constexpr int W = kWave / G;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t slice =
-        wave_uniform(xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + (threadIdx.x >> 6));
-    if (slice >= A.nslices) return;
-    const int inst = A.slice_inst[slice];
-    const InstParams P = A.params[inst];
-    const int w = lane / G, g = lane % G;
-    const int64_t node = slice * W + w;
+    const double xi0 = p0.x - X0, xi1 = p0.y - X1, xi2 = p1.x - X2;
+    const double e0 = p1.y - U0, e1 = p2.x - U1, e2 = p2.y - U2;
+    const double y0 = xi0 + e0, y1 = xi1 + e1, y2 = xi2 + e2;
+    // |y|^2 - |xi|^2 = eta . (xi + y)
+    const double z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
+    const double tq = __builtin_fma(e2, z2, __builtin_fma(e1, z1, e0 * z0));
+    const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
+    const double iL = rsq64<1>(L2);
+    const double q = tq * (iL * iL);
+    const bool brk = c >= 0 && q >= q0;
+    const bool alive = c >= 0 && !brk;
+    // broken and padding slots evaluate g(0) = 0 and add nothing
+    const double coef = (kv * iL) * one_minus_rsqrt1p(alive ? q : 0.0);
+    F0 = __builtin_fma(coef, y0, F0);
+    F1 = __builtin_fma(coef, y1, F1);
+    F2 = __builtin_fma(coef, y2, F2);
+    return brk;
+}
 
-    const double2* rin = reinterpret_cast<const double2*>(A.rec_in);
-    const double2 o0 = rin[3 * node], o1 = rin[3 * node + 1], o2 = rin[3 * node + 2];
-    const double X0 = o0.x, X1 = o0.y, X2 = o1.x;
-    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;
-
-    const int64_t base = A.slice_ptr[slice];
-    const int T = A.slice_T[slice];
-    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
-    for (int t = 0; t < T; ++t) {
-        const int64_t idx = base + static_cast<int64_t>(t) * kWave + lane;
-        const int32_t c = A.col[idx];
-        const int32_t j = c >= 0 ? c : ~c;
-        const double2* rj = rin + 3 * static_cast<int64_t>(j);
-        const double2 p0 = rj[0], p1 = rj[1], p2 = rj[2];
-        const double xi0 = p0.x - X0, xi1 = p0.y - X1, xi2 = p1.x - X2;
-        const double e0 = p1.y - U0, e1 = p2.x - U1, e2 = p2.y - U2;
-        const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
-        const double xe = __builtin_fma(xi2, e2, __builtin_fma(xi1, e1, xi0 * e0));
-        const double ee = __builtin_fma(e2, e2, __builtin_fma(e1, e1, e0 * e0));
-        const double iL = rsq64(L2);
-        double q = __builtin_fma(2.0, xe, ee) * (iL * iL);
-        bool alive = c >= 0;
-        if (alive && q >= P.q0) {
-            A.col[idx] = ~c;  // irreversible; contributes nothing from this step on
-            alive = false;
-        }
-        q = alive ? q : 0.0;
-        const double gq = one_minus_rsqrt1p(q);
-        const double kb = STIFF ? A.kslot[idx] : P.c;
-        const double vj = A.vol ? A.vol[j] : P.volume;
-        const double coef = alive ? kb * vj * iL * gq : 0.0;
-        F0 = __builtin_fma(coef, xi0 + e0, F0);
-        F1 = __builtin_fma(coef, xi1 + e1, F1);
-        F2 = __builtin_fma(coef, xi2 + e2, F2);
-    }
-#pragma unroll
-    for (int m = 1; m < G; m <<= 1) {
-        F0 += __shfl_xor(F0, m);
-        F1 += __shfl_xor(F1, m);
-        F2 += __shfl_xor(F2, m);
-    }
-    if (g != 0) return;
+// Integration and boundary conditions of one node given its force density F (the tail
+// of every step kernel).  U is the node's displacement at the level the forces used.
+template <int MODE>
+__device__ __forceinline__ void node_update(const StepArgs<double>& A, const InstParams& P, int64_t node,
+                                            double U0, double U1, double U2, double F0, double F1, double F2)
+{
     const int32_t bcid = A.bc_id[node];
     if (bcid == kNodePad) return;
 
@@ -215,6 +195,244 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs<double> A)
         for (int d = 0; d < 3; ++d) A.a[d * nn + node] = an[d];
 }
 
+template <int G, int MODE, bool STIFF, bool VOLN>
+__global__ __launch_bounds__(kBlock) void step_f64(StepArgs<double> A)
+{
+    constexpr int W = kWave / G;
+    constexpr int U = kRowUnroll;  // slot rows in flight per iteration
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t slice =
+        wave_uniform(xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + (threadIdx.x >> 6));
+    if (slice >= A.nslices) return;
+    const int inst = A.slice_inst[slice];
+    const InstParams P = A.params[inst];
+    const int w = lane / G, g = lane % G;
+    const int64_t node = slice * W + w;
+
+    const double2* __restrict__ rin = reinterpret_cast<const double2*>(A.rec_in);
+    const double2 o0 = rin[3 * node], o1 = rin[3 * node + 1], o2 = rin[3 * node + 2];
+    const double X0 = o0.x, X1 = o0.y, X2 = o1.x;
+    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;
+    // 32-bit byte offsets from wave-uniform bases (the host keeps every offset below 2^32)
+    const char* __restrict__ recb = reinterpret_cast<const char*>(A.rec_in);
+    const int64_t base = A.slice_ptr[slice];
+    const int T = A.slice_T[slice];
+    const char* __restrict__ colb = reinterpret_cast<const char*>(A.col + base);
+    const char* __restrict__ kb = STIFF ? reinterpret_cast<const char*>(A.kslot + base) : nullptr;
+    const double* __restrict__ volp = A.vol;
+    const uint32_t lane4 = static_cast<uint32_t>(lane) * 4u;
+    const double cv = P.c * P.volume;
+
+    // Rows are fetched one iteration ahead.  T is a multiple of kRowUnroll and the slot
+    // arrays end with kRowUnroll spare rows, so every prefetch is in bounds and no load
+    // sits behind a branch (rows prefetched past T belong to the next slice; unused).
+    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+    if (T > 0) {
+        auto col_at = [&](int t) -> int32_t {
+            const uint32_t off = static_cast<uint32_t>(t) * (kWave * 4u) + lane4;
+            return __builtin_nontemporal_load(reinterpret_cast<const int32_t*>(colb + off));
+        };
+        int32_t cn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cn[u] = col_at(u);
+        for (int t = 0; t < T; t += U) {
+            int32_t c[U];
+            double2 p[U][3];
+            double kv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c[u] = cn[u];
+                const uint32_t j = static_cast<uint32_t>(c[u] ^ (c[u] >> 31));
+                const char* rj = recb + __umul24(j, 48u);  // full-rate 24-bit multiply: j < 2^24
+                p[u][0] = *reinterpret_cast<const double2*>(rj);
+                p[u][1] = *reinterpret_cast<const double2*>(rj + 16);
+                p[u][2] = *reinterpret_cast<const double2*>(rj + 32);
+                if (STIFF || VOLN) {
+                    double k = P.c;
+                    if (STIFF) {
+                        const uint32_t off = static_cast<uint32_t>(t + u) * (kWave * 8u) + 2u * lane4;
+                        k = __builtin_nontemporal_load(reinterpret_cast<const double*>(kb + off));
+                    }
+                    kv[u] = k * (VOLN ? volp[j] : P.volume);
+                } else {
+                    kv[u] = cv;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) cn[u] = col_at(t + U + u);
+            bool brk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                brk[u] = slot_force(c[u], p[u][0], p[u][1], p[u][2], X0, X1, X2, U0, U1, U2, kv[u], P.q0, F0, F1, F2);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (brk[u]) A.col[base + static_cast<int64_t>(t + u) * kWave + lane] = ~c[u];  // irreversible
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) {
+        F0 += __shfl_xor(F0, m);
+        F1 += __shfl_xor(F1, m);
+        F2 += __shfl_xor(F2, m);
+    }
+    if (g != 0) return;
+    node_update<MODE>(A, P, node, U0, U1, U2, F0, F1, F2);
+}
+
+// Staged step kernel: one wavefront per 64-node slice, one lane per node.  For every
+// piece, the wavefront copies the range's node records (and volumes) and the piece's slot
+// entries into LDS with coalesced loads (the next piece's loads are in flight while the
+// current one is computed), then every slot reads its neighbour from LDS.  Each record
+// crosses the vector-memory path once per slice instead of once per slot.  Per-slot
+// stiffness, when present, streams from global memory one piece ahead.
+template <int MODE, bool STIFF, bool VOLN>
+__global__ __launch_bounds__(kWave) void step_staged_f64(StepArgs<double> A)
+{
+    constexpr int kRecChunks = 3 * (kSegMax + 1);            // 16-byte chunks of records
+    constexpr int kEntChunks = kPieceRows * kWave * 2 / 16;  // 16-byte chunks of entries
+    constexpr int kVolWords = VOLN ? kSegMax + 2 : 0;        // doubles of staged volumes
+    constexpr int kBuf = kRecChunks + kEntChunks + kVolWords / 2;
+    constexpr int kLoads = (3 * kSegMax + kEntChunks + kWave - 1) / kWave;
+    __shared__ double2 lds[2 * kBuf];
+
+    const int lane = threadIdx.x;
+    const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
+    if (slice >= A.nslices) return;
+    const InstParams P = A.params[A.slice_inst[slice]];
+    const int64_t node = slice * kWave + lane;
+    const double2* __restrict__ rin = reinterpret_cast<const double2*>(A.rec_in);
+    const double2 o0 = rin[3 * node], o1 = rin[3 * node + 1], o2 = rin[3 * node + 2];
+    const double X0 = o0.x, X1 = o0.y, X2 = o1.x;
+    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;
+    const double cv = P.c * P.volume;
+
+    // sentinel record (padding entries point at it) in both buffers, volume 0
+    if (lane < 3) {
+        const double2 sv = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
+        lds[3 * kSegMax + lane] = sv;
+        lds[kBuf + 3 * kSegMax + lane] = sv;
+    }
+    if (VOLN && lane == 0) {
+        reinterpret_cast<double*>(lds + kRecChunks + kEntChunks)[kSegMax] = 0.0;
+        reinterpret_cast<double*>(lds + kBuf + kRecChunks + kEntChunks)[kSegMax] = 0.0;
+    }
+    const int p0 = A.slice_piece[slice], p1 = A.slice_piece[slice + 1];
+    int64_t ent = A.slice_ptr[slice];  // first entry of the current piece
+    const double2* __restrict__ ent2 = reinterpret_cast<const double2*>(A.ent);
+    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+
+    double2 stage[kLoads];
+    double vstage[2];
+    double kcur[kPieceRows], knext[kPieceRows];
+    auto issue = [&](int p, int64_t e) {
+        const int2 m = A.pieces[p];
+        const int len = m.y & 0xff;
+        const int nrec = 3 * len, ntot = nrec + ((m.y >> 8) & 0xff) * (kWave * 2 / 16);
+        const double2* rsrc = rin + 3 * static_cast<int64_t>(m.x);
+        const double2* esrc = ent2 + e / 8;
+#pragma unroll
+        for (int c = 0; c < kLoads; ++c) {
+            const int gi = c * kWave + lane;
+            if (gi < nrec)
+                stage[c] = rsrc[gi];
+            else if (gi < ntot)
+                stage[c] = esrc[gi - nrec];
+        }
+        if (VOLN) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                if (c * kWave + lane < len) vstage[c] = A.vol[m.x + c * kWave + lane];
+        }
+        if (STIFF) {
+            // rows past the piece read the next piece or the spare rows; never used
+#pragma unroll
+            for (int t = 0; t < kPieceRows; ++t)
+                knext[t] = __builtin_nontemporal_load(A.kslot + e + t * kWave + lane);
+        }
+    };
+    auto commit = [&](int p, int buf) {
+        const int2 m = A.pieces[p];
+        const int len = m.y & 0xff;
+        const int nrec = 3 * len, ntot = nrec + ((m.y >> 8) & 0xff) * (kWave * 2 / 16);
+        double2* dst = lds + buf * kBuf;
+#pragma unroll
+        for (int c = 0; c < kLoads; ++c) {
+            const int gi = c * kWave + lane;
+            if (gi < nrec)
+                dst[gi] = stage[c];
+            else if (gi < ntot)
+                dst[kRecChunks + gi - nrec] = stage[c];
+        }
+        if (VOLN) {
+            double* vd = reinterpret_cast<double*>(dst + kRecChunks + kEntChunks);
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                if (c * kWave + lane < len) vd[c * kWave + lane] = vstage[c];
+        }
+    };
+
+    if (p1 > p0) {
+        issue(p0, ent);
+        commit(p0, 0);
+        for (int p = p0; p < p1; ++p) {
+            const int buf = (p - p0) & 1;
+            const int T = (A.pieces[p].y >> 8) & 0xff;
+            const int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;
+            if (STIFF)
+#pragma unroll
+                for (int t = 0; t < kPieceRows; ++t) kcur[t] = knext[t];
+            if (p + 1 < p1) issue(p + 1, ent_next);
+            __syncthreads();  // the piece's LDS copy is complete
+            const double2* rec = lds + buf * kBuf;
+            const uint16_t* le = reinterpret_cast<const uint16_t*>(rec + kRecChunks);
+            const double* lv = reinterpret_cast<const double*>(rec + kRecChunks + kEntChunks);
+#pragma unroll
+            for (int t = 0; t < kPieceRows; ++t) {
+                if (t >= T) break;
+                const uint16_t e = le[t * kWave + lane];
+                const int idx = e & 0x7f;
+                const double2 q0 = rec[3 * idx], q1 = rec[3 * idx + 1], q2 = rec[3 * idx + 2];
+                const int32_t c = (e & 0x8000) ? -1 : 0;  // sign carries the alive flag
+                double kv = cv;
+                if (STIFF || VOLN) kv = (STIFF ? kcur[t] : P.c) * (VOLN ? lv[idx] : P.volume);
+                if (slot_force(c, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2))
+                    A.ent[ent + t * kWave + lane] = static_cast<uint16_t>(e | 0x8000);  // irreversible
+            }
+            __syncthreads();  // every lane is done with buffer 1-buf before it is refilled
+            if (p + 1 < p1) commit(p + 1, buf ^ 1);
+            ent = ent_next;
+        }
+    }
+    node_update<MODE>(A, P, node, U0, U1, U2, F0, F1, F2);
+}
+
+// Local damage on the staged layout.
+__global__ __launch_bounds__(kWave) void damage_staged(DamageArgs A)
+{
+    const int lane = threadIdx.x;
+    const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
+    if (slice >= A.nslices) return;
+    const InstParams P = A.params[A.slice_inst[slice]];
+    const int64_t node = slice * kWave + lane;
+    const int p0 = A.slice_piece[slice], p1 = A.slice_piece[slice + 1];
+    int64_t ent = A.slice_ptr[slice];
+    double num = 0.0, den = 0.0;
+    for (int p = p0; p < p1; ++p) {
+        const int2 m = A.pieces[p];
+        const int T = (m.y >> 8) & 0xff;
+        for (int t = 0; t < T; ++t) {
+            const uint16_t e = A.ent[ent + t * kWave + lane];
+            const int idx = e & 0x7f;
+            if (idx == kSegMax) continue;  // padding
+            const double vj = A.vol ? A.vol[m.x + idx] : P.volume;
+            den += vj;
+            if (!(e & 0x8000)) num += vj;
+        }
+        ent += static_cast<int64_t>(T) * kWave;
+    }
+    A.phi[node] = den > 0.0 ? 1.0 - num / den : 0.0;
+}
+
 // Velocity-Verlet position update u_{k+1} = u_k + dt v_k + dt^2/2 a_k with the
 // displacement constraints of t_{k+1}; one thread per device node.
 __global__ __launch_bounds__(kBlock) void drift_f64(StepArgs<double> A)
@@ -258,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void damage_kernel(DamageArgs A)
     for (int t = 0; t < T; ++t) {
         const int32_t c = A.col[base + static_cast<int64_t>(t) * kWave + lane];
         const int32_t j = c >= 0 ? c : ~c;
-        if (j == node) continue;  // padding
+        if (j == A.sentinel) continue;  // padding
         const double vj = A.vol ? A.vol[j] : P.volume;
         den += vj;
         if (c >= 0) num += vj;
@@ -276,30 +494,26 @@ __global__ void advance_kernel(int64_t* step_base, int64_t by)
     if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += by;
 }
 
+template <int G, bool STIFF, bool VOLN>
+hipError_t launch_step_gsv(const StepArgs<double>& a, int mode, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>((a.nslices + 3) / 4)), block(kBlock);
+    switch (mode) {
+    case kModeEC: hipLaunchKernelGGL((step_f64<G, kModeEC, STIFF, VOLN>), grid, block, 0, s, a); break;
+    case kModeVV: hipLaunchKernelGGL((step_f64<G, kModeVV, STIFF, VOLN>), grid, block, 0, s, a); break;
+    case kModeVVInit: hipLaunchKernelGGL((step_f64<G, kModeVVInit, STIFF, VOLN>), grid, block, 0, s, a); break;
+    case kModeFE: hipLaunchKernelGGL((step_f64<G, kModeFE, STIFF, VOLN>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int G>
 hipError_t launch_step_g(const StepArgs<double>& a, int mode, bool stiff, hipStream_t s)
 {
-    const dim3 grid(static_cast<unsigned>((a.nslices + 3) / 4)), block(kBlock);
-#define PD_LAUNCH(M, S) hipLaunchKernelGGL((step_f64<G, M, S>), grid, block, 0, s, a)
-    if (stiff) {
-        switch (mode) {
-        case kModeEC: PD_LAUNCH(kModeEC, true); break;
-        case kModeVV: PD_LAUNCH(kModeVV, true); break;
-        case kModeVVInit: PD_LAUNCH(kModeVVInit, true); break;
-        case kModeFE: PD_LAUNCH(kModeFE, true); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else {
-        switch (mode) {
-        case kModeEC: PD_LAUNCH(kModeEC, false); break;
-        case kModeVV: PD_LAUNCH(kModeVV, false); break;
-        case kModeVVInit: PD_LAUNCH(kModeVVInit, false); break;
-        case kModeFE: PD_LAUNCH(kModeFE, false); break;
-        default: return hipErrorInvalidValue;
-        }
-    }
-#undef PD_LAUNCH
-    return hipGetLastError();
+    const bool voln = a.vol != nullptr;
+    if (stiff) return voln ? launch_step_gsv<G, true, true>(a, mode, s) : launch_step_gsv<G, true, false>(a, mode, s);
+    return voln ? launch_step_gsv<G, false, true>(a, mode, s) : launch_step_gsv<G, false, false>(a, mode, s);
 }
 
 }  // namespace
@@ -351,6 +565,42 @@ hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s)
     case 64: hipLaunchKernelGGL(damage_kernel<64>, grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <bool STIFF, bool VOLN>
+hipError_t launch_staged_sv(const StepArgs<double>& a, int mode, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>(a.nslices)), block(kWave);
+    switch (mode) {
+    case kModeEC: hipLaunchKernelGGL((step_staged_f64<kModeEC, STIFF, VOLN>), grid, block, 0, s, a); break;
+    case kModeVV: hipLaunchKernelGGL((step_staged_f64<kModeVV, STIFF, VOLN>), grid, block, 0, s, a); break;
+    case kModeVVInit: hipLaunchKernelGGL((step_staged_f64<kModeVVInit, STIFF, VOLN>), grid, block, 0, s, a); break;
+    case kModeFE: hipLaunchKernelGGL((step_staged_f64<kModeFE, STIFF, VOLN>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_step_staged<double>(const StepArgs<double>& a, int mode, hipStream_t s)
+{
+    if (a.nslices <= 0) return hipSuccess;
+    const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
+    if (stiff) return voln ? launch_staged_sv<true, true>(a, mode, s) : launch_staged_sv<true, false>(a, mode, s);
+    return voln ? launch_staged_sv<false, true>(a, mode, s) : launch_staged_sv<false, false>(a, mode, s);
+}
+
+template <>
+hipError_t launch_step_staged<float>(const StepArgs<float>&, int, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s)
+{
+    if (a.nslices <= 0) return hipSuccess;
+    hipLaunchKernelGGL(damage_staged, dim3(static_cast<unsigned>(a.nslices)), dim3(kWave), 0, s, a);
     return hipGetLastError();
 }
 

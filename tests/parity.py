@@ -29,9 +29,9 @@ def oracle_run(w, steps, nthreads=0, record_breaks=False):
     return sim
 
 
-def gpu_run(w, steps, precision=0, lanes=0, order=None, chunks=None):
+def gpu_run(w, steps, precision=0, lanes=0, order=None, chunks=None, mapping="sliced"):
     from paper_2105_04150_amd import simulation_for
-    sim = simulation_for(w, precision=precision, lanes=lanes, order=order)
+    sim = simulation_for(w, precision=precision, lanes=lanes, order=order, mapping=mapping)
     if chunks:
         for c in chunks:
             sim.step(c)

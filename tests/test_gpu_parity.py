@@ -34,54 +34,60 @@ def test_family_bit_exact(oracle_lib, name, over, order):
     assert np.array_equal(rp, grp) and np.array_equal(col, gcol)
 
 
-@pytest.mark.parametrize("lanes", [1, 4, 16, 64])
-def test_block10_euler_cromer(oracle_lib, lanes):
+MAPPINGS = [("sliced", 1), ("sliced", 4), ("sliced", 16), ("sliced", 64), ("staged", 1)]
+
+
+@pytest.mark.parametrize("mapping,lanes", MAPPINGS)
+def test_block10_euler_cromer(oracle_lib, mapping, lanes):
     """1,000-node jittered block, 1,000 Euler-Cromer steps, fractures (about 7.8k slots)."""
     w = pi.workload("block10")
     o = oracle_run(w, w.steps)
-    say(f"[run] block10 lanes={lanes}")
-    g = gpu_run(w, w.steps, lanes=lanes)
-    eu, ev, mism, ephi = compare(g, o, TOL_FP64, f"block10 lanes={lanes}")
+    say(f"[run] block10 {mapping} lanes={lanes}")
+    g = gpu_run(w, w.steps, lanes=lanes, mapping=mapping)
+    eu, ev, mism, ephi = compare(g, o, TOL_FP64, f"block10 {mapping} lanes={lanes}")
     assert o.broken_mask.sum() > 5000
     assert mism == 0
     assert eu <= TOL_FP64 and ev <= TOL_FP64
     assert ephi <= 1e-13
 
 
-@pytest.mark.parametrize("lanes", [1, 16])
-def test_notched_beam_velocity_verlet(oracle_lib, lanes):
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 1), ("sliced", 16), ("staged", 1)])
+def test_notched_beam_velocity_verlet(oracle_lib, mapping, lanes):
     """Notched three-point-bend beam (reduced length), velocity Verlet, velocity-controlled load."""
     w = pi.workload("beam3pb", dims=(60, 12, 12), steps=1500)
     o = oracle_run(w, w.steps)
-    say(f"[run] beam3pb-60 lanes={lanes}")
-    g = gpu_run(w, w.steps, lanes=lanes, chunks=[1, 700, 799])
+    say(f"[run] beam3pb-60 {mapping} lanes={lanes}")
+    g = gpu_run(w, w.steps, lanes=lanes, chunks=[1, 700, 799], mapping=mapping)
     eu, ev, mism, ephi = compare(g, o, TOL_FP64, f"beam3pb-60 lanes={lanes}")
     assert mism == 0 and eu <= TOL_FP64 and ev <= TOL_FP64 and ephi <= 1e-13
     assert rate_err(g.a(), o.a, w.dt, o.u, power=2) <= TOL_FP64
 
 
 @pytest.mark.parametrize("name", ["cube100", "cube100_wide"])
-def test_cube_morton(oracle_lib, name):
-    """Uniaxial tension of a cube in Morton order with a short horizon and a wide one."""
+@pytest.mark.parametrize("order,mapping", [("morton", "sliced"), ("natural", "staged"), ("morton", "staged")])
+def test_cube(oracle_lib, name, order, mapping):
+    """Uniaxial tension of a cube, short and wide horizons, both node orders and mappings."""
     w = pi.workload(name, dims=(24, 20, 18), steps=300)
     o = oracle_run(w, w.steps)
-    say(f"[run] {name}-small morton")
-    g = gpu_run(w, w.steps)
-    eu, ev, mism, ephi = compare(g, o, TOL_FP64, f"{name} 24x20x18")
+    say(f"[run] {name}-small {order} {mapping}")
+    g = gpu_run(w, w.steps, order=order, mapping=mapping)
+    eu, ev, mism, ephi = compare(g, o, TOL_FP64, f"{name} 24x20x18 {order} {mapping}")
     assert mism == 0 and eu <= TOL_FP64 and ephi <= 1e-13
 
 
-def test_stiffness_field_body_force(oracle_lib):
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 4), ("staged", 1)])
+def test_stiffness_field_body_force(oracle_lib, mapping, lanes):
     """Per-slot stiffness field c exp(g) and a body-force load (the adjoint workload, reduced)."""
     w = pi.workload("adjoint_beam", dims=(30, 10, 8), steps=400)
     o = oracle_run(w, w.steps)
-    say("[run] adjoint_beam-30 forward")
-    g = gpu_run(w, w.steps, lanes=4)
+    say(f"[run] adjoint_beam-30 forward {mapping}")
+    g = gpu_run(w, w.steps, lanes=lanes, mapping=mapping)
     eu, ev, mism, ephi = compare(g, o, TOL_FP64, "adjoint_beam 30x10x8")
     assert mism == 0 and eu <= TOL_FP64
 
 
-def test_nonuniform_volumes_and_damping(oracle_lib):
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 16), ("staged", 1)])
+def test_nonuniform_volumes_and_damping(oracle_lib, mapping, lanes):
     """Per-node volumes and dynamic-relaxation damping with Euler-Cromer."""
     from paper_2105_04150_amd import Simulation
     w = pi.workload("block10", dims=(9, 8, 7), steps=400)
@@ -92,9 +98,9 @@ def test_nonuniform_volumes_and_damping(oracle_lib):
     o = oracle_lib.OracleSim(w.coords, rp, col, c=w.c, s0=w.s0, rho=w.rho, dt=w.dt, vol=vols,
                              eta=eta, bcs=w.bcs)
     o.run(w.steps)
-    say("[run] block 9x8x7 volumes + damping")
+    say(f"[run] block 9x8x7 volumes + damping {mapping}")
     with Simulation() as g:
-        g.set_lanes_per_node(16)
+        g.set_mapping(mapping, lanes)
         g.build_family(w.coords, w.horizon)
         g.set_integrator("euler_cromer", w.dt)
         g.set_material(w.rho, w.c, w.s0, eta, volumes=vols)
@@ -105,12 +111,14 @@ def test_nonuniform_volumes_and_damping(oracle_lib):
     assert mism == 0 and eu <= TOL_FP64 and ephi <= 1e-13
 
 
-def test_batched_instances_match_independent_oracles(oracle_lib):
+@pytest.mark.parametrize("mapping", ["sliced", "staged"])
+def test_batched_instances_match_independent_oracles(oracle_lib, mapping):
     """Three uneven beams advanced together equal three independent oracle runs."""
     from paper_2105_04150_amd import Simulation, apply_workload
     ws = pi.batch_instances(count=3, scale_lo=0.4, scale_hi=0.7, steps=300)
-    say("[run] batch of 3: " + ", ".join(str(w.dims) for w in ws))
+    say(f"[run] batch of 3 ({mapping}): " + ", ".join(str(w.dims) for w in ws))
     with Simulation() as g:
+        g.set_mapping(mapping, 4 if mapping == "sliced" else 0)
         g.build_family_batch([w.coords for w in ws], [w.horizon for w in ws])
         g.set_integrator("euler_cromer", ws[0].dt)
         for b, w in enumerate(ws):
@@ -122,38 +130,56 @@ def test_batched_instances_match_independent_oracles(oracle_lib):
             assert mism == 0 and eu <= TOL_FP64 and ephi <= 1e-13
 
 
-def test_deterministic_and_restartable():
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 4), ("staged", 1)])
+def test_deterministic_and_restartable(mapping, lanes):
     """Bitwise-equal reruns; a 400 + restore + 300 run equals 700 straight steps."""
     from paper_2105_04150_amd import simulation_for
     w = pi.workload("block10", steps=700)
-    say("[run] determinism + checkpoint")
-    a = simulation_for(w, lanes=4)
+    say(f"[run] determinism + checkpoint {mapping}")
+    a = simulation_for(w, lanes=lanes, mapping=mapping)
     a.step(700)
-    b = simulation_for(w, lanes=4)
+    b = simulation_for(w, lanes=lanes, mapping=mapping)
     b.step(700)
     assert np.array_equal(a.u(), b.u()) and np.array_equal(a.broken(), b.broken())
-    c = simulation_for(w, lanes=4)
+    c = simulation_for(w, lanes=lanes, mapping=mapping)
     c.step(400)
     u, v, br = c.u(), c.v(), c.broken()
-    d = simulation_for(w, lanes=4)
+    d = simulation_for(w, lanes=lanes, mapping=mapping)
     d.set_state(u=u, v=v, broken=br)
     d.set_step(400)
     d.step(300)
     assert np.array_equal(d.u(), a.u()) and np.array_equal(d.broken(), a.broken())
 
 
-def test_lanes_change_keeps_state():
+def test_mapping_change_keeps_state():
     from paper_2105_04150_amd import simulation_for
     w = pi.workload("block10", steps=600)
     say("[run] relayout mid-run")
     a = simulation_for(w, lanes=1)
     a.step(600)
     b = simulation_for(w, lanes=1)
-    b.step(300)
+    b.step(200)
     b.set_lanes_per_node(64)
-    b.step(300)
+    b.step(200)
+    b.set_mapping("staged")
+    b.step(200)
     assert rel_err(b.u(), a.u()) <= 1e-12
     assert np.array_equal(a.broken(), b.broken())
+
+
+def test_autotune_restores_state(oracle_lib):
+    from paper_2105_04150_amd import simulation_for
+    w = pi.workload("block10", steps=300)
+    say("[run] autotune mid-run")
+    o = oracle_run(w, 300)
+    g = simulation_for(w)
+    g.step(100)
+    chosen = g.autotune(trial_steps=5)
+    say(f"[autotune] chose {chosen}")
+    assert g.step_count == 100
+    g.step(200)
+    eu, ev, mism, ephi = compare(g, o, TOL_FP64, "after autotune")
+    assert mism == 0 and eu <= TOL_FP64
 
 
 def test_nonfinite_reported():
@@ -188,9 +214,9 @@ def test_small_and_ragged_problems(oracle_lib, n):
     o.set_state(u=u0)
     o.run(50)
     say(f"[run] random cloud n={n} nnz={rp[-1]}")
-    for lanes in (1, 64):
+    for mapping, lanes in (("sliced", 1), ("sliced", 64), ("staged", 1)):
         with Simulation() as g:
-            g.set_lanes_per_node(lanes)
+            g.set_mapping(mapping, lanes)
             g.build_family(x, delta)
             g.set_material(2400.0, 1e20, 2e-3, 0.0, 1e-9)
             g.set_state(u=u0)
