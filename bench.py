@@ -65,9 +65,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="cube100", choices=["cube100", "cube100_wide", "block10", "beam3pb"])
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--lanes", type=int, default=0, help="lanes per node (0: autotune)")
-    ap.add_argument("--order", default=None, choices=[None, "natural", "morton"],
-                    help="device node order (default: the workload's)")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per node of the sliced mapping")
+    ap.add_argument("--mapping", default="auto", choices=["auto", "sliced", "staged"],
+                    help="step-kernel mapping (auto: the library's autotuner picks)")
+    ap.add_argument("--order", default="auto", choices=["auto", "natural", "morton"],
+                    help="device node order (auto: the autotuner tries both)")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -95,18 +97,22 @@ def main():
     import paper_2105_04150_amd as P
 
     w = pi.workload(args.workload)
-    if args.order:
-        w.order = args.order
+    w.order = args.order
     prec = P.PD_FP64 if args.precision == "f64" else P.PD_FP32
     t0 = time.perf_counter()
-    sim = P.simulation_for(w, precision=prec, lanes=args.lanes or 1)
+    if args.mapping == "auto":
+        sim = P.simulation_for(w, precision=prec)
+        sim.autotune(trial_steps=10)
+    else:
+        sim = P.simulation_for(w, precision=prec, lanes=args.lanes, mapping=args.mapping)
     setup_s = time.perf_counter() - t0
-    lanes = args.lanes
-    if not lanes:
-        lanes = sim.autotune(trial_steps=10)
     info = sim.info()
+    mapping = "staged" if info["mapping"] == P.PD_MAP_STAGED else "sliced"
+    order = "morton" if info["order"] == P.PD_ORDER_MORTON else "natural"
+    lanes = info["lanes_per_node"]
     print(f"# setup {setup_s:.1f} s, nodes {info['n_nodes']}, slots {info['n_slots']}, "
-          f"device slots {info['n_slots_dev']}, lanes {lanes}", file=sys.stderr, flush=True)
+          f"device slots {info['n_slots_dev']}, mapping {mapping}, lanes {lanes}, order {order}",
+          file=sys.stderr, flush=True)
 
     try:
         import torch
@@ -144,8 +150,9 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"{args.workload} {w.dims[0]}x{w.dims[1]}x{w.dims[2]} lattice, "
-                               f"horizon {w.horizon / w.dx:.3f} dx, {w.scheme}, {w.order} order",
-                   "nodes": info["n_nodes"], "bond_slots": nnz, "lanes_per_node": lanes,
+                               f"horizon {w.horizon / w.dx:.3f} dx, {w.scheme}",
+                   "nodes": info["n_nodes"], "bond_slots": nnz, "mapping": mapping, "lanes_per_node": lanes,
+                   "device_node_order": order,
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,

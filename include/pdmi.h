@@ -50,6 +50,7 @@ extern "C" {
 
 #define PD_ORDER_NATURAL 0  /* keep the caller's node order in device memory */
 #define PD_ORDER_MORTON 1   /* renumber nodes internally along a Morton (Z-order) curve */
+#define PD_ORDER_AUTO 2     /* natural order until pd_autotune, which also tries Morton order */
 
 #define PD_EULER_CROMER 0     /* v += dt (F - eta v)/rho; u += dt v_new */
 #define PD_VELOCITY_VERLET 1  /* Eqs. Velocity_Verlet1-3 */
@@ -90,7 +91,7 @@ typedef struct pd_info {
     int32_t precision;      /* PD_FP64 / PD_FP32 */
     int32_t scheme;         /* integrator */
     int32_t mapping;        /* PD_MAP_SLICED / PD_MAP_STAGED */
-    int32_t pad_;
+    int32_t order;          /* device node order in use: PD_ORDER_NATURAL / PD_ORDER_MORTON */
     double model_bytes_per_step; /* algorithmic HBM bytes of one step (see the design notes) */
 } pd_info;
 
@@ -223,7 +224,8 @@ int pd_set_mapping(pd_ctx *ctx, int mapping, int lanes);
 int pd_set_lanes_per_node(pd_ctx *ctx, int lanes);
 
 /* Time `trial_steps` steps (after as many untimed ones) of every mapping candidate on
- * the current problem and keep the fastest; the state is restored afterwards.
+ * the current problem (and both device node orders if the family was built with
+ * PD_ORDER_AUTO) and keep the fastest; the state is restored afterwards.
  * *chosen (may be NULL) receives the lanes-per-node of the chosen sliced mapping, or
  * -1 for the staged mapping. */
 int pd_autotune(pd_ctx *ctx, int64_t trial_steps, int32_t *chosen);

@@ -17,7 +17,7 @@ from ._binding import (PD_BC_DISP, PD_BC_VEL, PD_EULER_CROMER, PD_EULER_FORWARD,
 
 SCHEMES = {"euler_cromer": PD_EULER_CROMER, "velocity_verlet": PD_VELOCITY_VERLET,
            "forward_euler": PD_EULER_FORWARD}
-ORDERS = {"natural": PD_ORDER_NATURAL, "morton": PD_ORDER_MORTON}
+ORDERS = {"natural": PD_ORDER_NATURAL, "morton": PD_ORDER_MORTON, "auto": B.PD_ORDER_AUTO}
 
 
 class Simulation:

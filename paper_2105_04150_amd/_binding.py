@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpdmi.so"
 
 PD_OK, PD_EINVAL, PD_ENOMEM, PD_EHIP, PD_ESTATE, PD_ENONFINITE, PD_ERANGE = 0, -1, -2, -3, -4, -5, -6
 PD_FP64, PD_FP32 = 0, 1
-PD_ORDER_NATURAL, PD_ORDER_MORTON = 0, 1
+PD_ORDER_NATURAL, PD_ORDER_MORTON, PD_ORDER_AUTO = 0, 1, 2
 PD_EULER_CROMER, PD_VELOCITY_VERLET, PD_EULER_FORWARD = 0, 1, 2
 PD_BC_DISP, PD_BC_VEL = 1, 2
 PD_SCHED_CONST, PD_SCHED_LINEAR = 0, 1
@@ -46,7 +46,7 @@ class pd_material(C.Structure):
 class pd_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_slots", C.c_int64), ("n_nodes_dev", C.c_int64),
                 ("n_slots_dev", C.c_int64), ("n_instances", C.c_int32), ("lanes_per_node", C.c_int32),
-                ("precision", C.c_int32), ("scheme", C.c_int32), ("mapping", C.c_int32), ("pad_", C.c_int32),
+                ("precision", C.c_int32), ("scheme", C.c_int32), ("mapping", C.c_int32), ("order", C.c_int32),
                 ("model_bytes_per_step", C.c_double)]
 
 

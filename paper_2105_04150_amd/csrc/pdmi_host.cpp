@@ -112,6 +112,7 @@ struct pd_ctx {
 
     std::vector<Inst> inst;
     int order = PD_ORDER_NATURAL;
+    bool order_auto = false;         // the autotuner may change the device node order
     int lanes = kDefaultLanes;
     int mapping = PD_MAP_SLICED;
     int scheme = PD_EULER_CROMER;
@@ -581,9 +582,9 @@ void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
             for (int64_t d = s0; d < s1; ++d) {
                 const int32_t b = I.dslot_user[d];
                 if (b < 0)
-                    e[d] = static_cast<uint16_t>(0x8000 | kSegMax);
+                    e[d] = static_cast<uint16_t>(0x8000 | (3 * kSegMax));
                 else
-                    e[d] = static_cast<uint16_t>(I.ent_idx[d] | ((broken && broken[b]) ? 0x8000 : 0));
+                    e[d] = static_cast<uint16_t>((3 * I.ent_idx[d]) | ((broken && broken[b]) ? 0x8000 : 0));
             }
         });
         upload(ctx->ent, e.data(), e.size() * sizeof(uint16_t), I.dslot_off * sizeof(uint16_t), ctx->stream);
@@ -918,7 +919,8 @@ void validate_coords(int64_t n, const double* coords, double horizon)
 void new_problem(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* const* coords, const double* horizon,
                  int order)
 {
-    if (order != PD_ORDER_NATURAL && order != PD_ORDER_MORTON) fail(PD_EINVAL, "unknown node order");
+    if (order != PD_ORDER_NATURAL && order != PD_ORDER_MORTON && order != PD_ORDER_AUTO)
+        fail(PD_EINVAL, "unknown node order");
     if (ninst < 1) fail(PD_EINVAL, "need at least one instance");
     std::vector<Inst> insts(static_cast<size_t>(ninst));
     int64_t total = 0;
@@ -939,7 +941,8 @@ void new_problem(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* con
     set_device(ctx);
     ctx->built = false;
     ctx->inst = std::move(insts);
-    ctx->order = order;
+    ctx->order = order == PD_ORDER_AUTO ? PD_ORDER_NATURAL : order;
+    ctx->order_auto = order == PD_ORDER_AUTO;
     ctx->step = 0;
     ctx->a_valid = false;
     ctx->vv_ahead = false;
@@ -1519,15 +1522,21 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
         const int64_t step0 = ctx->step;
         const bool av = ctx->a_valid;
         struct Cand {
-            int mapping, lanes;
+            int mapping, lanes, order;
         };
-        const Cand cands[] = {{PD_MAP_SLICED, 1}, {PD_MAP_SLICED, 4}, {PD_MAP_SLICED, 16}, {PD_MAP_SLICED, 64},
-                              {PD_MAP_STAGED, 1}};
-        Cand best{ctx->mapping, ctx->lanes};
+        std::vector<Cand> cands;
+        const int orders[] = {PD_ORDER_NATURAL, PD_ORDER_MORTON};
+        for (int o : orders) {
+            if (!ctx->order_auto && o != ctx->order) continue;
+            for (int L : {1, 4, 16, 64}) cands.push_back({PD_MAP_SLICED, L, o});
+            cands.push_back({PD_MAP_STAGED, 1, o});
+        }
+        Cand best{ctx->mapping, ctx->lanes, ctx->order};
         double best_ms = std::numeric_limits<double>::infinity();
         for (const Cand& cd : cands) {
             ctx->mapping = cd.mapping;
             ctx->lanes = cd.lanes;
+            ctx->order = cd.order;
             build_layout(ctx, &S);
             ctx->a_valid = av;
             for (int rep = 0; rep < 2; ++rep) {  // first pass builds graphs and warms caches
@@ -1545,6 +1554,7 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
             }
             ctx->step = step0;
         }
+        ctx->order = best.order;
         ctx->mapping = best.mapping;
         ctx->lanes = best.lanes;
         build_layout(ctx, &S);
@@ -1575,6 +1585,7 @@ int pd_get_info(const pd_ctx* ctx, pd_info* info)
     info->n_instances = static_cast<int32_t>(ctx->inst.size());
     info->lanes_per_node = ctx->mapping == PD_MAP_STAGED ? 1 : ctx->lanes;
     info->mapping = ctx->mapping;
+    info->order = ctx->order;
     info->precision = ctx->precision;
     info->scheme = ctx->scheme;
     const double r = ctx->precision == PD_FP64 ? 8.0 : 4.0;

@@ -23,9 +23,11 @@
 // copies a piece's node records and entries into LDS, then reads neighbours from there.
 //   pieces        int2 {first node of the range, len | T << 8} per piece
 //   slice_piece   first piece of every slice (+ one past the last)
-//   ent[ns]       uint16 per slot: bits 0..6 index into the range (kSegMax = padding,
-//                 the LDS sentinel record), bit 15 = broken; slice_ptr gives each slice's
-//                 first entry
+//   ent[ns]       uint16 per slot: bits 0..14 = 3 x (index into the range), the record's
+//                 offset in 16-byte units (index kSegMax = padding, the LDS sentinel
+//                 record), bit 15 = broken; slice_ptr gives each slice's first entry.
+//                 The entry array ends with kPieceRows spare rows (whole 8-row blocks are
+//                 loaded).
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -204,8 +204,11 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs<double> A)
     const int64_t slice =
         wave_uniform(xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + (threadIdx.x >> 6));
     if (slice >= A.nslices) return;
-    const int inst = A.slice_inst[slice];
-    const InstParams P = A.params[inst];
+    const int32_t* __restrict__ slice_inst = A.slice_inst;
+    const InstParams* __restrict__ params = A.params;
+    const int64_t* __restrict__ slice_ptr = A.slice_ptr;
+    const int32_t* __restrict__ slice_T = A.slice_T;
+    const InstParams P = params[slice_inst[slice]];
     const int w = lane / G, g = lane % G;
     const int64_t node = slice * W + w;
 
@@ -215,8 +218,8 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs<double> A)
     const double U0 = o1.y, U1 = o2.x, U2 = o2.y;
     // 32-bit byte offsets from wave-uniform bases (the host keeps every offset below 2^32)
     const char* __restrict__ recb = reinterpret_cast<const char*>(A.rec_in);
-    const int64_t base = A.slice_ptr[slice];
-    const int T = A.slice_T[slice];
+    const int64_t base = slice_ptr[slice];
+    const int T = slice_T[slice];
     const char* __restrict__ colb = reinterpret_cast<const char*>(A.col + base);
     const char* __restrict__ kb = STIFF ? reinterpret_cast<const char*>(A.kslot + base) : nullptr;
     const double* __restrict__ volp = A.vol;
@@ -280,126 +283,121 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs<double> A)
 }
 
 // Staged step kernel: one wavefront per 64-node slice, one lane per node.  For every
-// piece, the wavefront copies the range's node records (and volumes) and the piece's slot
-// entries into LDS with coalesced loads (the next piece's loads are in flight while the
-// current one is computed), then every slot reads its neighbour from LDS.  Each record
-// crosses the vector-memory path once per slice instead of once per slot.  Per-slot
-// stiffness, when present, streams from global memory one piece ahead.
+// piece, the wavefront loads the range's node records (and volumes) and the piece's slot
+// entries into registers while the previous piece is being computed, then copies them
+// to LDS; every slot reads its neighbour from LDS.  Each record crosses the vector-memory
+// path once per slice instead of once per slot.  Per-slot stiffness, when present,
+// streams from global memory one piece ahead.  Rows are processed in pairs so the LDS
+// reads of one row overlap the arithmetic of the other.
 template <int MODE, bool STIFF, bool VOLN>
-__global__ __launch_bounds__(kWave) void step_staged_f64(StepArgs<double> A)
+__global__ __launch_bounds__(kWave) void step_staged_f64(StepArgs<double> A, const int2* __restrict__ pieces,
+                                                         const int32_t* __restrict__ slice_piece,
+                                                         const int64_t* __restrict__ slice_ptr)
 {
-    constexpr int kRecChunks = 3 * (kSegMax + 1);            // 16-byte chunks of records
+    constexpr int kRecChunks = 3 * (kSegMax + 1);            // 16-byte chunks of records + sentinel
     constexpr int kEntChunks = kPieceRows * kWave * 2 / 16;  // 16-byte chunks of entries
-    constexpr int kVolWords = VOLN ? kSegMax + 2 : 0;        // doubles of staged volumes
-    constexpr int kBuf = kRecChunks + kEntChunks + kVolWords / 2;
-    constexpr int kLoads = (3 * kSegMax + kEntChunks + kWave - 1) / kWave;
-    __shared__ double2 lds[2 * kBuf];
+    constexpr int kVolWords = VOLN ? kSegMax + 2 : 0;        // staged volumes (doubles)
+    constexpr int kLds = kRecChunks + kEntChunks + kVolWords / 2;
+    constexpr int kRecLoads = (3 * kSegMax + kWave - 1) / kWave;  // 4
+    static_assert(kRecLoads == 4 && kEntChunks == kWave, "staging uses four record loads and one entry load");
+    __shared__ double2 lds[kLds];
+    double2* const lrec = lds;
+    uint16_t* const lent = reinterpret_cast<uint16_t*>(lds + kRecChunks);
+    double* const lvol = reinterpret_cast<double*>(lds + kRecChunks + kEntChunks);
 
     const int lane = threadIdx.x;
     const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
     if (slice >= A.nslices) return;
-    const InstParams P = A.params[A.slice_inst[slice]];
+    const int32_t* __restrict__ slice_inst = A.slice_inst;
+    const InstParams* __restrict__ params = A.params;
+    const InstParams P = params[slice_inst[slice]];
     const int64_t node = slice * kWave + lane;
     const double2* __restrict__ rin = reinterpret_cast<const double2*>(A.rec_in);
     const double2 o0 = rin[3 * node], o1 = rin[3 * node + 1], o2 = rin[3 * node + 2];
     const double X0 = o0.x, X1 = o0.y, X2 = o1.x;
     const double U0 = o1.y, U1 = o2.x, U2 = o2.y;
     const double cv = P.c * P.volume;
-
-    // sentinel record (padding entries point at it) in both buffers, volume 0
-    if (lane < 3) {
-        const double2 sv = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
-        lds[3 * kSegMax + lane] = sv;
-        lds[kBuf + 3 * kSegMax + lane] = sv;
-    }
-    if (VOLN && lane == 0) {
-        reinterpret_cast<double*>(lds + kRecChunks + kEntChunks)[kSegMax] = 0.0;
-        reinterpret_cast<double*>(lds + kBuf + kRecChunks + kEntChunks)[kSegMax] = 0.0;
-    }
-    const int p0 = A.slice_piece[slice], p1 = A.slice_piece[slice + 1];
-    int64_t ent = A.slice_ptr[slice];  // first entry of the current piece
+    uint16_t* __restrict__ entw = A.ent;
     const double2* __restrict__ ent2 = reinterpret_cast<const double2*>(A.ent);
+
+    // sentinel record (padding entries point at it), volume 0
+    if (lane < 3) lrec[3 * kSegMax + lane] = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
+    if (VOLN && lane == 0) lvol[kSegMax] = 0.0;
+
+    const int p0 = __builtin_amdgcn_readfirstlane(slice_piece[slice]);
+    const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
+    int64_t ent = wave_uniform(slice_ptr[slice]);  // first entry of the current piece
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
 
-    double2 stage[kLoads];
-    double vstage[2];
+    // staging registers of the next piece
+    double2 r0, r1, r2, r3, e0;
+    int nrec = 0;
+    double vs0 = 0.0, vs1 = 0.0;
+    int vlen = 0;
     double kcur[kPieceRows], knext[kPieceRows];
+
+    // Loads of piece p (first entry e): unconditional, from clamped addresses.
     auto issue = [&](int p, int64_t e) {
-        const int2 m = A.pieces[p];
+        const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
         const int len = m.y & 0xff;
-        const int nrec = 3 * len, ntot = nrec + ((m.y >> 8) & 0xff) * (kWave * 2 / 16);
-        const double2* rsrc = rin + 3 * static_cast<int64_t>(m.x);
-        const double2* esrc = ent2 + e / 8;
-#pragma unroll
-        for (int c = 0; c < kLoads; ++c) {
-            const int gi = c * kWave + lane;
-            if (gi < nrec)
-                stage[c] = rsrc[gi];
-            else if (gi < ntot)
-                stage[c] = esrc[gi - nrec];
-        }
+        nrec = 3 * len;
+        const double2* rs = rin + 3 * static_cast<int64_t>(m.x);
+        r0 = rs[min(lane, nrec - 1)];
+        r1 = rs[min(lane + kWave, nrec - 1)];
+        r2 = rs[min(lane + 2 * kWave, nrec - 1)];
+        r3 = rs[min(lane + 3 * kWave, nrec - 1)];
+        e0 = ent2[e / 8 + lane];  // the whole 8-row entry block; rows >= T are never read
         if (VOLN) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-                if (c * kWave + lane < len) vstage[c] = A.vol[m.x + c * kWave + lane];
+            vlen = len;
+            vs0 = A.vol[m.x + min(lane, len - 1)];
+            vs1 = A.vol[m.x + min(lane + kWave, len - 1)];
         }
-        if (STIFF) {
-            // rows past the piece read the next piece or the spare rows; never used
+        if (STIFF)
 #pragma unroll
-            for (int t = 0; t < kPieceRows; ++t)
-                knext[t] = __builtin_nontemporal_load(A.kslot + e + t * kWave + lane);
+            for (int t = 0; t < kPieceRows; ++t) knext[t] = __builtin_nontemporal_load(A.kslot + e + t * kWave + lane);
+    };
+    auto commit = [&]() {
+        if (lane < nrec) lrec[lane] = r0;
+        if (lane + kWave < nrec) lrec[lane + kWave] = r1;
+        if (lane + 2 * kWave < nrec) lrec[lane + 2 * kWave] = r2;
+        if (lane + 3 * kWave < nrec) lrec[lane + 3 * kWave] = r3;
+        reinterpret_cast<double2*>(lent)[lane] = e0;
+        if (VOLN) {
+            if (lane < vlen) lvol[lane] = vs0;
+            if (lane + kWave < vlen) lvol[lane + kWave] = vs1;
         }
     };
-    auto commit = [&](int p, int buf) {
-        const int2 m = A.pieces[p];
-        const int len = m.y & 0xff;
-        const int nrec = 3 * len, ntot = nrec + ((m.y >> 8) & 0xff) * (kWave * 2 / 16);
-        double2* dst = lds + buf * kBuf;
-#pragma unroll
-        for (int c = 0; c < kLoads; ++c) {
-            const int gi = c * kWave + lane;
-            if (gi < nrec)
-                dst[gi] = stage[c];
-            else if (gi < ntot)
-                dst[kRecChunks + gi - nrec] = stage[c];
-        }
-        if (VOLN) {
-            double* vd = reinterpret_cast<double*>(dst + kRecChunks + kEntChunks);
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-                if (c * kWave + lane < len) vd[c * kWave + lane] = vstage[c];
-        }
+    auto row = [&](uint16_t e, double kst) {
+        const int ri = e & 0x7fff;  // record offset in 16-byte units (3 * index)
+        const double2 q0 = lrec[ri], q1 = lrec[ri + 1], q2 = lrec[ri + 2];
+        const int32_t c = (e & 0x8000) ? -1 : 0;  // sign carries the alive flag
+        double kv = cv;
+        if (STIFF || VOLN) kv = (STIFF ? kst : P.c) * (VOLN ? lvol[ri / 3] : P.volume);
+        return slot_force(c, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2);
     };
 
     if (p1 > p0) {
         issue(p0, ent);
-        commit(p0, 0);
         for (int p = p0; p < p1; ++p) {
-            const int buf = (p - p0) & 1;
-            const int T = (A.pieces[p].y >> 8) & 0xff;
+            const int T = (pieces[__builtin_amdgcn_readfirstlane(p)].y >> 8) & 0xff;
             const int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;
+            __syncthreads();  // the previous piece is no longer read
+            commit();
             if (STIFF)
 #pragma unroll
                 for (int t = 0; t < kPieceRows; ++t) kcur[t] = knext[t];
             if (p + 1 < p1) issue(p + 1, ent_next);
             __syncthreads();  // the piece's LDS copy is complete
-            const double2* rec = lds + buf * kBuf;
-            const uint16_t* le = reinterpret_cast<const uint16_t*>(rec + kRecChunks);
-            const double* lv = reinterpret_cast<const double*>(rec + kRecChunks + kEntChunks);
 #pragma unroll
-            for (int t = 0; t < kPieceRows; ++t) {
+            for (int t = 0; t < kPieceRows; t += 2) {
                 if (t >= T) break;
-                const uint16_t e = le[t * kWave + lane];
-                const int idx = e & 0x7f;
-                const double2 q0 = rec[3 * idx], q1 = rec[3 * idx + 1], q2 = rec[3 * idx + 2];
-                const int32_t c = (e & 0x8000) ? -1 : 0;  // sign carries the alive flag
-                double kv = cv;
-                if (STIFF || VOLN) kv = (STIFF ? kcur[t] : P.c) * (VOLN ? lv[idx] : P.volume);
-                if (slot_force(c, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2))
-                    A.ent[ent + t * kWave + lane] = static_cast<uint16_t>(e | 0x8000);  // irreversible
+                const uint16_t ea = lent[t * kWave + lane];
+                const uint16_t eb = (t + 1 < T) ? lent[(t + 1) * kWave + lane] : static_cast<uint16_t>(0x8000 | 3 * kSegMax);
+                const bool ba = row(ea, STIFF ? kcur[t] : 0.0);
+                const bool bb = row(eb, STIFF ? kcur[t + 1] : 0.0);
+                if (ba) entw[ent + t * kWave + lane] = static_cast<uint16_t>(ea | 0x8000);  // irreversible
+                if (bb) entw[ent + (t + 1) * kWave + lane] = static_cast<uint16_t>(eb | 0x8000);
             }
-            __syncthreads();  // every lane is done with buffer 1-buf before it is refilled
-            if (p + 1 < p1) commit(p + 1, buf ^ 1);
             ent = ent_next;
         }
     }
@@ -422,7 +420,7 @@ __global__ __launch_bounds__(kWave) void damage_staged(DamageArgs A)
         const int T = (m.y >> 8) & 0xff;
         for (int t = 0; t < T; ++t) {
             const uint16_t e = A.ent[ent + t * kWave + lane];
-            const int idx = e & 0x7f;
+            const int idx = (e & 0x7fff) / 3;
             if (idx == kSegMax) continue;  // padding
             const double vj = A.vol ? A.vol[m.x + idx] : P.volume;
             den += vj;
@@ -573,10 +571,14 @@ hipError_t launch_staged_sv(const StepArgs<double>& a, int mode, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>(a.nslices)), block(kWave);
     switch (mode) {
-    case kModeEC: hipLaunchKernelGGL((step_staged_f64<kModeEC, STIFF, VOLN>), grid, block, 0, s, a); break;
-    case kModeVV: hipLaunchKernelGGL((step_staged_f64<kModeVV, STIFF, VOLN>), grid, block, 0, s, a); break;
-    case kModeVVInit: hipLaunchKernelGGL((step_staged_f64<kModeVVInit, STIFF, VOLN>), grid, block, 0, s, a); break;
-    case kModeFE: hipLaunchKernelGGL((step_staged_f64<kModeFE, STIFF, VOLN>), grid, block, 0, s, a); break;
+#define PD_L(M)                                                                                   \
+    hipLaunchKernelGGL((step_staged_f64<M, STIFF, VOLN>), grid, block, 0, s, a, a.pieces, a.slice_piece, \
+                       a.slice_ptr)
+    case kModeEC: PD_L(kModeEC); break;
+    case kModeVV: PD_L(kModeVV); break;
+    case kModeVVInit: PD_L(kModeVVInit); break;
+    case kModeFE: PD_L(kModeFE); break;
+#undef PD_L
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
