@@ -126,8 +126,8 @@ struct pd_ctx {
 
     int64_t nn = 0, ns = 0, nslices = 0;
     bool has_stiff = false, has_vol = false, has_body = false;
-    DevBuf rec[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc, step_base,
-        status, phi, pieces, slice_piece, ent;
+    DevBuf rec[2], um[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc,
+        step_base, status, phi, pieces, slice_piece, ent;
 
     // graphs: [parity][mode] for chunks of kGraphChunk steps
     hipGraphExec_t graph[2][4] = {{nullptr}};
@@ -420,7 +420,7 @@ void download(void* dst, const DevBuf& b, size_t bytes, size_t offset_bytes, hip
 
 void sync(pd_ctx* ctx) { hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize"); }
 
-size_t real_size(const pd_ctx* ctx) { return ctx->precision == PD_FP64 ? 8 : 4; }
+bool fp32(const pd_ctx* ctx) { return ctx->precision == PD_FP32; }
 
 // (Re)build the whole device problem for the current lanes-per-node, keeping the state
 // given in user order (nullptr = zero / intact).
@@ -535,13 +535,19 @@ void upload_body(pd_ctx* ctx)
 void upload_state(pd_ctx* ctx, const Inst& I, const double* u, const double* v, const double* a)
 {
     const int64_t nn = ctx->nn;
+    auto soa = [&](const double* src, int d) {
+        std::vector<double> h(static_cast<size_t>(I.n_pad), 0.0);
+        for (int64_t l = 0; l < I.n_pad; ++l)
+            if (I.perm[l] >= 0) h[l] = src[3 * I.perm[l] + d];
+        return h;
+    };
     if (u) {
         std::vector<double> rec(static_cast<size_t>(6 * I.n_pad), 0.0);
         for (int64_t l = 0; l < I.n_pad; ++l) {
             const int64_t p = I.perm[l];
             if (p < 0) continue;
             for (int d = 0; d < 3; ++d) rec[6 * l + d] = I.x[3 * p + d];
-            if (ctx->precision == PD_FP64) {
+            if (!fp32(ctx)) {
                 for (int d = 0; d < 3; ++d) rec[6 * l + 3 + d] = u[3 * p + d];
             } else {
                 float f[3] = {float(u[3 * p]), float(u[3 * p + 1]), float(u[3 * p + 2])};
@@ -550,28 +556,23 @@ void upload_state(pd_ctx* ctx, const Inst& I, const double* u, const double* v, 
         }
         for (int b = 0; b < 2; ++b)
             upload(ctx->rec[b], rec.data(), rec.size() * sizeof(double), I.node_off * 48, ctx->stream);
-        sync(ctx);
-    }
-    auto put_soa = [&](DevBuf& buf, const double* src) {
-        if (!src) return;
-        for (int d = 0; d < 3; ++d) {
-            if (ctx->precision == PD_FP64) {
-                std::vector<double> h(static_cast<size_t>(I.n_pad), 0.0);
-                for (int64_t l = 0; l < I.n_pad; ++l)
-                    if (I.perm[l] >= 0) h[l] = src[3 * I.perm[l] + d];
-                upload(buf, h.data(), h.size() * 8, (d * nn + I.node_off) * 8, ctx->stream);
-                sync(ctx);
-            } else {
-                std::vector<float> h(static_cast<size_t>(I.n_pad), 0.0f);
-                for (int64_t l = 0; l < I.n_pad; ++l)
-                    if (I.perm[l] >= 0) h[l] = float(src[3 * I.perm[l] + d]);
-                upload(buf, h.data(), h.size() * 4, (d * nn + I.node_off) * 4, ctx->stream);
-                sync(ctx);
+        if (fp32(ctx))
+            for (int d = 0; d < 3; ++d) {
+                const std::vector<double> h = soa(u, d);
+                for (int b = 0; b < 2; ++b)
+                    upload(ctx->um[b], h.data(), h.size() * 8, (d * nn + I.node_off) * 8, ctx->stream);
             }
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (v) {
+            const std::vector<double> h = soa(v, d);
+            upload(ctx->v, h.data(), h.size() * 8, (d * nn + I.node_off) * 8, ctx->stream);
         }
-    };
-    put_soa(ctx->v, v);
-    put_soa(ctx->a, a);
+        if (a) {
+            const std::vector<double> h = soa(a, d);
+            upload(ctx->a, h.data(), h.size() * 8, (d * nn + I.node_off) * 8, ctx->stream);
+        }
+    }
 }
 
 void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
@@ -638,26 +639,19 @@ std::vector<double> soa_of(pd_ctx* ctx, const Inst& I, const DevBuf& buf)
 {
     const int64_t nn = ctx->nn;
     std::vector<double> out(static_cast<size_t>(3 * I.n), 0.0);
+    std::vector<double> h(static_cast<size_t>(I.n_pad));
     for (int d = 0; d < 3; ++d) {
-        if (ctx->precision == PD_FP64) {
-            std::vector<double> h(static_cast<size_t>(I.n_pad));
-            download(h.data(), buf, h.size() * 8, (d * nn + I.node_off) * 8, ctx->stream);
-            sync(ctx);
-            for (int64_t l = 0; l < I.n_pad; ++l)
-                if (I.perm[l] >= 0) out[3 * I.perm[l] + d] = h[l];
-        } else {
-            std::vector<float> h(static_cast<size_t>(I.n_pad));
-            download(h.data(), buf, h.size() * 4, (d * nn + I.node_off) * 4, ctx->stream);
-            sync(ctx);
-            for (int64_t l = 0; l < I.n_pad; ++l)
-                if (I.perm[l] >= 0) out[3 * I.perm[l] + d] = h[l];
-        }
+        download(h.data(), buf, h.size() * 8, (d * nn + I.node_off) * 8, ctx->stream);
+        sync(ctx);
+        for (int64_t l = 0; l < I.n_pad; ++l)
+            if (I.perm[l] >= 0) out[3 * I.perm[l] + d] = h[l];
     }
     return out;
 }
 
 std::vector<double> u_of(pd_ctx* ctx, const Inst& I)
 {
+    if (fp32(ctx)) return soa_of(ctx, I, ctx->um[ctx->cur]);  // the f64 master displacement
     std::vector<double> rec(static_cast<size_t>(6 * I.n_pad));
     download(rec.data(), ctx->rec[ctx->cur], rec.size() * 8, I.node_off * 48, ctx->stream);
     sync(ctx);
@@ -665,13 +659,7 @@ std::vector<double> u_of(pd_ctx* ctx, const Inst& I)
     for (int64_t l = 0; l < I.n_pad; ++l) {
         const int64_t p = I.perm[l];
         if (p < 0) continue;
-        if (ctx->precision == PD_FP64) {
-            for (int d = 0; d < 3; ++d) out[3 * p + d] = rec[6 * l + 3 + d];
-        } else {
-            float f[3];
-            std::memcpy(f, &rec[6 * l + 3], sizeof f);
-            for (int d = 0; d < 3; ++d) out[3 * p + d] = f[d];
-        }
+        for (int d = 0; d < 3; ++d) out[3 * p + d] = rec[6 * l + 3 + d];
     }
     return out;
 }
@@ -842,10 +830,15 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     ctx->nn = nn;
     ctx->nslices = nsl;
     ctx->ns = ns;
-    const size_t rs = real_size(ctx);
-    for (int b = 0; b < 2; ++b) ctx->rec[b].alloc(static_cast<size_t>(nn + 1) * 48);
-    ctx->v.alloc(static_cast<size_t>(3 * nn) * rs);
-    ctx->a.alloc(static_cast<size_t>(3 * nn) * rs);
+    for (int b = 0; b < 2; ++b) {
+        ctx->rec[b].alloc(static_cast<size_t>(nn + 1) * 48);
+        if (fp32(ctx))
+            ctx->um[b].alloc(static_cast<size_t>(3 * nn) * sizeof(double));
+        else
+            ctx->um[b].release();
+    }
+    ctx->v.alloc(static_cast<size_t>(3 * nn) * sizeof(double));
+    ctx->a.alloc(static_cast<size_t>(3 * nn) * sizeof(double));
     const size_t spare = kSpareRows * kWave;
     if (ctx->mapping == PD_MAP_STAGED) {
         ctx->col.release();
@@ -873,6 +866,8 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     hip_check(hipMemsetAsync(ctx->rec[0].p, 0, ctx->rec[0].bytes, ctx->stream), "hipMemsetAsync");
     hip_check(hipMemsetAsync(ctx->rec[1].p, 0, ctx->rec[1].bytes, ctx->stream), "hipMemsetAsync");
     hip_check(hipMemsetAsync(ctx->v.p, 0, ctx->v.bytes, ctx->stream), "hipMemsetAsync");
+    for (int b = 0; b < 2; ++b)
+        if (ctx->um[b].p) hip_check(hipMemsetAsync(ctx->um[b].p, 0, ctx->um[b].bytes, ctx->stream), "hipMemsetAsync");
     hip_check(hipMemsetAsync(ctx->a.p, 0, ctx->a.bytes, ctx->stream), "hipMemsetAsync");
     hip_check(hipMemsetAsync(ctx->status.p, 0, sizeof(int32_t), ctx->stream), "hipMemsetAsync");
     if (ctx->col.p) hip_check(hipMemsetAsync(ctx->col.p, 0, ctx->col.bytes, ctx->stream), "hipMemsetAsync");
@@ -951,14 +946,15 @@ void new_problem(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* con
 
 // ------------------------------------------------------------------ stepping
 
-template <typename Real>
-StepArgs<Real> step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
+StepArgs step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
 {
-    StepArgs<Real> A{};
+    StepArgs A{};
     A.rec_in = ctx->rec[in].as<double>();
     A.rec_out = ctx->rec[out].as<double>();
-    A.v = ctx->v.as<Real>();
-    A.a = ctx->a.as<Real>();
+    A.v = ctx->v.as<double>();
+    A.a = ctx->a.as<double>();
+    A.um_in = ctx->um[in].as<double>();
+    A.um_out = ctx->um[out].as<double>();
     A.col = ctx->col.as<int32_t>();
     A.kslot = ctx->has_stiff ? ctx->kslot.as<double>() : nullptr;
     A.vol = ctx->has_vol ? ctx->vol.as<double>() : nullptr;
@@ -986,31 +982,28 @@ int step_mode(int scheme)
     return scheme == PD_VELOCITY_VERLET ? kModeVV : scheme == PD_EULER_FORWARD ? kModeFE : kModeEC;
 }
 
-template <typename Real>
 void launch_one(pd_ctx* ctx, int mode, int in, int out, int64_t step_local)
 {
-    const StepArgs<Real> A = step_args<Real>(ctx, in, out, step_local);
+    const StepArgs A = step_args(ctx, in, out, step_local);
     if (ctx->mapping == PD_MAP_STAGED)
-        hip_check(launch_step_staged<Real>(A, mode, ctx->stream), "step kernel launch");
+        hip_check(launch_step_staged(A, mode, fp32(ctx), ctx->stream), "step kernel launch");
     else
-        hip_check(launch_step<Real>(A, ctx->lanes, mode, ctx->has_stiff, ctx->stream), "step kernel launch");
+        hip_check(launch_step(A, ctx->lanes, mode, ctx->has_stiff, ctx->stream), "step kernel launch");
 }
 
 // Launch `count` consecutive steps starting at buffer parity `cur`, step_local offsets
 // 0..count-1 relative to the device step base, then advance the base.
-template <typename Real>
 void launch_steps(pd_ctx* ctx, int mode, int cur, int64_t count)
 {
     for (int64_t i = 0; i < count; ++i) {
         const int in = (mode == kModeVV) ? 1 - cur : cur;
         const int out = 1 - in;
-        launch_one<Real>(ctx, mode, in, out, i);
+        launch_one(ctx, mode, in, out, i);
         cur ^= 1;
     }
     hip_check(launch_advance(ctx->step_base.as<int64_t>(), count, ctx->stream), "advance launch");
 }
 
-template <typename Real>
 hipGraphExec_t chunk_graph(pd_ctx* ctx, int mode, int parity)
 {
     hipGraphExec_t& g = ctx->graph[parity][mode];
@@ -1018,7 +1011,7 @@ hipGraphExec_t chunk_graph(pd_ctx* ctx, int mode, int parity)
     hipGraph_t graph = nullptr;
     hip_check(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-        launch_steps<Real>(ctx, mode, parity, kGraphChunk);
+        launch_steps(ctx, mode, parity, kGraphChunk);
     } catch (...) {
         (void)hipStreamEndCapture(ctx->stream, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1031,7 +1024,6 @@ hipGraphExec_t chunk_graph(pd_ctx* ctx, int mode, int parity)
     return g;
 }
 
-template <typename Real>
 void do_steps(pd_ctx* ctx, int64_t nsteps)
 {
     const int mode = step_mode(ctx->scheme);
@@ -1042,24 +1034,23 @@ void do_steps(pd_ctx* ctx, int64_t nsteps)
     hip_check(hipEventRecord(ctx->ev0, ctx->stream), "hipEventRecord");
     if (mode == kModeVV && nsteps > 0) {
         if (!ctx->a_valid) {
-            launch_one<Real>(ctx, kModeVVInit, ctx->cur, 1 - ctx->cur, 0);
+            launch_one(ctx, kModeVVInit, ctx->cur, 1 - ctx->cur, 0);
             ctx->a_valid = true;
             ctx->vv_ahead = true;
         } else if (!ctx->vv_ahead) {
-            hip_check(launch_drift<Real>(step_args<Real>(ctx, ctx->cur, 1 - ctx->cur, 0), ctx->lanes, ctx->stream),
-                      "drift launch");
+            hip_check(launch_drift(step_args(ctx, ctx->cur, 1 - ctx->cur, 0), fp32(ctx), ctx->stream), "drift launch");
             ctx->vv_ahead = true;
         }
     }
     int64_t left = nsteps;
     if (ctx->use_graphs) {
         while (left >= kGraphChunk) {
-            hip_check(hipGraphLaunch(chunk_graph<Real>(ctx, mode, ctx->cur), ctx->stream), "hipGraphLaunch");
+            hip_check(hipGraphLaunch(chunk_graph(ctx, mode, ctx->cur), ctx->stream), "hipGraphLaunch");
             left -= kGraphChunk;  // even chunk: parity unchanged
         }
     }
     if (left > 0) {
-        launch_steps<Real>(ctx, mode, ctx->cur, left);
+        launch_steps(ctx, mode, ctx->cur, left);
         if (left & 1) ctx->cur ^= 1;
     }
     hip_check(hipEventRecord(ctx->ev1, ctx->stream), "hipEventRecord");
@@ -1112,6 +1103,7 @@ int pd_create(pd_ctx** out, int device, int precision, void* hip_stream)
         if (device < 0 || device >= count) fail(PD_EINVAL, "device index out of range");
         ctx->device = device;
         ctx->precision = precision;
+        if (precision == PD_FP32) ctx->mapping = PD_MAP_STAGED;  // FP32 bond arithmetic lives in the staged kernel
         set_device(ctx.get());
         if (hip_stream) {
             ctx->stream = static_cast<hipStream_t>(hip_stream);
@@ -1344,10 +1336,7 @@ int pd_step(pd_ctx* ctx, int64_t nsteps)
         if (ctx->step + nsteps >= std::numeric_limits<int32_t>::max())
             fail(PD_ERANGE, "step counter would exceed 2^31 - 1");
         set_device(ctx);
-        if (ctx->precision == PD_FP64)
-            do_steps<double>(ctx, nsteps);
-        else
-            do_steps<float>(ctx, nsteps);
+        do_steps(ctx, nsteps);
     });
 }
 
@@ -1490,6 +1479,7 @@ int pd_set_mapping(pd_ctx* ctx, int mapping, int lanes)
     if (!ctx) return PD_EINVAL;
     return guarded(ctx, [&] {
         if (mapping != PD_MAP_SLICED && mapping != PD_MAP_STAGED) fail(PD_EINVAL, "unknown mapping");
+        if (fp32(ctx) && mapping != PD_MAP_STAGED) fail(PD_EINVAL, "the FP32 build runs the staged mapping only");
         if (mapping == PD_MAP_STAGED) lanes = 1;
         if (lanes == 0) lanes = kDefaultLanes;
         if (!lanes_supported(lanes)) fail(PD_EINVAL, "unsupported lanes-per-node");
@@ -1528,7 +1518,8 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
         const int orders[] = {PD_ORDER_NATURAL, PD_ORDER_MORTON};
         for (int o : orders) {
             if (!ctx->order_auto && o != ctx->order) continue;
-            for (int L : {1, 4, 16, 64}) cands.push_back({PD_MAP_SLICED, L, o});
+            if (!fp32(ctx))
+                for (int L : {1, 4, 16, 64}) cands.push_back({PD_MAP_SLICED, L, o});
             cands.push_back({PD_MAP_STAGED, 1, o});
         }
         Cand best{ctx->mapping, ctx->lanes, ctx->order};
@@ -1539,12 +1530,8 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
             ctx->order = cd.order;
             build_layout(ctx, &S);
             ctx->a_valid = av;
-            for (int rep = 0; rep < 2; ++rep) {  // first pass builds graphs and warms caches
-                if (ctx->precision == PD_FP64)
-                    do_steps<double>(ctx, trial_steps);
-                else
-                    do_steps<float>(ctx, trial_steps);
-            }
+            for (int rep = 0; rep < 2; ++rep)  // first pass builds graphs and warms caches
+                do_steps(ctx, trial_steps);
             float ms = 0.f;
             sync(ctx);
             hip_check(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "hipEventElapsedTime");
@@ -1588,10 +1575,11 @@ int pd_get_info(const pd_ctx* ctx, pd_info* info)
     info->order = ctx->order;
     info->precision = ctx->precision;
     info->scheme = ctx->scheme;
-    const double r = ctx->precision == PD_FP64 ? 8.0 : 4.0;
     // algorithmic bytes: 4 per slot (+8 with a stiffness field); per node x (24 B) read,
-    // u read + write, v read + write, a read + write (velocity Verlet)
-    double per_node = 24.0 + 4.0 * 3.0 * r + (ctx->scheme == PD_VELOCITY_VERLET ? 2.0 * 3.0 * r : 0.0);
+    // u read + write, v read + write, a read + write (velocity Verlet); the FP32 build also
+    // reads and writes the f32 displacement copy (12 + 12 B)
+    double per_node = 24.0 + 4.0 * 24.0 + (ctx->scheme == PD_VELOCITY_VERLET ? 2.0 * 24.0 : 0.0) +
+                      (ctx->precision == PD_FP32 ? 24.0 : 0.0);
     info->model_bytes_per_step = static_cast<double>(nnz) * (4.0 + (ctx->has_stiff ? 8.0 : 0.0)) +
                                  static_cast<double>(n) * per_node;
     return PD_OK;

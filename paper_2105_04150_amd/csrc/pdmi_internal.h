@@ -5,8 +5,11 @@
 //                                 FP32: u as 3 x f32 at byte 24, bytes 36..47 unused.  Two
 //                                 copies hold consecutive displacement levels (ping-pong);
 //                                 x is written once into both.
-//   velocity      v[3][nn]        structure of arrays, Real
-//   acceleration  a[3][nn]        structure of arrays, Real (velocity Verlet)
+//   master u      um[2][3][nn]    FP32 build only: the f64 displacement the integrator
+//                                 advances (the records carry its f32 rounding for the
+//                                 bond arithmetic); ping-pong like the records
+//   velocity      v[3][nn]        structure of arrays, f64
+//   acceleration  a[3][nn]        structure of arrays, f64 (velocity Verlet)
 //   sentinel      rec[*][nn]      one extra record far from every node; padding slots point at it
 //   slots         col[ns]         int32 per slot in "slices": a slice is the W = 64/G nodes one
 //                                 wavefront serves (G lanes per node); its slots are stored as
@@ -66,12 +69,13 @@ struct BCRec {
 
 enum StepMode : int { kModeEC = 0, kModeVV = 1, kModeVVInit = 2, kModeFE = 3 };
 
-template <typename Real>
 struct StepArgs {
     const double* rec_in;       // 6 doubles per node
     double* rec_out;
-    Real* v;                    // v + d*nn
-    Real* a;                    // a + d*nn
+    double* v;                  // v + d*nn
+    double* a;                  // a + d*nn
+    const double* um_in;        // FP32 build: master displacement of the level read (d*nn + node)
+    double* um_out;             // FP32 build: master displacement of the level written
     int32_t* col;
     const double* kslot;        // nullptr unless STIFF
     const double* vol;          // nullptr unless per-node volumes
@@ -108,16 +112,16 @@ struct DamageArgs {
     const uint16_t* ent;
 };
 
-template <typename Real>
-hipError_t launch_step(const StepArgs<Real>& a, int lanes, int mode, bool stiff, hipStream_t s);
+// sliced mapping (FP64)
+hipError_t launch_step(const StepArgs& a, int lanes, int mode, bool stiff, hipStream_t s);
 
-template <typename Real>
-hipError_t launch_drift(const StepArgs<Real>& a, int lanes, hipStream_t s);
+// velocity-Verlet drift of every node (fp32: master displacement and f32 records)
+hipError_t launch_drift(const StepArgs& a, bool fp32, hipStream_t s);
 
 hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s);
 
-template <typename Real>
-hipError_t launch_step_staged(const StepArgs<Real>& a, int mode, hipStream_t s);
+// staged mapping, FP64 or FP32 bond arithmetic
+hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, hipStream_t s);
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
 

@@ -116,10 +116,49 @@ __device__ __forceinline__ bool slot_force(int32_t c, const double2 p0, const do
     return brk;
 }
 
+// FP32 bond arithmetic (same formulas): the bond vector is formed in f64 from the f64
+// coordinates and rounded once, displacements are the f32 values of the records.
+// 1 - (1+q)^(-1/2) uses four series terms (below 1.3e-10 relative for |q| < 4e-3).
+__device__ __forceinline__ bool slot_force32(int32_t c, const double2 p0, const double2 p1, const double2 p2,
+                                             double X0, double X1, double X2, float U0, float U1, float U2,
+                                             float kv, float q0, float& F0, float& F1, float& F2)
+{
+    const float xi0 = static_cast<float>(p0.x - X0), xi1 = static_cast<float>(p0.y - X1),
+                xi2 = static_cast<float>(p1.x - X2);
+    const uint64_t b1 = __double_as_longlong(p1.y), b2 = __double_as_longlong(p2.x);
+    const float uj0 = __uint_as_float(static_cast<uint32_t>(b1)), uj1 = __uint_as_float(static_cast<uint32_t>(b1 >> 32)),
+                uj2 = __uint_as_float(static_cast<uint32_t>(b2));
+    const float e0 = uj0 - U0, e1 = uj1 - U1, e2 = uj2 - U2;
+    const float y0 = xi0 + e0, y1 = xi1 + e1, y2 = xi2 + e2;
+    const float z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
+    const float tq = __builtin_fmaf(e2, z2, __builtin_fmaf(e1, z1, e0 * z0));
+    const float L2 = __builtin_fmaf(xi2, xi2, __builtin_fmaf(xi1, xi1, xi0 * xi0));
+    const float iL = __builtin_amdgcn_rsqf(L2);
+    const float q = tq * (iL * iL);
+    const bool brk = c >= 0 && q >= q0;
+    const bool alive = c >= 0 && !brk;
+    const float qa = alive ? q : 0.0f;
+    float g;
+    if (fabsf(qa) < 4.0e-3f) {
+        float p = -35.0f / 128.0f;
+        p = __builtin_fmaf(p, qa, 5.0f / 16.0f);
+        p = __builtin_fmaf(p, qa, -3.0f / 8.0f);
+        p = __builtin_fmaf(p, qa, 0.5f);
+        g = qa * p;
+    } else {
+        g = 1.0f - __builtin_amdgcn_rsqf(1.0f + qa);
+    }
+    const float coef = (kv * iL) * g;
+    F0 = __builtin_fmaf(coef, y0, F0);
+    F1 = __builtin_fmaf(coef, y1, F1);
+    F2 = __builtin_fmaf(coef, y2, F2);
+    return brk;
+}
+
 // Integration and boundary conditions of one node given its force density F (the tail
 // of every step kernel).  U is the node's displacement at the level the forces used.
-template <int MODE>
-__device__ __forceinline__ void node_update(const StepArgs<double>& A, const InstParams& P, int64_t node,
+template <int MODE, bool FP32 = false>
+__device__ __forceinline__ void node_update(const StepArgs& A, const InstParams& P, int64_t node,
                                             double U0, double U1, double U2, double F0, double F1, double F2)
 {
     const int32_t bcid = A.bc_id[node];
@@ -131,7 +170,9 @@ __device__ __forceinline__ void node_update(const StepArgs<double>& A, const Ins
     double F[3] = {F0, F1, F2};
     if (P.has_body)
         for (int d = 0; d < 3; ++d) F[d] += P.bmag * A.bhat[d * nn + node];
-    const double u[3] = {U0, U1, U2};
+    double u[3] = {U0, U1, U2};
+    if (FP32)  // the integrator advances the f64 master displacement
+        for (int d = 0; d < 3; ++d) u[d] = A.um_in[d * nn + node];
     double vv[3], un[3], vn[3], an[3];
     for (int d = 0; d < 3; ++d) vv[d] = A.v[d * nn + node];
     BCRec bc;
@@ -186,9 +227,17 @@ __device__ __forceinline__ void node_update(const StepArgs<double>& A, const Ins
     for (int d = 0; d < 3; ++d) finite = finite && __builtin_isfinite(un[d]) && __builtin_isfinite(vn[d]);
     if (!finite) atomicOr(A.status, 1);
     double* ro = A.rec_out + 6 * node;
-    ro[3] = un[0];
-    ro[4] = un[1];
-    ro[5] = un[2];
+    if (FP32) {
+        float* rf = reinterpret_cast<float*>(ro + 3);
+        for (int d = 0; d < 3; ++d) {
+            rf[d] = static_cast<float>(un[d]);
+            A.um_out[d * nn + node] = un[d];
+        }
+    } else {
+        ro[3] = un[0];
+        ro[4] = un[1];
+        ro[5] = un[2];
+    }
     if (MODE != kModeVVInit)
         for (int d = 0; d < 3; ++d) A.v[d * nn + node] = vn[d];
     if (MODE == kModeVV || MODE == kModeVVInit)
@@ -196,7 +245,7 @@ __device__ __forceinline__ void node_update(const StepArgs<double>& A, const Ins
 }
 
 template <int G, int MODE, bool STIFF, bool VOLN>
-__global__ __launch_bounds__(kBlock) void step_f64(StepArgs<double> A)
+__global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
 {
     constexpr int W = kWave / G;
     constexpr int U = kRowUnroll;  // slot rows in flight per iteration
@@ -289,8 +338,8 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs<double> A)
 // path once per slice instead of once per slot.  Per-slot stiffness, when present,
 // streams from global memory one piece ahead.  Rows are processed in pairs so the LDS
 // reads of one row overlap the arithmetic of the other.
-template <int MODE, bool STIFF, bool VOLN>
-__global__ __launch_bounds__(kWave) void step_staged_f64(StepArgs<double> A, const int2* __restrict__ pieces,
+template <bool FP32, int MODE, bool STIFF, bool VOLN>
+__global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __restrict__ pieces,
                                                          const int32_t* __restrict__ slice_piece,
                                                          const int64_t* __restrict__ slice_ptr)
 {
@@ -315,8 +364,12 @@ __global__ __launch_bounds__(kWave) void step_staged_f64(StepArgs<double> A, con
     const double2* __restrict__ rin = reinterpret_cast<const double2*>(A.rec_in);
     const double2 o0 = rin[3 * node], o1 = rin[3 * node + 1], o2 = rin[3 * node + 2];
     const double X0 = o0.x, X1 = o0.y, X2 = o1.x;
-    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;
+    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;  // FP64 build
+    const uint64_t ub1 = __double_as_longlong(o1.y), ub2 = __double_as_longlong(o2.x);
+    const float Uf0 = __uint_as_float(static_cast<uint32_t>(ub1)), Uf1 = __uint_as_float(static_cast<uint32_t>(ub1 >> 32)),
+                Uf2 = __uint_as_float(static_cast<uint32_t>(ub2));  // FP32 build
     const double cv = P.c * P.volume;
+    const float cvf = static_cast<float>(cv), q0f = static_cast<float>(P.q0);
     uint16_t* __restrict__ entw = A.ent;
     const double2* __restrict__ ent2 = reinterpret_cast<const double2*>(A.ent);
 
@@ -328,6 +381,7 @@ __global__ __launch_bounds__(kWave) void step_staged_f64(StepArgs<double> A, con
     const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
     int64_t ent = wave_uniform(slice_ptr[slice]);  // first entry of the current piece
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+    float Ff0 = 0.0f, Ff1 = 0.0f, Ff2 = 0.0f;
 
     // staging registers of the next piece
     double2 r0, r1, r2, r3, e0;
@@ -373,6 +427,9 @@ __global__ __launch_bounds__(kWave) void step_staged_f64(StepArgs<double> A, con
         const int32_t c = (e & 0x8000) ? -1 : 0;  // sign carries the alive flag
         double kv = cv;
         if (STIFF || VOLN) kv = (STIFF ? kst : P.c) * (VOLN ? lvol[ri / 3] : P.volume);
+        if (FP32)
+            return slot_force32(c, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2, (STIFF || VOLN) ? static_cast<float>(kv) : cvf,
+                                q0f, Ff0, Ff1, Ff2);
         return slot_force(c, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2);
     };
 
@@ -401,7 +458,12 @@ __global__ __launch_bounds__(kWave) void step_staged_f64(StepArgs<double> A, con
             ent = ent_next;
         }
     }
-    node_update<MODE>(A, P, node, U0, U1, U2, F0, F1, F2);
+    if (FP32) {
+        F0 = Ff0;
+        F1 = Ff1;
+        F2 = Ff2;
+    }
+    node_update<MODE, FP32>(A, P, node, U0, U1, U2, F0, F1, F2);
 }
 
 // Local damage on the staged layout.
@@ -433,7 +495,8 @@ __global__ __launch_bounds__(kWave) void damage_staged(DamageArgs A)
 
 // Velocity-Verlet position update u_{k+1} = u_k + dt v_k + dt^2/2 a_k with the
 // displacement constraints of t_{k+1}; one thread per device node.
-__global__ __launch_bounds__(kBlock) void drift_f64(StepArgs<double> A)
+template <bool FP32>
+__global__ __launch_bounds__(kBlock) void drift_kernel(StepArgs A)
 {
     const int64_t node = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (node >= A.nn) return;
@@ -449,10 +512,15 @@ __global__ __launch_bounds__(kBlock) void drift_f64(StepArgs<double> A)
     const double* ri = A.rec_in + 6 * node;
     double* ro = A.rec_out + 6 * node;
     for (int d = 0; d < 3; ++d) {
-        const double u = ri[3 + d];
+        const double u = FP32 ? A.um_in[d * nn + node] : ri[3 + d];
         double un = (u + dt * A.v[d * nn + node]) + hdt2 * A.a[d * nn + node];
         if (constrained(bc, d)) un = bc_disp(bc, d, t1, u, dt);
-        ro[3 + d] = un;
+        if (FP32) {
+            reinterpret_cast<float*>(ro + 3)[d] = static_cast<float>(un);
+            A.um_out[d * nn + node] = un;
+        } else {
+            ro[3 + d] = un;
+        }
     }
 }
 
@@ -493,7 +561,7 @@ __global__ void advance_kernel(int64_t* step_base, int64_t by)
 }
 
 template <int G, bool STIFF, bool VOLN>
-hipError_t launch_step_gsv(const StepArgs<double>& a, int mode, hipStream_t s)
+hipError_t launch_step_gsv(const StepArgs& a, int mode, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>((a.nslices + 3) / 4)), block(kBlock);
     switch (mode) {
@@ -507,7 +575,7 @@ hipError_t launch_step_gsv(const StepArgs<double>& a, int mode, hipStream_t s)
 }
 
 template <int G>
-hipError_t launch_step_g(const StepArgs<double>& a, int mode, bool stiff, hipStream_t s)
+hipError_t launch_step_g(const StepArgs& a, int mode, bool stiff, hipStream_t s)
 {
     const bool voln = a.vol != nullptr;
     if (stiff) return voln ? launch_step_gsv<G, true, true>(a, mode, s) : launch_step_gsv<G, true, false>(a, mode, s);
@@ -518,8 +586,7 @@ hipError_t launch_step_g(const StepArgs<double>& a, int mode, bool stiff, hipStr
 
 bool lanes_supported(int lanes) { return lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64; }
 
-template <>
-hipError_t launch_step<double>(const StepArgs<double>& a, int lanes, int mode, bool stiff, hipStream_t s)
+hipError_t launch_step(const StepArgs& a, int lanes, int mode, bool stiff, hipStream_t s)
 {
     if (a.nslices <= 0) return hipSuccess;
     switch (lanes) {
@@ -531,25 +598,15 @@ hipError_t launch_step<double>(const StepArgs<double>& a, int lanes, int mode, b
     }
 }
 
-template <>
-hipError_t launch_drift<double>(const StepArgs<double>& a, int /*lanes*/, hipStream_t s)
+hipError_t launch_drift(const StepArgs& a, bool fp32, hipStream_t s)
 {
     if (a.nn <= 0) return hipSuccess;
-    hipLaunchKernelGGL(drift_f64, dim3(static_cast<unsigned>((a.nn + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, s, a);
+    const dim3 grid(static_cast<unsigned>((a.nn + kBlock - 1) / kBlock)), block(kBlock);
+    if (fp32)
+        hipLaunchKernelGGL(drift_kernel<true>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(drift_kernel<false>, grid, block, 0, s, a);
     return hipGetLastError();
-}
-
-template <>
-hipError_t launch_step<float>(const StepArgs<float>&, int, int, bool, hipStream_t)
-{
-    return hipErrorNotSupported;
-}
-
-template <>
-hipError_t launch_drift<float>(const StepArgs<float>&, int, hipStream_t)
-{
-    return hipErrorNotSupported;
 }
 
 hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s)
@@ -566,13 +623,13 @@ hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool STIFF, bool VOLN>
-hipError_t launch_staged_sv(const StepArgs<double>& a, int mode, hipStream_t s)
+template <bool FP32, bool STIFF, bool VOLN>
+hipError_t launch_staged_sv(const StepArgs& a, int mode, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>(a.nslices)), block(kWave);
     switch (mode) {
 #define PD_L(M)                                                                                   \
-    hipLaunchKernelGGL((step_staged_f64<M, STIFF, VOLN>), grid, block, 0, s, a, a.pieces, a.slice_piece, \
+    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN>), grid, block, 0, s, a, a.pieces, a.slice_piece, \
                        a.slice_ptr)
     case kModeEC: PD_L(kModeEC); break;
     case kModeVV: PD_L(kModeVV); break;
@@ -584,19 +641,19 @@ hipError_t launch_staged_sv(const StepArgs<double>& a, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-template <>
-hipError_t launch_step_staged<double>(const StepArgs<double>& a, int mode, hipStream_t s)
+template <bool FP32>
+hipError_t launch_staged_p(const StepArgs& a, int mode, hipStream_t s)
 {
-    if (a.nslices <= 0) return hipSuccess;
     const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
-    if (stiff) return voln ? launch_staged_sv<true, true>(a, mode, s) : launch_staged_sv<true, false>(a, mode, s);
-    return voln ? launch_staged_sv<false, true>(a, mode, s) : launch_staged_sv<false, false>(a, mode, s);
+    if (stiff)
+        return voln ? launch_staged_sv<FP32, true, true>(a, mode, s) : launch_staged_sv<FP32, true, false>(a, mode, s);
+    return voln ? launch_staged_sv<FP32, false, true>(a, mode, s) : launch_staged_sv<FP32, false, false>(a, mode, s);
 }
 
-template <>
-hipError_t launch_step_staged<float>(const StepArgs<float>&, int, hipStream_t)
+hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, hipStream_t s)
 {
-    return hipErrorNotSupported;
+    if (a.nslices <= 0) return hipSuccess;
+    return fp32 ? launch_staged_p<true>(a, mode, s) : launch_staged_p<false>(a, mode, s);
 }
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s)

@@ -1,0 +1,47 @@
+"""FP32 build (f32 bond arithmetic, f64 master displacement) against the FP64 oracle.
+
+Bar: displacement within 1e-5 norm-wise relative; broken-bond mismatches are counted
+and reported (f32 stretches can reach the threshold one step earlier or later).
+"""
+import pytest
+
+import pd_inputs as pi
+from parity import TOL_FP32, compare, gpu_run, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2105_04150_amd import _binding as B
+    B.load()
+
+
+CASES = [
+    ("block10", {}, "natural"),
+    ("beam3pb", {"dims": (60, 12, 12), "steps": 1500}, "natural"),
+    ("cube100", {"dims": (24, 20, 18), "steps": 300}, "natural"),
+    ("cube100_wide", {"dims": (24, 20, 18), "steps": 300}, "morton"),
+    ("adjoint_beam", {"dims": (30, 10, 8), "steps": 400}, "natural"),
+]
+
+
+@pytest.mark.parametrize("name,over,order", CASES)
+def test_fp32_against_fp64_oracle(oracle_lib, name, over, order):
+    from paper_2105_04150_amd import PD_FP32
+    w = pi.workload(name, **over)
+    o = oracle_run(w, w.steps)
+    say(f"[run] fp32 {name} {over} {order}")
+    g = gpu_run(w, w.steps, precision=PD_FP32, order=order, mapping="staged")
+    eu, ev, mism, ephi = compare(g, o, TOL_FP32, f"fp32 {name}")
+    nb = max(int(o.broken_mask.sum()), 1)
+    say(f"[fp32] {name}: broken-bond mismatches {mism} of {nb} broken slots ({100.0 * mism / nb:.3f}%)")
+    assert eu <= TOL_FP32
+    assert mism <= 0.01 * nb
+
+
+def test_fp32_rejects_sliced_mapping():
+    from paper_2105_04150_amd import PD_FP32, PdmiError, Simulation
+    with Simulation(precision=PD_FP32) as g:
+        with pytest.raises(PdmiError):
+            g.set_mapping("sliced", 4)
