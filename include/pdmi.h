@@ -213,6 +213,39 @@ int pd_set_state(pd_ctx *ctx, int32_t inst, const double *u, const double *v, co
                  const uint8_t *broken);
 int pd_set_step(pd_ctx *ctx, int64_t step);
 
+/* ---------------------------------------------------------------- adjoint */
+
+/* Reverse-mode gradients of a displacement misfit after an Euler-Cromer run with the
+ * bond-break schedule of that run frozen (a slot acts in pass k iff it had not broken
+ * by the end of pass k; the critical-stretch rule of Sec. 2 is not differentiated).
+ * FP64 build, single-instance problems, Euler-Cromer scheme; every bond's two slots
+ * must carry the same stiffness and broken flag (PD_EINVAL otherwise).
+ *
+ * pd_adj_forward advances the problem by nsteps >= 1 steps exactly as pd_step does,
+ * recording the pass in which each slot breaks and a device checkpoint of (u, v)
+ * every ckpt_every >= 1 steps ((nn + 1) * 48 + nn * 24 bytes each, nn = padded node
+ * count).  Any later change to the problem or state (pd_step included) discards the
+ * recording.  Asynchronous like pd_step. */
+int pd_adj_forward(pd_ctx *ctx, int64_t nsteps, int32_t ckpt_every);
+
+/* Gradient of a loss L(u^T) at the end of the recorded run.  The caller passes
+ * dL/du^T for m >= 0 sensor nodes: sensors (host, m user node ids, repeats add up) and
+ * dL_du (host, m x 3).  Outputs: grad_k (host, nnz doubles, user CSR order) = dL/dk
+ * for every slot's stiffness (slots of a bond are separate parameters), and *grad_A =
+ * dL/dA for the body-force magnitude of pd_set_body_force (0 without a body force).
+ * Each segment between checkpoints is recomputed with the forward kernel (same
+ * results bit for bit) into a trajectory buffer of min(ckpt_every, nsteps) + 1 levels,
+ * then the reverse passes run last to first.  The problem state is left unchanged.
+ * Synchronising; PD_ESTATE if there is no valid recording. */
+int pd_adj_backward(pd_ctx *ctx, int64_t m, const int64_t *sensors, const double *dL_du, double *grad_k,
+                    double *grad_A);
+
+/* Pass index in which each slot broke during the recording (host out[nnz], user CSR
+ * order): INT32_MAX = intact, INT32_MIN = broken before pd_adj_forward.  PD_ESTATE
+ * when nothing is being recorded (recording starts with pd_adj_forward and continues
+ * through later steps until the broken set or the layout is replaced). */
+int pd_get_break_steps(pd_ctx *ctx, int32_t inst, int32_t *out);
+
 /* ---------------------------------------------------------------- tuning and introspection */
 
 /* Work mapping of the step kernel: PD_MAP_SLICED with `lanes` work-items cooperating on

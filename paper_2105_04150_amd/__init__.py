@@ -120,6 +120,17 @@ class Simulation:
     def set_step(self, step):
         B.pd_set_step(self.ctx, step)
 
+    # adjoint (Euler-Cromer, frozen break schedule)
+    def adj_forward(self, nsteps, ckpt_every=100):
+        B.pd_adj_forward(self.ctx, nsteps, ckpt_every)
+
+    def adj_backward(self, sensors, dL_du):
+        """(grad_k[nnz], grad_A) of a loss whose gradient at the sensors is dL_du (m x 3)."""
+        return B.pd_adj_backward(self.ctx, sensors, dL_du)
+
+    def break_steps(self, inst=0):
+        return B.pd_get_break_steps(self.ctx, inst)
+
     def info(self):
         return B.pd_get_info(self.ctx)
 

@@ -28,7 +28,7 @@ SYMBOLS = [
     "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_body_force", "pd_set_integrator",
     "pd_step", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
-    "pd_get_info", "pd_last_step_ms",
+    "pd_get_info", "pd_last_step_ms", "pd_adj_forward", "pd_adj_backward", "pd_get_break_steps",
 ]
 
 
@@ -90,6 +90,9 @@ def load() -> C.CDLL:
         "pd_autotune": [P, i64, P],
         "pd_get_info": [P, P],
         "pd_last_step_ms": [P, P],
+        "pd_adj_forward": [P, i64, i32],
+        "pd_adj_backward": [P, i64, P, P, P, P],
+        "pd_get_break_steps": [P, i32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -289,3 +292,25 @@ def pd_last_step_ms(ctx) -> float:
     v = C.c_double()
     _check(ctx, load().pd_last_step_ms(ctx, C.byref(v)))
     return v.value
+
+
+def pd_adj_forward(ctx, nsteps: int, ckpt_every: int) -> None:
+    _check(ctx, load().pd_adj_forward(ctx, int(nsteps), int(ckpt_every)))
+
+
+def pd_adj_backward(ctx, sensors, dL_du):
+    """Returns (grad_k[nnz], grad_A) for dL/du^T given at the sensor nodes (m x 3)."""
+    sn = np.ascontiguousarray(sensors, dtype=np.int64).reshape(-1)
+    dl = _f64(dL_du, (sn.shape[0], 3))
+    nnz = pd_instance_size(ctx, 0)[1]
+    gk = np.zeros(max(nnz, 1))
+    gA = C.c_double()
+    _check(ctx, load().pd_adj_backward(ctx, sn.shape[0], _p(sn), _p(dl), _p(gk), C.byref(gA)))
+    return gk[:nnz], gA.value
+
+
+def pd_get_break_steps(ctx, inst: int = 0) -> np.ndarray:
+    nnz = pd_instance_size(ctx, inst)[1]
+    out = np.zeros(max(nnz, 1), dtype=np.int32)
+    _check(ctx, load().pd_get_break_steps(ctx, inst, _p(out)))
+    return out[:nnz]

@@ -29,18 +29,26 @@ def _run(cmd):
     return r.stdout
 
 
+KERNEL_SOURCES = ("pdmi_kernels.hip", "pdmi_adjoint.hip")
+
+
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD_DIR, exist_ok=True)
-    kern_o = os.path.join(BUILD_DIR, "pdmi_kernels.o")
+    objs, cmds = [], []
+    for src in KERNEL_SOURCES:
+        o = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
+        objs.append(o)
+        cmds.append(["hipcc", "-c", "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *NO_PACKED_FP32,
+                     "-munsafe-fp-atomics", os.path.join(CSRC, src), "-o", o])
     host_o = os.path.join(BUILD_DIR, "pdmi_host.o")
-    out = _run(["hipcc", "-c", "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *NO_PACKED_FP32,
-                "-munsafe-fp-atomics", os.path.join(CSRC, "pdmi_kernels.hip"), "-o", kern_o])
-    out += _run(["hipcc", "-c", "-x", "c++", *COMMON, "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__",
-                 "-I", os.path.join(ROCM, "include"),
-                 os.path.join(CSRC, "pdmi_host.cpp"), "-o", host_o])
+    objs.append(host_o)
+    cmds.append(["hipcc", "-c", "-x", "c++", *COMMON, "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__",
+                 "-I", os.path.join(ROCM, "include"), os.path.join(CSRC, "pdmi_host.cpp"), "-o", host_o])
+    with ThreadPoolExecutor(len(cmds)) as ex:
+        out = "".join(ex.map(_run, cmds))
     tmp = LIB + ".tmp"
-    out += _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, kern_o, host_o,
-                 "-lpthread"])
+    out += _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)
     if verbose:
         print(out)

@@ -1,0 +1,288 @@
+// pdmi_adjoint.hip -- reverse pass of the Euler-Cromer step with a frozen break schedule.
+//
+// Forward pass k (Sec. 2, Eq. simpleBond, with the semi-implicit Euler update):
+//   v^{k+1} = d v^k + h (F(u^k; k) + A bhat),  u^{k+1} = u^k + dt v^{k+1},
+//   then the boundary conditions overwrite prescribed components,
+// with h = dt/rho and d = 1 - dt eta/rho.  A slot acts in pass k iff k < bstep (the pass
+// in which it broke).  Reverse pass k, given lam_u = dL/du^{k+1} and the adjoint nu of
+// the unconstrained v^{k+1} (zero on prescribed components):
+//   dL/dk_b += h V_j (s/r)_b (y_b . nu_i)          (f_b = k_b V_j (s/r) y)
+//   dL/dA   += h bhat_i . nu_i
+//   lam_u    = [0 on displacement-controlled components] lam_u + h J_F^T nu
+//   nu'      = d nu + dt lam_u on free components, 0 on prescribed ones (pass k-1)
+// The tangent of one slot is k_b K_b with K_b = (1/L - 1/r) I + y y^T / r^3, symmetric and
+// even in y.  With symmetric stiffness and schedule, (J_F^T nu)_i is the gather
+//   sum over the family of i of k_b K_b (V_i nu_j - V_j nu_i),
+// the same shape as the force, so the reverse pass walks the forward slot layout and
+// needs no reverse-slot index.  1/L - 1/r = (1/L)(1 - (1+q)^(-1/2)) and 1/r = (1/L)(1+q)^(-1/2)
+// use the cancellation-free q = |y|^2/|xi|^2 - 1 of the step kernel.
+#include "pdmi_device.h"
+
+namespace pdmi {
+namespace {
+
+// One active slot: adds k_b K_b (V_i nu_j - V_j nu_i) to J and returns the slot's
+// stiffness-gradient increment h V_j (s/r) (y . nu_i).
+__device__ __forceinline__ double adj_slot(const double2 p0, const double2 p1, const double2 p2, double X0,
+                                           double X1, double X2, double U0, double U1, double U2, const double nj[3],
+                                           const double ni[3], double Vi, double Vj, double kb, double h, double J[3])
+{
+    const double xi0 = p0.x - X0, xi1 = p0.y - X1, xi2 = p1.x - X2;
+    const double e0 = p1.y - U0, e1 = p2.x - U1, e2 = p2.y - U2;
+    const double y0 = xi0 + e0, y1 = xi1 + e1, y2 = xi2 + e2;
+    const double z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
+    const double tq = __builtin_fma(e2, z2, __builtin_fma(e1, z1, e0 * z0));
+    const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
+    const double iL = rsq64<1>(L2);
+    const double q = tq * (iL * iL);
+    const double sr = iL * one_minus_rsqrt1p(q);  // s/r = 1/L - 1/r
+    const double ir = iL * rsq64<2>(1.0 + q);     // 1/r
+    const double ir3 = ir * ir * ir;
+    const double w0 = Vi * nj[0] - Vj * ni[0], w1 = Vi * nj[1] - Vj * ni[1], w2 = Vi * nj[2] - Vj * ni[2];
+    const double yw = __builtin_fma(y2, w2, __builtin_fma(y1, w1, y0 * w0));
+    const double a = kb * sr, b = kb * (yw * ir3);
+    J[0] += a * w0 + b * y0;
+    J[1] += a * w1 + b * y1;
+    J[2] += a * w2 + b * y2;
+    const double yn = __builtin_fma(y2, ni[2], __builtin_fma(y1, ni[1], y0 * ni[0]));
+    return h * Vj * sr * yn;
+}
+
+// Node tail of a reverse pass: body-force gradient, boundary masks, lam_u and next nu.
+__device__ __forceinline__ void adj_node(const AdjArgs& A, const InstParams& P, int64_t node, const double ni[3],
+                                         const double J[3], double h)
+{
+    const int32_t bcid = A.bc_id[node];
+    if (bcid == kNodePad) return;
+    const int64_t nn = A.nn;
+    int code = 0;
+    if (bcid >= 0) code = A.bc[bcid].code;
+    if (P.has_body)
+        A.gacc[node] += h * (A.bhat[node] * ni[0] + A.bhat[nn + node] * ni[1] + A.bhat[2 * nn + node] * ni[2]);
+    const double damp = 1.0 - A.dt * P.eta / P.rho;
+    for (int d = 0; d < 3; ++d) {
+        const int kind = (code >> (2 * d)) & 3;
+        const double lu = A.lam_u[d * nn + node];
+        const double ln = (kind == 1 ? 0.0 : lu) + h * J[d];
+        A.lam_u[d * nn + node] = ln;
+        A.nu_out[3 * node + d] = kind == 0 ? damp * ni[d] + A.dt * ln : 0.0;
+    }
+}
+
+// Sliced layout: G lanes per node, partial sums meet in a shuffle butterfly.
+template <int G, bool STIFF, bool VOLN>
+__global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
+{
+    constexpr int W = kWave / G;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t slice =
+        wave_uniform(xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + (threadIdx.x >> 6));
+    if (slice >= A.nslices) return;
+    const InstParams P = A.params[A.slice_inst[slice]];
+    const int w = lane / G, g = lane % G;
+    const int64_t node = slice * W + w;
+    const double2* __restrict__ rec = reinterpret_cast<const double2*>(A.rec);
+    const double2 o0 = rec[3 * node], o1 = rec[3 * node + 1], o2 = rec[3 * node + 2];
+    const double ni[3] = {A.nu_in[3 * node], A.nu_in[3 * node + 1], A.nu_in[3 * node + 2]};
+    const double Vi = VOLN ? A.vol[node] : P.volume;
+    const double h = A.dt / P.rho;
+    const int64_t base = A.slice_ptr[slice];
+    const int T = A.slice_T[slice];
+    double J[3] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < T; ++t) {
+        const int64_t ds = base + static_cast<int64_t>(t) * kWave + lane;
+        if (!(A.k < static_cast<int64_t>(A.bstep[ds]))) continue;
+        const int32_t c = A.col[ds];
+        const int64_t j = c ^ (c >> 31);
+        const double2 p0 = rec[3 * j], p1 = rec[3 * j + 1], p2 = rec[3 * j + 2];
+        const double nj[3] = {A.nu_in[3 * j], A.nu_in[3 * j + 1], A.nu_in[3 * j + 2]};
+        const double kb = STIFF ? A.kslot[ds] : P.c;
+        const double Vj = VOLN ? A.vol[j] : P.volume;
+        A.grad[ds] += adj_slot(p0, p1, p2, o0.x, o0.y, o1.x, o1.y, o2.x, o2.y, nj, ni, Vi, Vj, kb, h, J);
+    }
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1)
+        for (int d = 0; d < 3; ++d) J[d] += __shfl_xor(J[d], m);
+    if (g != 0) return;
+    adj_node(A, P, node, ni, J, h);
+}
+
+// Staged layout: one lane per node; neighbours are read from global memory.
+template <bool STIFF, bool VOLN>
+__global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
+{
+    const int lane = threadIdx.x;
+    const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
+    if (slice >= A.nslices) return;
+    const InstParams P = A.params[A.slice_inst[slice]];
+    const int64_t node = slice * kWave + lane;
+    const double2* __restrict__ rec = reinterpret_cast<const double2*>(A.rec);
+    const double2 o0 = rec[3 * node], o1 = rec[3 * node + 1], o2 = rec[3 * node + 2];
+    const double ni[3] = {A.nu_in[3 * node], A.nu_in[3 * node + 1], A.nu_in[3 * node + 2]};
+    const double Vi = VOLN ? A.vol[node] : P.volume;
+    const double h = A.dt / P.rho;
+    const int pb = A.slice_piece[slice], pe = A.slice_piece[slice + 1];
+    int64_t ent = A.slice_ptr[slice];
+    double J[3] = {0.0, 0.0, 0.0};
+    for (int p = pb; p < pe; ++p) {
+        const int2 m = A.pieces[p];
+        const int T = (m.y >> 8) & 0xff;
+        for (int t = 0; t < T; ++t) {
+            const int64_t ds = ent + static_cast<int64_t>(t) * kWave + lane;
+            if (!(A.k < static_cast<int64_t>(A.bstep[ds]))) continue;
+            const int64_t j = m.x + (A.ent[ds] & 0x7fff) / 3;
+            const double2 p0 = rec[3 * j], p1 = rec[3 * j + 1], p2 = rec[3 * j + 2];
+            const double nj[3] = {A.nu_in[3 * j], A.nu_in[3 * j + 1], A.nu_in[3 * j + 2]};
+            const double kb = STIFF ? A.kslot[ds] : P.c;
+            const double Vj = VOLN ? A.vol[j] : P.volume;
+            A.grad[ds] += adj_slot(p0, p1, p2, o0.x, o0.y, o1.x, o1.y, o2.x, o2.y, nj, ni, Vi, Vj, kb, h, J);
+        }
+        ent += static_cast<int64_t>(T) * kWave;
+    }
+    adj_node(A, P, node, ni, J, h);
+}
+
+__global__ __launch_bounds__(kBlock) void bstep_init_kernel(int32_t* bstep, const int32_t* col, const uint16_t* ent,
+                                                            int64_t ns)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= ns) return;
+    const bool broken = col ? col[i] < 0 : (ent[i] & 0x8000) != 0;
+    bstep[i] = broken ? kBrokeBefore : kNeverBroke;
+}
+
+__global__ __launch_bounds__(kBlock) void flags_at_kernel(const int32_t* bstep, int32_t* col, uint16_t* ent,
+                                                          int64_t ns, int64_t step)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= ns) return;
+    const bool broken = static_cast<int64_t>(bstep[i]) < step;
+    if (col) {
+        const int32_t c = col[i], j = c ^ (c >> 31);
+        col[i] = broken ? ~j : j;
+    } else {
+        const uint16_t e = ent[i];
+        ent[i] = static_cast<uint16_t>((e & 0x7fff) | (broken ? 0x8000 : 0));
+    }
+}
+
+__global__ void adj_seed_kernel(double* lam_u, int64_t nn, const int64_t* sensors, const double* dldu, int64_t m)
+{
+    const int d = threadIdx.x;
+    if (blockIdx.x != 0 || d >= 3) return;
+    for (int64_t p = 0; p < m; ++p) lam_u[d * nn + sensors[p]] += dldu[3 * p + d];
+}
+
+__global__ __launch_bounds__(kBlock) void adj_nu0_kernel(double* nu, const double* lam_u, const int32_t* bc_id,
+                                                         const BCRec* bc, int64_t nn, double dt)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= nn) return;
+    const int32_t id = bc_id[i];
+    const int code = id >= 0 ? bc[id].code : 0;
+    for (int d = 0; d < 3; ++d) {
+        const bool free_comp = id != kNodePad && ((code >> (2 * d)) & 3) == 0;
+        nu[3 * i + d] = free_comp ? dt * lam_u[d * nn + i] : 0.0;
+    }
+}
+
+// Deterministic single-workgroup sum.
+__global__ __launch_bounds__(kBlock) void sum_kernel(const double* x, int64_t n, double* out)
+{
+    __shared__ double part[kBlock];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) acc += x[i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (static_cast<int>(threadIdx.x) < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = part[0];
+}
+
+__global__ void set_i64_kernel(int64_t* p, int64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+template <int G, bool STIFF, bool VOLN>
+void adj_launch_sliced(const AdjArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((adjoint_sliced<G, STIFF, VOLN>), dim3(static_cast<unsigned>((a.nslices + 3) / 4)),
+                       dim3(kBlock), 0, s, a);
+}
+
+template <bool STIFF, bool VOLN>
+hipError_t adj_launch_sv(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
+{
+    if (staged) {
+        hipLaunchKernelGGL((adjoint_staged<STIFF, VOLN>), dim3(static_cast<unsigned>(a.nslices)), dim3(kWave), 0, s,
+                           a);
+        return hipGetLastError();
+    }
+    switch (lanes) {
+    case 1: adj_launch_sliced<1, STIFF, VOLN>(a, s); break;
+    case 4: adj_launch_sliced<4, STIFF, VOLN>(a, s); break;
+    case 16: adj_launch_sliced<16, STIFF, VOLN>(a, s); break;
+    case 64: adj_launch_sliced<64, STIFF, VOLN>(a, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
+{
+    if (a.nslices <= 0) return hipSuccess;
+    const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
+    if (stiff) return voln ? adj_launch_sv<true, true>(a, staged, lanes, s) : adj_launch_sv<true, false>(a, staged, lanes, s);
+    return voln ? adj_launch_sv<false, true>(a, staged, lanes, s) : adj_launch_sv<false, false>(a, staged, lanes, s);
+}
+
+hipError_t launch_bstep_init(int32_t* bstep, const int32_t* col, const uint16_t* ent, int64_t ns, hipStream_t s)
+{
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bstep_init_kernel, dim3(blocks_for(ns)), dim3(kBlock), 0, s, bstep, col, ent, ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags_at(const int32_t* bstep, int32_t* col, uint16_t* ent, int64_t ns, int64_t step, hipStream_t s)
+{
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(flags_at_kernel, dim3(blocks_for(ns)), dim3(kBlock), 0, s, bstep, col, ent, ns, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_seed(double* lam_u, int64_t nn, const int64_t* sensors, const double* dldu, int64_t m,
+                           hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adj_seed_kernel, dim3(1), dim3(kWave), 0, s, lam_u, nn, sensors, dldu, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_nu0(double* nu, const double* lam_u, const int32_t* bc_id, const BCRec* bc, int64_t nn,
+                          double dt, hipStream_t s)
+{
+    if (nn <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adj_nu0_kernel, dim3(blocks_for(nn)), dim3(kBlock), 0, s, nu, lam_u, bc_id, bc, nn, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* x, int64_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kBlock), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_i64(int64_t* p, int64_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(kWave), 0, s, p, value);
+    return hipGetLastError();
+}
+
+}  // namespace pdmi

@@ -1,0 +1,77 @@
+// pdmi_device.h -- device helpers shared by the step and adjoint kernels.
+#pragma once
+
+#include "pdmi_internal.h"
+
+namespace pdmi {
+namespace {
+
+// 1/sqrt(x): hardware estimate (specified to 2^29 ulp, i.e. about 2^-23 relative) and NR
+// Newton steps; one step leaves a relative error near 1e-14, two reach rounding level.
+template <int NR>
+__device__ __forceinline__ double rsq64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const double h = x * y;
+        const double e = __builtin_fma(-h, y, 1.0);
+        y = __builtin_fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// 1 - (1+q)^(-1/2).  Series q/2 - 3q^2/8 + 5q^3/16 - 35q^4/128 + 63q^5/256 - 231q^6/1024;
+// the first omitted term, 429q^7/2048, is below 2e-15 of the sum for |q| < 4e-3.  Larger
+// |q| (strongly compressed or broken bonds) takes the closed form, whose cancellation
+// costs at most 1e-16/|q| < 3e-14 relative there.
+__device__ __forceinline__ double one_minus_rsqrt1p(double q)
+{
+    if (fabs(q) < 4.0e-3) {
+        double p = -231.0 / 1024.0;
+        p = __builtin_fma(p, q, 63.0 / 256.0);
+        p = __builtin_fma(p, q, -35.0 / 128.0);
+        p = __builtin_fma(p, q, 5.0 / 16.0);
+        p = __builtin_fma(p, q, -3.0 / 8.0);
+        p = __builtin_fma(p, q, 0.5);
+        return q * p;
+    }
+    return 1.0 - rsq64<2>(1.0 + q);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that each XCD
+// works on one contiguous range of slices (neighbouring nodes share its L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    constexpr int64_t X = 8;
+    const int64_t m = nb / X, r = nb % X, x = b % X, j = b / X;
+    return (x < r) ? x * (m + 1) + j : r * (m + 1) + (x - r) * m + j;
+}
+
+__device__ __forceinline__ double sched(int lin, double t) { return lin ? t : 1.0; }
+
+// Prescribed velocity of component d at time t.
+__device__ __forceinline__ double bc_vel(const BCRec& r, int d, double t)
+{
+    const int kind = (r.code >> (2 * d)) & 3, lin = (r.code >> (8 + d)) & 1;
+    return kind == 1 ? r.A[d] * (lin ? 1.0 : 0.0) : r.A[d] * sched(lin, t);
+}
+
+// Prescribed displacement of component d at time t; uprev one step earlier.
+__device__ __forceinline__ double bc_disp(const BCRec& r, int d, double t, double uprev, double dt)
+{
+    const int kind = (r.code >> (2 * d)) & 3, lin = (r.code >> (8 + d)) & 1;
+    return kind == 1 ? r.A[d] * sched(lin, t) : uprev + dt * (r.A[d] * sched(lin, t));
+}
+
+__device__ __forceinline__ bool constrained(const BCRec& r, int d) { return ((r.code >> (2 * d)) & 3) != 0; }
+
+__device__ __forceinline__ int64_t wave_uniform(int64_t v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(static_cast<int>(v & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32));
+    return (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo);
+}
+
+}  // namespace
+}  // namespace pdmi

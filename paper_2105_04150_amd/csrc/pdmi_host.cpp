@@ -98,6 +98,7 @@ struct Inst {
     std::vector<int2> pieces;        // staged layout: {first device node, len | rows << 8}
     std::vector<int32_t> slice_piece;  // staged layout: first piece of each slice (+ end), local
     std::vector<uint8_t> ent_idx;    // staged layout: range index of every device slot
+    std::vector<int64_t> rev_slot;   // user slot of the reverse bond (filled on first use)
     int64_t node_off = 0, n_pad = 0, slice_off = 0, nslices = 0, dslot_off = 0, n_dslots = 0;
 };
 
@@ -128,6 +129,12 @@ struct pd_ctx {
     bool has_stiff = false, has_vol = false, has_body = false;
     DevBuf rec[2], um[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc,
         step_base, status, phi, pieces, slice_piece, ent;
+
+    // adjoint: per-slot break steps (recorded by every step while allocated) and the
+    // (u, v) checkpoints of the last recorded forward run
+    DevBuf bstep, ck;
+    bool tape_valid = false;
+    int64_t tape_step0 = 0, tape_nsteps = 0, tape_every = 0;
 
     // graphs: [parity][mode] for chunks of kGraphChunk steps
     hipGraphExec_t graph[2][4] = {{nullptr}};
@@ -431,6 +438,7 @@ struct HostState {
 
 void upload_params(pd_ctx* ctx)
 {
+    ctx->tape_valid = false;
     std::vector<InstParams> p;
     for (auto& I : ctx->inst) p.push_back(make_params(I));
     upload(ctx->params, p.data(), p.size() * sizeof(InstParams), 0, ctx->stream);
@@ -438,6 +446,7 @@ void upload_params(pd_ctx* ctx)
 
 void upload_bcs(pd_ctx* ctx)
 {
+    ctx->tape_valid = false;
     std::vector<int32_t> id(static_cast<size_t>(ctx->nn), kNodePad);
     std::vector<BCRec> recs;
     for (auto& I : ctx->inst) {
@@ -470,6 +479,7 @@ void upload_bcs(pd_ctx* ctx)
 
 void upload_stiffness(pd_ctx* ctx)
 {
+    ctx->tape_valid = false;
     ctx->has_stiff = false;
     for (auto& I : ctx->inst) ctx->has_stiff |= !I.kslot.empty();
     if (!ctx->has_stiff) {
@@ -510,6 +520,7 @@ void upload_volumes(pd_ctx* ctx)
 
 void upload_body(pd_ctx* ctx)
 {
+    ctx->tape_valid = false;
     ctx->has_body = false;
     for (auto& I : ctx->inst) ctx->has_body |= !I.bhat.empty();
     if (!ctx->has_body) {
@@ -534,6 +545,7 @@ void upload_body(pd_ctx* ctx)
 // Write one instance's state (user order) into the device buffers.
 void upload_state(pd_ctx* ctx, const Inst& I, const double* u, const double* v, const double* a)
 {
+    ctx->tape_valid = false;
     const int64_t nn = ctx->nn;
     auto soa = [&](const double* src, int d) {
         std::vector<double> h(static_cast<size_t>(I.n_pad), 0.0);
@@ -577,6 +589,12 @@ void upload_state(pd_ctx* ctx, const Inst& I, const double* u, const double* v, 
 
 void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
 {
+    // a broken set from outside ends break-step recording (the recorded steps would be stale)
+    ctx->tape_valid = false;
+    if (ctx->bstep.p) {
+        ctx->bstep.release();
+        ctx->drop_graphs();
+    }
     if (ctx->mapping == PD_MAP_STAGED) {
         std::vector<uint16_t> e(static_cast<size_t>(I.n_dslots));
         parallel_for(I.n_dslots, [&](int64_t s0, int64_t s1) {
@@ -762,6 +780,9 @@ void build_layout(pd_ctx* ctx, const HostState* S)
 {
     const int G = ctx->mapping == PD_MAP_STAGED ? 1 : ctx->lanes, W = kWave / G;
     ctx->drop_graphs();
+    ctx->tape_valid = false;
+    ctx->bstep.release();
+    ctx->ck.release();
     int64_t nn = 0, nsl = 0, ns = 0;
     std::vector<int64_t> sp;
     std::vector<int32_t> sT, sI, spc;
@@ -970,6 +991,7 @@ StepArgs step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
     A.ent = ctx->ent.as<uint16_t>();
     A.step_base = ctx->step_base.as<int64_t>();
     A.status = ctx->status.as<int32_t>();
+    A.bstep = ctx->bstep.as<int32_t>();
     A.nn = ctx->nn;
     A.nslices = ctx->nslices;
     A.step_local = step_local;
@@ -1027,6 +1049,7 @@ hipGraphExec_t chunk_graph(pd_ctx* ctx, int mode, int parity)
 void do_steps(pd_ctx* ctx, int64_t nsteps)
 {
     const int mode = step_mode(ctx->scheme);
+    ctx->tape_valid = false;
     if (!ctx->ev0) {
         hip_check(hipEventCreate(&ctx->ev0), "hipEventCreate");
         hip_check(hipEventCreate(&ctx->ev1), "hipEventCreate");
@@ -1073,6 +1096,55 @@ void reset_flags_after_state_change(pd_ctx* ctx, bool a_given)
     const int32_t z = 0;
     upload(ctx->status, &z, sizeof z, 0, ctx->stream);
     sync(ctx);
+}
+
+// ------------------------------------------------------------------ adjoint
+
+// Slot of the reverse bond (j, i) of every user slot (i, j); rows are sorted.
+const std::vector<int64_t>& reverse_slots(Inst& I)
+{
+    if (static_cast<int64_t>(I.rev_slot.size()) == I.nnz) return I.rev_slot;
+    I.rev_slot.assign(static_cast<size_t>(I.nnz), -1);
+    parallel_for(I.n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            for (int64_t b = I.row_ptr[i]; b < I.row_ptr[i + 1]; ++b) {
+                const int32_t j = I.col[b];
+                const auto first = I.col.begin() + I.row_ptr[j], last = I.col.begin() + I.row_ptr[j + 1];
+                const auto it = std::lower_bound(first, last, static_cast<int32_t>(i));
+                if (it != last && *it == i) I.rev_slot[b] = it - I.col.begin();
+            }
+    });
+    return I.rev_slot;
+}
+
+void adjoint_checks(pd_ctx* ctx)
+{
+    require_built(ctx);
+    if (fp32(ctx)) fail(PD_EINVAL, "the adjoint runs in the FP64 build only");
+    if (ctx->scheme != PD_EULER_CROMER) fail(PD_EINVAL, "the adjoint differentiates the Euler-Cromer scheme only");
+    if (ctx->inst.size() != 1) fail(PD_EINVAL, "the adjoint needs a single-instance problem");
+}
+
+// The reverse pass gathers the transposed tangent over each node's own family, which
+// needs every bond's two slots to carry the same stiffness and broken flag.
+void check_symmetric(pd_ctx* ctx, Inst& I)
+{
+    const std::vector<int64_t>& rev = reverse_slots(I);
+    const std::vector<uint8_t> br = broken_of(ctx, I);
+    for (int64_t b = 0; b < I.nnz; ++b) {
+        if (rev[b] < 0) fail(PD_EINVAL, "internal: family is not symmetric");
+        if (!I.kslot.empty() && I.kslot[b] != I.kslot[rev[b]])
+            fail(PD_EINVAL, "the adjoint needs symmetric bond stiffness (slots (i,j) and (j,i) equal)");
+        if (br[b] != br[rev[b]]) fail(PD_EINVAL, "the adjoint needs both slots of a bond broken together");
+    }
+}
+
+void launch_ec(pd_ctx* ctx, const StepArgs& A)
+{
+    if (ctx->mapping == PD_MAP_STAGED)
+        hip_check(launch_step_staged(A, kModeEC, false, ctx->stream), "step kernel launch");
+    else
+        hip_check(launch_step(A, ctx->lanes, kModeEC, ctx->has_stiff, ctx->stream), "step kernel launch");
 }
 
 }  // namespace
@@ -1318,6 +1390,7 @@ int pd_set_integrator(pd_ctx* ctx, int scheme, double dt)
             fail(PD_EINVAL, "unknown scheme");
         if (!(dt > 0.0) || !std::isfinite(dt)) fail(PD_EINVAL, "dt must be positive and finite");
         if (scheme != ctx->scheme || dt != ctx->dt) {
+            ctx->tape_valid = false;
             ctx->scheme = scheme;
             ctx->dt = dt;
             ctx->a_valid = false;
@@ -1467,6 +1540,7 @@ int pd_set_step(pd_ctx* ctx, int64_t step)
         require_built(ctx);
         if (step < 0 || step >= std::numeric_limits<int32_t>::max()) fail(PD_EINVAL, "step out of range");
         set_device(ctx);
+        ctx->tape_valid = false;
         ctx->step = step;
         upload(ctx->step_base, &step, sizeof step, 0, ctx->stream);
         sync(ctx);
@@ -1552,6 +1626,184 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
         ctx->a_valid = av;
         reset_flags_after_state_change(ctx, av);
         if (chosen) *chosen = best.mapping == PD_MAP_STAGED ? -1 : best.lanes;
+    });
+}
+
+int pd_adj_forward(pd_ctx* ctx, int64_t nsteps, int32_t ckpt_every)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        adjoint_checks(ctx);
+        if (nsteps < 1) fail(PD_EINVAL, "nsteps must be >= 1");
+        if (ckpt_every < 1) fail(PD_EINVAL, "ckpt_every must be >= 1");
+        if (ctx->step + nsteps >= std::numeric_limits<int32_t>::max())
+            fail(PD_ERANGE, "step counter would exceed 2^31 - 1");
+        set_device(ctx);
+        Inst& I = ctx->inst[0];
+        check_symmetric(ctx, I);
+        if (!ctx->bstep.p) {
+            ctx->bstep.alloc((static_cast<size_t>(ctx->ns) + kSpareRows * kWave) * sizeof(int32_t));
+            ctx->drop_graphs();  // captured launches carry the recording pointer
+        }
+        hip_check(launch_bstep_init(ctx->bstep.as<int32_t>(), ctx->col.as<int32_t>(), ctx->ent.as<uint16_t>(),
+                                    ctx->ns, ctx->stream),
+                  "break-step init launch");
+        const int64_t nn = ctx->nn;
+        const size_t Rb = static_cast<size_t>(nn + 1) * 48, Vb = static_cast<size_t>(3 * nn) * sizeof(double);
+        const int64_t C = (nsteps + ckpt_every - 1) / ckpt_every;
+        ctx->ck.alloc(static_cast<size_t>(C) * (Rb + Vb));
+        const int64_t step0 = ctx->step;
+        for (int64_t c = 0; c < C; ++c) {
+            char* dst = ctx->ck.as<char>() + static_cast<size_t>(c) * (Rb + Vb);
+            hip_check(hipMemcpyAsync(dst, ctx->rec[ctx->cur].p, Rb, hipMemcpyDeviceToDevice, ctx->stream),
+                      "checkpoint copy");
+            hip_check(hipMemcpyAsync(dst + Rb, ctx->v.p, Vb, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint copy");
+            do_steps(ctx, std::min<int64_t>(ckpt_every, nsteps - c * ckpt_every));
+        }
+        ctx->tape_valid = true;
+        ctx->tape_step0 = step0;
+        ctx->tape_nsteps = nsteps;
+        ctx->tape_every = ckpt_every;
+    });
+}
+
+int pd_adj_backward(pd_ctx* ctx, int64_t m, const int64_t* sensors, const double* dL_du, double* grad_k,
+                    double* grad_A)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        adjoint_checks(ctx);
+        if (!ctx->tape_valid) fail(PD_ESTATE, "no recorded forward run (pd_adj_forward) for the current problem");
+        if (m < 0 || (m > 0 && (!sensors || !dL_du))) fail(PD_EINVAL, "bad sensor arguments");
+        if (!grad_k || !grad_A) fail(PD_EINVAL, "gradient outputs are NULL");
+        const Inst& I = ctx->inst[0];
+        std::vector<int64_t> dsens(static_cast<size_t>(m));
+        for (int64_t p = 0; p < m; ++p) {
+            if (sensors[p] < 0 || sensors[p] >= I.n) fail(PD_EINVAL, "sensor node id out of range");
+            dsens[p] = I.node_off + I.iperm[sensors[p]];
+        }
+        for (int64_t q = 0; q < 3 * m; ++q)
+            if (!std::isfinite(dL_du[q])) fail(PD_EINVAL, "dL_du must be finite");
+        set_device(ctx);
+        hipStream_t st = ctx->stream;
+        const int64_t nn = ctx->nn, ns = ctx->ns, S = ctx->tape_every, T = ctx->tape_nsteps, step0 = ctx->tape_step0;
+        const size_t Rb = static_cast<size_t>(nn + 1) * 48, Vb = static_cast<size_t>(3 * nn) * sizeof(double),
+                     Nb = static_cast<size_t>(3 * (nn + 1)) * sizeof(double);
+        const int64_t Lmax = std::min(S, T);
+        DevBuf traj, vwork, nu[2], lam, grad, gacc, base, sum, dsn, ddl;
+        traj.alloc(static_cast<size_t>(Lmax + 1) * Rb);
+        vwork.alloc(Vb);
+        nu[0].alloc(Nb);
+        nu[1].alloc(Nb);
+        lam.alloc(Vb);
+        grad.alloc(static_cast<size_t>(ns) * sizeof(double));
+        gacc.alloc(static_cast<size_t>(nn) * sizeof(double));
+        base.alloc(sizeof(int64_t));
+        sum.alloc(sizeof(double));
+        dsn.alloc(static_cast<size_t>(m) * sizeof(int64_t));
+        ddl.alloc(static_cast<size_t>(3 * m) * sizeof(double));
+        auto at = [](const DevBuf& b, size_t off) { return static_cast<char*>(b.p) + off; };
+        // every level carries the positions and the sentinel record
+        for (int64_t s = 0; s <= Lmax; ++s)
+            hip_check(hipMemcpyAsync(at(traj, s * Rb), ctx->rec[ctx->cur].p, Rb, hipMemcpyDeviceToDevice, st),
+                      "trajectory init");
+        for (DevBuf* b : {&nu[0], &nu[1], &lam, &grad, &gacc})
+            hip_check(hipMemsetAsync(b->p, 0, b->bytes, st), "hipMemsetAsync");
+        upload(dsn, dsens.data(), dsens.size() * sizeof(int64_t), 0, st);
+        upload(ddl, dL_du, static_cast<size_t>(3 * m) * sizeof(double), 0, st);
+        hip_check(launch_adj_seed(lam.as<double>(), nn, dsn.as<int64_t>(), ddl.as<double>(), m, st), "seed launch");
+        hip_check(launch_adj_nu0(nu[0].as<double>(), lam.as<double>(), ctx->bc_id.as<int32_t>(), ctx->bc.as<BCRec>(),
+                                 nn, ctx->dt, st),
+                  "seed launch");
+
+        AdjArgs a{};
+        a.lam_u = lam.as<double>();
+        a.grad = grad.as<double>();
+        a.gacc = gacc.as<double>();
+        a.bstep = ctx->bstep.as<int32_t>();
+        a.col = ctx->col.as<int32_t>();
+        a.ent = ctx->ent.as<uint16_t>();
+        a.pieces = ctx->pieces.as<int2>();
+        a.slice_piece = ctx->slice_piece.as<int32_t>();
+        a.kslot = ctx->has_stiff ? ctx->kslot.as<double>() : nullptr;
+        a.vol = ctx->has_vol ? ctx->vol.as<double>() : nullptr;
+        a.bhat = ctx->has_body ? ctx->bhat.as<double>() : nullptr;
+        a.slice_ptr = ctx->slice_ptr.as<int64_t>();
+        a.slice_T = ctx->slice_T.as<int32_t>();
+        a.slice_inst = ctx->slice_inst.as<int32_t>();
+        a.params = ctx->params.as<InstParams>();
+        a.bc_id = ctx->bc_id.as<int32_t>();
+        a.bc = ctx->bc.as<BCRec>();
+        a.nn = nn;
+        a.nslices = ctx->nslices;
+        a.dt = ctx->dt;
+        const bool staged = ctx->mapping == PD_MAP_STAGED;
+        int nin = 0;
+        const int64_t C = (T + S - 1) / S;
+        for (int64_t c = C - 1; c >= 0; --c) {
+            const int64_t s0 = step0 + c * S, len = std::min(S, T - c * S);
+            // recompute the segment with the forward kernel from its checkpoint
+            hip_check(launch_flags_at(ctx->bstep.as<int32_t>(), ctx->col.as<int32_t>(), ctx->ent.as<uint16_t>(), ns, s0,
+                                      st),
+                      "flags launch");
+            const char* ck = ctx->ck.as<char>() + static_cast<size_t>(c) * (Rb + Vb);
+            hip_check(hipMemcpyAsync(traj.p, ck, Rb, hipMemcpyDeviceToDevice, st), "checkpoint restore");
+            hip_check(hipMemcpyAsync(vwork.p, ck + Rb, Vb, hipMemcpyDeviceToDevice, st), "checkpoint restore");
+            hip_check(launch_set_i64(base.as<int64_t>(), s0, st), "base launch");
+            for (int64_t s = 0; s < len; ++s) {
+                StepArgs A = step_args(ctx, ctx->cur, 1 - ctx->cur, s);
+                A.rec_in = reinterpret_cast<const double*>(at(traj, s * Rb));
+                A.rec_out = reinterpret_cast<double*>(at(traj, (s + 1) * Rb));
+                A.v = vwork.as<double>();
+                A.step_base = base.as<int64_t>();
+                A.bstep = nullptr;
+                launch_ec(ctx, A);
+            }
+            // reverse passes of the segment, last first
+            for (int64_t s = len - 1; s >= 0; --s) {
+                a.rec = reinterpret_cast<const double*>(at(traj, s * Rb));
+                a.nu_in = nu[nin].as<double>();
+                a.nu_out = nu[1 - nin].as<double>();
+                a.k = s0 + s;
+                hip_check(launch_adjoint(a, staged, ctx->lanes, st), "adjoint launch");
+                nin ^= 1;
+            }
+        }
+        // leave the broken flags as the forward run left them
+        hip_check(launch_flags_at(ctx->bstep.as<int32_t>(), ctx->col.as<int32_t>(), ctx->ent.as<uint16_t>(), ns,
+                                  step0 + T, st),
+                  "flags launch");
+        hip_check(launch_sum(gacc.as<double>(), nn, sum.as<double>(), st), "sum launch");
+        std::vector<double> g(static_cast<size_t>(I.n_dslots));
+        double gA = 0.0;
+        download(g.data(), grad, g.size() * sizeof(double), static_cast<size_t>(I.dslot_off) * sizeof(double), st);
+        download(&gA, sum, sizeof gA, 0, st);
+        sync(ctx);
+        std::fill(grad_k, grad_k + I.nnz, 0.0);
+        for (int64_t d = 0; d < I.n_dslots; ++d) {
+            const int32_t b = I.dslot_user[d];
+            if (b >= 0) grad_k[b] = g[d];
+        }
+        *grad_A = gA;
+    });
+}
+
+int pd_get_break_steps(pd_ctx* ctx, int32_t inst, int32_t* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        if (!ctx->bstep.p) fail(PD_ESTATE, "break steps are recorded only after pd_adj_forward");
+        set_device(ctx);
+        std::vector<int32_t> h(static_cast<size_t>(I.n_dslots));
+        download(h.data(), ctx->bstep, h.size() * sizeof(int32_t), static_cast<size_t>(I.dslot_off) * sizeof(int32_t),
+                 ctx->stream);
+        sync(ctx);
+        for (int64_t d = 0; d < I.n_dslots; ++d) {
+            const int32_t b = I.dslot_user[d];
+            if (b >= 0) out[b] = h[d];
+        }
     });
 }
 

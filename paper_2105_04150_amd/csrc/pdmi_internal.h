@@ -91,6 +91,7 @@ struct StepArgs {
     uint16_t* ent;              // staged layout only
     const int64_t* step_base;   // completed steps when the launch sequence started
     int32_t* status;            // bit 0: a non-finite u or v was produced
+    int32_t* bstep;             // nullptr, or per slot: the pass in which the slot broke
     int64_t nn;                 // device node count (SoA stride); record nn is the sentinel
     int64_t nslices;
     int64_t step_local;         // this launch advances step *step_base + step_local
@@ -126,6 +127,59 @@ hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, hipStream_
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
 
 hipError_t launch_advance(int64_t* step_base, int64_t by, hipStream_t s);
+hipError_t launch_set_i64(int64_t* p, int64_t value, hipStream_t s);
+
+// ---------------------------------------------------------------- adjoint (Euler-Cromer)
+//
+// Break schedule per slot: bstep[ds] = pass in which the slot broke; kNeverBroke if it is
+// intact, kBrokeBefore if it was broken before recording started (and for padding).  A
+// slot acts in pass k iff k < bstep.
+constexpr int32_t kNeverBroke = 0x7fffffff;
+constexpr int32_t kBrokeBefore = -0x7fffffff - 1;
+
+// One reverse pass k.  nu_in holds the adjoint of the unconstrained velocity of level
+// k+1 (AoS, (nn+1) x 3, the last entry zero); lam_u (SoA) the adjoint of u^{k+1} on
+// entry and of u^k on exit; nu_out receives the next pass's nu.
+struct AdjArgs {
+    const double* rec;          // node records (x, u^k), nn+1 of them
+    const double* nu_in;
+    double* nu_out;
+    double* lam_u;
+    double* grad;               // per device slot: d loss / d stiffness, accumulated
+    double* gacc;               // per node: accumulated h * bhat . nu (body-force magnitude)
+    const int32_t* bstep;
+    const int32_t* col;         // sliced layout
+    const uint16_t* ent;        // staged layout
+    const int2* pieces;
+    const int32_t* slice_piece;
+    const double* kslot;
+    const double* vol;
+    const double* bhat;
+    const int64_t* slice_ptr;
+    const int32_t* slice_T;
+    const int32_t* slice_inst;
+    const InstParams* params;
+    const int32_t* bc_id;
+    const BCRec* bc;
+    int64_t nn;
+    int64_t nslices;
+    int64_t k;                  // pass index
+    double dt;
+};
+
+hipError_t launch_adjoint(const AdjArgs& a, bool staged, int lanes, hipStream_t s);
+// bstep from the current broken flags: broken or padding -> kBrokeBefore, else kNeverBroke
+hipError_t launch_bstep_init(int32_t* bstep, const int32_t* col, const uint16_t* ent, int64_t ns, hipStream_t s);
+// broken flags as of level `step`: broken iff bstep < step
+hipError_t launch_flags_at(const int32_t* bstep, int32_t* col, uint16_t* ent, int64_t ns, int64_t step, hipStream_t s);
+// lam_u (SoA) += dL/du at the sensors, in order (repeated sensors add up)
+hipError_t launch_adj_seed(double* lam_u, int64_t nn, const int64_t* sensors, const double* dldu, int64_t m,
+                           hipStream_t s);
+// nu = dt * lam_u on unconstrained components, 0 elsewhere (first reverse pass)
+hipError_t launch_adj_nu0(double* nu, const double* lam_u, const int32_t* bc_id, const BCRec* bc, int64_t nn,
+                          double dt, hipStream_t s);
+// out[0] = sum of x[0..n)
+hipError_t launch_sum(const double* x, int64_t n, double* out, hipStream_t s);
 
 // lanes-per-node values with compiled kernels
 bool lanes_supported(int lanes);

@@ -300,6 +300,18 @@ def _bcs_tension_x_clamp_only(ijk, dims):
 WORKLOADS = ("block10", "beam3pb", "cube100", "cube100_wide", "adjoint_beam")
 
 
+def adjoint_sensors(w: Workload, m: Optional[int] = None, seed: Optional[int] = None):
+    """Sensor node ids and target displacements of the misfit loss.
+
+    m distinct nodes (default: the workload's n_sensors, at most n) drawn with the
+    sensor seed; targets are 1e-5 m times seeded standard normals (target seed).
+    """
+    m = min(w.n, m if m is not None else int(w.meta.get("n_sensors", 200)))
+    sensors = sample_nodes(w.n, m, int(w.meta.get("sensor_seed", 7)) if seed is None else seed)
+    target = 1.0e-5 * normal(int(w.meta.get("target_seed", 2001)), 3 * m).reshape(m, 3)
+    return sensors, target
+
+
 def batch_instances(count: int = 64, scale_lo: float = 1.0, scale_hi: float = 3.0,
                     base=(80, 10, 10), steps: int = 5000) -> List[Workload]:
     """Uneven-size beams for the batched uncertainty-quantification sweep.
