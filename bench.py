@@ -14,6 +14,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -58,6 +60,88 @@ def cpu_baseline(w, steps: int, threads: int):
                       f"(family built by the oracle, not timed)"}
 
 
+def _timed(fn, sync):
+    sync()
+    t0 = time.perf_counter()
+    fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def adjoint_extra(P, pi, sync, steps: int, ckpt: int):
+    """Adjoint on the 100 x 25 x 20 beam (Euler-Cromer, stiffness field, tip load, 200
+    sensors): plain steps, the recording forward run and the reverse pass, timed on the
+    same problem.  Rates are bond-updates per second of simulated forward steps."""
+    w = pi.workload("adjoint_beam", steps=steps)
+    sim = P.simulation_for(w, lanes=4)
+    sim.autotune(trial_steps=10)
+    info = sim.info()
+    nnz = info["n_slots"]
+    sensors, target = pi.adjoint_sensors(w)
+    z = np.zeros((w.n, 3))
+    sim.step(50)  # warm-up (graphs, caches)
+    sim.sync()
+    sim.set_state(u=z, v=z, a=z)
+    sim.set_step(0)
+    t_plain = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    sim.set_state(u=z, v=z, a=z, broken=np.zeros(nnz, dtype=np.uint8))
+    sim.set_step(0)
+    t_fwd = _timed(lambda: (sim.adj_forward(steps, ckpt), sim.sync()), sync)
+    dldu = 2.0 * (sim.u()[sensors] - target)
+    t_bwd = _timed(lambda: sim.adj_backward(sensors, dldu), sync)
+    mapping = "staged" if info["mapping"] == P.PD_MAP_STAGED else f"sliced-{info['lanes_per_node']}"
+    sim.close()
+    plain = nnz * steps / t_plain
+    return {"config": f"adjoint_beam {w.dims[0]}x{w.dims[1]}x{w.dims[2]}, {steps} Euler-Cromer steps, "
+                      f"checkpoint every {ckpt}, {len(sensors)} sensors, f64",
+            "bond_slots": nnz, "mapping": mapping,
+            "plain_step_rate": plain, "plain_ms": t_plain * 1e3,
+            "forward_recording_ms": t_fwd * 1e3, "backward_ms": t_bwd * 1e3,
+            "adjoint_rate": nnz * steps / (t_fwd + t_bwd),
+            "adjoint_vs_plain": (nnz * steps / (t_fwd + t_bwd)) / plain,
+            "backward_vs_plain_step": t_plain / t_bwd}
+
+
+def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int, mapping: str, lanes: int):
+    """Many uneven uncertainty-quantification beams advanced together, against the same
+    instances advanced one problem at a time (a sample of them) on the same GPU, both
+    with the mapping the autotuner chose for the headline workload."""
+    ws = pi.batch_instances(count=count, steps=steps)
+    t0 = time.perf_counter()
+    sim = P.Simulation()
+    sim.set_mapping(mapping, lanes)
+    sim.build_family_batch([w.coords for w in ws], [w.horizon for w in ws])
+    print(f"# batched: {count} families built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    sim.set_integrator("euler_cromer", ws[0].dt)
+    for b, w in enumerate(ws):
+        P.apply_workload(sim, w, inst=b)
+    setup = time.perf_counter() - t0
+    info = sim.info()
+    nnz = info["n_slots"]
+    sim.step(20)
+    sim.sync()
+    t_b = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    sim.close()
+    idx = np.unique(np.linspace(0, count - 1, min(seq_sample, count)).round().astype(int))
+    seq_slots, seq_t = 0, 0.0
+    print(f"# batched: {t_b * 1e3 / steps:.3f} ms/step; sequential sample next", file=sys.stderr, flush=True)
+    for b in idx:
+        s1 = P.simulation_for(ws[b], lanes=lanes, mapping=mapping)
+        s1.step(20)
+        s1.sync()
+        seq_t += _timed(lambda: (s1.step(steps), s1.sync()), sync)
+        seq_slots += s1.info()["n_slots"]
+        s1.close()
+    batched = nnz * steps / t_b
+    seq = seq_slots * steps / seq_t
+    return {"config": f"{count} beams, dims {ws[0].dims}..{ws[-1].dims}, {steps} Euler-Cromer steps, f64",
+            "instances": count, "nodes": info["n_nodes"], "bond_slots": nnz,
+            "mapping": mapping if mapping == "staged" else f"sliced-{lanes}",
+            "setup_s": setup, "batched_rate": batched, "ms_per_step": t_b * 1e3 / steps,
+            "sequential_rate": seq, "sequential_sample": [int(b) for b in idx],
+            "batched_vs_sequential": batched / seq}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +156,10 @@ def main():
                     help="device node order (auto: the autotuner tries both)")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batched measurements")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=300)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -160,6 +248,13 @@ def main():
                      "avg_launch_ms": per_launch_s * 1e3},
     }
     sim.close()
+    if not args.no_extras:
+        out["adjoint"] = adjoint_extra(P, pi, torch_sync, args.adjoint_steps, 100)
+        out["adjoint"]["adjoint_vs_headline_step"] = out["adjoint"]["adjoint_rate"] / value
+        print(f"# adjoint {out['adjoint']}", file=sys.stderr, flush=True)
+        out["batched"] = batched_extra(P, pi, torch_sync, args.batch_count, args.batch_steps, 8, mapping, lanes)
+        out["batched"]["batched_vs_headline_step"] = out["batched"]["batched_rate"] / value
+        print(f"# batched {out['batched']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, threads)

@@ -477,18 +477,27 @@ void upload_bcs(pd_ctx* ctx)
     sync(ctx);
 }
 
-void upload_stiffness(pd_ctx* ctx)
+// Per-slot stiffness of every instance (instances without a field get their c), or only
+// of instance `only` when the array already exists.
+void upload_stiffness(pd_ctx* ctx, int32_t only = -1)
 {
     ctx->tape_valid = false;
-    ctx->has_stiff = false;
-    for (auto& I : ctx->inst) ctx->has_stiff |= !I.kslot.empty();
-    if (!ctx->has_stiff) {
+    bool any = false;
+    for (auto& I : ctx->inst) any |= !I.kslot.empty();
+    if (!any) {
+        ctx->has_stiff = false;
         ctx->kslot.release();
         return;
     }
-    ctx->kslot.alloc((static_cast<size_t>(ctx->ns) + kSpareRows * kWave) * sizeof(double));
-    hip_check(hipMemsetAsync(ctx->kslot.p, 0, ctx->kslot.bytes, ctx->stream), "hipMemsetAsync");
-    for (auto& I : ctx->inst) {
+    const bool fresh = !ctx->has_stiff || !ctx->kslot.p;
+    ctx->has_stiff = true;
+    if (fresh) {
+        ctx->kslot.alloc((static_cast<size_t>(ctx->ns) + kSpareRows * kWave) * sizeof(double));
+        hip_check(hipMemsetAsync(ctx->kslot.p, 0, ctx->kslot.bytes, ctx->stream), "hipMemsetAsync");
+    }
+    for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
+        if (!fresh && only >= 0 && static_cast<int32_t>(ii) != only) continue;
+        const Inst& I = ctx->inst[ii];
         std::vector<double> k(static_cast<size_t>(I.n_dslots), 0.0);
         for (int64_t s = 0; s < I.n_dslots; ++s) {
             const int32_t b = I.dslot_user[s];
@@ -783,6 +792,7 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     ctx->tape_valid = false;
     ctx->bstep.release();
     ctx->ck.release();
+    ctx->kslot.release();  // slot layout changes: re-uploaded in full below
     int64_t nn = 0, nsl = 0, ns = 0;
     std::vector<int64_t> sp;
     std::vector<int32_t> sT, sI, spc;
@@ -1272,7 +1282,7 @@ int pd_set_material(pd_ctx* ctx, int32_t inst, const pd_material* m)
         I.vols = std::move(vols);
         upload_params(ctx);
         upload_volumes(ctx);
-        if (ctx->has_stiff) upload_stiffness(ctx);
+        if (ctx->has_stiff) upload_stiffness(ctx, inst);
         ctx->a_valid = false;
         ctx->vv_ahead = false;
         ctx->drop_graphs();
@@ -1293,7 +1303,7 @@ int pd_set_bond_stiffness(pd_ctx* ctx, int32_t inst, const double* k)
         }
         set_device(ctx);
         I.kslot = std::move(kv);
-        upload_stiffness(ctx);
+        upload_stiffness(ctx, inst);
         ctx->a_valid = false;
         ctx->vv_ahead = false;
         ctx->drop_graphs();
