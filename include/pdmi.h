@@ -240,10 +240,10 @@ int pd_adj_forward(pd_ctx *ctx, int64_t nsteps, int32_t ckpt_every);
 int pd_adj_backward(pd_ctx *ctx, int64_t m, const int64_t *sensors, const double *dL_du, double *grad_k,
                     double *grad_A);
 
-/* Pass index in which each slot broke during the recording (host out[nnz], user CSR
- * order): INT32_MAX = intact, INT32_MIN = broken before pd_adj_forward.  PD_ESTATE
- * when nothing is being recorded (recording starts with pd_adj_forward and continues
- * through later steps until the broken set or the layout is replaced). */
+/* Pass index in which each slot broke (host out[nnz], user CSR order): INT32_MAX =
+ * intact, INT32_MIN = already broken when the broken set was last established (problem
+ * build, mapping change, pd_break_bonds, pd_set_state with a broken set, or the start
+ * of pd_adj_forward).  Every step records the passes of the bonds it breaks. */
 int pd_get_break_steps(pd_ctx *ctx, int32_t inst, int32_t *out);
 
 /* ---------------------------------------------------------------- tuning and introspection */

@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
         for (int t = 0; t < T; ++t) {
             const int64_t ds = ent + static_cast<int64_t>(t) * kWave + lane;
             if (!(A.k < static_cast<int64_t>(A.bstep[ds]))) continue;
-            const int64_t j = m.x + (A.ent[ds] & 0x7fff) / 3;
+            const int64_t j = m.x + (A.ent[ds] & 0x7fff) / 48;
             const double2 p0 = rec[3 * j], p1 = rec[3 * j + 1], p2 = rec[3 * j + 2];
             const double nj[3] = {A.nu_in[3 * j], A.nu_in[3 * j + 1], A.nu_in[3 * j + 2]};
             const double kb = STIFF ? A.kslot[ds] : P.c;

@@ -429,6 +429,9 @@ void sync(pd_ctx* ctx) { hip_check(hipStreamSynchronize(ctx->stream), "hipStream
 
 bool fp32(const pd_ctx* ctx) { return ctx->precision == PD_FP32; }
 
+// Bytes of one node-record buffer: nn records, the sentinel and kRecPad spare records.
+size_t rec_bytes(int64_t nn) { return static_cast<size_t>(nn + 1 + kRecPad) * 48; }
+
 // (Re)build the whole device problem for the current lanes-per-node, keeping the state
 // given in user order (nullptr = zero / intact).
 struct HostState {
@@ -596,26 +599,32 @@ void upload_state(pd_ctx* ctx, const Inst& I, const double* u, const double* v, 
     }
 }
 
+// Break steps of one instance from its current flags: broken -> kBrokeBefore, intact ->
+// kNeverBroke (padding counts as broken).
+void init_break_steps(pd_ctx* ctx, const Inst& I)
+{
+    const int64_t off = I.dslot_off;
+    hip_check(launch_bstep_init(ctx->bstep.as<int32_t>() + off, ctx->col.p ? ctx->col.as<int32_t>() + off : nullptr,
+                                ctx->ent.p ? ctx->ent.as<uint16_t>() + off : nullptr, I.n_dslots, ctx->stream),
+              "break-step init launch");
+}
+
 void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
 {
-    // a broken set from outside ends break-step recording (the recorded steps would be stale)
     ctx->tape_valid = false;
-    if (ctx->bstep.p) {
-        ctx->bstep.release();
-        ctx->drop_graphs();
-    }
     if (ctx->mapping == PD_MAP_STAGED) {
         std::vector<uint16_t> e(static_cast<size_t>(I.n_dslots));
         parallel_for(I.n_dslots, [&](int64_t s0, int64_t s1) {
             for (int64_t d = s0; d < s1; ++d) {
                 const int32_t b = I.dslot_user[d];
                 if (b < 0)
-                    e[d] = static_cast<uint16_t>(0x8000 | (3 * kSegMax));
+                    e[d] = static_cast<uint16_t>(0x8000 | kEntPad);
                 else
-                    e[d] = static_cast<uint16_t>((3 * I.ent_idx[d]) | ((broken && broken[b]) ? 0x8000 : 0));
+                    e[d] = static_cast<uint16_t>((48 * I.ent_idx[d]) | ((broken && broken[b]) ? 0x8000 : 0));
             }
         });
         upload(ctx->ent, e.data(), e.size() * sizeof(uint16_t), I.dslot_off * sizeof(uint16_t), ctx->stream);
+        init_break_steps(ctx, I);
         return;
     }
     std::vector<int32_t> colv(static_cast<size_t>(I.n_dslots));
@@ -634,6 +643,7 @@ void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
                 }
     });
     upload(ctx->col, colv.data(), colv.size() * sizeof(int32_t), I.dslot_off * sizeof(int32_t), ctx->stream);
+    init_break_steps(ctx, I);
     sync(ctx);
 }
 
@@ -790,7 +800,6 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     const int G = ctx->mapping == PD_MAP_STAGED ? 1 : ctx->lanes, W = kWave / G;
     ctx->drop_graphs();
     ctx->tape_valid = false;
-    ctx->bstep.release();
     ctx->ck.release();
     ctx->kslot.release();  // slot layout changes: re-uploaded in full below
     int64_t nn = 0, nsl = 0, ns = 0;
@@ -862,7 +871,7 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     ctx->nslices = nsl;
     ctx->ns = ns;
     for (int b = 0; b < 2; ++b) {
-        ctx->rec[b].alloc(static_cast<size_t>(nn + 1) * 48);
+        ctx->rec[b].alloc(rec_bytes(nn));
         if (fp32(ctx))
             ctx->um[b].alloc(static_cast<size_t>(3 * nn) * sizeof(double));
         else
@@ -871,6 +880,7 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     ctx->v.alloc(static_cast<size_t>(3 * nn) * sizeof(double));
     ctx->a.alloc(static_cast<size_t>(3 * nn) * sizeof(double));
     const size_t spare = kSpareRows * kWave;
+    ctx->bstep.alloc((static_cast<size_t>(ns) + spare) * sizeof(int32_t));
     if (ctx->mapping == PD_MAP_STAGED) {
         ctx->col.release();
         ctx->ent.alloc((static_cast<size_t>(ns) + spare) * sizeof(uint16_t));
@@ -1651,15 +1661,9 @@ int pd_adj_forward(pd_ctx* ctx, int64_t nsteps, int32_t ckpt_every)
         set_device(ctx);
         Inst& I = ctx->inst[0];
         check_symmetric(ctx, I);
-        if (!ctx->bstep.p) {
-            ctx->bstep.alloc((static_cast<size_t>(ctx->ns) + kSpareRows * kWave) * sizeof(int32_t));
-            ctx->drop_graphs();  // captured launches carry the recording pointer
-        }
-        hip_check(launch_bstep_init(ctx->bstep.as<int32_t>(), ctx->col.as<int32_t>(), ctx->ent.as<uint16_t>(),
-                                    ctx->ns, ctx->stream),
-                  "break-step init launch");
+        init_break_steps(ctx, I);
         const int64_t nn = ctx->nn;
-        const size_t Rb = static_cast<size_t>(nn + 1) * 48, Vb = static_cast<size_t>(3 * nn) * sizeof(double);
+        const size_t Rb = rec_bytes(nn), Vb = static_cast<size_t>(3 * nn) * sizeof(double);
         const int64_t C = (nsteps + ckpt_every - 1) / ckpt_every;
         ctx->ck.alloc(static_cast<size_t>(C) * (Rb + Vb));
         const int64_t step0 = ctx->step;
@@ -1697,7 +1701,7 @@ int pd_adj_backward(pd_ctx* ctx, int64_t m, const int64_t* sensors, const double
         set_device(ctx);
         hipStream_t st = ctx->stream;
         const int64_t nn = ctx->nn, ns = ctx->ns, S = ctx->tape_every, T = ctx->tape_nsteps, step0 = ctx->tape_step0;
-        const size_t Rb = static_cast<size_t>(nn + 1) * 48, Vb = static_cast<size_t>(3 * nn) * sizeof(double),
+        const size_t Rb = rec_bytes(nn), Vb = static_cast<size_t>(3 * nn) * sizeof(double),
                      Nb = static_cast<size_t>(3 * (nn + 1)) * sizeof(double);
         const int64_t Lmax = std::min(S, T);
         DevBuf traj, vwork, nu[2], lam, grad, gacc, base, sum, dsn, ddl;
@@ -1765,8 +1769,7 @@ int pd_adj_backward(pd_ctx* ctx, int64_t m, const int64_t* sensors, const double
                 A.rec_in = reinterpret_cast<const double*>(at(traj, s * Rb));
                 A.rec_out = reinterpret_cast<double*>(at(traj, (s + 1) * Rb));
                 A.v = vwork.as<double>();
-                A.step_base = base.as<int64_t>();
-                A.bstep = nullptr;
+                A.step_base = base.as<int64_t>();  // breaks re-record the same passes
                 launch_ec(ctx, A);
             }
             // reverse passes of the segment, last first
@@ -1804,7 +1807,7 @@ int pd_get_break_steps(pd_ctx* ctx, int32_t inst, int32_t* out)
     return guarded(ctx, [&] {
         const Inst& I = instance(ctx, inst);
         if (!out) fail(PD_EINVAL, "out is NULL");
-        if (!ctx->bstep.p) fail(PD_ESTATE, "break steps are recorded only after pd_adj_forward");
+        require_built(ctx);
         set_device(ctx);
         std::vector<int32_t> h(static_cast<size_t>(I.n_dslots));
         download(h.data(), ctx->bstep, h.size() * sizeof(int32_t), static_cast<size_t>(I.dslot_off) * sizeof(int32_t),

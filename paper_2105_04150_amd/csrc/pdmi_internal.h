@@ -10,7 +10,9 @@
 //                                 bond arithmetic); ping-pong like the records
 //   velocity      v[3][nn]        structure of arrays, f64
 //   acceleration  a[3][nn]        structure of arrays, f64 (velocity Verlet)
-//   sentinel      rec[*][nn]      one extra record far from every node; padding slots point at it
+//   sentinel      rec[*][nn]      one extra record far from every node; padding slots point at it,
+//                                 followed by kRecPad zero records so the staged kernel's
+//                                 fixed-size range loads stay in bounds
 //   slots         col[ns]         int32 per slot in "slices": a slice is the W = 64/G nodes one
 //                                 wavefront serves (G lanes per node); its slots are stored as
 //                                 T rows of 64 entries, entry (t, w*G + g) = slot t*G + g of the
@@ -26,9 +28,9 @@
 // copies a piece's node records and entries into LDS, then reads neighbours from there.
 //   pieces        int2 {first node of the range, len | T << 8} per piece
 //   slice_piece   first piece of every slice (+ one past the last)
-//   ent[ns]       uint16 per slot: bits 0..14 = 3 x (index into the range), the record's
-//                 offset in 16-byte units (index kSegMax = padding, the LDS sentinel
-//                 record), bit 15 = broken; slice_ptr gives each slice's first entry.
+//   ent[ns]       uint16 per slot: bits 0..14 = byte offset of the neighbour's record in the
+//                 staged copy (48 x index into the range; kEntPad for padding, the LDS
+//                 sentinel record), bit 15 = broken; slice_ptr gives each slice's first entry.
 //                 The entry array ends with kPieceRows spare rows (whole 8-row blocks are
 //                 loaded).
 #pragma once
@@ -45,6 +47,11 @@ constexpr int kRowUnroll = 2;           // slot rows per step-kernel iteration; 
                                         // many spare rows at the end
 constexpr int kSegMax = 80;             // node records per staged range (LDS slot kSegMax: sentinel)
 constexpr int kPieceRows = 8;           // slot rows per staged piece
+constexpr int kStageChunks = 4 * 64;    // 16-byte record chunks one staged range load covers
+constexpr int kEntPad = kStageChunks * 16;  // entry byte offset of the LDS sentinel record
+constexpr int kRecPad = kStageChunks / 3 + 2;  // zero records after the sentinel
+static_assert(3 * kSegMax <= kStageChunks, "a range fits the staged record loads");
+static_assert(kEntPad < 0x8000, "entry offsets fit 15 bits");
 constexpr int32_t kNodeFree = -1;       // bc_id of an unconstrained node
 constexpr int32_t kNodePad = -2;        // bc_id of a padding node (never updated)
 
@@ -91,7 +98,7 @@ struct StepArgs {
     uint16_t* ent;              // staged layout only
     const int64_t* step_base;   // completed steps when the launch sequence started
     int32_t* status;            // bit 0: a non-finite u or v was produced
-    int32_t* bstep;             // nullptr, or per slot: the pass in which the slot broke
+    int32_t* bstep;             // per slot: the pass in which the slot broke (written on breaking)
     int64_t nn;                 // device node count (SoA stride); record nn is the sentinel
     int64_t nslices;
     int64_t step_local;         // this launch advances step *step_base + step_local

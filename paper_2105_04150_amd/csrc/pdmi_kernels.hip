@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
                 if (brk[u]) {
                     const int64_t ds = base + static_cast<int64_t>(t + u) * kWave + lane;
                     A.col[ds] = ~c[u];  // irreversible
-                    if (A.bstep) A.bstep[ds] = static_cast<int32_t>(*A.step_base + A.step_local);
+                    A.bstep[ds] = static_cast<int32_t>(*A.step_base + A.step_local);
                 }
         }
     }
@@ -274,20 +274,20 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
 // to LDS; every slot reads its neighbour from LDS.  Each record crosses the vector-memory
 // path once per slice instead of once per slot.  Per-slot stiffness, when present,
 // streams from global memory one piece ahead.  Rows are processed in pairs so the LDS
-// reads of one row overlap the arithmetic of the other.
+// reads of one row overlap the arithmetic of the other; an odd last row runs alone.
 template <bool FP32, int MODE, bool STIFF, bool VOLN>
 __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __restrict__ pieces,
                                                          const int32_t* __restrict__ slice_piece,
                                                          const int64_t* __restrict__ slice_ptr)
 {
-    constexpr int kRecChunks = 3 * (kSegMax + 1);            // 16-byte chunks of records + sentinel
+    constexpr int kRecChunks = kStageChunks + 3;             // staged records, then the sentinel
     constexpr int kEntChunks = kPieceRows * kWave * 2 / 16;  // 16-byte chunks of entries
-    constexpr int kVolWords = VOLN ? kSegMax + 2 : 0;        // staged volumes (doubles)
+    constexpr int kVolWords = VOLN ? (kEntPad / 48 + 2) / 2 * 2 : 0;  // staged volumes (doubles), sentinel last
     constexpr int kLds = kRecChunks + kEntChunks + kVolWords / 2;
-    constexpr int kRecLoads = (3 * kSegMax + kWave - 1) / kWave;  // 4
-    static_assert(kRecLoads == 4 && kEntChunks == kWave, "staging uses four record loads and one entry load");
+    static_assert(kStageChunks == 4 * kWave && kEntChunks == kWave, "four record loads and one entry load");
     __shared__ double2 lds[kLds];
     double2* const lrec = lds;
+    const char* const lrecb = reinterpret_cast<const char*>(lds);
     uint16_t* const lent = reinterpret_cast<uint16_t*>(lds + kRecChunks);
     double* const lvol = reinterpret_cast<double*>(lds + kRecChunks + kEntChunks);
 
@@ -308,11 +308,12 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
     const double cv = P.c * P.volume;
     const float cvf = static_cast<float>(cv), q0f = static_cast<float>(P.q0);
     uint16_t* __restrict__ entw = A.ent;
+    int32_t* __restrict__ bstep = A.bstep;
     const double2* __restrict__ ent2 = reinterpret_cast<const double2*>(A.ent);
 
     // sentinel record (padding entries point at it), volume 0
-    if (lane < 3) lrec[3 * kSegMax + lane] = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
-    if (VOLN && lane == 0) lvol[kSegMax] = 0.0;
+    if (lane < 3) lrec[kStageChunks + lane] = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
+    if (VOLN && lane == 0) lvol[kEntPad / 48] = 0.0;
 
     const int p0 = __builtin_amdgcn_readfirstlane(slice_piece[slice]);
     const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
@@ -322,23 +323,23 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
 
     // staging registers of the next piece
     double2 r0, r1, r2, r3, e0;
-    int nrec = 0;
     double vs0 = 0.0, vs1 = 0.0;
     int vlen = 0;
     double kcur[kPieceRows], knext[kPieceRows];
 
-    // Loads of piece p (first entry e): unconditional, from clamped addresses.
+    // Loads of piece p (first entry e): a fixed 256-chunk window from the range start
+    // (the record buffers end with kRecPad spare records) and the whole 8-row entry block
+    // (rows >= T are never read); volumes from clamped addresses.
     auto issue = [&](int p, int64_t e) {
         const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
-        const int len = m.y & 0xff;
-        nrec = 3 * len;
-        const double2* rs = rin + 3 * static_cast<int64_t>(m.x);
-        r0 = rs[min(lane, nrec - 1)];
-        r1 = rs[min(lane + kWave, nrec - 1)];
-        r2 = rs[min(lane + 2 * kWave, nrec - 1)];
-        r3 = rs[min(lane + 3 * kWave, nrec - 1)];
-        e0 = ent2[e / 8 + lane];  // the whole 8-row entry block; rows >= T are never read
+        const double2* rs = rin + 3 * static_cast<int64_t>(m.x) + lane;
+        r0 = rs[0];
+        r1 = rs[kWave];
+        r2 = rs[2 * kWave];
+        r3 = rs[3 * kWave];
+        e0 = ent2[e / 8 + lane];
         if (VOLN) {
+            const int len = m.y & 0xff;
             vlen = len;
             vs0 = A.vol[m.x + min(lane, len - 1)];
             vs1 = A.vol[m.x + min(lane + kWave, len - 1)];
@@ -348,10 +349,10 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
             for (int t = 0; t < kPieceRows; ++t) knext[t] = __builtin_nontemporal_load(A.kslot + e + t * kWave + lane);
     };
     auto commit = [&]() {
-        if (lane < nrec) lrec[lane] = r0;
-        if (lane + kWave < nrec) lrec[lane + kWave] = r1;
-        if (lane + 2 * kWave < nrec) lrec[lane + 2 * kWave] = r2;
-        if (lane + 3 * kWave < nrec) lrec[lane + 3 * kWave] = r3;
+        lrec[lane] = r0;
+        lrec[lane + kWave] = r1;
+        lrec[lane + 2 * kWave] = r2;
+        lrec[lane + 3 * kWave] = r3;
         reinterpret_cast<double2*>(lent)[lane] = e0;
         if (VOLN) {
             if (lane < vlen) lvol[lane] = vs0;
@@ -359,15 +360,22 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
         }
     };
     auto row = [&](uint16_t e, double kst) {
-        const int ri = e & 0x7fff;  // record offset in 16-byte units (3 * index)
-        const double2 q0 = lrec[ri], q1 = lrec[ri + 1], q2 = lrec[ri + 2];
+        const uint32_t off = e & 0x7fff;  // byte offset of the neighbour's staged record
+        const double2 q0 = *reinterpret_cast<const double2*>(lrecb + off);
+        const double2 q1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
+        const double2 q2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
         const int32_t c = (e & 0x8000) ? -1 : 0;  // sign carries the alive flag
         double kv = cv;
-        if (STIFF || VOLN) kv = (STIFF ? kst : P.c) * (VOLN ? lvol[ri / 3] : P.volume);
+        if (STIFF || VOLN) kv = (STIFF ? kst : P.c) * (VOLN ? lvol[(off * 0xAAABu) >> 21] : P.volume);  // off / 48
         if (FP32)
             return slot_force32(c, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2, (STIFF || VOLN) ? static_cast<float>(kv) : cvf,
                                 q0f, Ff0, Ff1, Ff2);
         return slot_force(c, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2);
+    };
+    // a slot that broke in this pass: flag it (irreversible) and record the pass
+    auto broke = [&](int64_t ds, uint16_t e) {
+        entw[ds] = static_cast<uint16_t>(e | 0x8000);
+        bstep[ds] = static_cast<int32_t>(*A.step_base + A.step_local);
     };
 
     if (p1 > p0) {
@@ -386,16 +394,14 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
             for (int t = 0; t < kPieceRows; t += 2) {
                 if (t >= T) break;
                 const uint16_t ea = lent[t * kWave + lane];
-                const uint16_t eb = (t + 1 < T) ? lent[(t + 1) * kWave + lane] : static_cast<uint16_t>(0x8000 | 3 * kSegMax);
-                const bool ba = row(ea, STIFF ? kcur[t] : 0.0);
-                const bool bb = row(eb, STIFF ? kcur[t + 1] : 0.0);
-                if (ba) {
-                    entw[ent + t * kWave + lane] = static_cast<uint16_t>(ea | 0x8000);  // irreversible
-                    if (A.bstep) A.bstep[ent + t * kWave + lane] = static_cast<int32_t>(*A.step_base + A.step_local);
-                }
-                if (bb) {
-                    entw[ent + (t + 1) * kWave + lane] = static_cast<uint16_t>(eb | 0x8000);
-                    if (A.bstep) A.bstep[ent + (t + 1) * kWave + lane] = static_cast<int32_t>(*A.step_base + A.step_local);
+                if (t + 1 < T) {
+                    const uint16_t eb = lent[(t + 1) * kWave + lane];
+                    const bool ba = row(ea, STIFF ? kcur[t] : 0.0);
+                    const bool bb = row(eb, STIFF ? kcur[t + 1] : 0.0);
+                    if (ba) broke(ent + t * kWave + lane, ea);
+                    if (bb) broke(ent + (t + 1) * kWave + lane, eb);
+                } else {
+                    if (row(ea, STIFF ? kcur[t] : 0.0)) broke(ent + t * kWave + lane, ea);
                 }
             }
             ent = ent_next;
@@ -425,9 +431,9 @@ __global__ __launch_bounds__(kWave) void damage_staged(DamageArgs A)
         const int T = (m.y >> 8) & 0xff;
         for (int t = 0; t < T; ++t) {
             const uint16_t e = A.ent[ent + t * kWave + lane];
-            const int idx = (e & 0x7fff) / 3;
-            if (idx == kSegMax) continue;  // padding
-            const double vj = A.vol ? A.vol[m.x + idx] : P.volume;
+            const int off = e & 0x7fff;
+            if (off == kEntPad) continue;  // padding
+            const double vj = A.vol ? A.vol[m.x + off / 48] : P.volume;
             den += vj;
             if (!(e & 0x8000)) num += vj;
         }
