@@ -20,12 +20,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2105_04150_amd", "csrc", "pdmi_kernels.hip")
+# MI355X vector peaks (256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz)
+PEAK_VALU_TFLOPS = {"f64": 78.6, "f32": 157.3}
+# Algorithmic flops of one slot update as the step kernel evaluates it (an FMA counts 2):
+# bond vector, displacement difference, y and xi + y (12); |y|^2 - |xi|^2 and |xi|^2 (5 + 5);
+# 1/|xi| by rsqrt and one Newton step (7); q (2); the series for 1 - (1+q)^(-1/2) (11 in
+# FP64 with six terms, 7 in FP32 with four); the coefficient (2); the force update (6).
+FLOPS_PER_SLOT = {"f64": 50, "f32": 46}
+STEP_SOURCES = [os.path.join(ROOT, "paper_2105_04150_amd", "csrc", f)
+                for f in ("pdmi_kernels.hip", "pdmi_device.h", "pdmi_internal.h")]
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in STEP_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str, precision: str):
@@ -102,15 +113,29 @@ def adjoint_extra(P, pi, sync, steps: int, ckpt: int):
             "backward_vs_plain_step": t_plain / t_bwd}
 
 
-def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int, mapping: str, lanes: int):
+def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
     """Many uneven uncertainty-quantification beams advanced together, against the same
-    instances advanced one problem at a time (a sample of them) on the same GPU, both
-    with the mapping the autotuner chose for the headline workload."""
+    instances advanced one problem at a time (a sample of them) on the same GPU.  The
+    mapping and node order come from the library's autotuner run on four of the beams
+    (the full batch takes tens of seconds per layout build)."""
     ws = pi.batch_instances(count=count, steps=steps)
     t0 = time.perf_counter()
+    sub = [ws[b] for b in np.unique(np.linspace(0, count - 1, min(4, count)).round().astype(int))]
+    tun = P.Simulation()
+    tun.build_family_batch([w.coords for w in sub], [w.horizon for w in sub], order="auto")
+    tun.set_integrator("euler_cromer", ws[0].dt)
+    for b, w in enumerate(sub):
+        P.apply_workload(tun, w, inst=b)
+    tun.autotune(trial_steps=5)
+    ti = tun.info()
+    tun.close()
+    mapping = "staged" if ti["mapping"] == P.PD_MAP_STAGED else "sliced"
+    lanes = ti["lanes_per_node"]
+    order = "morton" if ti["order"] == P.PD_ORDER_MORTON else "natural"
+    print(f"# batched: autotuned on {len(sub)} beams: {mapping}-{lanes}, {order}", file=sys.stderr, flush=True)
     sim = P.Simulation()
     sim.set_mapping(mapping, lanes)
-    sim.build_family_batch([w.coords for w in ws], [w.horizon for w in ws])
+    sim.build_family_batch([w.coords for w in ws], [w.horizon for w in ws], order=order)
     print(f"# batched: {count} families built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     sim.set_integrator("euler_cromer", ws[0].dt)
     for b, w in enumerate(ws):
@@ -126,7 +151,7 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int, mapping:
     seq_slots, seq_t = 0, 0.0
     print(f"# batched: {t_b * 1e3 / steps:.3f} ms/step; sequential sample next", file=sys.stderr, flush=True)
     for b in idx:
-        s1 = P.simulation_for(ws[b], lanes=lanes, mapping=mapping)
+        s1 = P.simulation_for(ws[b], lanes=lanes, mapping=mapping, order=order)
         s1.step(20)
         s1.sync()
         seq_t += _timed(lambda: (s1.step(steps), s1.sync()), sync)
@@ -136,7 +161,7 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int, mapping:
     seq = seq_slots * steps / seq_t
     return {"config": f"{count} beams, dims {ws[0].dims}..{ws[-1].dims}, {steps} Euler-Cromer steps, f64",
             "instances": count, "nodes": info["n_nodes"], "bond_slots": nnz,
-            "mapping": mapping if mapping == "staged" else f"sliced-{lanes}",
+            "mapping": mapping if mapping == "staged" else f"sliced-{lanes}", "node_order": order,
             "setup_s": setup, "batched_rate": batched, "ms_per_step": t_b * 1e3 / steps,
             "sequential_rate": seq, "sequential_sample": [int(b) for b in idx],
             "batched_vs_sequential": batched / seq}
@@ -222,8 +247,10 @@ def main():
     value = nnz * args.steps / wall
     per_launch_s = dev_ms / 1e3 / args.steps
     model_bytes = info["model_bytes_per_step"]
-    achieved = model_bytes / per_launch_s / 1e9
+    achieved_gbs = model_bytes / per_launch_s / 1e9
     traffic = measured_traffic(args.workload, args.precision)
+    tflops = nnz * FLOPS_PER_SLOT[args.precision] / per_launch_s / 1e12
+    peak = PEAK_VALU_TFLOPS[args.precision]
     out = {
         "metric": "bond-updates/s (bonds*steps/s) & % HBM peak; batched/adjoint vs plain step",
         "value": value,
@@ -242,17 +269,22 @@ def main():
                    "nodes": info["n_nodes"], "bond_slots": nnz, "mapping": mapping, "lanes_per_node": lanes,
                    "device_node_order": order,
                    "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": model_bytes,
-                     "avg_launch_ms": per_launch_s * 1e3},
+        # the step kernel issues FP64 (or FP32) vector arithmetic faster than HBM can feed
+        # it only at a fraction of the HBM rate: it is bound by vector ALU issue
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+                     "frac": tflops / peak, "traffic": traffic,
+                     "algorithmic_flops_per_slot": FLOPS_PER_SLOT[args.precision],
+                     "avg_launch_ms": per_launch_s * 1e3,
+                     "hbm": {"achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": achieved_gbs / PEAK_HBM_GBS,
+                             "algorithmic_bytes_per_launch": model_bytes, "measured_bytes_per_launch": traffic}},
     }
     sim.close()
     if not args.no_extras:
         out["adjoint"] = adjoint_extra(P, pi, torch_sync, args.adjoint_steps, 100)
         out["adjoint"]["adjoint_vs_headline_step"] = out["adjoint"]["adjoint_rate"] / value
         print(f"# adjoint {out['adjoint']}", file=sys.stderr, flush=True)
-        out["batched"] = batched_extra(P, pi, torch_sync, args.batch_count, args.batch_steps, 8, mapping, lanes)
+        out["batched"] = batched_extra(P, pi, torch_sync, args.batch_count, args.batch_steps, 8)
         out["batched"]["batched_vs_headline_step"] = out["batched"]["batched_rate"] / value
         print(f"# batched {out['batched']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
