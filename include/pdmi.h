@@ -223,9 +223,10 @@ int pd_set_step(pd_ctx *ctx, int64_t step);
  *
  * pd_adj_forward advances the problem by nsteps >= 1 steps exactly as pd_step does,
  * recording the pass in which each slot breaks and a device checkpoint of (u, v)
- * every ckpt_every >= 1 steps ((nn + 1) * 48 + nn * 24 bytes each, nn = padded node
- * count).  Any later change to the problem or state (pd_step included) discards the
- * recording.  Asynchronous like pd_step. */
+ * every ckpt_every >= 1 steps ((nn + 89) * 48 + nn * 24 bytes each, nn = padded node
+ * count; with ckpt_every = 1 every level is kept, v is not, and the reverse pass
+ * recomputes nothing).  Any later change to the problem or state (pd_step included)
+ * discards the recording.  Asynchronous like pd_step. */
 int pd_adj_forward(pd_ctx *ctx, int64_t nsteps, int32_t ckpt_every);
 
 /* Gradient of a loss L(u^T) at the end of the recorded run.  The caller passes
@@ -234,7 +235,7 @@ int pd_adj_forward(pd_ctx *ctx, int64_t nsteps, int32_t ckpt_every);
  * for every slot's stiffness (slots of a bond are separate parameters), and *grad_A =
  * dL/dA for the body-force magnitude of pd_set_body_force (0 without a body force).
  * Each segment between checkpoints is recomputed with the forward kernel (same
- * results bit for bit) into a trajectory buffer of min(ckpt_every, nsteps) + 1 levels,
+ * results bit for bit) into a trajectory buffer of min(ckpt_every, nsteps) levels,
  * then the reverse passes run last to first.  The problem state is left unchanged.
  * Synchronising; PD_ESTATE if there is no valid recording. */
 int pd_adj_backward(pd_ctx *ctx, int64_t m, const int64_t *sensors, const double *dL_du, double *grad_k,

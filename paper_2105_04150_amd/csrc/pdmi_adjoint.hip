@@ -21,11 +21,13 @@
 namespace pdmi {
 namespace {
 
-// One active slot: adds k_b K_b (V_i nu_j - V_j nu_i) to J and returns the slot's
-// stiffness-gradient increment h V_j (s/r) (y . nu_i).
-__device__ __forceinline__ double adj_slot(const double2 p0, const double2 p1, const double2 p2, double X0,
-                                           double X1, double X2, double U0, double U1, double U2, const double nj[3],
-                                           const double ni[3], double Vi, double Vj, double kb, double h, double J[3])
+// One slot: adds k_b K_b (V_i nu_j - V_j nu_i) to J and returns the slot's
+// stiffness-gradient increment h V_j (s/r) (y . nu_i).  An inactive slot (broken in an
+// earlier pass, or padding) evaluates q = 0 with zero weights and adds nothing.
+__device__ __forceinline__ double adj_slot(bool active, const double2 p0, const double2 p1, const double2 p2,
+                                           double X0, double X1, double X2, double U0, double U1, double U2,
+                                           const double nj[3], const double ni[3], double Vi, double Vj, double kb,
+                                           double h, double J[3])
 {
     const double xi0 = p0.x - X0, xi1 = p0.y - X1, xi2 = p1.x - X2;
     const double e0 = p1.y - U0, e1 = p2.x - U1, e2 = p2.y - U2;
@@ -34,18 +36,19 @@ __device__ __forceinline__ double adj_slot(const double2 p0, const double2 p1, c
     const double tq = __builtin_fma(e2, z2, __builtin_fma(e1, z1, e0 * z0));
     const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
     const double iL = rsq64<1>(L2);
-    const double q = tq * (iL * iL);
+    const double q = active ? tq * (iL * iL) : 0.0;
     const double sr = iL * one_minus_rsqrt1p(q);  // s/r = 1/L - 1/r
     const double ir = iL * rsq64<2>(1.0 + q);     // 1/r
     const double ir3 = ir * ir * ir;
     const double w0 = Vi * nj[0] - Vj * ni[0], w1 = Vi * nj[1] - Vj * ni[1], w2 = Vi * nj[2] - Vj * ni[2];
     const double yw = __builtin_fma(y2, w2, __builtin_fma(y1, w1, y0 * w0));
-    const double a = kb * sr, b = kb * (yw * ir3);
+    const double ka = active ? kb : 0.0;
+    const double a = ka * sr, b = ka * (yw * ir3);
     J[0] += a * w0 + b * y0;
     J[1] += a * w1 + b * y1;
     J[2] += a * w2 + b * y2;
     const double yn = __builtin_fma(y2, ni[2], __builtin_fma(y1, ni[1], y0 * ni[0]));
-    return h * Vj * sr * yn;
+    return active ? h * Vj * sr * yn : 0.0;
 }
 
 // Node tail of a reverse pass: body-force gradient, boundary masks, lam_u and next nu.
@@ -69,7 +72,37 @@ __device__ __forceinline__ void adj_node(const AdjArgs& A, const InstParams& P, 
     }
 }
 
-// Sliced layout: G lanes per node, partial sums meet in a shuffle butterfly.
+// Per-slot streams of one row (index ds) and the neighbour data they point at.
+struct AdjRow {
+    int64_t ds;
+    bool active;
+    double kb, g;
+    double2 p0, p1, p2;
+    double nj[3];
+    double Vj;
+};
+
+template <bool STIFF, bool VOLN>
+__device__ __forceinline__ void adj_load(const AdjArgs& A, const InstParams& P, int64_t ds, int64_t j, AdjRow& r)
+{
+    const double2* __restrict__ rec = reinterpret_cast<const double2*>(A.rec);
+    r.ds = ds;
+    r.active = A.k < static_cast<int64_t>(A.bstep[ds]);
+    r.p0 = rec[3 * j];
+    r.p1 = rec[3 * j + 1];
+    r.p2 = rec[3 * j + 2];
+    r.nj[0] = A.nu_in[3 * j];
+    r.nj[1] = A.nu_in[3 * j + 1];
+    r.nj[2] = A.nu_in[3 * j + 2];
+    r.kb = STIFF ? A.kslot[ds] : P.c;
+    r.Vj = VOLN ? A.vol[j] : P.volume;
+    r.g = A.grad[ds];
+}
+
+// Sliced layout: G lanes per node, partial sums meet in a shuffle butterfly.  Two rows
+// are loaded before either is computed (every slice's row count is even and the slot
+// arrays end with spare rows, so the loads stay in bounds); padding slots point at the
+// sentinel record, whose adjoint velocity is zero.
 template <int G, bool STIFF, bool VOLN>
 __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
 {
@@ -86,19 +119,23 @@ __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
     const double ni[3] = {A.nu_in[3 * node], A.nu_in[3 * node + 1], A.nu_in[3 * node + 2]};
     const double Vi = VOLN ? A.vol[node] : P.volume;
     const double h = A.dt / P.rho;
-    const int64_t base = A.slice_ptr[slice];
+    const int64_t base = wave_uniform(A.slice_ptr[slice]);
     const int T = A.slice_T[slice];
     double J[3] = {0.0, 0.0, 0.0};
-    for (int t = 0; t < T; ++t) {
-        const int64_t ds = base + static_cast<int64_t>(t) * kWave + lane;
-        if (!(A.k < static_cast<int64_t>(A.bstep[ds]))) continue;
-        const int32_t c = A.col[ds];
-        const int64_t j = c ^ (c >> 31);
-        const double2 p0 = rec[3 * j], p1 = rec[3 * j + 1], p2 = rec[3 * j + 2];
-        const double nj[3] = {A.nu_in[3 * j], A.nu_in[3 * j + 1], A.nu_in[3 * j + 2]};
-        const double kb = STIFF ? A.kslot[ds] : P.c;
-        const double Vj = VOLN ? A.vol[j] : P.volume;
-        A.grad[ds] += adj_slot(p0, p1, p2, o0.x, o0.y, o1.x, o1.y, o2.x, o2.y, nj, ni, Vi, Vj, kb, h, J);
+    for (int t = 0; t < T; t += 2) {
+        AdjRow r[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t ds = base + static_cast<int64_t>(t + u) * kWave + lane;
+            const int32_t c = A.col[ds];
+            adj_load<STIFF, VOLN>(A, P, ds, c ^ (c >> 31), r[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const double d = adj_slot(r[u].active, r[u].p0, r[u].p1, r[u].p2, o0.x, o0.y, o1.x, o1.y, o2.x, o2.y,
+                                      r[u].nj, ni, Vi, r[u].Vj, r[u].kb, h, J);
+            if (r[u].active) A.grad[r[u].ds] = r[u].g + d;
+        }
     }
 #pragma unroll
     for (int m = 1; m < G; m <<= 1)
@@ -107,7 +144,9 @@ __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
     adj_node(A, P, node, ni, J, h);
 }
 
-// Staged layout: one lane per node; neighbours are read from global memory.
+// Staged layout: one lane per node; neighbours are read from global memory, two rows
+// of a piece in flight (a piece's odd last row pairs with a padding row of the next
+// block: the entry array ends with spare rows, and padding entries are inactive).
 template <bool STIFF, bool VOLN>
 __global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
 {
@@ -121,21 +160,31 @@ __global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
     const double ni[3] = {A.nu_in[3 * node], A.nu_in[3 * node + 1], A.nu_in[3 * node + 2]};
     const double Vi = VOLN ? A.vol[node] : P.volume;
     const double h = A.dt / P.rho;
-    const int pb = A.slice_piece[slice], pe = A.slice_piece[slice + 1];
-    int64_t ent = A.slice_ptr[slice];
+    const int pb = __builtin_amdgcn_readfirstlane(A.slice_piece[slice]);
+    const int pe = __builtin_amdgcn_readfirstlane(A.slice_piece[slice + 1]);
+    int64_t ent = wave_uniform(A.slice_ptr[slice]);
     double J[3] = {0.0, 0.0, 0.0};
     for (int p = pb; p < pe; ++p) {
         const int2 m = A.pieces[p];
         const int T = (m.y >> 8) & 0xff;
-        for (int t = 0; t < T; ++t) {
-            const int64_t ds = ent + static_cast<int64_t>(t) * kWave + lane;
-            if (!(A.k < static_cast<int64_t>(A.bstep[ds]))) continue;
-            const int64_t j = m.x + (A.ent[ds] & 0x7fff) / 48;
-            const double2 p0 = rec[3 * j], p1 = rec[3 * j + 1], p2 = rec[3 * j + 2];
-            const double nj[3] = {A.nu_in[3 * j], A.nu_in[3 * j + 1], A.nu_in[3 * j + 2]};
-            const double kb = STIFF ? A.kslot[ds] : P.c;
-            const double Vj = VOLN ? A.vol[j] : P.volume;
-            A.grad[ds] += adj_slot(p0, p1, p2, o0.x, o0.y, o1.x, o1.y, o2.x, o2.y, nj, ni, Vi, Vj, kb, h, J);
+        for (int t = 0; t < T; t += 2) {
+            AdjRow r[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int64_t ds = ent + static_cast<int64_t>(t + u) * kWave + lane;
+                const int off = A.ent[ds] & 0x7fff;
+                // rows past T (and padding entries) are inactive; their neighbour index
+                // is clamped to the range start so the loads stay in bounds
+                const int64_t j = m.x + (t + u < T && off != kEntPad ? off / 48 : 0);
+                adj_load<STIFF, VOLN>(A, P, ds, j, r[u]);
+                if (t + u >= T) r[u].active = false;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const double d = adj_slot(r[u].active, r[u].p0, r[u].p1, r[u].p2, o0.x, o0.y, o1.x, o1.y, o2.x,
+                                          o2.y, r[u].nj, ni, Vi, r[u].Vj, r[u].kb, h, J);
+                if (r[u].active) A.grad[r[u].ds] = r[u].g + d;
+            }
         }
         ent += static_cast<int64_t>(T) * kWave;
     }

@@ -99,6 +99,8 @@ struct Inst {
     std::vector<int32_t> slice_piece;  // staged layout: first piece of each slice (+ end), local
     std::vector<uint8_t> ent_idx;    // staged layout: range index of every device slot
     std::vector<int64_t> rev_slot;   // user slot of the reverse bond (filled on first use)
+    bool k_sym = true;               // both slots of every bond carry the same stiffness
+    bool br_sym = true;              // both slots of every bond share the broken flag
     int64_t node_off = 0, n_pad = 0, slice_off = 0, nslices = 0, dslot_off = 0, n_dslots = 0;
 };
 
@@ -519,7 +521,7 @@ void upload_volumes(pd_ctx* ctx)
         ctx->vol.release();
         return;
     }
-    std::vector<double> V(static_cast<size_t>(ctx->nn), 0.0);
+    std::vector<double> V(static_cast<size_t>(ctx->nn) + 1, 0.0);  // entry nn: the sentinel record, volume 0
     for (auto& I : ctx->inst)
         for (int64_t l = 0; l < I.n_pad; ++l) {
             const int64_t u = I.perm[l];
@@ -599,6 +601,40 @@ void upload_state(pd_ctx* ctx, const Inst& I, const double* u, const double* v, 
     }
 }
 
+// Slot of the reverse bond (j, i) of every user slot (i, j); rows are sorted.
+const std::vector<int64_t>& reverse_slots(Inst& I)
+{
+    if (static_cast<int64_t>(I.rev_slot.size()) == I.nnz) return I.rev_slot;
+    I.rev_slot.assign(static_cast<size_t>(I.nnz), -1);
+    parallel_for(I.n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            for (int64_t b = I.row_ptr[i]; b < I.row_ptr[i + 1]; ++b) {
+                const int32_t j = I.col[b];
+                const auto first = I.col.begin() + I.row_ptr[j], last = I.col.begin() + I.row_ptr[j + 1];
+                const auto it = std::lower_bound(first, last, static_cast<int32_t>(i));
+                if (it != last && *it == i) I.rev_slot[b] = it - I.col.begin();
+            }
+    });
+    return I.rev_slot;
+}
+
+// Whether a per-slot array (nullptr: uniform) is equal on the two slots of every bond.
+template <typename T>
+bool bond_symmetric(Inst& I, const T* a)
+{
+    if (!a) return true;
+    const std::vector<int64_t>& rev = reverse_slots(I);
+    std::atomic<bool> ok{true};
+    parallel_for(I.nnz, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b)
+            if (rev[b] < 0 || a[b] != a[rev[b]]) {
+                ok = false;
+                return;
+            }
+    });
+    return ok;
+}
+
 // Break steps of one instance from its current flags: broken -> kBrokeBefore, intact ->
 // kNeverBroke (padding counts as broken).
 void init_break_steps(pd_ctx* ctx, const Inst& I)
@@ -609,9 +645,10 @@ void init_break_steps(pd_ctx* ctx, const Inst& I)
               "break-step init launch");
 }
 
-void upload_col(pd_ctx* ctx, const Inst& I, const uint8_t* broken)
+void upload_col(pd_ctx* ctx, Inst& I, const uint8_t* broken)
 {
     ctx->tape_valid = false;
+    I.br_sym = bond_symmetric(I, broken);
     if (ctx->mapping == PD_MAP_STAGED) {
         std::vector<uint16_t> e(static_cast<size_t>(I.n_dslots));
         parallel_for(I.n_dslots, [&](int64_t s0, int64_t s1) {
@@ -931,7 +968,7 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     upload_volumes(ctx);
     upload_body(ctx);
     for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
-        const Inst& I = ctx->inst[ii];
+        Inst& I = ctx->inst[ii];
         std::vector<double> zeros(static_cast<size_t>(3 * I.n), 0.0);
         upload_state(ctx, I, S ? S->u[ii].data() : zeros.data(), S ? S->v[ii].data() : nullptr,
                      S ? S->a[ii].data() : nullptr);
@@ -1120,23 +1157,6 @@ void reset_flags_after_state_change(pd_ctx* ctx, bool a_given)
 
 // ------------------------------------------------------------------ adjoint
 
-// Slot of the reverse bond (j, i) of every user slot (i, j); rows are sorted.
-const std::vector<int64_t>& reverse_slots(Inst& I)
-{
-    if (static_cast<int64_t>(I.rev_slot.size()) == I.nnz) return I.rev_slot;
-    I.rev_slot.assign(static_cast<size_t>(I.nnz), -1);
-    parallel_for(I.n, [&](int64_t i0, int64_t i1) {
-        for (int64_t i = i0; i < i1; ++i)
-            for (int64_t b = I.row_ptr[i]; b < I.row_ptr[i + 1]; ++b) {
-                const int32_t j = I.col[b];
-                const auto first = I.col.begin() + I.row_ptr[j], last = I.col.begin() + I.row_ptr[j + 1];
-                const auto it = std::lower_bound(first, last, static_cast<int32_t>(i));
-                if (it != last && *it == i) I.rev_slot[b] = it - I.col.begin();
-            }
-    });
-    return I.rev_slot;
-}
-
 void adjoint_checks(pd_ctx* ctx)
 {
     require_built(ctx);
@@ -1146,17 +1166,12 @@ void adjoint_checks(pd_ctx* ctx)
 }
 
 // The reverse pass gathers the transposed tangent over each node's own family, which
-// needs every bond's two slots to carry the same stiffness and broken flag.
-void check_symmetric(pd_ctx* ctx, Inst& I)
+// needs every bond's two slots to carry the same stiffness and broken flag (bonds that
+// break while stepping always break on both slots in the same pass).
+void check_symmetric(const Inst& I)
 {
-    const std::vector<int64_t>& rev = reverse_slots(I);
-    const std::vector<uint8_t> br = broken_of(ctx, I);
-    for (int64_t b = 0; b < I.nnz; ++b) {
-        if (rev[b] < 0) fail(PD_EINVAL, "internal: family is not symmetric");
-        if (!I.kslot.empty() && I.kslot[b] != I.kslot[rev[b]])
-            fail(PD_EINVAL, "the adjoint needs symmetric bond stiffness (slots (i,j) and (j,i) equal)");
-        if (br[b] != br[rev[b]]) fail(PD_EINVAL, "the adjoint needs both slots of a bond broken together");
-    }
+    if (!I.k_sym) fail(PD_EINVAL, "the adjoint needs symmetric bond stiffness (slots (i,j) and (j,i) equal)");
+    if (!I.br_sym) fail(PD_EINVAL, "the adjoint needs both slots of a bond broken together");
 }
 
 void launch_ec(pd_ctx* ctx, const StepArgs& A)
@@ -1312,6 +1327,7 @@ int pd_set_bond_stiffness(pd_ctx* ctx, int32_t inst, const double* k)
                 if (!std::isfinite(x)) fail(PD_EINVAL, "stiffness must be finite");
         }
         set_device(ctx);
+        I.k_sym = bond_symmetric(I, kv.empty() ? static_cast<const double*>(nullptr) : kv.data());
         I.kslot = std::move(kv);
         upload_stiffness(ctx, inst);
         ctx->a_valid = false;
@@ -1660,18 +1676,22 @@ int pd_adj_forward(pd_ctx* ctx, int64_t nsteps, int32_t ckpt_every)
             fail(PD_ERANGE, "step counter would exceed 2^31 - 1");
         set_device(ctx);
         Inst& I = ctx->inst[0];
-        check_symmetric(ctx, I);
+        check_symmetric(I);
         init_break_steps(ctx, I);
         const int64_t nn = ctx->nn;
         const size_t Rb = rec_bytes(nn), Vb = static_cast<size_t>(3 * nn) * sizeof(double);
         const int64_t C = (nsteps + ckpt_every - 1) / ckpt_every;
-        ctx->ck.alloc(static_cast<size_t>(C) * (Rb + Vb));
+        // with a checkpoint at every level nothing is recomputed and v is not needed
+        const size_t stride = Rb + (ckpt_every > 1 ? Vb : 0);
+        ctx->ck.alloc(static_cast<size_t>(C) * stride);
         const int64_t step0 = ctx->step;
         for (int64_t c = 0; c < C; ++c) {
-            char* dst = ctx->ck.as<char>() + static_cast<size_t>(c) * (Rb + Vb);
+            char* dst = ctx->ck.as<char>() + static_cast<size_t>(c) * stride;
             hip_check(hipMemcpyAsync(dst, ctx->rec[ctx->cur].p, Rb, hipMemcpyDeviceToDevice, ctx->stream),
                       "checkpoint copy");
-            hip_check(hipMemcpyAsync(dst + Rb, ctx->v.p, Vb, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint copy");
+            if (ckpt_every > 1)
+                hip_check(hipMemcpyAsync(dst + Rb, ctx->v.p, Vb, hipMemcpyDeviceToDevice, ctx->stream),
+                          "checkpoint copy");
             do_steps(ctx, std::min<int64_t>(ckpt_every, nsteps - c * ckpt_every));
         }
         ctx->tape_valid = true;
@@ -1704,21 +1724,22 @@ int pd_adj_backward(pd_ctx* ctx, int64_t m, const int64_t* sensors, const double
         const size_t Rb = rec_bytes(nn), Vb = static_cast<size_t>(3 * nn) * sizeof(double),
                      Nb = static_cast<size_t>(3 * (nn + 1)) * sizeof(double);
         const int64_t Lmax = std::min(S, T);
+        const size_t stride = Rb + (S > 1 ? Vb : 0);
         DevBuf traj, vwork, nu[2], lam, grad, gacc, base, sum, dsn, ddl;
-        traj.alloc(static_cast<size_t>(Lmax + 1) * Rb);
+        traj.alloc(static_cast<size_t>(Lmax) * Rb);  // levels 1 .. Lmax-1 of a segment (level 0: its checkpoint)
         vwork.alloc(Vb);
         nu[0].alloc(Nb);
         nu[1].alloc(Nb);
         lam.alloc(Vb);
-        grad.alloc(static_cast<size_t>(ns) * sizeof(double));
+        grad.alloc((static_cast<size_t>(ns) + kSpareRows * kWave) * sizeof(double));  // slot layout, spare rows
         gacc.alloc(static_cast<size_t>(nn) * sizeof(double));
         base.alloc(sizeof(int64_t));
         sum.alloc(sizeof(double));
         dsn.alloc(static_cast<size_t>(m) * sizeof(int64_t));
         ddl.alloc(static_cast<size_t>(3 * m) * sizeof(double));
         auto at = [](const DevBuf& b, size_t off) { return static_cast<char*>(b.p) + off; };
-        // every level carries the positions and the sentinel record
-        for (int64_t s = 0; s <= Lmax; ++s)
+        // every level carries the positions, the sentinel and the spare records
+        for (int64_t s = 1; s < Lmax; ++s)
             hip_check(hipMemcpyAsync(at(traj, s * Rb), ctx->rec[ctx->cur].p, Rb, hipMemcpyDeviceToDevice, st),
                       "trajectory init");
         for (DevBuf* b : {&nu[0], &nu[1], &lam, &grad, &gacc})
@@ -1756,25 +1777,30 @@ int pd_adj_backward(pd_ctx* ctx, int64_t m, const int64_t* sensors, const double
         const int64_t C = (T + S - 1) / S;
         for (int64_t c = C - 1; c >= 0; --c) {
             const int64_t s0 = step0 + c * S, len = std::min(S, T - c * S);
-            // recompute the segment with the forward kernel from its checkpoint
-            hip_check(launch_flags_at(ctx->bstep.as<int32_t>(), ctx->col.as<int32_t>(), ctx->ent.as<uint16_t>(), ns, s0,
-                                      st),
-                      "flags launch");
-            const char* ck = ctx->ck.as<char>() + static_cast<size_t>(c) * (Rb + Vb);
-            hip_check(hipMemcpyAsync(traj.p, ck, Rb, hipMemcpyDeviceToDevice, st), "checkpoint restore");
-            hip_check(hipMemcpyAsync(vwork.p, ck + Rb, Vb, hipMemcpyDeviceToDevice, st), "checkpoint restore");
-            hip_check(launch_set_i64(base.as<int64_t>(), s0, st), "base launch");
-            for (int64_t s = 0; s < len; ++s) {
-                StepArgs A = step_args(ctx, ctx->cur, 1 - ctx->cur, s);
-                A.rec_in = reinterpret_cast<const double*>(at(traj, s * Rb));
-                A.rec_out = reinterpret_cast<double*>(at(traj, (s + 1) * Rb));
-                A.v = vwork.as<double>();
-                A.step_base = base.as<int64_t>();  // breaks re-record the same passes
-                launch_ec(ctx, A);
+            const char* ck = ctx->ck.as<char>() + static_cast<size_t>(c) * stride;
+            auto level = [&](int64_t s) {
+                return reinterpret_cast<const double*>(s == 0 ? ck : at(traj, s * Rb));
+            };
+            if (len > 1) {
+                // recompute levels 1 .. len-1 with the forward kernel from the checkpoint
+                // (the reverse passes read levels 0 .. len-1)
+                hip_check(launch_flags_at(ctx->bstep.as<int32_t>(), ctx->col.as<int32_t>(), ctx->ent.as<uint16_t>(),
+                                          ns, s0, st),
+                          "flags launch");
+                hip_check(hipMemcpyAsync(vwork.p, ck + Rb, Vb, hipMemcpyDeviceToDevice, st), "checkpoint restore");
+                hip_check(launch_set_i64(base.as<int64_t>(), s0, st), "base launch");
+                for (int64_t s = 0; s + 1 < len; ++s) {
+                    StepArgs A = step_args(ctx, ctx->cur, 1 - ctx->cur, s);
+                    A.rec_in = level(s);
+                    A.rec_out = reinterpret_cast<double*>(at(traj, (s + 1) * Rb));
+                    A.v = vwork.as<double>();
+                    A.step_base = base.as<int64_t>();  // breaks re-record the same passes
+                    launch_ec(ctx, A);
+                }
             }
             // reverse passes of the segment, last first
             for (int64_t s = len - 1; s >= 0; --s) {
-                a.rec = reinterpret_cast<const double*>(at(traj, s * Rb));
+                a.rec = level(s);
                 a.nu_in = nu[nin].as<double>();
                 a.nu_out = nu[1 - nin].as<double>();
                 a.k = s0 + s;

@@ -55,3 +55,26 @@ def test_create_without_device_fails_cleanly(lib):
     h = C.c_void_p()
     rc = lib.pd_create(C.byref(h), 0, 0, None)
     assert rc in (0, -1, -3)
+
+
+def test_header_is_c99_and_links(tmp_path, lib):
+    """A C99 translation unit that takes the address of every declared entry point
+    compiles with -Wall -Werror and links against the library (nothing is called)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    from paper_2105_04150_amd import _binding as B
+    names = _declared()
+    src = tmp_path / "abi.c"
+    src.write_text("#include \"pdmi.h\"\n#include <stdio.h>\n"
+                   "int main(void) {\n  const void *f[] = {\n" +
+                   "".join(f"    (const void *)&{n},\n" for n in names) +
+                   "  };\n  printf(\"%d\\n\", (int)(sizeof f / sizeof f[0]));\n  return 0;\n}\n")
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(B.LIB_PATH)
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-Wno-pedantic", "-I",
+                        os.path.join(ROOT, "include"), str(src), "-o", str(exe), "-L", libdir, "-lpdmi",
+                        f"-Wl,-rpath,{libdir}", "-Wl,--allow-shlib-undefined"],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    assert r.returncode == 0, r.stdout

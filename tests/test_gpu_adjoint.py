@@ -78,6 +78,7 @@ CASES = [
     ("block10", {"steps": 700}, 37, "sliced", 16),                              # linear BC schedule
     ("block10", {"steps": 700}, 700, "sliced", 1),                              # one segment
     ("block10", {"dims": (9, 7, 6), "steps": 300}, 1, "staged", 1),             # checkpoint every step
+    ("adjoint_beam", {"dims": (30, 10, 8), "steps": 400}, 1, "sliced", 4),      # every level kept
 ]
 
 
