@@ -117,7 +117,8 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
     """Many uneven uncertainty-quantification beams advanced together, against the same
     instances advanced one problem at a time (a sample of them) on the same GPU.  The
     mapping and node order come from the library's autotuner run on four of the beams
-    (the full batch takes tens of seconds per layout build)."""
+    (the full batch takes tens of seconds per layout build).  Each beam's log-normal
+    stiffness field is passed as its node values (bond stiffness sqrt(k_i k_j))."""
     ws = pi.batch_instances(count=count, steps=steps)
     t0 = time.perf_counter()
     sub = [ws[b] for b in np.unique(np.linspace(0, count - 1, min(4, count)).round().astype(int))]
@@ -125,7 +126,7 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
     tun.build_family_batch([w.coords for w in sub], [w.horizon for w in sub], order="auto")
     tun.set_integrator("euler_cromer", ws[0].dt)
     for b, w in enumerate(sub):
-        P.apply_workload(tun, w, inst=b)
+        P.apply_workload(tun, w, inst=b, stiffness="node")
     tun.autotune(trial_steps=5)
     ti = tun.info()
     tun.close()
@@ -139,7 +140,7 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
     print(f"# batched: {count} families built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     sim.set_integrator("euler_cromer", ws[0].dt)
     for b, w in enumerate(ws):
-        P.apply_workload(sim, w, inst=b)
+        P.apply_workload(sim, w, inst=b, stiffness="node")
     setup = time.perf_counter() - t0
     info = sim.info()
     nnz = info["n_slots"]
@@ -151,7 +152,7 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
     seq_slots, seq_t = 0, 0.0
     print(f"# batched: {t_b * 1e3 / steps:.3f} ms/step; sequential sample next", file=sys.stderr, flush=True)
     for b in idx:
-        s1 = P.simulation_for(ws[b], lanes=lanes, mapping=mapping, order=order)
+        s1 = P.simulation_for(ws[b], lanes=lanes, mapping=mapping, order=order, stiffness="node")
         s1.step(20)
         s1.sync()
         seq_t += _timed(lambda: (s1.step(steps), s1.sync()), sync)
@@ -165,6 +166,25 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
             "setup_s": setup, "batched_rate": batched, "ms_per_step": t_b * 1e3 / steps,
             "sequential_rate": seq, "sequential_sample": [int(b) for b in idx],
             "batched_vs_sequential": batched / seq}
+
+
+def fp32_extra(P, pi, sync, workload: str, steps: int):
+    """The FP32 build (f32 bond arithmetic, f64 master displacement) on the headline
+    workload with the staged mapping, the only mapping it runs."""
+    w = pi.workload(workload)
+    w.order = "natural"
+    sim = P.simulation_for(w, precision=P.PD_FP32, mapping="staged")
+    info = sim.info()
+    sim.step(20)
+    sim.sync()
+    t = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    dev_ms = sim.last_step_ms() / steps
+    sim.close()
+    nnz = info["n_slots"]
+    return {"config": f"{workload}, FP32 build, staged mapping, natural order", "steps": steps,
+            "value": nnz * steps / t, "unit": "bond-updates/s", "ms_per_step": t * 1e3 / steps,
+            "avg_launch_ms": dev_ms,
+            "hbm_frac": info["model_bytes_per_step"] / (dev_ms / 1e3) / 1e9 / PEAK_HBM_GBS}
 
 
 def main():
@@ -281,6 +301,10 @@ def main():
     }
     sim.close()
     if not args.no_extras:
+        if args.precision == "f64":
+            out["fp32"] = fp32_extra(P, pi, torch_sync, args.workload, args.steps)
+            out["fp32"]["vs_fp64"] = out["fp32"]["value"] / value
+            print(f"# fp32 {out['fp32']}", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_extra(P, pi, torch_sync, args.adjoint_steps, 100)
         out["adjoint"]["adjoint_vs_headline_step"] = out["adjoint"]["adjoint_rate"] / value
         print(f"# adjoint {out['adjoint']}", file=sys.stderr, flush=True)

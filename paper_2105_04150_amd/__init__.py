@@ -62,6 +62,10 @@ class Simulation:
     def set_bond_stiffness(self, k, inst=0):
         B.pd_set_bond_stiffness(self.ctx, inst, k)
 
+    def set_node_stiffness(self, k_node, inst=0):
+        """Bond stiffness sqrt(k_i k_j) from a per-node field (None removes it)."""
+        B.pd_set_node_stiffness(self.ctx, inst, k_node)
+
     def break_bonds(self, broken, inst=0):
         B.pd_break_bonds(self.ctx, inst, broken)
 
@@ -138,12 +142,14 @@ class Simulation:
         return B.pd_last_step_ms(self.ctx)
 
 
-def apply_workload(sim: Simulation, w, inst: int = 0, row_ptr=None, col=None) -> None:
+def apply_workload(sim: Simulation, w, inst: int = 0, row_ptr=None, col=None, stiffness: str = "slot") -> None:
     """Install a synthetic workload's material, BCs, notch, stiffness field and loads.
 
     ``w`` is a ``pd_inputs.Workload``; its family must already be built on ``sim``.
     The notch mask and stiffness field are input data generated from the library's own
-    family (pd_get_family).
+    family (pd_get_family).  ``stiffness``: "slot" passes the field as per-slot values
+    c exp((g_i + g_j)/2); "node" passes the node values c exp(g_i), whose geometric
+    mean over a bond is the same field.
     """
     import pd_inputs as pi
     if row_ptr is None:
@@ -156,19 +162,22 @@ def apply_workload(sim: Simulation, w, inst: int = 0, row_ptr=None, col=None) ->
     if w.stiffness_field is not None:
         sig, ell, seed = w.stiffness_field
         g = pi.gaussian_node_field(w.dims, sig, ell, seed)
-        sim.set_bond_stiffness(pi.slot_stiffness(w.c, g, row_ptr, col), inst=inst)
+        if stiffness == "node":
+            sim.set_node_stiffness(w.c * np.exp(g), inst=inst)
+        else:
+            sim.set_bond_stiffness(pi.slot_stiffness(w.c, g, row_ptr, col), inst=inst)
     if w.body_force is not None:
         bhat, bmag = w.body_force
         sim.set_body_force(bhat, bmag, inst=inst)
 
 
 def simulation_for(w, precision: int = PD_FP64, lanes: int = 0, device: int = 0, order=None,
-                   mapping="sliced") -> Simulation:
+                   mapping="sliced", stiffness: str = "slot") -> Simulation:
     """A single-instance Simulation set up for workload ``w`` (family built on the host)."""
     sim = Simulation(device, precision)
     if lanes or mapping != "sliced":
         sim.set_mapping(mapping, lanes)
     sim.build_family(w.coords, w.horizon, order or w.order)
     sim.set_integrator(w.scheme, w.dt)
-    apply_workload(sim, w)
+    apply_workload(sim, w, stiffness=stiffness)
     return sim

@@ -25,6 +25,7 @@ PD_MAP_SLICED, PD_MAP_STAGED = 0, 1
 SYMBOLS = [
     "pd_create", "pd_destroy", "pd_last_error", "pd_build_family", "pd_build_family_batch",
     "pd_num_instances", "pd_instance_size", "pd_get_family", "pd_set_material", "pd_set_bond_stiffness",
+    "pd_set_node_stiffness",
     "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_body_force", "pd_set_integrator",
     "pd_step", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
@@ -72,6 +73,7 @@ def load() -> C.CDLL:
         "pd_get_family": [P, i32, P, P, P],
         "pd_set_material": [P, i32, P],
         "pd_set_bond_stiffness": [P, i32, P],
+        "pd_set_node_stiffness": [P, i32, P],
         "pd_break_bonds": [P, i32, P],
         "pd_set_bcs": [P, i32, i64, P, C.c_int, C.c_int, P, C.c_int],
         "pd_clear_bcs": [P, i32],
@@ -186,6 +188,11 @@ def pd_set_material(ctx, inst: int, rho: float, c: float, s0: float, eta: float 
 def pd_set_bond_stiffness(ctx, inst: int, k) -> None:
     kk = _f64(k)
     _check(ctx, load().pd_set_bond_stiffness(ctx, inst, _p(kk)))
+
+
+def pd_set_node_stiffness(ctx, inst: int, k_node) -> None:
+    kk = _f64(k_node)
+    _check(ctx, load().pd_set_node_stiffness(ctx, inst, _p(kk)))
 
 
 def pd_break_bonds(ctx, inst: int, broken) -> None:

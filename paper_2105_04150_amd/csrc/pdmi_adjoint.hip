@@ -82,8 +82,13 @@ struct AdjRow {
     double Vj;
 };
 
-template <bool STIFF, bool VOLN>
-__device__ __forceinline__ void adj_load(const AdjArgs& A, const InstParams& P, int64_t ds, int64_t j, AdjRow& r)
+// Stiffness of a slot: KM = kKUniform (c), kKSlot (per-slot array) or kKNode
+// (sqrt(k_i) sqrt(k_j) from per-node factors; ai = sqrt(k_i) of the own node).
+constexpr int kKUniform = 0, kKSlot = 1, kKNode = 2;
+
+template <int KM, bool VOLN>
+__device__ __forceinline__ void adj_load(const AdjArgs& A, const InstParams& P, double ai, int64_t ds, int64_t j,
+                                         AdjRow& r)
 {
     const double2* __restrict__ rec = reinterpret_cast<const double2*>(A.rec);
     r.ds = ds;
@@ -94,7 +99,7 @@ __device__ __forceinline__ void adj_load(const AdjArgs& A, const InstParams& P, 
     r.nj[0] = A.nu_in[3 * j];
     r.nj[1] = A.nu_in[3 * j + 1];
     r.nj[2] = A.nu_in[3 * j + 2];
-    r.kb = STIFF ? A.kslot[ds] : P.c;
+    r.kb = KM == kKSlot ? A.kslot[ds] : KM == kKNode ? ai * A.na[j] : P.c;
     r.Vj = VOLN ? A.vol[j] : P.volume;
     r.g = A.grad[ds];
 }
@@ -103,7 +108,7 @@ __device__ __forceinline__ void adj_load(const AdjArgs& A, const InstParams& P, 
 // are loaded before either is computed (every slice's row count is even and the slot
 // arrays end with spare rows, so the loads stay in bounds); padding slots point at the
 // sentinel record, whose adjoint velocity is zero.
-template <int G, bool STIFF, bool VOLN>
+template <int G, int KM, bool VOLN>
 __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
 {
     constexpr int W = kWave / G;
@@ -118,6 +123,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
     const double2 o0 = rec[3 * node], o1 = rec[3 * node + 1], o2 = rec[3 * node + 2];
     const double ni[3] = {A.nu_in[3 * node], A.nu_in[3 * node + 1], A.nu_in[3 * node + 2]};
     const double Vi = VOLN ? A.vol[node] : P.volume;
+    const double ai = KM == kKNode ? A.na[node] : 0.0;
     const double h = A.dt / P.rho;
     const int64_t base = wave_uniform(A.slice_ptr[slice]);
     const int T = A.slice_T[slice];
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
         for (int u = 0; u < 2; ++u) {
             const int64_t ds = base + static_cast<int64_t>(t + u) * kWave + lane;
             const int32_t c = A.col[ds];
-            adj_load<STIFF, VOLN>(A, P, ds, c ^ (c >> 31), r[u]);
+            adj_load<KM, VOLN>(A, P, ai, ds, c ^ (c >> 31), r[u]);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -147,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
 // Staged layout: one lane per node; neighbours are read from global memory, two rows
 // of a piece in flight (a piece's odd last row pairs with a padding row of the next
 // block: the entry array ends with spare rows, and padding entries are inactive).
-template <bool STIFF, bool VOLN>
+template <int KM, bool VOLN>
 __global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
 {
     const int lane = threadIdx.x;
@@ -159,6 +165,7 @@ __global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
     const double2 o0 = rec[3 * node], o1 = rec[3 * node + 1], o2 = rec[3 * node + 2];
     const double ni[3] = {A.nu_in[3 * node], A.nu_in[3 * node + 1], A.nu_in[3 * node + 2]};
     const double Vi = VOLN ? A.vol[node] : P.volume;
+    const double ai = KM == kKNode ? A.na[node] : 0.0;
     const double h = A.dt / P.rho;
     const int pb = __builtin_amdgcn_readfirstlane(A.slice_piece[slice]);
     const int pe = __builtin_amdgcn_readfirstlane(A.slice_piece[slice + 1]);
@@ -176,7 +183,7 @@ __global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
                 // rows past T (and padding entries) are inactive; their neighbour index
                 // is clamped to the range start so the loads stay in bounds
                 const int64_t j = m.x + (t + u < T && off != kEntPad ? off / 48 : 0);
-                adj_load<STIFF, VOLN>(A, P, ds, j, r[u]);
+                adj_load<KM, VOLN>(A, P, ai, ds, j, r[u]);
                 if (t + u >= T) r[u].active = false;
             }
 #pragma unroll
@@ -255,29 +262,34 @@ __global__ void set_i64_kernel(int64_t* p, int64_t v)
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-template <int G, bool STIFF, bool VOLN>
+template <int G, int KM, bool VOLN>
 void adj_launch_sliced(const AdjArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((adjoint_sliced<G, STIFF, VOLN>), dim3(static_cast<unsigned>((a.nslices + 3) / 4)),
+    hipLaunchKernelGGL((adjoint_sliced<G, KM, VOLN>), dim3(static_cast<unsigned>((a.nslices + 3) / 4)),
                        dim3(kBlock), 0, s, a);
 }
 
-template <bool STIFF, bool VOLN>
-hipError_t adj_launch_sv(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
+template <int KM, bool VOLN>
+hipError_t adj_launch_kv(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
 {
     if (staged) {
-        hipLaunchKernelGGL((adjoint_staged<STIFF, VOLN>), dim3(static_cast<unsigned>(a.nslices)), dim3(kWave), 0, s,
-                           a);
+        hipLaunchKernelGGL((adjoint_staged<KM, VOLN>), dim3(static_cast<unsigned>(a.nslices)), dim3(kWave), 0, s, a);
         return hipGetLastError();
     }
     switch (lanes) {
-    case 1: adj_launch_sliced<1, STIFF, VOLN>(a, s); break;
-    case 4: adj_launch_sliced<4, STIFF, VOLN>(a, s); break;
-    case 16: adj_launch_sliced<16, STIFF, VOLN>(a, s); break;
-    case 64: adj_launch_sliced<64, STIFF, VOLN>(a, s); break;
+    case 1: adj_launch_sliced<1, KM, VOLN>(a, s); break;
+    case 4: adj_launch_sliced<4, KM, VOLN>(a, s); break;
+    case 16: adj_launch_sliced<16, KM, VOLN>(a, s); break;
+    case 64: adj_launch_sliced<64, KM, VOLN>(a, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int KM>
+hipError_t adj_launch_k(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
+{
+    return a.vol ? adj_launch_kv<KM, true>(a, staged, lanes, s) : adj_launch_kv<KM, false>(a, staged, lanes, s);
 }
 
 unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
@@ -287,9 +299,9 @@ unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) /
 hipError_t launch_adjoint(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
 {
     if (a.nslices <= 0) return hipSuccess;
-    const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
-    if (stiff) return voln ? adj_launch_sv<true, true>(a, staged, lanes, s) : adj_launch_sv<true, false>(a, staged, lanes, s);
-    return voln ? adj_launch_sv<false, true>(a, staged, lanes, s) : adj_launch_sv<false, false>(a, staged, lanes, s);
+    if (a.kslot) return adj_launch_k<kKSlot>(a, staged, lanes, s);
+    if (a.na) return adj_launch_k<kKNode>(a, staged, lanes, s);
+    return adj_launch_k<kKUniform>(a, staged, lanes, s);
 }
 
 hipError_t launch_bstep_init(int32_t* bstep, const int32_t* col, const uint16_t* ent, int64_t ns, hipStream_t s)

@@ -85,6 +85,7 @@ struct Inst {
     double rho = 1.0, c = 1.0, s0 = std::numeric_limits<double>::infinity(), eta = 0.0, volume = 1.0;
     std::vector<double> vols;        // user order; empty = uniform
     std::vector<double> kslot;       // user CSR order; empty = c
+    std::vector<double> knode;       // user order, per-node stiffness (bond: sqrt(k_i k_j)); empty = none
     std::vector<double> bhat;        // user order n*3; empty = none
     double bmag = 0.0;
     std::vector<uint8_t> bc_kind, bc_sched;  // n*3
@@ -128,13 +129,14 @@ struct pd_ctx {
     bool use_graphs = true;
 
     int64_t nn = 0, ns = 0, nslices = 0;
-    bool has_stiff = false, has_vol = false, has_body = false;
+    bool has_stiff = false, has_vol = false, has_body = false, has_knode = false;
     DevBuf rec[2], um[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc,
         step_base, status, phi, pieces, slice_piece, ent;
 
     // adjoint: per-slot break steps (recorded by every step while allocated) and the
     // (u, v) checkpoints of the last recorded forward run
     DevBuf bstep, ck;
+    DevBuf na, nw;                   // per-node stiffness: sqrt(k_i) and sqrt(k_j) V_j (entry nn: 0)
     bool tape_valid = false;
     int64_t tape_step0 = 0, tape_nsteps = 0, tape_every = 0;
 
@@ -504,13 +506,51 @@ void upload_stiffness(pd_ctx* ctx, int32_t only = -1)
         if (!fresh && only >= 0 && static_cast<int32_t>(ii) != only) continue;
         const Inst& I = ctx->inst[ii];
         std::vector<double> k(static_cast<size_t>(I.n_dslots), 0.0);
+        std::vector<double> sq;  // a per-node field in per-slot mode: sqrt(k_i) sqrt(k_j)
+        std::vector<int32_t> row;
+        if (I.kslot.empty() && !I.knode.empty()) {
+            sq.resize(static_cast<size_t>(I.n));
+            for (int64_t i = 0; i < I.n; ++i) sq[i] = std::sqrt(I.knode[i]);
+            row.resize(static_cast<size_t>(I.nnz));
+            for (int64_t i = 0; i < I.n; ++i)
+                for (int64_t b = I.row_ptr[i]; b < I.row_ptr[i + 1]; ++b) row[b] = static_cast<int32_t>(i);
+        }
         for (int64_t s = 0; s < I.n_dslots; ++s) {
             const int32_t b = I.dslot_user[s];
-            if (b >= 0) k[s] = I.kslot.empty() ? I.c : I.kslot[b];
+            if (b < 0) continue;
+            k[s] = !I.kslot.empty() ? I.kslot[b] : !sq.empty() ? sq[row[b]] * sq[I.col[b]] : I.c;
         }
         upload(ctx->kslot, k.data(), k.size() * sizeof(double), I.dslot_off * sizeof(double), ctx->stream);
         sync(ctx);
     }
+}
+
+// Per-node stiffness factors when no instance carries a per-slot field: na = sqrt(k_i)
+// (sqrt(c) for instances without a node field), nw = na V; padding and the sentinel 0.
+void upload_node_weights(pd_ctx* ctx)
+{
+    ctx->tape_valid = false;
+    bool any = false;
+    for (auto& I : ctx->inst) any |= !I.knode.empty();
+    ctx->has_knode = any && !ctx->has_stiff;
+    if (!ctx->has_knode) {
+        ctx->na.release();
+        ctx->nw.release();
+        return;
+    }
+    std::vector<double> a(static_cast<size_t>(ctx->nn) + 1, 0.0), w(static_cast<size_t>(ctx->nn) + 1, 0.0);
+    for (auto& I : ctx->inst)
+        for (int64_t l = 0; l < I.n_pad; ++l) {
+            const int64_t p = I.perm[l];
+            if (p < 0) continue;
+            const double sk = std::sqrt(I.knode.empty() ? I.c : I.knode[p]);
+            a[I.node_off + l] = sk;
+            w[I.node_off + l] = sk * (I.vols.empty() ? I.volume : I.vols[p]);
+        }
+    ctx->na.alloc(a.size() * sizeof(double));
+    ctx->nw.alloc(w.size() * sizeof(double));
+    upload(ctx->na, a.data(), a.size() * sizeof(double), 0, ctx->stream);
+    upload(ctx->nw, w.data(), w.size() * sizeof(double), 0, ctx->stream);
 }
 
 void upload_volumes(pd_ctx* ctx)
@@ -966,6 +1006,7 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     upload_bcs(ctx);
     upload_stiffness(ctx);
     upload_volumes(ctx);
+    upload_node_weights(ctx);
     upload_body(ctx);
     for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
         Inst& I = ctx->inst[ii];
@@ -1036,6 +1077,8 @@ StepArgs step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
     A.col = ctx->col.as<int32_t>();
     A.kslot = ctx->has_stiff ? ctx->kslot.as<double>() : nullptr;
     A.vol = ctx->has_vol ? ctx->vol.as<double>() : nullptr;
+    A.na = ctx->has_knode ? ctx->na.as<double>() : nullptr;
+    A.nw = ctx->has_knode ? ctx->nw.as<double>() : nullptr;
     A.bhat = ctx->has_body ? ctx->bhat.as<double>() : nullptr;
     A.slice_ptr = ctx->slice_ptr.as<int64_t>();
     A.slice_T = ctx->slice_T.as<int32_t>();
@@ -1308,6 +1351,7 @@ int pd_set_material(pd_ctx* ctx, int32_t inst, const pd_material* m)
         upload_params(ctx);
         upload_volumes(ctx);
         if (ctx->has_stiff) upload_stiffness(ctx, inst);
+        upload_node_weights(ctx);
         ctx->a_valid = false;
         ctx->vv_ahead = false;
         ctx->drop_graphs();
@@ -1328,8 +1372,34 @@ int pd_set_bond_stiffness(pd_ctx* ctx, int32_t inst, const double* k)
         }
         set_device(ctx);
         I.k_sym = bond_symmetric(I, kv.empty() ? static_cast<const double*>(nullptr) : kv.data());
+        const bool mode_change = kv.empty() != I.kslot.empty() || !I.knode.empty();
         I.kslot = std::move(kv);
-        upload_stiffness(ctx, inst);
+        I.knode.clear();
+        upload_stiffness(ctx, mode_change ? -1 : inst);
+        upload_node_weights(ctx);
+        ctx->a_valid = false;
+        ctx->vv_ahead = false;
+        ctx->drop_graphs();
+    });
+}
+
+int pd_set_node_stiffness(pd_ctx* ctx, int32_t inst, const double* k_node)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        std::vector<double> kn;
+        if (k_node) {
+            kn.assign(k_node, k_node + I.n);
+            for (double x : kn)
+                if (!(x >= 0.0) || !std::isfinite(x)) fail(PD_EINVAL, "node stiffness must be finite and >= 0");
+        }
+        set_device(ctx);
+        I.knode = std::move(kn);
+        I.kslot.clear();
+        I.k_sym = true;  // sqrt(k_i k_j) is the same on both slots of a bond
+        upload_stiffness(ctx);
+        upload_node_weights(ctx);
         ctx->a_valid = false;
         ctx->vv_ahead = false;
         ctx->drop_graphs();
@@ -1762,6 +1832,7 @@ int pd_adj_backward(pd_ctx* ctx, int64_t m, const int64_t* sensors, const double
         a.slice_piece = ctx->slice_piece.as<int32_t>();
         a.kslot = ctx->has_stiff ? ctx->kslot.as<double>() : nullptr;
         a.vol = ctx->has_vol ? ctx->vol.as<double>() : nullptr;
+        a.na = ctx->has_knode ? ctx->na.as<double>() : nullptr;
         a.bhat = ctx->has_body ? ctx->bhat.as<double>() : nullptr;
         a.slice_ptr = ctx->slice_ptr.as<int64_t>();
         a.slice_T = ctx->slice_T.as<int32_t>();
@@ -1871,6 +1942,7 @@ int pd_get_info(const pd_ctx* ctx, pd_info* info)
     // reads and writes the f32 displacement copy (12 + 12 B)
     double per_node = 24.0 + 4.0 * 24.0 + (ctx->scheme == PD_VELOCITY_VERLET ? 2.0 * 24.0 : 0.0) +
                       (ctx->precision == PD_FP32 ? 24.0 : 0.0);
+    per_node += ctx->has_knode ? 16.0 : 0.0;  // per-node stiffness factors (own and neighbour weight)
     info->model_bytes_per_step = static_cast<double>(nnz) * (4.0 + (ctx->has_stiff ? 8.0 : 0.0)) +
                                  static_cast<double>(n) * per_node;
     return PD_OK;

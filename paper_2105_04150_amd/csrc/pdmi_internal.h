@@ -19,7 +19,10 @@
 //                                 slice's node w.  col >= 0: intact bond to device node col;
 //                                 col < 0: ~col is the neighbour of a broken bond, or the
 //                                 sentinel nn for padding.
-//   stiffness     kslot[ns]       f64 per slot, same layout (only with a stiffness field)
+//   stiffness     kslot[ns]       f64 per slot, same layout (only with a per-slot stiffness field)
+//   node stiffness na[nn+1], nw[nn+1]  f64 per node (only with a per-node stiffness field,
+//                                 bond stiffness sqrt(k_i k_j)): na = sqrt(k_i), nw = sqrt(k_j) V_j;
+//                                 entry nn (the sentinel) is 0
 //   slices        slice_ptr/T/inst first entry, row count and instance of every slice
 //
 // Staged layout (one lane per node, 64 nodes per slice).  The neighbours of a slice are
@@ -86,6 +89,8 @@ struct StepArgs {
     int32_t* col;
     const double* kslot;        // nullptr unless STIFF
     const double* vol;          // nullptr unless per-node volumes
+    const double* na;           // nullptr unless per-node stiffness (then kslot is nullptr)
+    const double* nw;
     const double* bhat;         // bhat + d*nn, nullptr without body forces
     const int64_t* slice_ptr;
     const int32_t* slice_T;
@@ -161,6 +166,7 @@ struct AdjArgs {
     const int32_t* slice_piece;
     const double* kslot;
     const double* vol;
+    const double* na;           // per-node stiffness factors sqrt(k_i) (or nullptr)
     const double* bhat;
     const int64_t* slice_ptr;
     const int32_t* slice_T;

@@ -177,7 +177,7 @@ __device__ __forceinline__ void node_update(const StepArgs& A, const InstParams&
         for (int d = 0; d < 3; ++d) A.a[d * nn + node] = an[d];
 }
 
-template <int G, int MODE, bool STIFF, bool VOLN>
+template <int G, int MODE, bool STIFF, bool VOLN, bool KNODE>
 __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
 {
     constexpr int W = kWave / G;
@@ -205,6 +205,8 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
     const char* __restrict__ colb = reinterpret_cast<const char*>(A.col + base);
     const char* __restrict__ kb = STIFF ? reinterpret_cast<const char*>(A.kslot + base) : nullptr;
     const double* __restrict__ volp = A.vol;
+    const double* __restrict__ nwp = A.nw;
+    const double ai = KNODE ? A.na[node] : 0.0;  // own stiffness factor
     const uint32_t lane4 = static_cast<uint32_t>(lane) * 4u;
     const double cv = P.c * P.volume;
 
@@ -232,7 +234,9 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
                 p[u][0] = *reinterpret_cast<const double2*>(rj);
                 p[u][1] = *reinterpret_cast<const double2*>(rj + 16);
                 p[u][2] = *reinterpret_cast<const double2*>(rj + 32);
-                if (STIFF || VOLN) {
+                if (KNODE) {
+                    kv[u] = ai * nwp[j];  // sqrt(k_i) sqrt(k_j) V_j
+                } else if (STIFF || VOLN) {
                     double k = P.c;
                     if (STIFF) {
                         const uint32_t off = static_cast<uint32_t>(t + u) * (kWave * 8u) + 2u * lane4;
@@ -275,14 +279,15 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
 // path once per slice instead of once per slot.  Per-slot stiffness, when present,
 // streams from global memory one piece ahead.  Rows are processed in pairs so the LDS
 // reads of one row overlap the arithmetic of the other; an odd last row runs alone.
-template <bool FP32, int MODE, bool STIFF, bool VOLN>
+template <bool FP32, int MODE, bool STIFF, bool VOLN, bool KNODE>
 __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __restrict__ pieces,
                                                          const int32_t* __restrict__ slice_piece,
                                                          const int64_t* __restrict__ slice_ptr)
 {
     constexpr int kRecChunks = kStageChunks + 3;             // staged records, then the sentinel
     constexpr int kEntChunks = kPieceRows * kWave * 2 / 16;  // 16-byte chunks of entries
-    constexpr int kVolWords = VOLN ? (kEntPad / 48 + 2) / 2 * 2 : 0;  // staged volumes (doubles), sentinel last
+    constexpr bool WSTAGE = VOLN || KNODE;  // a per-node weight is staged beside the records
+    constexpr int kVolWords = WSTAGE ? (kEntPad / 48 + 2) / 2 * 2 : 0;  // staged weights (doubles), sentinel last
     constexpr int kLds = kRecChunks + kEntChunks + kVolWords / 2;
     static_assert(kStageChunks == 4 * kWave && kEntChunks == kWave, "four record loads and one entry load");
     __shared__ double2 lds[kLds];
@@ -313,7 +318,10 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
 
     // sentinel record (padding entries point at it), volume 0
     if (lane < 3) lrec[kStageChunks + lane] = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
-    if (VOLN && lane == 0) lvol[kEntPad / 48] = 0.0;
+    if (WSTAGE && lane == 0) lvol[kEntPad / 48] = 0.0;
+    // staged weight: V_j, or sqrt(k_j) V_j with per-node stiffness (times the own sqrt(k_i))
+    const double* __restrict__ wsrc = KNODE ? A.nw : A.vol;
+    const double ai = KNODE ? A.na[node] : 0.0;
 
     const int p0 = __builtin_amdgcn_readfirstlane(slice_piece[slice]);
     const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
@@ -338,11 +346,11 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
         r2 = rs[2 * kWave];
         r3 = rs[3 * kWave];
         e0 = ent2[e / 8 + lane];
-        if (VOLN) {
+        if (WSTAGE) {
             const int len = m.y & 0xff;
             vlen = len;
-            vs0 = A.vol[m.x + min(lane, len - 1)];
-            vs1 = A.vol[m.x + min(lane + kWave, len - 1)];
+            vs0 = wsrc[m.x + min(lane, len - 1)];
+            vs1 = wsrc[m.x + min(lane + kWave, len - 1)];
         }
         if (STIFF)
 #pragma unroll
@@ -354,7 +362,7 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
         lrec[lane + 2 * kWave] = r2;
         lrec[lane + 3 * kWave] = r3;
         reinterpret_cast<double2*>(lent)[lane] = e0;
-        if (VOLN) {
+        if (WSTAGE) {
             if (lane < vlen) lvol[lane] = vs0;
             if (lane + kWave < vlen) lvol[lane + kWave] = vs1;
         }
@@ -366,9 +374,14 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
         const double2 q2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
         const int32_t c = (e & 0x8000) ? -1 : 0;  // sign carries the alive flag
         double kv = cv;
-        if (STIFF || VOLN) kv = (STIFF ? kst : P.c) * (VOLN ? lvol[(off * 0xAAABu) >> 21] : P.volume);  // off / 48
+        const uint32_t widx = (off * 0xAAABu) >> 21;  // off / 48
+        if (KNODE)
+            kv = ai * lvol[widx];
+        else if (STIFF || VOLN)
+            kv = (STIFF ? kst : P.c) * (VOLN ? lvol[widx] : P.volume);
         if (FP32)
-            return slot_force32(c, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2, (STIFF || VOLN) ? static_cast<float>(kv) : cvf,
+            return slot_force32(c, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2,
+                                (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : cvf,
                                 q0f, Ff0, Ff1, Ff2);
         return slot_force(c, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2);
     };
@@ -509,15 +522,15 @@ __global__ void advance_kernel(int64_t* step_base, int64_t by)
     if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += by;
 }
 
-template <int G, bool STIFF, bool VOLN>
+template <int G, bool STIFF, bool VOLN, bool KNODE = false>
 hipError_t launch_step_gsv(const StepArgs& a, int mode, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>((a.nslices + 3) / 4)), block(kBlock);
     switch (mode) {
-    case kModeEC: hipLaunchKernelGGL((step_f64<G, kModeEC, STIFF, VOLN>), grid, block, 0, s, a); break;
-    case kModeVV: hipLaunchKernelGGL((step_f64<G, kModeVV, STIFF, VOLN>), grid, block, 0, s, a); break;
-    case kModeVVInit: hipLaunchKernelGGL((step_f64<G, kModeVVInit, STIFF, VOLN>), grid, block, 0, s, a); break;
-    case kModeFE: hipLaunchKernelGGL((step_f64<G, kModeFE, STIFF, VOLN>), grid, block, 0, s, a); break;
+    case kModeEC: hipLaunchKernelGGL((step_f64<G, kModeEC, STIFF, VOLN, KNODE>), grid, block, 0, s, a); break;
+    case kModeVV: hipLaunchKernelGGL((step_f64<G, kModeVV, STIFF, VOLN, KNODE>), grid, block, 0, s, a); break;
+    case kModeVVInit: hipLaunchKernelGGL((step_f64<G, kModeVVInit, STIFF, VOLN, KNODE>), grid, block, 0, s, a); break;
+    case kModeFE: hipLaunchKernelGGL((step_f64<G, kModeFE, STIFF, VOLN, KNODE>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -527,6 +540,7 @@ template <int G>
 hipError_t launch_step_g(const StepArgs& a, int mode, bool stiff, hipStream_t s)
 {
     const bool voln = a.vol != nullptr;
+    if (a.nw) return launch_step_gsv<G, false, false, true>(a, mode, s);  // per-node stiffness (volumes folded in)
     if (stiff) return voln ? launch_step_gsv<G, true, true>(a, mode, s) : launch_step_gsv<G, true, false>(a, mode, s);
     return voln ? launch_step_gsv<G, false, true>(a, mode, s) : launch_step_gsv<G, false, false>(a, mode, s);
 }
@@ -572,13 +586,13 @@ hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool FP32, bool STIFF, bool VOLN>
+template <bool FP32, bool STIFF, bool VOLN, bool KNODE = false>
 hipError_t launch_staged_sv(const StepArgs& a, int mode, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>(a.nslices)), block(kWave);
     switch (mode) {
 #define PD_L(M)                                                                                   \
-    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN>), grid, block, 0, s, a, a.pieces, a.slice_piece, \
+    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN, KNODE>), grid, block, 0, s, a, a.pieces, a.slice_piece, \
                        a.slice_ptr)
     case kModeEC: PD_L(kModeEC); break;
     case kModeVV: PD_L(kModeVV); break;
@@ -594,6 +608,7 @@ template <bool FP32>
 hipError_t launch_staged_p(const StepArgs& a, int mode, hipStream_t s)
 {
     const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
+    if (a.nw) return launch_staged_sv<FP32, false, false, true>(a, mode, s);  // per-node stiffness
     if (stiff)
         return voln ? launch_staged_sv<FP32, true, true>(a, mode, s) : launch_staged_sv<FP32, true, false>(a, mode, s);
     return voln ? launch_staged_sv<FP32, false, true>(a, mode, s) : launch_staged_sv<FP32, false, false>(a, mode, s);
