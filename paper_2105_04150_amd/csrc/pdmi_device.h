@@ -21,15 +21,16 @@ __device__ __forceinline__ double rsq64(double x)
     return y;
 }
 
-// 1 - (1+q)^(-1/2).  Series q/2 - 3q^2/8 + 5q^3/16 - 35q^4/128 + 63q^5/256 - 231q^6/1024;
+// 1 - (1+q)^(-1/2).  Series q/2 - 3q^2/8 + 5q^3/16 - 35q^4/128 + 63q^5/256 - 231q^6/1024
+// (c6, c5 are the two innermost coefficients; callers in hot loops pass them from
+// registers, since an FMA with two constant operands costs two extra moves here);
 // the first omitted term, 429q^7/2048, is below 2e-15 of the sum for |q| < 4e-3.  Larger
 // |q| (strongly compressed or broken bonds) takes the closed form, whose cancellation
 // costs at most 1e-16/|q| < 3e-14 relative there.
-__device__ __forceinline__ double one_minus_rsqrt1p(double q)
+__device__ __forceinline__ double one_minus_rsqrt1p(double q, double c6 = -231.0 / 1024.0, double c5 = 63.0 / 256.0)
 {
     if (fabs(q) < 4.0e-3) {
-        double p = -231.0 / 1024.0;
-        p = __builtin_fma(p, q, 63.0 / 256.0);
+        double p = __builtin_fma(c6, q, c5);
         p = __builtin_fma(p, q, -35.0 / 128.0);
         p = __builtin_fma(p, q, 5.0 / 16.0);
         p = __builtin_fma(p, q, -3.0 / 8.0);
