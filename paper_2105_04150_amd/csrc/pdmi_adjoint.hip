@@ -151,8 +151,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
 }
 
 // Staged layout: one lane per node; neighbours are read from global memory, two rows
-// of a piece in flight (a piece's odd last row pairs with a padding row of the next
-// block: the entry array ends with spare rows, and padding entries are inactive).
+// of a piece in flight (a piece's odd last row pairs with a row beyond it: the slot
+// arrays end with spare rows, and such rows are inactive).
 template <int KM, bool VOLN>
 __global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
 {
@@ -180,9 +180,9 @@ __global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
             for (int u = 0; u < 2; ++u) {
                 const int64_t ds = ent + static_cast<int64_t>(t + u) * kWave + lane;
                 const int off = A.ent[ds] & 0x7fff;
-                // rows past T (and padding entries) are inactive; their neighbour index
-                // is clamped to the range start so the loads stay in bounds
-                const int64_t j = m.x + (t + u < T && off != kEntPad ? off / 48 : 0);
+                // rows past T and padding entries are inactive and read the sentinel record
+                // (far from every node, zero adjoint velocity, volume and stiffness factor)
+                const int64_t j = (t + u < T && off != kEntPad) ? m.x + off / 48 : A.nn;
                 adj_load<KM, VOLN>(A, P, ai, ds, j, r[u]);
                 if (t + u >= T) r[u].active = false;
             }
