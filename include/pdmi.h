@@ -93,6 +93,8 @@ typedef struct pd_info {
     int32_t mapping;        /* PD_MAP_SLICED / PD_MAP_STAGED */
     int32_t order;          /* device node order in use: PD_ORDER_NATURAL / PD_ORDER_MORTON */
     double model_bytes_per_step; /* algorithmic HBM bytes of one step (see the design notes) */
+    int32_t waves_per_slice; /* staged mapping: wavefronts sharing one 64-node slice (1 otherwise) */
+    int32_t reserved_;
 } pd_info;
 
 /* ---------------------------------------------------------------- lifetime */
@@ -260,8 +262,10 @@ int pd_get_break_steps(pd_ctx *ctx, int32_t inst, int32_t *out);
 /* ---------------------------------------------------------------- tuning and introspection */
 
 /* Work mapping of the step kernel: PD_MAP_SLICED with `lanes` work-items cooperating on
- * one node's bonds (1, 4, 16 or 64; 0 = library default), or PD_MAP_STAGED (lanes
- * ignored).  Rebuilds the device layout; the state (u, v, a, broken bonds, step) is kept. */
+ * one node's bonds (1, 4, 16 or 64; 0 = library default), or PD_MAP_STAGED with `lanes`
+ * wavefronts sharing each 64-node slice (1, 2 or 4; 0 = 1; more than one fills the chip
+ * on problems with fewer slices than SIMDs).  Rebuilds the device layout when the
+ * mapping changes; the state (u, v, a, broken bonds, step) is kept. */
 int pd_set_mapping(pd_ctx *ctx, int mapping, int lanes);
 
 /* Shorthand for pd_set_mapping(ctx, PD_MAP_SLICED, lanes). */
@@ -271,7 +275,7 @@ int pd_set_lanes_per_node(pd_ctx *ctx, int lanes);
  * the current problem (and both device node orders if the family was built with
  * PD_ORDER_AUTO) and keep the fastest; the state is restored afterwards.
  * *chosen (may be NULL) receives the lanes-per-node of the chosen sliced mapping, or
- * -1 for the staged mapping. */
+ * minus the wavefronts per slice of the chosen staged mapping. */
 int pd_autotune(pd_ctx *ctx, int64_t trial_steps, int32_t *chosen);
 
 /* Problem and layout sizes. */

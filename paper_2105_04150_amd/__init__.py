@@ -85,7 +85,8 @@ class Simulation:
         B.pd_set_lanes_per_node(self.ctx, lanes)
 
     def set_mapping(self, mapping, lanes=0):
-        """mapping: "sliced" (with lanes per node) or "staged"."""
+        """mapping: "sliced" (lanes = work-items per node) or "staged" (lanes = wavefronts
+        per 64-node slice)."""
         m = {"sliced": PD_MAP_SLICED, "staged": PD_MAP_STAGED}.get(mapping, mapping)
         B.pd_set_mapping(self.ctx, m, lanes)
 

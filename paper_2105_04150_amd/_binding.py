@@ -48,7 +48,7 @@ class pd_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_slots", C.c_int64), ("n_nodes_dev", C.c_int64),
                 ("n_slots_dev", C.c_int64), ("n_instances", C.c_int32), ("lanes_per_node", C.c_int32),
                 ("precision", C.c_int32), ("scheme", C.c_int32), ("mapping", C.c_int32), ("order", C.c_int32),
-                ("model_bytes_per_step", C.c_double)]
+                ("model_bytes_per_step", C.c_double), ("waves_per_slice", C.c_int32), ("reserved_", C.c_int32)]
 
 
 _lib = None

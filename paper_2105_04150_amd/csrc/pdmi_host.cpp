@@ -117,7 +117,7 @@ struct pd_ctx {
     std::vector<Inst> inst;
     int order = PD_ORDER_NATURAL;
     bool order_auto = false;         // the autotuner may change the device node order
-    int lanes = kDefaultLanes;
+    int lanes = kDefaultLanes;       // sliced: lanes per node; staged: wavefronts per slice
     int mapping = PD_MAP_SLICED;
     int scheme = PD_EULER_CROMER;
     double dt = 1.0e-7;
@@ -1108,7 +1108,7 @@ void launch_one(pd_ctx* ctx, int mode, int in, int out, int64_t step_local)
 {
     const StepArgs A = step_args(ctx, in, out, step_local);
     if (ctx->mapping == PD_MAP_STAGED)
-        hip_check(launch_step_staged(A, mode, fp32(ctx), ctx->stream), "step kernel launch");
+        hip_check(launch_step_staged(A, mode, fp32(ctx), ctx->lanes, ctx->stream), "step kernel launch");
     else
         hip_check(launch_step(A, ctx->lanes, mode, ctx->has_stiff, ctx->stream), "step kernel launch");
 }
@@ -1220,7 +1220,7 @@ void check_symmetric(const Inst& I)
 void launch_ec(pd_ctx* ctx, const StepArgs& A)
 {
     if (ctx->mapping == PD_MAP_STAGED)
-        hip_check(launch_step_staged(A, kModeEC, false, ctx->stream), "step kernel launch");
+        hip_check(launch_step_staged(A, kModeEC, false, ctx->lanes, ctx->stream), "step kernel launch");
     else
         hip_check(launch_step(A, ctx->lanes, kModeEC, ctx->has_stiff, ctx->stream), "step kernel launch");
 }
@@ -1660,9 +1660,10 @@ int pd_set_mapping(pd_ctx* ctx, int mapping, int lanes)
     return guarded(ctx, [&] {
         if (mapping != PD_MAP_SLICED && mapping != PD_MAP_STAGED) fail(PD_EINVAL, "unknown mapping");
         if (fp32(ctx) && mapping != PD_MAP_STAGED) fail(PD_EINVAL, "the FP32 build runs the staged mapping only");
-        if (mapping == PD_MAP_STAGED) lanes = 1;
-        if (lanes == 0) lanes = kDefaultLanes;
-        if (!lanes_supported(lanes)) fail(PD_EINVAL, "unsupported lanes-per-node");
+        if (lanes == 0) lanes = mapping == PD_MAP_STAGED ? 1 : kDefaultLanes;
+        if (mapping == PD_MAP_STAGED && !split_supported(lanes))
+            fail(PD_EINVAL, "unsupported wavefronts per slice (staged mapping: 1, 2 or 4)");
+        if (mapping == PD_MAP_SLICED && !lanes_supported(lanes)) fail(PD_EINVAL, "unsupported lanes-per-node");
         if (!ctx->built) {
             ctx->mapping = mapping;
             ctx->lanes = lanes;
@@ -1670,6 +1671,11 @@ int pd_set_mapping(pd_ctx* ctx, int mapping, int lanes)
         }
         if (lanes == ctx->lanes && mapping == ctx->mapping) return;
         set_device(ctx);
+        if (mapping == ctx->mapping && mapping == PD_MAP_STAGED) {  // same layout, other launch shape
+            ctx->lanes = lanes;
+            ctx->drop_graphs();
+            return;
+        }
         HostState S = snapshot(ctx);
         const bool av = ctx->a_valid;
         ctx->mapping = mapping;
@@ -1700,7 +1706,7 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
             if (!ctx->order_auto && o != ctx->order) continue;
             if (!fp32(ctx))
                 for (int L : {1, 4, 16, 64}) cands.push_back({PD_MAP_SLICED, L, o});
-            cands.push_back({PD_MAP_STAGED, 1, o});
+            for (int S : {1, 2, 4}) cands.push_back({PD_MAP_STAGED, S, o});
         }
         Cand best{ctx->mapping, ctx->lanes, ctx->order};
         double best_ms = std::numeric_limits<double>::infinity();
@@ -1731,7 +1737,7 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
         sync(ctx);
         ctx->a_valid = av;
         reset_flags_after_state_change(ctx, av);
-        if (chosen) *chosen = best.mapping == PD_MAP_STAGED ? -1 : best.lanes;
+        if (chosen) *chosen = best.mapping == PD_MAP_STAGED ? -best.lanes : best.lanes;
     });
 }
 
@@ -1933,6 +1939,7 @@ int pd_get_info(const pd_ctx* ctx, pd_info* info)
     info->n_slots_dev = ctx->ns;
     info->n_instances = static_cast<int32_t>(ctx->inst.size());
     info->lanes_per_node = ctx->mapping == PD_MAP_STAGED ? 1 : ctx->lanes;
+    info->waves_per_slice = ctx->mapping == PD_MAP_STAGED ? ctx->lanes : 1;
     info->mapping = ctx->mapping;
     info->order = ctx->order;
     info->precision = ctx->precision;

@@ -133,8 +133,8 @@ hipError_t launch_drift(const StepArgs& a, bool fp32, hipStream_t s);
 
 hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s);
 
-// staged mapping, FP64 or FP32 bond arithmetic
-hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, hipStream_t s);
+// staged mapping, FP64 or FP32 bond arithmetic, `split` wavefronts per slice
+hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, int split, hipStream_t s);
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
 
@@ -194,7 +194,9 @@ hipError_t launch_adj_nu0(double* nu, const double* lam_u, const int32_t* bc_id,
 // out[0] = sum of x[0..n)
 hipError_t launch_sum(const double* x, int64_t n, double* out, hipStream_t s);
 
-// lanes-per-node values with compiled kernels
+// lanes-per-node values with compiled kernels (sliced mapping)
 bool lanes_supported(int lanes);
+// wavefronts-per-slice values with compiled kernels (staged mapping)
+bool split_supported(int split);
 
 }  // namespace pdmi

@@ -276,17 +276,27 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
     node_update<MODE>(A, P, node, U0, U1, U2, F0, F1, F2);
 }
 
-// Staged step kernel: one wavefront per 64-node slice, one lane per node.  For every
-// piece, the wavefront loads the range's node records (and volumes) and the piece's slot
-// entries into registers while the previous piece is being computed, then copies them
-// to LDS; every slot reads its neighbour from LDS.  Each record crosses the vector-memory
-// path once per slice instead of once per slot.  Per-slot stiffness, when present,
-// streams from global memory one piece ahead.  Rows are processed in pairs so the LDS
-// reads of one row overlap the arithmetic of the other; an odd last row runs alone.
-template <bool FP32, int MODE, bool STIFF, bool VOLN, bool KNODE>
-__global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __restrict__ pieces,
-                                                         const int32_t* __restrict__ slice_piece,
-                                                         const int64_t* __restrict__ slice_ptr)
+// Orders a wavefront's own LDS writes before its later LDS reads (no workgroup barrier).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Staged step kernel: one workgroup of S wavefronts per 64-node slice, one lane per node.
+// Wavefront w takes the slice's pieces w, w + S, w + 2S, ...  For every piece, the
+// wavefront loads the range's node records (and volumes) and the piece's slot entries
+// into registers while its previous piece is being computed, then copies them to its
+// own LDS area; every slot reads its neighbour from LDS.  Each record crosses the
+// vector-memory path once per piece instead of once per slot.  Per-slot stiffness, when
+// present, streams from global memory one piece ahead.  Rows are processed in pairs so
+// the LDS reads of one row overlap the arithmetic of the other; an odd last row runs
+// alone.  With S > 1 the partial forces meet in LDS in a fixed order (S > 1 fills the
+// chip on problems with fewer slices than SIMDs).
+template <bool FP32, int MODE, bool STIFF, bool VOLN, bool KNODE, int S>
+__global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2* __restrict__ pieces,
+                                                             const int32_t* __restrict__ slice_piece,
+                                                             const int64_t* __restrict__ slice_ptr)
 {
     constexpr int kRecChunks = kStageChunks + 3;             // staged records, then the sentinel
     constexpr int kEntChunks = kPieceRows * kWave * 2 / 16;  // 16-byte chunks of entries
@@ -294,13 +304,15 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
     constexpr int kVolWords = WSTAGE ? (kEntPad / 48 + 2) / 2 * 2 : 0;  // staged weights (doubles), sentinel last
     constexpr int kLds = kRecChunks + kEntChunks + kVolWords / 2;
     static_assert(kStageChunks == 4 * kWave && kEntChunks == kWave, "four record loads and one entry load");
-    __shared__ double2 lds[kLds];
-    double2* const lrec = lds;
-    const char* const lrecb = reinterpret_cast<const char*>(lds);
-    uint16_t* const lent = reinterpret_cast<uint16_t*>(lds + kRecChunks);
-    double* const lvol = reinterpret_cast<double*>(lds + kRecChunks + kEntChunks);
+    __shared__ double2 lds[S * kLds];
+    __shared__ double red[S > 1 ? (S - 1) * 3 * kWave : 1];  // partial forces of wavefronts 1..S-1
+    const int wv = S > 1 ? __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave) : 0;
+    double2* const lrec = lds + wv * kLds;
+    const char* const lrecb = reinterpret_cast<const char*>(lrec);
+    uint16_t* const lent = reinterpret_cast<uint16_t*>(lrec + kRecChunks);
+    double* const lvol = reinterpret_cast<double*>(lrec + kRecChunks + kEntChunks);
 
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
     if (slice >= A.nslices) return;
     const int32_t* __restrict__ slice_inst = A.slice_inst;
@@ -332,7 +344,10 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
 
     const int p0 = __builtin_amdgcn_readfirstlane(slice_piece[slice]);
     const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
+    auto rows_of = [&](int p) { return (pieces[__builtin_amdgcn_readfirstlane(p)].y >> 8) & 0xff; };
     int64_t ent = wave_uniform(slice_ptr[slice]);  // first entry of the current piece
+    const int pa = p0 + wv;                         // this wavefront's first piece
+    for (int q = p0; q < pa && q < p1; ++q) ent += static_cast<int64_t>(rows_of(q)) * kWave;
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
     float Ff0 = 0.0f, Ff1 = 0.0f, Ff2 = 0.0f;
 
@@ -398,18 +413,19 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
         bstep[ds] = static_cast<int32_t>(*A.step_base + A.step_local);
     };
 
-    if (p1 > p0) {
-        issue(p0, ent);
-        for (int p = p0; p < p1; ++p) {
-            const int T = (pieces[__builtin_amdgcn_readfirstlane(p)].y >> 8) & 0xff;
-            const int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;
-            __syncthreads();  // the previous piece is no longer read
+    if (pa < p1) {
+        issue(pa, ent);
+        for (int p = pa; p < p1; p += S) {
+            const int T = rows_of(p);
+            int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;  // first entry of piece p + S
+            for (int q = p + 1; q < p + S && q < p1; ++q) ent_next += static_cast<int64_t>(rows_of(q)) * kWave;
+            wave_sync();  // the previous piece is no longer read
             commit();
             if (STIFF)
 #pragma unroll
                 for (int t = 0; t < kPieceRows; ++t) kcur[t] = knext[t];
-            if (p + 1 < p1) issue(p + 1, ent_next);
-            __syncthreads();  // the piece's LDS copy is complete
+            if (p + S < p1) issue(p + S, ent_next);
+            wave_sync();  // the piece's LDS copy is complete
 #pragma unroll
             for (int t = 0; t < kPieceRows; t += 2) {
                 if (t >= T) break;
@@ -431,6 +447,23 @@ __global__ __launch_bounds__(kWave) void step_staged(StepArgs A, const int2* __r
         F0 = Ff0;
         F1 = Ff1;
         F2 = Ff2;
+    }
+    if (S > 1) {  // wavefront 0 adds the partial forces of 1..S-1 in that order
+        if (wv > 0) {
+            double* r = red + (wv - 1) * 3 * kWave + lane;
+            r[0] = F0;
+            r[kWave] = F1;
+            r[2 * kWave] = F2;
+        }
+        __syncthreads();  // every wavefront of the workgroup reaches this once
+        if (wv > 0) return;
+#pragma unroll
+        for (int w = 1; w < S; ++w) {
+            const double* r = red + (w - 1) * 3 * kWave + lane;
+            F0 += r[0];
+            F1 += r[kWave];
+            F2 += r[2 * kWave];
+        }
     }
     node_update<MODE, FP32>(A, P, node, U0, U1, U2, F0, F1, F2);
 }
@@ -556,6 +589,8 @@ hipError_t launch_step_g(const StepArgs& a, int mode, bool stiff, hipStream_t s)
 
 bool lanes_supported(int lanes) { return lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64; }
 
+bool split_supported(int split) { return split == 1 || split == 2 || split == 4; }
+
 hipError_t launch_step(const StepArgs& a, int lanes, int mode, bool stiff, hipStream_t s)
 {
     if (a.nslices <= 0) return hipSuccess;
@@ -593,13 +628,13 @@ hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool FP32, bool STIFF, bool VOLN, bool KNODE = false>
-hipError_t launch_staged_sv(const StepArgs& a, int mode, hipStream_t s)
+template <bool FP32, bool STIFF, bool VOLN, bool KNODE, int S>
+hipError_t launch_staged_svs(const StepArgs& a, int mode, hipStream_t s)
 {
-    const dim3 grid(static_cast<unsigned>(a.nslices)), block(kWave);
+    const dim3 grid(static_cast<unsigned>(a.nslices)), block(kWave * S);
     switch (mode) {
 #define PD_L(M)                                                                                   \
-    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN, KNODE>), grid, block, 0, s, a, a.pieces, a.slice_piece, \
+    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN, KNODE, S>), grid, block, 0, s, a, a.pieces, a.slice_piece, \
                        a.slice_ptr)
     case kModeEC: PD_L(kModeEC); break;
     case kModeVV: PD_L(kModeVV); break;
@@ -611,20 +646,33 @@ hipError_t launch_staged_sv(const StepArgs& a, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool FP32>
-hipError_t launch_staged_p(const StepArgs& a, int mode, hipStream_t s)
+template <bool FP32, bool STIFF, bool VOLN, bool KNODE = false>
+hipError_t launch_staged_sv(const StepArgs& a, int mode, int split, hipStream_t s)
 {
-    const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
-    if (a.nw) return launch_staged_sv<FP32, false, false, true>(a, mode, s);  // per-node stiffness
-    if (stiff)
-        return voln ? launch_staged_sv<FP32, true, true>(a, mode, s) : launch_staged_sv<FP32, true, false>(a, mode, s);
-    return voln ? launch_staged_sv<FP32, false, true>(a, mode, s) : launch_staged_sv<FP32, false, false>(a, mode, s);
+    switch (split) {
+    case 1: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 1>(a, mode, s);
+    case 2: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 2>(a, mode, s);
+    case 4: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 4>(a, mode, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
-hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, hipStream_t s)
+template <bool FP32>
+hipError_t launch_staged_p(const StepArgs& a, int mode, int split, hipStream_t s)
+{
+    const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
+    if (a.nw) return launch_staged_sv<FP32, false, false, true>(a, mode, split, s);  // per-node stiffness
+    if (stiff)
+        return voln ? launch_staged_sv<FP32, true, true>(a, mode, split, s)
+                    : launch_staged_sv<FP32, true, false>(a, mode, split, s);
+    return voln ? launch_staged_sv<FP32, false, true>(a, mode, split, s)
+                : launch_staged_sv<FP32, false, false>(a, mode, split, s);
+}
+
+hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, int split, hipStream_t s)
 {
     if (a.nslices <= 0) return hipSuccess;
-    return fp32 ? launch_staged_p<true>(a, mode, s) : launch_staged_p<false>(a, mode, s);
+    return fp32 ? launch_staged_p<true>(a, mode, split, s) : launch_staged_p<false>(a, mode, split, s);
 }
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s)

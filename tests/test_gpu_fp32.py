@@ -40,6 +40,16 @@ def test_fp32_against_fp64_oracle(oracle_lib, name, over, order):
     assert mism <= 0.01 * nb
 
 
+def test_fp32_split_slices(oracle_lib):
+    """FP32 with four wavefronts per slice (partial forces meet in f64)."""
+    from paper_2105_04150_amd import PD_FP32
+    w = pi.workload("block10")
+    o = oracle_run(w, w.steps)
+    g = gpu_run(w, w.steps, precision=PD_FP32, lanes=4, mapping="staged")
+    eu, ev, mism, ephi = compare(g, o, TOL_FP32, "fp32 block10 staged-4")
+    assert eu <= TOL_FP32 and mism <= 0.01 * max(int(o.broken_mask.sum()), 1)
+
+
 def test_fp32_rejects_sliced_mapping():
     from paper_2105_04150_amd import PD_FP32, PdmiError, Simulation
     with Simulation(precision=PD_FP32) as g:

@@ -34,7 +34,8 @@ def test_family_bit_exact(oracle_lib, name, over, order):
     assert np.array_equal(rp, grp) and np.array_equal(col, gcol)
 
 
-MAPPINGS = [("sliced", 1), ("sliced", 4), ("sliced", 16), ("sliced", 64), ("staged", 1)]
+MAPPINGS = [("sliced", 1), ("sliced", 4), ("sliced", 16), ("sliced", 64), ("staged", 1), ("staged", 2),
+            ("staged", 4)]
 
 
 @pytest.mark.parametrize("mapping,lanes", MAPPINGS)
@@ -51,7 +52,7 @@ def test_block10_euler_cromer(oracle_lib, mapping, lanes):
     assert ephi <= 1e-13
 
 
-@pytest.mark.parametrize("mapping,lanes", [("sliced", 1), ("sliced", 16), ("staged", 1)])
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 1), ("sliced", 16), ("staged", 1), ("staged", 4)])
 def test_notched_beam_velocity_verlet(oracle_lib, mapping, lanes):
     """Notched three-point-bend beam (reduced length), velocity Verlet, velocity-controlled load."""
     w = pi.workload("beam3pb", dims=(60, 12, 12), steps=1500)
@@ -75,7 +76,7 @@ def test_cube(oracle_lib, name, order, mapping):
     assert mism == 0 and eu <= TOL_FP64 and ephi <= 1e-13
 
 
-@pytest.mark.parametrize("mapping,lanes", [("sliced", 4), ("staged", 1)])
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 4), ("staged", 1), ("staged", 2)])
 def test_stiffness_field_body_force(oracle_lib, mapping, lanes):
     """Per-slot stiffness field c exp(g) and a body-force load (the adjoint workload, reduced)."""
     w = pi.workload("adjoint_beam", dims=(30, 10, 8), steps=400)
@@ -86,7 +87,7 @@ def test_stiffness_field_body_force(oracle_lib, mapping, lanes):
     assert mism == 0 and eu <= TOL_FP64
 
 
-@pytest.mark.parametrize("mapping,lanes", [("sliced", 16), ("staged", 1)])
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 16), ("staged", 1), ("staged", 4)])
 def test_nonuniform_volumes_and_damping(oracle_lib, mapping, lanes):
     """Per-node volumes and dynamic-relaxation damping with Euler-Cromer."""
     from paper_2105_04150_amd import Simulation
@@ -130,7 +131,7 @@ def test_batched_instances_match_independent_oracles(oracle_lib, mapping):
             assert mism == 0 and eu <= TOL_FP64 and ephi <= 1e-13
 
 
-@pytest.mark.parametrize("mapping,lanes", [("sliced", 4), ("staged", 1)])
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 4), ("staged", 1), ("staged", 4)])
 def test_deterministic_and_restartable(mapping, lanes):
     """Bitwise-equal reruns; a 400 + restore + 300 run equals 700 straight steps."""
     from paper_2105_04150_amd import simulation_for
@@ -162,7 +163,9 @@ def test_mapping_change_keeps_state():
     b.set_lanes_per_node(64)
     b.step(200)
     b.set_mapping("staged")
-    b.step(200)
+    b.step(100)
+    b.set_mapping("staged", 2)  # same layout, two wavefronts per slice
+    b.step(100)
     assert rel_err(b.u(), a.u()) <= 1e-12
     assert np.array_equal(a.broken(), b.broken())
 
