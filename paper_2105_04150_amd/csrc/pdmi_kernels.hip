@@ -289,7 +289,8 @@ __device__ __forceinline__ void wave_sync()
 // into registers while its previous piece is being computed, then copies them to its
 // own LDS area; every slot reads its neighbour from LDS.  Each record crosses the
 // vector-memory path once per piece instead of once per slot.  Per-slot stiffness, when
-// present, streams from global memory one piece ahead.  Rows are processed in pairs so
+// present, streams from global memory (two rows one piece ahead, the rest when the piece
+// starts, which keeps the register count at four wavefronts per SIMD).  Rows are processed in pairs so
 // the LDS reads of one row overlap the arithmetic of the other; an odd last row runs
 // alone.  With S > 1 the partial forces meet in LDS in a fixed order (S > 1 fills the
 // chip on problems with fewer slices than SIMDs).
@@ -355,7 +356,8 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     double2 r0, r1, r2, r3, e0;
     double vs0 = 0.0, vs1 = 0.0;
     int vlen = 0;
-    double kcur[kPieceRows], knext[kPieceRows];
+    constexpr int kKPre = 2;  // stiffness rows fetched a piece ahead; the rest when the piece starts
+    double kcur[kPieceRows], knext[kKPre];
 
     // Loads of piece p (first entry e): a fixed 256-chunk window from the range start
     // (the record buffers end with kRecPad spare records) and the whole 8-row entry block
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
         }
         if (STIFF)
 #pragma unroll
-            for (int t = 0; t < kPieceRows; ++t) knext[t] = __builtin_nontemporal_load(A.kslot + e + t * kWave + lane);
+            for (int t = 0; t < kKPre; ++t) knext[t] = __builtin_nontemporal_load(A.kslot + e + t * kWave + lane);
     };
     auto commit = [&]() {
         lrec[lane] = r0;
@@ -423,7 +425,8 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             commit();
             if (STIFF)
 #pragma unroll
-                for (int t = 0; t < kPieceRows; ++t) kcur[t] = knext[t];
+                for (int t = 0; t < kPieceRows; ++t)
+                    kcur[t] = t < kKPre ? knext[t] : __builtin_nontemporal_load(A.kslot + ent + t * kWave + lane);
             if (p + S < p1) issue(p + S, ent_next);
             wave_sync();  // the piece's LDS copy is complete
 #pragma unroll
