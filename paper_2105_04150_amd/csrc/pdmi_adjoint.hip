@@ -150,13 +150,42 @@ __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
     adj_node(A, P, node, ni, J, h);
 }
 
-// Staged layout: one lane per node; neighbours are read from global memory, two rows
-// of a piece in flight (a piece's odd last row pairs with a row beyond it: the slot
-// arrays end with spare rows, and such rows are inactive).
-template <int KM, bool VOLN>
-__global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
+// Orders a wavefront's own LDS writes before its later LDS reads (no workgroup barrier).
+__device__ __forceinline__ void adj_wave_sync()
 {
-    const int lane = threadIdx.x;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Staged layout: a workgroup of S wavefronts per 64-node slice, one lane per node;
+// wavefront w takes the slice's pieces w, w + S, ...  For each piece the wavefront
+// stages the range's records (x, u^k), adjoint velocities and per-node weights in its
+// own LDS area one piece ahead (the record and adjoint-velocity buffers end with spare
+// entries, so the fixed windows need no clamping); per-slot break steps, stiffness and
+// the gradient stream by row.  Padding entries point at an LDS sentinel (far record,
+// zero adjoint velocity and weights).  Partial sums of J meet in LDS in a fixed order.
+template <int KM, bool VOLN, int S>
+__global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
+{
+    constexpr bool KNODE = KM == kKNode;
+    constexpr int kW = (kEntPad / 48 + 2) / 2 * 2;  // staged weights per array (sentinel at kEntPad / 48)
+    constexpr int kRecChunks = kStageChunks + 3;     // records, then the sentinel record
+    constexpr int kNuChunks = kStageChunks / 2 + 2;  // 2 * kStageChunks / 3 adjoint-velocity triples + sentinel
+    constexpr int kEntChunks = kWave;                // one 8-row entry block
+    constexpr int kWChunks = ((VOLN ? kW : 0) + (KNODE ? kW : 0)) / 2;
+    constexpr int kLds = kRecChunks + kNuChunks + kEntChunks + kWChunks;
+    static_assert(kStageChunks == 4 * kWave, "four record loads per piece");
+    __shared__ double2 lds[S * kLds];
+    __shared__ double red[S > 1 ? (S - 1) * 3 * kWave : 1];
+    const int wv = S > 1 ? __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave) : 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    double2* const lrec = lds + wv * kLds;
+    const char* const lrecb = reinterpret_cast<const char*>(lrec);
+    double* const lnu = reinterpret_cast<double*>(lrec + kRecChunks);
+    uint16_t* const lent = reinterpret_cast<uint16_t*>(lrec + kRecChunks + kNuChunks);
+    double* const lvol = reinterpret_cast<double*>(lrec + kRecChunks + kNuChunks + kEntChunks);
+    double* const lna = lvol + (VOLN ? kW : 0);
+
     const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
     if (slice >= A.nslices) return;
     const InstParams P = A.params[A.slice_inst[slice]];
@@ -165,35 +194,123 @@ __global__ __launch_bounds__(kWave) void adjoint_staged(AdjArgs A)
     const double2 o0 = rec[3 * node], o1 = rec[3 * node + 1], o2 = rec[3 * node + 2];
     const double ni[3] = {A.nu_in[3 * node], A.nu_in[3 * node + 1], A.nu_in[3 * node + 2]};
     const double Vi = VOLN ? A.vol[node] : P.volume;
-    const double ai = KM == kKNode ? A.na[node] : 0.0;
+    const double ai = KNODE ? A.na[node] : 0.0;
     const double h = A.dt / P.rho;
-    const int pb = __builtin_amdgcn_readfirstlane(A.slice_piece[slice]);
-    const int pe = __builtin_amdgcn_readfirstlane(A.slice_piece[slice + 1]);
+    const double2* __restrict__ ent2 = reinterpret_cast<const double2*>(A.ent);
+
+    // sentinels: record far from every node; zero adjoint velocity and weights
+    if (lane < 3) lrec[kStageChunks + lane] = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
+    if (lane < 4) lnu[kStageChunks + lane] = 0.0;
+    if (VOLN && lane == 0) lvol[kEntPad / 48] = 0.0;
+    if (KNODE && lane == 0) lna[kEntPad / 48] = 0.0;
+
+    const int p0 = __builtin_amdgcn_readfirstlane(A.slice_piece[slice]);
+    const int p1 = __builtin_amdgcn_readfirstlane(A.slice_piece[slice + 1]);
+    auto rows_of = [&](int p) { return (A.pieces[__builtin_amdgcn_readfirstlane(p)].y >> 8) & 0xff; };
     int64_t ent = wave_uniform(A.slice_ptr[slice]);
-    double J[3] = {0.0, 0.0, 0.0};
-    for (int p = pb; p < pe; ++p) {
-        const int2 m = A.pieces[p];
-        const int T = (m.y >> 8) & 0xff;
-        for (int t = 0; t < T; t += 2) {
-            AdjRow r[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int64_t ds = ent + static_cast<int64_t>(t + u) * kWave + lane;
-                const int off = A.ent[ds] & 0x7fff;
-                // rows past T and padding entries are inactive and read the sentinel record
-                // (far from every node, zero adjoint velocity, volume and stiffness factor)
-                const int64_t j = (t + u < T && off != kEntPad) ? m.x + off / 48 : A.nn;
-                adj_load<KM, VOLN>(A, P, ai, ds, j, r[u]);
-                if (t + u >= T) r[u].active = false;
+    const int pa = p0 + wv;
+    for (int q = p0; q < pa && q < p1; ++q) ent += static_cast<int64_t>(rows_of(q)) * kWave;
+
+    double2 r0, r1, r2, r3, e0;
+    double n0, n1, n2, n3, vs0 = 0.0, vs1 = 0.0, as0 = 0.0, as1 = 0.0;
+    int vlen = 0;
+    auto issue = [&](int p, int64_t e) {
+        const int2 m = A.pieces[__builtin_amdgcn_readfirstlane(p)];
+        const double2* rs = rec + 3 * static_cast<int64_t>(m.x) + lane;
+        r0 = rs[0];
+        r1 = rs[kWave];
+        r2 = rs[2 * kWave];
+        r3 = rs[3 * kWave];
+        const double* ns = A.nu_in + 3 * static_cast<int64_t>(m.x) + lane;
+        n0 = ns[0];
+        n1 = ns[kWave];
+        n2 = ns[2 * kWave];
+        n3 = ns[3 * kWave];
+        e0 = ent2[e / 8 + lane];
+        if (VOLN || KNODE) {
+            const int len = m.y & 0xff;
+            vlen = len;
+            if (VOLN) {
+                vs0 = A.vol[m.x + min(lane, len - 1)];
+                vs1 = A.vol[m.x + min(lane + kWave, len - 1)];
             }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const double d = adj_slot(r[u].active, r[u].p0, r[u].p1, r[u].p2, o0.x, o0.y, o1.x, o1.y, o2.x,
-                                          o2.y, r[u].nj, ni, Vi, r[u].Vj, r[u].kb, h, J);
-                if (r[u].active) A.grad[r[u].ds] = r[u].g + d;
+            if (KNODE) {
+                as0 = A.na[m.x + min(lane, len - 1)];
+                as1 = A.na[m.x + min(lane + kWave, len - 1)];
             }
         }
-        ent += static_cast<int64_t>(T) * kWave;
+    };
+    auto commit = [&]() {
+        lrec[lane] = r0;
+        lrec[lane + kWave] = r1;
+        lrec[lane + 2 * kWave] = r2;
+        lrec[lane + 3 * kWave] = r3;
+        lnu[lane] = n0;
+        lnu[lane + kWave] = n1;
+        lnu[lane + 2 * kWave] = n2;
+        lnu[lane + 3 * kWave] = n3;
+        reinterpret_cast<double2*>(lent)[lane] = e0;
+        if (VOLN) {
+            if (lane < vlen) lvol[lane] = vs0;
+            if (lane + kWave < vlen) lvol[lane + kWave] = vs1;
+        }
+        if (KNODE) {
+            if (lane < vlen) lna[lane] = as0;
+            if (lane + kWave < vlen) lna[lane + kWave] = as1;
+        }
+    };
+    // one slot of row t of the current piece
+    double J[3] = {0.0, 0.0, 0.0};
+    auto slot = [&](int64_t ds, uint16_t e) {
+        const uint32_t off = e & 0x7fff;  // byte offset of the record; 3 * index = off / 16 for nu
+        const double2 q0 = *reinterpret_cast<const double2*>(lrecb + off);
+        const double2 q1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
+        const double2 q2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
+        const double* nu = lnu + off / 16;
+        const double nj[3] = {nu[0], nu[1], nu[2]};
+        const uint32_t widx = (off * 0xAAABu) >> 21;  // off / 48
+        const bool active = A.k < static_cast<int64_t>(A.bstep[ds]);
+        const double kb = KM == kKSlot ? A.kslot[ds] : KNODE ? ai * lna[widx] : P.c;
+        const double Vj = VOLN ? lvol[widx] : P.volume;
+        const double g = A.grad[ds];
+        const double d = adj_slot(active, q0, q1, q2, o0.x, o0.y, o1.x, o1.y, o2.x, o2.y, nj, ni, Vi, Vj, kb, h, J);
+        if (active) A.grad[ds] = g + d;
+    };
+
+    if (pa < p1) {
+        issue(pa, ent);
+        for (int p = pa; p < p1; p += S) {
+            const int T = rows_of(p);
+            int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;
+            for (int q = p + 1; q < p + S && q < p1; ++q) ent_next += static_cast<int64_t>(rows_of(q)) * kWave;
+            adj_wave_sync();  // the previous piece is no longer read
+            commit();
+            if (p + S < p1) issue(p + S, ent_next);
+            adj_wave_sync();  // the piece's LDS copy is complete
+#pragma unroll
+            for (int t = 0; t < kPieceRows; ++t) {
+                if (t >= T) break;
+                slot(ent + t * kWave + lane, lent[t * kWave + lane]);
+            }
+            ent = ent_next;
+        }
+    }
+    if (S > 1) {
+        if (wv > 0) {
+            double* r = red + (wv - 1) * 3 * kWave + lane;
+            r[0] = J[0];
+            r[kWave] = J[1];
+            r[2 * kWave] = J[2];
+        }
+        __syncthreads();  // every wavefront of the workgroup reaches this once
+        if (wv > 0) return;
+#pragma unroll
+        for (int w = 1; w < S; ++w) {
+            const double* r = red + (w - 1) * 3 * kWave + lane;
+            J[0] += r[0];
+            J[1] += r[kWave];
+            J[2] += r[2 * kWave];
+        }
     }
     adj_node(A, P, node, ni, J, h);
 }
@@ -272,8 +389,14 @@ void adj_launch_sliced(const AdjArgs& a, hipStream_t s)
 template <int KM, bool VOLN>
 hipError_t adj_launch_kv(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
 {
+    const dim3 grid(static_cast<unsigned>(a.nslices));
     if (staged) {
-        hipLaunchKernelGGL((adjoint_staged<KM, VOLN>), dim3(static_cast<unsigned>(a.nslices)), dim3(kWave), 0, s, a);
+        switch (lanes) {  // wavefronts per slice
+        case 1: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 1>), grid, dim3(kWave), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 2>), grid, dim3(2 * kWave), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 4>), grid, dim3(4 * kWave), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     }
     switch (lanes) {

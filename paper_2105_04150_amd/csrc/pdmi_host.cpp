@@ -1797,8 +1797,10 @@ int pd_adj_backward(pd_ctx* ctx, int64_t m, const int64_t* sensors, const double
         set_device(ctx);
         hipStream_t st = ctx->stream;
         const int64_t nn = ctx->nn, ns = ctx->ns, S = ctx->tape_every, T = ctx->tape_nsteps, step0 = ctx->tape_step0;
+        // adjoint velocities: nn + 1 triples (the last one, the sentinel's, zero) and spare zero
+        // entries for the staged kernel's fixed-size range windows
         const size_t Rb = rec_bytes(nn), Vb = static_cast<size_t>(3 * nn) * sizeof(double),
-                     Nb = static_cast<size_t>(3 * (nn + 1)) * sizeof(double);
+                     Nb = (static_cast<size_t>(3 * (nn + 1)) + kStageChunks) * sizeof(double);
         const int64_t Lmax = std::min(S, T);
         const size_t stride = Rb + (S > 1 ? Vb : 0);
         DevBuf traj, vwork, nu[2], lam, grad, gacc, base, sum, dsn, ddl;

@@ -75,6 +75,8 @@ CASES = [
     # name, overrides, checkpoint interval, mapping, lanes
     ("adjoint_beam", {"dims": (40, 12, 10), "steps": 1500}, 100, "sliced", 4),
     ("adjoint_beam", {"dims": (40, 12, 10), "steps": 1500}, 64, "staged", 1),   # ragged last segment
+    ("adjoint_beam", {"dims": (40, 12, 10), "steps": 1500}, 100, "staged", 4),  # four wavefronts per slice
+    ("block10", {"steps": 700}, 37, "staged", 2),
     ("block10", {"steps": 700}, 37, "sliced", 16),                              # linear BC schedule
     ("block10", {"steps": 700}, 700, "sliced", 1),                              # one segment
     ("block10", {"dims": (9, 7, 6), "steps": 300}, 1, "staged", 1),             # checkpoint every step

@@ -86,7 +86,7 @@ def test_mixed_slot_and_node_instances():
         assert np.array_equal(g.u(1), u_before)
 
 
-@pytest.mark.parametrize("mapping,lanes", [("sliced", 4), ("staged", 1)])
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 4), ("staged", 1), ("staged", 4)])
 def test_adjoint_with_node_field(oracle_lib, mapping, lanes):
     from paper_2105_04150_amd import simulation_for
     w = pi.workload("adjoint_beam", dims=(30, 10, 8), steps=400)
