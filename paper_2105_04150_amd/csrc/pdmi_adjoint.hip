@@ -259,9 +259,12 @@ __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
             if (lane + kWave < vlen) lna[lane + kWave] = as1;
         }
     };
-    // one slot of row t of the current piece
+    // one slot of row t of the current piece; its break step, gradient and stiffness were
+    // loaded with the rest of the piece's rows (bs, gr, kr)
     double J[3] = {0.0, 0.0, 0.0};
-    auto slot = [&](int64_t ds, uint16_t e) {
+    int32_t bs[kPieceRows];
+    double gr[kPieceRows], kr[kPieceRows];
+    auto slot = [&](int t, int64_t ds, uint16_t e) {
         const uint32_t off = e & 0x7fff;  // byte offset of the record; 3 * index = off / 16 for nu
         const double2 q0 = *reinterpret_cast<const double2*>(lrecb + off);
         const double2 q1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
@@ -269,12 +272,11 @@ __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
         const double* nu = lnu + off / 16;
         const double nj[3] = {nu[0], nu[1], nu[2]};
         const uint32_t widx = (off * 0xAAABu) >> 21;  // off / 48
-        const bool active = A.k < static_cast<int64_t>(A.bstep[ds]);
-        const double kb = KM == kKSlot ? A.kslot[ds] : KNODE ? ai * lna[widx] : P.c;
+        const bool active = A.k < static_cast<int64_t>(bs[t]);
+        const double kb = KM == kKSlot ? kr[t] : KNODE ? ai * lna[widx] : P.c;
         const double Vj = VOLN ? lvol[widx] : P.volume;
-        const double g = A.grad[ds];
         const double d = adj_slot(active, q0, q1, q2, o0.x, o0.y, o1.x, o1.y, o2.x, o2.y, nj, ni, Vi, Vj, kb, h, J);
-        if (active) A.grad[ds] = g + d;
+        if (active) A.grad[ds] = gr[t] + d;
     };
 
     if (pa < p1) {
@@ -286,11 +288,20 @@ __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
             adj_wave_sync();  // the previous piece is no longer read
             commit();
             if (p + S < p1) issue(p + S, ent_next);
+            // the piece's per-slot streams, all eight rows of its block at once (rows past T
+            // belong to the next piece or the spare rows and are not used)
+#pragma unroll
+            for (int t = 0; t < kPieceRows; ++t) {
+                const int64_t ds = ent + t * kWave + lane;
+                bs[t] = A.bstep[ds];
+                gr[t] = A.grad[ds];
+                if (KM == kKSlot) kr[t] = A.kslot[ds];
+            }
             adj_wave_sync();  // the piece's LDS copy is complete
 #pragma unroll
             for (int t = 0; t < kPieceRows; ++t) {
                 if (t >= T) break;
-                slot(ent + t * kWave + lane, lent[t * kWave + lane]);
+                slot(t, ent + t * kWave + lane, lent[t * kWave + lane]);
             }
             ent = ent_next;
         }
