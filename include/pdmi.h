@@ -118,8 +118,9 @@ const char *pd_last_error(const pd_ctx *ctx);
  * fused multiply-add) from `coords` (host, n x 3 row-major doubles, metres), sorted
  * ascending per row, and upload it.  `order` picks the device node order.  Resets
  * the state: u = v = a = 0, no broken bonds, no BCs, no body force, step 0.
- * Errors: PD_EINVAL (n < 1, NULL coords, horizon <= 0 or not finite, bad order),
- * PD_ERANGE (n or nnz >= 2^31), PD_ENOMEM, PD_EHIP. */
+ * Errors: PD_EINVAL (n < 1, NULL coords, non-finite coords, two nodes at the same
+ * position, horizon <= 0 or not finite, bad order), PD_ERANGE (n or nnz >= 2^31, or
+ * 2^24 or more device node records), PD_ENOMEM, PD_EHIP. */
 int pd_build_family(pd_ctx *ctx, int64_t n, const double *coords, double horizon, int order);
 
 /* Same for `ninst` independent instances advanced together: instance b has n[b]

@@ -272,6 +272,7 @@ void family_search(int64_t n, const double* x, double delta, std::vector<int64_t
     }
     const double d2max = delta * delta;
     std::vector<int64_t> count(n, 0);
+    std::atomic<bool> coincident{false};  // a zero-length bond has no stretch
     // pass 1: counts; pass 2: fill and sort
     for (int pass = 0; pass < 2; ++pass) {
         if (pass == 1) {
@@ -300,6 +301,7 @@ void family_search(int64_t n, const double* x, double delta, std::vector<int64_t
                                 double d2 = a * a + b * b;
                                 d2 = d2 + e * e;
                                 if (!(d2 <= d2max)) continue;
+                                if (d2 == 0.0) coincident = true;
                                 if (pass) col[w] = static_cast<int32_t>(j);
                                 ++w;
                             }
@@ -310,6 +312,7 @@ void family_search(int64_t n, const double* x, double delta, std::vector<int64_t
                     count[i] = w;
             }
         });
+        if (coincident) fail(PD_EINVAL, "two nodes share a position (a zero-length bond has no stretch)");
     }
 }
 

@@ -245,3 +245,42 @@ def test_argument_errors():
             g.set_integrator("euler_cromer", 0.0)
         with pytest.raises(PdmiError):
             g.set_lanes_per_node(3)
+
+
+@pytest.mark.parametrize("mapping,lanes", [("sliced", 4), ("staged", 2)])
+def test_all_bonds_broken_free_flight(oracle_lib, mapping, lanes):
+    """Every bond broken: no bond forces, damage 1 everywhere, and each node follows the
+    Euler-Cromer recurrence of a constant body force exactly (v_k = k h b, u_k = h b dt
+    k (k + 1) / 2 up to rounding), as the oracle does."""
+    from paper_2105_04150_amd import Simulation
+    w = pi.workload("block10", dims=(7, 6, 5), steps=50)
+    rp, col = oracle_lib.family(w.coords, w.horizon)
+    broken = np.ones(rp[-1], dtype=np.uint8)
+    bhat = np.tile([0.0, 0.0, -1.0], (w.n, 1))
+    bmag = 2.0e6
+    o = oracle_lib.OracleSim(w.coords, rp, col, c=w.c, s0=w.s0, rho=w.rho, dt=w.dt, vol=w.volume,
+                             bhat=bhat, bmag=bmag, broken=broken)
+    o.run(w.steps)
+    with Simulation() as g:
+        g.set_mapping(mapping, lanes)
+        g.build_family(w.coords, w.horizon)
+        g.set_integrator("euler_cromer", w.dt)
+        g.set_material(w.rho, w.c, w.s0, 0.0, w.volume)
+        g.break_bonds(broken)
+        g.set_body_force(bhat, bmag)
+        g.step(w.steps)
+        u = g.u()
+        k = w.steps
+        uz = (w.dt / w.rho) * bmag * w.dt * k * (k + 1) / 2.0
+        assert np.abs(u[:, 2] + uz).max() <= 1e-12 * uz and np.abs(u[:, :2]).max() == 0.0
+        assert rel_err(u, o.u) <= TOL_FP64
+        assert np.all(g.damage() == 1.0) and np.all(g.broken())
+
+
+def test_coincident_nodes_rejected():
+    from paper_2105_04150_amd import PdmiError, Simulation
+    x = pi.lattice((4, 4, 4), 1.0e-3)[0]
+    x[7] = x[3]  # two nodes at one position
+    with Simulation() as g:
+        with pytest.raises(PdmiError):
+            g.build_family(x, 3.015e-3)
