@@ -22,22 +22,36 @@ __device__ __forceinline__ double rsq64(double x)
 }
 
 // 1 - (1+q)^(-1/2).  Series q/2 - 3q^2/8 + 5q^3/16 - 35q^4/128 + 63q^5/256 - 231q^6/1024
-// (c6, c5 are the two innermost coefficients; callers in hot loops pass them from
-// registers, since an FMA with two constant operands costs two extra moves here);
+// (hot loops pass the coefficients from registers: series_coef_regs());
 // the first omitted term, 429q^7/2048, is below 2e-15 of the sum for |q| < 4e-3.  Larger
 // |q| (strongly compressed or broken bonds) takes the closed form, whose cancellation
 // costs at most 1e-16/|q| < 3e-14 relative there.
-__device__ __forceinline__ double one_minus_rsqrt1p(double q, double c6 = -231.0 / 1024.0, double c5 = 63.0 / 256.0)
+struct SeriesCoef {
+    double c6 = -231.0 / 1024.0, c5 = 63.0 / 256.0, c4 = -35.0 / 128.0, c3 = 5.0 / 16.0, c2 = -3.0 / 8.0;
+};
+
+__device__ __forceinline__ double one_minus_rsqrt1p(double q, const SeriesCoef& k = SeriesCoef())
 {
     if (fabs(q) < 4.0e-3) {
-        double p = __builtin_fma(c6, q, c5);
-        p = __builtin_fma(p, q, -35.0 / 128.0);
-        p = __builtin_fma(p, q, 5.0 / 16.0);
-        p = __builtin_fma(p, q, -3.0 / 8.0);
+        double p = __builtin_fma(k.c6, q, k.c5);
+        p = __builtin_fma(p, q, k.c4);
+        p = __builtin_fma(p, q, k.c3);
+        p = __builtin_fma(p, q, k.c2);
         p = __builtin_fma(p, q, 0.5);
         return q * p;
     }
     return 1.0 - rsq64<2>(1.0 + q);
+}
+
+// Series coefficients as opaque registers: the outer ones in scalar registers (each FMA
+// of the Horner chain reads one), the innermost in a vector register (the first FMA
+// reads two constants).
+__device__ __forceinline__ SeriesCoef series_coef_regs()
+{
+    SeriesCoef k;
+    asm volatile("" : "+s"(k.c6), "+s"(k.c4), "+s"(k.c3), "+s"(k.c2));
+    asm volatile("" : "+v"(k.c5));
+    return k;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that each XCD

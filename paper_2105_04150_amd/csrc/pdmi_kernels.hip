@@ -29,7 +29,7 @@ namespace {
 __device__ __forceinline__ bool slot_force(int32_t c, const double2 p0, const double2 p1, const double2 p2,
                                            double X0, double X1, double X2, double U0, double U1, double U2,
                                            double kv, double q0, double& F0, double& F1, double& F2,
-                                           double c6 = -231.0 / 1024.0, double c5 = 63.0 / 256.0)
+                                           const SeriesCoef& sk = SeriesCoef())
 {
     const double xi0 = p0.x - X0, xi1 = p0.y - X1, xi2 = p1.x - X2;
     const double e0 = p1.y - U0, e1 = p2.x - U1, e2 = p2.y - U2;
@@ -43,7 +43,7 @@ __device__ __forceinline__ bool slot_force(int32_t c, const double2 p0, const do
     const bool brk = c >= 0 && q >= q0;
     const bool alive = c >= 0 && !brk;
     // broken and padding slots evaluate g(0) = 0 and add nothing
-    const double coef = (kv * iL) * one_minus_rsqrt1p(alive ? q : 0.0, c6, c5);
+    const double coef = (kv * iL) * one_minus_rsqrt1p(alive ? q : 0.0, sk);
     F0 = __builtin_fma(coef, y0, F0);
     F1 = __builtin_fma(coef, y1, F1);
     F2 = __builtin_fma(coef, y2, F2);
@@ -215,8 +215,7 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
     // arrays end with kRowUnroll spare rows, so every prefetch is in bounds and no load
     // sits behind a branch (rows prefetched past T belong to the next slice; unused).
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
-    double c6 = -231.0 / 1024.0, c5 = 63.0 / 256.0;  // series coefficients kept in registers
-    asm volatile("" : "+v"(c6), "+v"(c5));
+    const SeriesCoef sk = series_coef_regs();
     if (T > 0) {
         auto col_at = [&](int t) -> int32_t {
             const uint32_t off = static_cast<uint32_t>(t) * (kWave * 4u) + lane4;
@@ -256,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 brk[u] = slot_force(c[u], p[u][0], p[u][1], p[u][2], X0, X1, X2, U0, U1, U2, kv[u], P.q0, F0, F1, F2,
-                                    c6, c5);
+                                    sk);
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (brk[u]) {
@@ -332,8 +331,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     uint16_t* __restrict__ entw = A.ent;
     int32_t* __restrict__ bstep = A.bstep;
     // the two innermost series coefficients stay in registers
-    double c6 = -231.0 / 1024.0, c5 = 63.0 / 256.0;
-    asm volatile("" : "+v"(c6), "+v"(c5));
+    const SeriesCoef sk = series_coef_regs();
     const double2* __restrict__ ent2 = reinterpret_cast<const double2*>(A.ent);
 
     // sentinel record (padding entries point at it), volume 0
@@ -407,7 +405,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             return slot_force32(c, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2,
                                 (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : cvf,
                                 q0f, Ff0, Ff1, Ff2);
-        return slot_force(c, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2, c6, c5);
+        return slot_force(c, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2, sk);
     };
     // a slot that broke in this pass: flag it (irreversible) and record the pass
     auto broke = [&](int64_t ds, uint16_t e) {
