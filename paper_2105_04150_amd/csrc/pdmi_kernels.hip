@@ -284,9 +284,10 @@ __device__ __forceinline__ void wave_sync()
 
 // Staged step kernel: one workgroup of S wavefronts per 64-node slice, one lane per node.
 // Wavefront w takes the slice's pieces w, w + S, w + 2S, ...  For every piece, the
-// wavefront loads the range's node records (and volumes) and the piece's slot entries
-// into registers while its previous piece is being computed, then copies them to its
-// own LDS area; every slot reads its neighbour from LDS.  Each record crosses the
+// wavefront loads the range's node records and the piece's slot entries straight into
+// its own LDS area (gfx950 global_load_lds_dwordx4, no staging registers, which leaves
+// room for six wavefronts per SIMD to cover the load latency); per-node weights come
+// through registers one piece ahead.  Every slot reads its neighbour from LDS.  Each record crosses the
 // vector-memory path once per piece instead of once per slot.  Per-slot stiffness, when
 // present, streams from global memory (two rows one piece ahead, the rest when the piece
 // starts, which keeps the register count at four wavefronts per SIMD).  Rows are processed in pairs so
@@ -350,8 +351,8 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
     float Ff0 = 0.0f, Ff1 = 0.0f, Ff2 = 0.0f;
 
-    // staging registers of the next piece
-    double2 r0, r1, r2, r3, e0;
+    // staging registers of the next piece (weights and stiffness; records and entries go
+    // straight to LDS)
     double vs0 = 0.0, vs1 = 0.0;
     int vlen = 0;
     constexpr int kKPre = 2;  // stiffness rows fetched a piece ahead; the rest when the piece starts
@@ -362,12 +363,6 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     // (rows >= T are never read); volumes from clamped addresses.
     auto issue = [&](int p, int64_t e) {
         const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
-        const double2* rs = rin + 3 * static_cast<int64_t>(m.x) + lane;
-        r0 = rs[0];
-        r1 = rs[kWave];
-        r2 = rs[2 * kWave];
-        r3 = rs[3 * kWave];
-        e0 = ent2[e / 8 + lane];
         if (WSTAGE) {
             const int len = m.y & 0xff;
             vlen = len;
@@ -378,12 +373,17 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
 #pragma unroll
             for (int t = 0; t < kKPre; ++t) knext[t] = __builtin_nontemporal_load(A.kslot + e + t * kWave + lane);
     };
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    auto dma = [&](int p, int64_t e) {
+        const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
+        const double2* rs = rin + 3 * static_cast<int64_t>(m.x) + lane;
+        __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs + kWave, (lds_ptr)(lrec + kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs + 2 * kWave, (lds_ptr)(lrec + 2 * kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs + 3 * kWave, (lds_ptr)(lrec + 3 * kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(ent2 + e / 8 + lane, (lds_ptr)(lent), 16, 0, 0);
+    };
     auto commit = [&]() {
-        lrec[lane] = r0;
-        lrec[lane + kWave] = r1;
-        lrec[lane + 2 * kWave] = r2;
-        lrec[lane + 3 * kWave] = r3;
-        reinterpret_cast<double2*>(lent)[lane] = e0;
         if (WSTAGE) {
             if (lane < vlen) lvol[lane] = vs0;
             if (lane + kWave < vlen) lvol[lane + kWave] = vs1;
@@ -420,6 +420,10 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;  // first entry of piece p + S
             for (int q = p + 1; q < p + S && q < p1; ++q) ent_next += static_cast<int64_t>(rows_of(q)) * kWave;
             wave_sync();  // the previous piece is no longer read
+            dma(p, ent);
+            // s_waitcnt with vmcnt = 0 (expcnt and lgkmcnt at their no-wait maxima): the
+            // piece's direct-to-LDS loads have landed
+            __builtin_amdgcn_s_waitcnt(0x0F70);
             commit();
             if (STIFF)
 #pragma unroll
