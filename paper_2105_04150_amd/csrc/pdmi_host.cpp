@@ -1677,6 +1677,7 @@ int pd_set_mapping(pd_ctx* ctx, int mapping, int lanes)
         if (mapping == ctx->mapping && mapping == PD_MAP_STAGED) {  // same layout, other launch shape
             ctx->lanes = lanes;
             ctx->drop_graphs();
+            ctx->tape_valid = false;  // a recompute would sum partial forces in another order
             return;
         }
         HostState S = snapshot(ctx);

@@ -184,6 +184,11 @@ def test_adjoint_argument_errors():
     g.step(1)  # the recording is discarded by any further step
     with pytest.raises(PdmiError):
         g.adj_backward(sensors, np.zeros((5, 3)))
+    g.set_mapping("staged", 1)
+    g.adj_forward(10, 4)
+    g.set_mapping("staged", 2)  # another launch shape discards it too
+    with pytest.raises(PdmiError):
+        g.adj_backward(sensors, np.zeros((5, 3)))
     with pytest.raises(PdmiError):
         g.adj_forward(0, 4)
     with pytest.raises(PdmiError):
