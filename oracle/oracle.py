@@ -59,7 +59,8 @@ class _Problem(C.Structure):
                 ("c", C.c_double), ("s0", C.c_double), ("rho", C.c_double),
                 ("eta", C.c_double), ("dt", C.c_double), ("bhat", C.c_void_p),
                 ("bmag", C.c_double), ("bc_kind", C.c_void_p), ("bc_sched", C.c_void_p),
-                ("bc_val", C.c_void_p), ("scheme", C.c_int32), ("nthreads", C.c_int32)]
+                ("bc_val", C.c_void_p), ("scheme", C.c_int32), ("nthreads", C.c_int32),
+                ("ramp_T", C.c_double), ("nofail", C.c_void_p)]
 
 
 class _State(C.Structure):
@@ -104,7 +105,7 @@ class OracleSim:
 
     def __init__(self, coords, row_ptr, col, *, c, s0, rho, dt, vol, scheme="euler_cromer",
                  eta=0.0, kslot=None, bhat=None, bmag=0.0, bcs=(), nthreads=0,
-                 record_breaks=False, frozen=None, broken=None):
+                 record_breaks=False, frozen=None, broken=None, ramp_T=1.0, nofail=None):
         lib = _load()
         self._lib = lib
         self.x = np.ascontiguousarray(coords, dtype=np.float64)
@@ -117,10 +118,15 @@ class OracleSim:
         self.kslot = None if kslot is None else np.ascontiguousarray(kslot, dtype=np.float64)
         self.bhat = None if bhat is None else np.ascontiguousarray(bhat, dtype=np.float64)
         self.bc_kind, self.bc_sched, self.bc_val = bc_arrays(n, bcs)
+        # per-node no-failure flags (bonds touching a flagged node never break)
+        self.nofail = None if nofail is None else np.ascontiguousarray(nofail, dtype=np.uint8)
+        if self.nofail is not None and self.nofail.shape != (n,):
+            raise ValueError("nofail needs one flag per node")
         self.P = _Problem(n, _ptr(self.x), _ptr(self.vol), _ptr(self.row_ptr), _ptr(self.col),
                           _ptr(self.kslot), float(c), float(s0), float(rho), float(eta), float(dt),
                           _ptr(self.bhat), float(bmag), _ptr(self.bc_kind), _ptr(self.bc_sched),
-                          _ptr(self.bc_val), SCHEMES[scheme], int(nthreads))
+                          _ptr(self.bc_val), SCHEMES[scheme], int(nthreads), float(ramp_T),
+                          _ptr(self.nofail))
         self.u = np.zeros((n, 3))
         self.v = np.zeros((n, 3))
         self.a = np.zeros((n, 3))

@@ -23,6 +23,9 @@
  *   damage          phi_i = 1 - sum_j mu_ij V_j / sum_j V_j            (Sec. 2.2, local damage)
  *   integrators     velocity Verlet (Eqs. Velocity_Verlet1-3), Euler-Cromer and forward Euler
  *                   (the integrator classes listed in Sec. 3.6; their update rules are not printed).
+ *   quasi-static    prescribed displacements ramped by a fifth-order polynomial in time with
+ *   loading         zero initial velocity and acceleration (Examples 2 and 3, Secs. 6-7), and
+ *                   'no-failure zones': bonds of flagged nodes never break (Secs. 5.1, 6, 7).
  *   adjoint         reverse-mode derivative of an Euler-Cromer run with the break schedule
  *                   frozen, w.r.t. per-slot stiffness and body-force magnitude.
  */
@@ -58,10 +61,12 @@ typedef struct pdo_problem {
     const double *bhat;      /* n*3 body-force direction field, or NULL */
     double bmag;             /* body-force magnitude: b_i = bmag * bhat_i */
     const uint8_t *bc_kind;  /* n*3: PDO_FREE / PDO_DISP / PDO_VEL, or NULL (no constraints) */
-    const uint8_t *bc_sched; /* n*3: 0 -> g(t) = 1, 1 -> g(t) = t */
+    const uint8_t *bc_sched; /* n*3: 0 -> g(t) = 1, 1 -> g(t) = t, 2 -> fifth-order ramp over ramp_T */
     const double *bc_val;    /* n*3 amplitudes A */
     int32_t scheme;          /* PDO_EC / PDO_VV / PDO_FE */
     int32_t nthreads;        /* <= 0: library default */
+    double ramp_T;           /* duration of the fifth-order ramp (schedule 2) */
+    const uint8_t *nofail;   /* n or NULL: 1 = no-failure zone, bonds touching the node never break */
 } pdo_problem;
 
 typedef struct pdo_state {
@@ -241,7 +246,8 @@ void pdo_force(const pdo_problem *P, pdo_state *S, const double *u, int64_t k, d
             double r = sqrt((y0 * y0 + y1 * y1) + y2 * y2);
             double L = sqrt((xi0 * xi0 + xi1 * xi1) + xi2 * xi2);
             double s = (r - L) / L;
-            if (!S->frozen && s >= P->s0) {
+            const int unbreakable = P->nofail && (P->nofail[i] || P->nofail[j]);
+            if (!S->frozen && !unbreakable && s >= P->s0) {
                 S->broken[b] = 1;
                 if (S->break_step) S->break_step[b] = (int32_t)k;
                 continue;
@@ -270,16 +276,40 @@ static int bc_kind(const pdo_problem *P, int64_t i, int d)
     return P->bc_kind ? P->bc_kind[3 * i + d] : PDO_FREE;
 }
 
-static double sched_g(int sched, double t) { return sched == 1 ? t : 1.0; }
-static double sched_dg(int sched) { return sched == 1 ? 1.0 : 0.0; }
+/* Time schedules g(t) of a prescribed quantity and their derivatives:
+ *   0: g = 1;   1: g = t;
+ *   2: the fifth-order ramp from 0 to 1 over [0, T] whose first and second derivatives
+ *      vanish at both ends, g = tau^3 (10 - 15 tau + 6 tau^2) with tau = t / T, and g = 1
+ *      from T on (displacements ramped smoothly by a fifth-order polynomial, Secs. 6-7). */
+static double sched_g(const pdo_problem *P, int sched, double t)
+{
+    if (sched == 1) return t;
+    if (sched == 2) {
+        if (t >= P->ramp_T) return 1.0;
+        double tau = t / P->ramp_T;
+        return tau * tau * tau * (10.0 - 15.0 * tau + 6.0 * tau * tau);
+    }
+    return 1.0;
+}
+
+static double sched_dg(const pdo_problem *P, int sched, double t)
+{
+    if (sched == 1) return 1.0;
+    if (sched == 2) {
+        if (t >= P->ramp_T) return 0.0;
+        double tau = t / P->ramp_T;
+        return 30.0 * tau * tau * (1.0 - tau) * (1.0 - tau) / P->ramp_T;
+    }
+    return 0.0;
+}
 
 /* Prescribed velocity of a constrained component at time t. */
 static double bc_velocity(const pdo_problem *P, int64_t i, int d, double t)
 {
     double A = P->bc_val[3 * i + d];
     int sc = P->bc_sched[3 * i + d];
-    if (P->bc_kind[3 * i + d] == PDO_DISP) return A * sched_dg(sc);
-    return A * sched_g(sc, t);
+    if (P->bc_kind[3 * i + d] == PDO_DISP) return A * sched_dg(P, sc, t);
+    return A * sched_g(P, sc, t);
 }
 
 /* Prescribed displacement at time t; uprev is the component's displacement one step earlier. */
@@ -287,8 +317,8 @@ static double bc_displacement(const pdo_problem *P, int64_t i, int d, double t, 
 {
     double A = P->bc_val[3 * i + d];
     int sc = P->bc_sched[3 * i + d];
-    if (P->bc_kind[3 * i + d] == PDO_DISP) return A * sched_g(sc, t);
-    return uprev + P->dt * (A * sched_g(sc, t));
+    if (P->bc_kind[3 * i + d] == PDO_DISP) return A * sched_g(P, sc, t);
+    return uprev + P->dt * (A * sched_g(P, sc, t));
 }
 
 /* ------------------------------------------------------------------ time integration */

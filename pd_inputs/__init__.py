@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "splitmix64", "uniform01", "normal",
     "lattice", "lattice_index", "face_nodes", "pmb_micromodulus",
-    "BC_DISP", "BC_VEL", "SCHED_CONST", "SCHED_LINEAR", "BCSpec",
+    "BC_DISP", "BC_VEL", "SCHED_CONST", "SCHED_LINEAR", "SCHED_RAMP5", "BCSpec",
     "notch_mask", "gaussian_node_field", "slot_stiffness", "sample_nodes",
     "Workload", "workload", "WORKLOADS", "batch_instances",
 ]
@@ -106,6 +106,7 @@ BC_DISP = 1      # prescribed displacement u_c = A_c g(t), velocity A_c g'(t)
 BC_VEL = 2       # prescribed velocity v_c = A_c g(t), displacement advanced by dt * v_c
 SCHED_CONST = 0  # g(t) = 1, g'(t) = 0
 SCHED_LINEAR = 1  # g(t) = t, g'(t) = 1
+SCHED_RAMP5 = 2  # fifth-order ramp from 0 to 1 over a ramp time T, then 1
 
 
 @dataclass
@@ -115,7 +116,7 @@ class BCSpec:
     comp_mask: int              # bit d set => component d constrained
     kind: int                   # BC_DISP or BC_VEL
     value: Tuple[float, float, float]
-    sched: int                  # SCHED_CONST or SCHED_LINEAR
+    sched: int                  # SCHED_CONST, SCHED_LINEAR or SCHED_RAMP5
 
 
 # --------------------------------------------------------------------------- notch, fields, sensors
