@@ -66,6 +66,10 @@ extern "C" {
 
 #define PD_SCHED_CONST 0    /* g(t) = 1 */
 #define PD_SCHED_LINEAR 1   /* g(t) = t */
+#define PD_SCHED_RAMP5 2    /* g(t) = 10 tau^3 - 15 tau^4 + 6 tau^5, tau = t / T, for t < T, then 1:
+                               a fifth-order ramp from 0 to 1 whose velocity and acceleration
+                               vanish at both ends (the smooth displacement loading of the
+                               quasi-static examples, Secs. 6-7); T set by pd_set_bc_ramp */
 
 typedef struct pd_ctx pd_ctx;
 
@@ -178,6 +182,16 @@ int pd_set_bcs(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes, int c
 /* Remove every boundary condition of instance `inst`. */
 int pd_clear_bcs(pd_ctx *ctx, int32_t inst);
 
+/* Ramp duration T > 0 (seconds) of every PD_SCHED_RAMP5 component of instance `inst`
+ * (default 1).  Errors: PD_EINVAL (T not positive and finite). */
+int pd_set_bc_ramp(pd_ctx *ctx, int32_t inst, double ramp_time);
+
+/* No-failure zones (Secs. 5.1, 6, 7): the m nodes (host ids, user order) of instance
+ * `inst` become the zone, replacing any earlier one; a bond with either end in the zone
+ * never breaks from now on (bonds already broken stay broken, recorded break steps are
+ * kept).  m = 0 removes the zone.  Errors: PD_EINVAL (node id out of range). */
+int pd_set_no_fail(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes);
+
 /* Body force density b_i = magnitude * b_hat_i (N/m^3) of instance `inst`;
  * b_hat: host n x 3, user order; NULL removes it. */
 int pd_set_body_force(pd_ctx *ctx, int32_t inst, const double *b_hat, double magnitude);
@@ -217,6 +231,18 @@ int pd_get_damage(pd_ctx *ctx, int32_t inst, double *out);
 
 /* Broken flags of every slot: out[nnz] (host, user CSR order), 1 = broken. */
 int pd_get_broken(pd_ctx *ctx, int32_t inst, uint8_t *out);
+
+/* Bond force density F_i = sum_j f_ij V_j (Eq. discrete EOM without the body force) at
+ * the current displacement, over the bonds intact now; no bond breaks and the state is
+ * not changed.  Evaluated on the device for every instance by the step kernel in a
+ * force-only mode.  out: host, n x 3 doubles, user order. */
+int pd_get_force(pd_ctx *ctx, int32_t inst, double *out);
+
+/* Resultant force of a node set: out[0..2] = sum over the m nodes (host ids, user order)
+ * of V_i F_i with F as pd_get_force, summed on the device in a fixed order (the load
+ * measured "in the bonds of the displacement-controlled particles", Sec. 6).
+ * Errors: PD_EINVAL (node id out of range, m < 1). */
+int pd_get_resultant(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes, double out[3]);
 
 /* Overwrite the state of instance `inst` (checkpoint / restart, Sec. 3.6 "initiating
  * a simulation from an intermediate state").  Any of u, v, a (host n x 3) or broken

@@ -215,8 +215,9 @@ def adjoint_ec(sim: OracleSim, *a, **kw):
     return sim.adjoint_ec(*a, **kw)
 
 
-def from_workload(w, nthreads: int = 0, record_breaks: bool = False, method: str = "cells"):
-    """Oracle simulation of a pd_inputs.Workload (family built by the oracle itself)."""
+def from_workload(w, nthreads: int = 0, record_breaks: bool = False, method: str = "cells", frozen=None):
+    """Oracle simulation of a pd_inputs.Workload (family built by the oracle itself);
+    ``frozen``: an optional fixed break schedule (slot b acts in pass k iff k < frozen[b])."""
     from pd_inputs import notch_mask, gaussian_node_field, slot_stiffness
     row_ptr, col = family(w.coords, w.horizon, method)
     broken = None
@@ -227,6 +228,11 @@ def from_workload(w, nthreads: int = 0, record_breaks: bool = False, method: str
         sig, ell, seed = w.stiffness_field
         kslot = slot_stiffness(w.c, gaussian_node_field(w.dims, sig, ell, seed), row_ptr, col)
     bhat, bmag = (None, 0.0) if w.body_force is None else w.body_force
+    nofail = None
+    if w.nofail is not None:
+        nofail = np.zeros(w.n, dtype=np.uint8)
+        nofail[w.nofail] = 1
     return OracleSim(w.coords, row_ptr, col, c=w.c, s0=w.s0, rho=w.rho, dt=w.dt, vol=w.volume,
-                     scheme=w.scheme, kslot=kslot, bhat=bhat, bmag=bmag, bcs=w.bcs,
-                     nthreads=nthreads, record_breaks=record_breaks, broken=broken)
+                     scheme=w.scheme, eta=w.eta, kslot=kslot, bhat=bhat, bmag=bmag, bcs=w.bcs,
+                     nthreads=nthreads, record_breaks=record_breaks, broken=broken,
+                     ramp_T=1.0 if w.ramp_T is None else w.ramp_T, nofail=nofail, frozen=frozen)

@@ -13,7 +13,7 @@ import numpy as np
 from . import _binding as B
 from ._binding import (PD_BC_DISP, PD_BC_VEL, PD_EULER_CROMER, PD_EULER_FORWARD, PD_FP32,  # noqa: F401
                        PD_FP64, PD_MAP_SLICED, PD_MAP_STAGED, PD_ORDER_MORTON, PD_ORDER_NATURAL,
-                       PD_SCHED_CONST, PD_SCHED_LINEAR, PD_VELOCITY_VERLET, PdmiError)
+                       PD_SCHED_CONST, PD_SCHED_LINEAR, PD_SCHED_RAMP5, PD_VELOCITY_VERLET, PdmiError)
 
 SCHEMES = {"euler_cromer": PD_EULER_CROMER, "velocity_verlet": PD_VELOCITY_VERLET,
            "forward_euler": PD_EULER_FORWARD}
@@ -74,6 +74,22 @@ class Simulation:
 
     def clear_bcs(self, inst=0):
         B.pd_clear_bcs(self.ctx, inst)
+
+    def set_bc_ramp(self, ramp_time, inst=0):
+        """Duration of the fifth-order ramp of every PD_SCHED_RAMP5 component."""
+        B.pd_set_bc_ramp(self.ctx, inst, ramp_time)
+
+    def set_no_fail(self, nodes, inst=0):
+        """No-failure zone (node ids; None or empty removes it): their bonds never break."""
+        B.pd_set_no_fail(self.ctx, inst, nodes)
+
+    def force(self, inst=0):
+        """Bond force density (n x 3) at the current displacement, intact bonds only."""
+        return B.pd_get_force(self.ctx, inst)
+
+    def resultant(self, nodes, inst=0):
+        """sum of V_i F_i over the given nodes (the reaction measured at a loaded set)."""
+        return B.pd_get_resultant(self.ctx, inst, nodes)
 
     def set_body_force(self, b_hat, magnitude, inst=0):
         B.pd_set_body_force(self.ctx, inst, b_hat, magnitude)
@@ -155,9 +171,13 @@ def apply_workload(sim: Simulation, w, inst: int = 0, row_ptr=None, col=None, st
     import pd_inputs as pi
     if row_ptr is None:
         row_ptr, col = sim.family(inst)
-    sim.set_material(w.rho, w.c, w.s0, 0.0, w.volume, inst=inst)
+    sim.set_material(w.rho, w.c, w.s0, w.eta, w.volume, inst=inst)
     for bc in w.bcs:
         sim.set_bcs(bc.nodes, bc.comp_mask, bc.kind, bc.value, bc.sched, inst=inst)
+    if w.ramp_T is not None:
+        sim.set_bc_ramp(w.ramp_T, inst=inst)
+    if w.nofail is not None:
+        sim.set_no_fail(w.nofail, inst=inst)
     if w.notch is not None:
         sim.break_bonds(pi.notch_mask(w.ijk, row_ptr, col, *w.notch), inst=inst)
     if w.stiffness_field is not None:

@@ -19,14 +19,15 @@ PD_FP64, PD_FP32 = 0, 1
 PD_ORDER_NATURAL, PD_ORDER_MORTON, PD_ORDER_AUTO = 0, 1, 2
 PD_EULER_CROMER, PD_VELOCITY_VERLET, PD_EULER_FORWARD = 0, 1, 2
 PD_BC_DISP, PD_BC_VEL = 1, 2
-PD_SCHED_CONST, PD_SCHED_LINEAR = 0, 1
+PD_SCHED_CONST, PD_SCHED_LINEAR, PD_SCHED_RAMP5 = 0, 1, 2
 PD_MAP_SLICED, PD_MAP_STAGED = 0, 1
 
 SYMBOLS = [
     "pd_create", "pd_destroy", "pd_last_error", "pd_build_family", "pd_build_family_batch",
     "pd_num_instances", "pd_instance_size", "pd_get_family", "pd_set_material", "pd_set_bond_stiffness",
     "pd_set_node_stiffness",
-    "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_body_force", "pd_set_integrator",
+    "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_bc_ramp", "pd_set_no_fail", "pd_get_force",
+    "pd_get_resultant", "pd_set_body_force", "pd_set_integrator",
     "pd_step", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
     "pd_get_info", "pd_last_step_ms", "pd_adj_forward", "pd_adj_backward", "pd_get_break_steps",
@@ -77,6 +78,10 @@ def load() -> C.CDLL:
         "pd_break_bonds": [P, i32, P],
         "pd_set_bcs": [P, i32, i64, P, C.c_int, C.c_int, P, C.c_int],
         "pd_clear_bcs": [P, i32],
+        "pd_set_bc_ramp": [P, i32, C.c_double],
+        "pd_set_no_fail": [P, i32, i64, P],
+        "pd_get_force": [P, i32, P],
+        "pd_get_resultant": [P, i32, i64, P, P],
         "pd_set_body_force": [P, i32, P, d],
         "pd_set_integrator": [P, C.c_int, d],
         "pd_step": [P, i64],
@@ -209,6 +214,26 @@ def pd_set_bcs(ctx, inst: int, nodes, comp_mask: int, kind: int, value, sched: i
 
 def pd_clear_bcs(ctx, inst: int = 0) -> None:
     _check(ctx, load().pd_clear_bcs(ctx, inst))
+
+
+def pd_set_bc_ramp(ctx, inst: int, ramp_time: float) -> None:
+    _check(ctx, load().pd_set_bc_ramp(ctx, inst, float(ramp_time)))
+
+
+def pd_set_no_fail(ctx, inst: int, nodes) -> None:
+    nd = np.ascontiguousarray(np.zeros(0) if nodes is None else nodes, dtype=np.int64)
+    _check(ctx, load().pd_set_no_fail(ctx, inst, nd.shape[0], _p(nd) if nd.shape[0] else None))
+
+
+def pd_get_force(ctx, inst: int = 0) -> np.ndarray:
+    return _get3(load().pd_get_force, ctx, inst)
+
+
+def pd_get_resultant(ctx, inst: int, nodes) -> np.ndarray:
+    nd = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros(3)
+    _check(ctx, load().pd_get_resultant(ctx, inst, nd.shape[0], _p(nd) if nd.shape[0] else None, _p(out)))
+    return out
 
 
 def pd_set_body_force(ctx, inst: int, b_hat, magnitude: float) -> None:

@@ -29,7 +29,8 @@ def _run(cmd):
     return r.stdout
 
 
-KERNEL_SOURCES = ("pdmi_kernels.hip", "pdmi_adjoint.hip")
+KERNEL_SOURCES = ("pdmi_step_sliced.hip", "pdmi_step_staged_f64.hip", "pdmi_step_staged_f32.hip",
+                  "pdmi_kernels.hip", "pdmi_adjoint.hip")
 
 
 def build(verbose: bool = False) -> str:

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sliced(AdjArgs A)
         for (int u = 0; u < 2; ++u) {
             const int64_t ds = base + static_cast<int64_t>(t + u) * kWave + lane;
             const int32_t c = A.col[ds];
-            adj_load<KM, VOLN>(A, P, ai, ds, c ^ (c >> 31), r[u]);
+            adj_load<KM, VOLN>(A, P, ai, ds, static_cast<int32_t>(col_node(c)), r[u]);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
     int32_t bs[kPieceRows];
     double gr[kPieceRows], kr[kPieceRows];
     auto slot = [&](int t, int64_t ds, uint16_t e) {
-        const uint32_t off = e & 0x7fff;  // byte offset of the record; 3 * index = off / 16 for nu
+        const uint32_t off = e & kEntOff;  // byte offset of the record; 3 * index = off / 16 for nu
         const double2 q0 = *reinterpret_cast<const double2*>(lrecb + off);
         const double2 q1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
         const double2 q2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void bstep_init_kernel(int32_t* bstep, cons
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= ns) return;
-    const bool broken = col ? col[i] < 0 : (ent[i] & 0x8000) != 0;
+    const bool broken = col ? col[i] < 0 : (ent[i] & kEntBroken) != 0;
     bstep[i] = broken ? kBrokeBefore : kNeverBroke;
 }
 
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void flags_at_kernel(const int32_t* bstep, 
         col[i] = broken ? ~j : j;
     } else {
         const uint16_t e = ent[i];
-        ent[i] = static_cast<uint16_t>((e & 0x7fff) | (broken ? 0x8000 : 0));
+        ent[i] = static_cast<uint16_t>((e & ~kEntBroken) | (broken ? kEntBroken : 0));
     }
 }
 

@@ -63,23 +63,54 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
     return (x < r) ? x * (m + 1) + j : r * (m + 1) + (x - r) * m + j;
 }
 
-__device__ __forceinline__ double sched(int lin, double t) { return lin ? t : 1.0; }
+// Time schedule g(t) of a prescribed quantity and its derivative: 0 constant, 1 linear,
+// 2 the fifth-order ramp tau^3 (10 - 15 tau + 6 tau^2), tau = t/T, from 0 to 1 over [0, T]
+// with zero first and second derivatives at both ends, then 1 (Secs. 6-7).  tau is
+// formed with the stored reciprocal iT = 1/T (no division in the node update).
+__device__ __forceinline__ double sched_g(int sc, double t, double T, double iT)
+{
+    if (sc == 1) return t;
+    if (sc == 2) {
+        if (t >= T) return 1.0;
+        const double tau = t * iT;
+        return tau * tau * tau * (10.0 - 15.0 * tau + 6.0 * tau * tau);
+    }
+    return 1.0;
+}
+
+__device__ __forceinline__ double sched_dg(int sc, double t, double T, double iT)
+{
+    if (sc == 1) return 1.0;
+    if (sc == 2) {
+        if (t >= T) return 0.0;
+        const double tau = t * iT;
+        return 30.0 * tau * tau * (1.0 - tau) * (1.0 - tau) * iT;
+    }
+    return 0.0;
+}
 
 // Prescribed velocity of component d at time t.
 __device__ __forceinline__ double bc_vel(const BCRec& r, int d, double t)
 {
-    const int kind = (r.code >> (2 * d)) & 3, lin = (r.code >> (8 + d)) & 1;
-    return kind == 1 ? r.A[d] * (lin ? 1.0 : 0.0) : r.A[d] * sched(lin, t);
+    const int kind = (r.code >> (2 * d)) & 3, sc = (r.code >> (8 + 2 * d)) & 3;
+    return kind == 1 ? r.A[d] * sched_dg(sc, t, r.T, r.iT) : r.A[d] * sched_g(sc, t, r.T, r.iT);
 }
 
 // Prescribed displacement of component d at time t; uprev one step earlier.
 __device__ __forceinline__ double bc_disp(const BCRec& r, int d, double t, double uprev, double dt)
 {
-    const int kind = (r.code >> (2 * d)) & 3, lin = (r.code >> (8 + d)) & 1;
-    return kind == 1 ? r.A[d] * sched(lin, t) : uprev + dt * (r.A[d] * sched(lin, t));
+    const int kind = (r.code >> (2 * d)) & 3, sc = (r.code >> (8 + 2 * d)) & 3;
+    const double g = sched_g(sc, t, r.T, r.iT);
+    return kind == 1 ? r.A[d] * g : uprev + dt * (r.A[d] * g);
 }
 
 __device__ __forceinline__ bool constrained(const BCRec& r, int d) { return ((r.code >> (2 * d)) & 3) != 0; }
+
+// Neighbour device index of a sliced slot word (intact or broken, no-failure bit dropped).
+__device__ __forceinline__ uint32_t col_node(int32_t c)
+{
+    return static_cast<uint32_t>(c ^ (c >> 31)) & static_cast<uint32_t>(kColNode);
+}
 
 __device__ __forceinline__ int64_t wave_uniform(int64_t v)
 {

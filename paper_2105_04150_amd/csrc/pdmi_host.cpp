@@ -90,6 +90,8 @@ struct Inst {
     double bmag = 0.0;
     std::vector<uint8_t> bc_kind, bc_sched;  // n*3
     std::vector<double> bc_val;              // n*3
+    double ramp_T = 1.0;                     // duration of the fifth-order ramp schedule
+    std::vector<uint8_t> nofail;             // user order, no-failure zone flags; empty = none
     // device layout
     std::vector<int64_t> perm;       // device-local node -> user node, -1 = padding
     std::vector<int64_t> iperm;      // user node -> device-local node
@@ -130,8 +132,10 @@ struct pd_ctx {
 
     int64_t nn = 0, ns = 0, nslices = 0;
     bool has_stiff = false, has_vol = false, has_body = false, has_knode = false;
+    bool has_nofail = false;         // some slot carries the no-failure bit
     DevBuf rec[2], um[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc,
         step_base, status, phi, pieces, slice_piece, ent;
+    DevBuf force, rset, rsum;        // force readout: F (SoA), node list and sum of a resultant
 
     // adjoint: per-slot break steps (recorded by every step while allocated) and the
     // (u, v) checkpoints of the last recorded forward run
@@ -469,13 +473,15 @@ void upload_bcs(pd_ctx* ctx)
                 const int kind = I.bc_kind[3 * u + d];
                 if (!kind) continue;
                 code |= kind << (2 * d);
-                code |= (I.bc_sched[3 * u + d] & 1) << (8 + d);
+                code |= (I.bc_sched[3 * u + d] & 3) << (8 + 2 * d);
                 r.A[d] = I.bc_val[3 * u + d];
             }
             if (code == 0) {
                 id[I.node_off + l] = kNodeFree;
             } else {
                 r.code = code;
+                r.T = I.ramp_T;
+                r.iT = 1.0 / I.ramp_T;
                 id[I.node_off + l] = static_cast<int32_t>(recs.size());
                 recs.push_back(r);
             }
@@ -688,23 +694,42 @@ void init_break_steps(pd_ctx* ctx, const Inst& I)
               "break-step init launch");
 }
 
-void upload_col(pd_ctx* ctx, Inst& I, const uint8_t* broken)
+// Per user slot: the bond touches a no-failure zone (empty without flags).
+std::vector<uint8_t> nofail_slots(const Inst& I)
+{
+    std::vector<uint8_t> nf;
+    if (I.nofail.empty()) return nf;
+    nf.assign(static_cast<size_t>(I.nnz), 0);
+    parallel_for(I.n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            for (int64_t b = I.row_ptr[i]; b < I.row_ptr[i + 1]; ++b) nf[b] = I.nofail[i] || I.nofail[I.col[b]];
+    });
+    return nf;
+}
+
+// Slot words of one instance from its broken flags and no-failure zones.  The recorded
+// break steps restart from the flags unless keep_bsteps (only the zones changed).
+void upload_col(pd_ctx* ctx, Inst& I, const uint8_t* broken, bool keep_bsteps = false)
 {
     ctx->tape_valid = false;
     I.br_sym = bond_symmetric(I, broken);
+    const std::vector<uint8_t> nf = nofail_slots(I);
+    const bool any_nf = !nf.empty();
     if (ctx->mapping == PD_MAP_STAGED) {
         std::vector<uint16_t> e(static_cast<size_t>(I.n_dslots));
         parallel_for(I.n_dslots, [&](int64_t s0, int64_t s1) {
             for (int64_t d = s0; d < s1; ++d) {
                 const int32_t b = I.dslot_user[d];
                 if (b < 0)
-                    e[d] = static_cast<uint16_t>(0x8000 | kEntPad);
+                    e[d] = static_cast<uint16_t>(kEntBroken | kEntPad);
                 else
-                    e[d] = static_cast<uint16_t>((48 * I.ent_idx[d]) | ((broken && broken[b]) ? 0x8000 : 0));
+                    e[d] = static_cast<uint16_t>((48 * I.ent_idx[d]) | ((broken && broken[b]) ? kEntBroken : 0) |
+                                                 ((any_nf && nf[b]) ? kEntNoFail : 0));
             }
         });
         upload(ctx->ent, e.data(), e.size() * sizeof(uint16_t), I.dslot_off * sizeof(uint16_t), ctx->stream);
-        init_break_steps(ctx, I);
+        if (!keep_bsteps) init_break_steps(ctx, I);
+        sync(ctx);
         return;
     }
     std::vector<int32_t> colv(static_cast<size_t>(I.n_dslots));
@@ -717,13 +742,14 @@ void upload_col(pd_ctx* ctx, Inst& I, const uint8_t* broken)
                     if (b < 0) {
                         colv[ds] = ~static_cast<int32_t>(ctx->nn);  // padding: the sentinel record
                     } else {
-                        const int32_t j = static_cast<int32_t>(I.node_off + I.iperm[I.col[b]]);
+                        const int32_t j = static_cast<int32_t>(I.node_off + I.iperm[I.col[b]]) |
+                                          ((any_nf && nf[b]) ? kColNoFail : 0);
                         colv[ds] = (broken && broken[b]) ? ~j : j;
                     }
                 }
     });
     upload(ctx->col, colv.data(), colv.size() * sizeof(int32_t), I.dslot_off * sizeof(int32_t), ctx->stream);
-    init_break_steps(ctx, I);
+    if (!keep_bsteps) init_break_steps(ctx, I);
     sync(ctx);
 }
 
@@ -737,7 +763,7 @@ std::vector<uint8_t> broken_of(pd_ctx* ctx, const Inst& I)
         std::vector<uint8_t> out(static_cast<size_t>(I.nnz), 0);
         for (int64_t d = 0; d < I.n_dslots; ++d) {
             const int32_t b = I.dslot_user[d];
-            if (b >= 0 && (e[d] & 0x8000)) out[b] = 1;
+            if (b >= 0 && (e[d] & kEntBroken)) out[b] = 1;
         }
         return out;
     }
@@ -1060,6 +1086,7 @@ void new_problem(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* con
     ctx->inst = std::move(insts);
     ctx->order = order == PD_ORDER_AUTO ? PD_ORDER_NATURAL : order;
     ctx->order_auto = order == PD_ORDER_AUTO;
+    ctx->has_nofail = false;
     ctx->step = 0;
     ctx->a_valid = false;
     ctx->vv_ahead = false;
@@ -1083,6 +1110,7 @@ StepArgs step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
     A.na = ctx->has_knode ? ctx->na.as<double>() : nullptr;
     A.nw = ctx->has_knode ? ctx->nw.as<double>() : nullptr;
     A.bhat = ctx->has_body ? ctx->bhat.as<double>() : nullptr;
+    A.force = ctx->force.p ? ctx->force.as<double>() : nullptr;
     A.slice_ptr = ctx->slice_ptr.as<int64_t>();
     A.slice_T = ctx->slice_T.as<int32_t>();
     A.slice_inst = ctx->slice_inst.as<int32_t>();
@@ -1111,13 +1139,24 @@ void launch_one(pd_ctx* ctx, int mode, int in, int out, int64_t step_local)
 {
     const StepArgs A = step_args(ctx, in, out, step_local);
     if (ctx->mapping == PD_MAP_STAGED)
-        hip_check(launch_step_staged(A, mode, fp32(ctx), ctx->lanes, ctx->stream), "step kernel launch");
+        hip_check(launch_step_staged(A, mode, fp32(ctx), ctx->lanes, ctx->has_nofail, ctx->stream),
+                  "step kernel launch");
     else
-        hip_check(launch_step(A, ctx->lanes, mode, ctx->has_stiff, ctx->stream), "step kernel launch");
+        hip_check(launch_step(A, ctx->lanes, mode, ctx->has_stiff, ctx->has_nofail, ctx->stream),
+                  "step kernel launch");
 }
 
 // Launch `count` consecutive steps starting at buffer parity `cur`, step_local offsets
 // 0..count-1 relative to the device step base, then advance the base.
+// Bond force density of the current level into ctx->force (SoA, stride nn): the step
+// kernel in its force-only mode, reading the record buffer that holds level `step`.
+void eval_force(pd_ctx* ctx)
+{
+    const size_t bytes = static_cast<size_t>(3 * ctx->nn) * sizeof(double);
+    if (!ctx->force.p || ctx->force.bytes < bytes) ctx->force.alloc(bytes);
+    launch_one(ctx, kModeForce, ctx->cur, 1 - ctx->cur, 0);
+}
+
 void launch_steps(pd_ctx* ctx, int mode, int cur, int64_t count)
 {
     for (int64_t i = 0; i < count; ++i) {
@@ -1223,9 +1262,11 @@ void check_symmetric(const Inst& I)
 void launch_ec(pd_ctx* ctx, const StepArgs& A)
 {
     if (ctx->mapping == PD_MAP_STAGED)
-        hip_check(launch_step_staged(A, kModeEC, false, ctx->lanes, ctx->stream), "step kernel launch");
+        hip_check(launch_step_staged(A, kModeEC, false, ctx->lanes, ctx->has_nofail, ctx->stream),
+                  "step kernel launch");
     else
-        hip_check(launch_step(A, ctx->lanes, kModeEC, ctx->has_stiff, ctx->stream), "step kernel launch");
+        hip_check(launch_step(A, ctx->lanes, kModeEC, ctx->has_stiff, ctx->has_nofail, ctx->stream),
+                  "step kernel launch");
 }
 
 }  // namespace
@@ -1433,7 +1474,8 @@ int pd_set_bcs(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t* nodes, int c
         if (m < 0 || (m > 0 && !nodes)) fail(PD_EINVAL, "bad node list");
         if (comp_mask < 1 || comp_mask > 7) fail(PD_EINVAL, "comp_mask must be in 1..7");
         if (kind != PD_BC_DISP && kind != PD_BC_VEL) fail(PD_EINVAL, "unknown BC kind");
-        if (sched != PD_SCHED_CONST && sched != PD_SCHED_LINEAR) fail(PD_EINVAL, "unknown schedule");
+        if (sched != PD_SCHED_CONST && sched != PD_SCHED_LINEAR && sched != PD_SCHED_RAMP5)
+            fail(PD_EINVAL, "unknown schedule");
         if (!value) fail(PD_EINVAL, "value is NULL");
         for (int d = 0; d < 3; ++d)
             if ((comp_mask >> d & 1) && !std::isfinite(value[d])) fail(PD_EINVAL, "BC value must be finite");
@@ -1464,6 +1506,42 @@ int pd_clear_bcs(pd_ctx* ctx, int32_t inst)
         std::fill(I.bc_val.begin(), I.bc_val.end(), 0.0);
         upload_bcs(ctx);
         ctx->vv_ahead = false;
+        ctx->drop_graphs();
+    });
+}
+
+int pd_set_bc_ramp(pd_ctx* ctx, int32_t inst, double ramp_time)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (!(ramp_time > 0.0) || !std::isfinite(ramp_time)) fail(PD_EINVAL, "ramp time must be positive and finite");
+        set_device(ctx);
+        I.ramp_T = ramp_time;
+        upload_bcs(ctx);
+        ctx->vv_ahead = false;
+        ctx->drop_graphs();
+    });
+}
+
+int pd_set_no_fail(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t* nodes)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (m < 0 || (m > 0 && !nodes)) fail(PD_EINVAL, "bad node list");
+        for (int64_t i = 0; i < m; ++i)
+            if (nodes[i] < 0 || nodes[i] >= I.n) fail(PD_EINVAL, "no-failure node id out of range");
+        set_device(ctx);
+        const std::vector<uint8_t> br = broken_of(ctx, I);
+        I.nofail.clear();
+        if (m > 0) {
+            I.nofail.assign(static_cast<size_t>(I.n), 0);
+            for (int64_t i = 0; i < m; ++i) I.nofail[nodes[i]] = 1;
+        }
+        ctx->has_nofail = false;
+        for (auto& J : ctx->inst) ctx->has_nofail |= !J.nofail.empty();
+        upload_col(ctx, I, br.data(), /*keep_bsteps=*/true);
         ctx->drop_graphs();
     });
 }
@@ -1618,6 +1696,44 @@ int pd_get_broken(pd_ctx* ctx, int32_t inst, uint8_t* out)
         set_device(ctx);
         auto b = broken_of(ctx, I);
         std::memcpy(out, b.data(), b.size());
+    });
+}
+
+int pd_get_force(pd_ctx* ctx, int32_t inst, double* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        set_device(ctx);
+        eval_force(ctx);
+        auto f = soa_of(ctx, I, ctx->force);
+        std::memcpy(out, f.data(), f.size() * sizeof(double));
+    });
+}
+
+int pd_get_resultant(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t* nodes, double out[3])
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (m < 1 || !nodes) fail(PD_EINVAL, "need at least one node");
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        std::vector<int64_t> idx(static_cast<size_t>(m));
+        for (int64_t i = 0; i < m; ++i) {
+            if (nodes[i] < 0 || nodes[i] >= I.n) fail(PD_EINVAL, "node id out of range");
+            idx[i] = I.node_off + I.iperm[nodes[i]];
+        }
+        set_device(ctx);
+        eval_force(ctx);
+        ctx->rset.alloc(idx.size() * sizeof(int64_t));
+        if (!ctx->rsum.p) ctx->rsum.alloc(3 * sizeof(double));
+        upload(ctx->rset, idx.data(), idx.size() * sizeof(int64_t), 0, ctx->stream);
+        hip_check(launch_resultant(ctx->force.as<double>(), ctx->nn, ctx->has_vol ? ctx->vol.as<double>() : nullptr,
+                                   I.volume, ctx->rset.as<int64_t>(), m, ctx->rsum.as<double>(), ctx->stream),
+                  "resultant launch");
+        download(out, ctx->rsum, 3 * sizeof(double), 0, ctx->stream);
+        sync(ctx);
     });
 }
 

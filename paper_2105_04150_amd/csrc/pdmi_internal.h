@@ -16,9 +16,10 @@
 //   slots         col[ns]         int32 per slot in "slices": a slice is the W = 64/G nodes one
 //                                 wavefront serves (G lanes per node); its slots are stored as
 //                                 T rows of 64 entries, entry (t, w*G + g) = slot t*G + g of the
-//                                 slice's node w.  col >= 0: intact bond to device node col;
-//                                 col < 0: ~col is the neighbour of a broken bond, or the
-//                                 sentinel nn for padding.
+//                                 slice's node w.  col >= 0: intact bond to device node
+//                                 col & kColNode, bit 30 (kColNoFail) set when the bond
+//                                 touches a no-failure zone; col < 0: ~col is the word of a
+//                                 broken bond, or the sentinel nn for padding.
 //   stiffness     kslot[ns]       f64 per slot, same layout (only with a per-slot stiffness field)
 //   node stiffness na[nn+1], nw[nn+1]  f64 per node (only with a per-node stiffness field,
 //                                 bond stiffness sqrt(k_i k_j)): na = sqrt(k_i), nw = sqrt(k_j) V_j;
@@ -31,9 +32,10 @@
 // copies a piece's node records and entries into LDS, then reads neighbours from there.
 //   pieces        int2 {first node of the range, len | T << 8} per piece
 //   slice_piece   first piece of every slice (+ one past the last)
-//   ent[ns]       uint16 per slot: bits 0..14 = byte offset of the neighbour's record in the
+//   ent[ns]       uint16 per slot: bits 0..13 = byte offset of the neighbour's record in the
 //                 staged copy (48 x index into the range; kEntPad for padding, the LDS
-//                 sentinel record), bit 15 = broken; slice_ptr gives each slice's first entry.
+//                 sentinel record), bit 14 = no-failure zone, bit 15 = broken; slice_ptr
+//                 gives each slice's first entry.
 //                 The entry array ends with kPieceRows spare rows (whole 8-row blocks are
 //                 loaded).
 #pragma once
@@ -53,8 +55,14 @@ constexpr int kPieceRows = 8;           // slot rows per staged piece
 constexpr int kStageChunks = 4 * 64;    // 16-byte record chunks one staged range load covers
 constexpr int kEntPad = kStageChunks * 16;  // entry byte offset of the LDS sentinel record
 constexpr int kRecPad = kStageChunks / 3 + 2;  // zero records after the sentinel
+// slot flags: a bond touching a no-failure zone never breaks (Secs. 5.1, 6, 7)
+constexpr int32_t kColNoFail = 0x40000000;  // sliced word: no-failure bit
+constexpr int32_t kColNode = 0x3fffffff;    // sliced word: neighbour index bits
+constexpr uint32_t kEntOff = 0x3fff;        // staged entry: record byte offset bits
+constexpr uint32_t kEntNoFail = 0x4000;     // staged entry: no-failure bit
+constexpr uint32_t kEntBroken = 0x8000;     // staged entry: broken bit
 static_assert(3 * kSegMax <= kStageChunks, "a range fits the staged record loads");
-static_assert(kEntPad < 0x8000, "entry offsets fit 15 bits");
+static_assert(kEntPad <= kEntOff, "entry offsets fit 14 bits");
 constexpr int32_t kNodeFree = -1;       // bc_id of an unconstrained node
 constexpr int32_t kNodePad = -2;        // bc_id of a padding node (never updated)
 
@@ -70,14 +78,18 @@ struct InstParams {
 };
 
 // Constraint of one node: per component d, kind in bits 2d..2d+1 (0 free, 1 displacement,
-// 2 velocity) and schedule in bit 8+d (0 constant, 1 linear in t).
+// 2 velocity) and schedule in bits 8+2d..9+2d (0 constant, 1 linear in t, 2 fifth-order
+// ramp over T).
 struct BCRec {
     double A[3];
+    double T, iT;   // ramp duration and its reciprocal
     int32_t code;
     int32_t pad_;
 };
 
-enum StepMode : int { kModeEC = 0, kModeVV = 1, kModeVVInit = 2, kModeFE = 3 };
+// kModeForce evaluates the bond force density of the current level into StepArgs::force
+// and changes nothing else (no integration, no breaking).
+enum StepMode : int { kModeEC = 0, kModeVV = 1, kModeVVInit = 2, kModeFE = 3, kModeForce = 4 };
 
 struct StepArgs {
     const double* rec_in;       // 6 doubles per node
@@ -92,6 +104,7 @@ struct StepArgs {
     const double* na;           // nullptr unless per-node stiffness (then kslot is nullptr)
     const double* nw;
     const double* bhat;         // bhat + d*nn, nullptr without body forces
+    double* force;              // kModeForce: bond force density out, force + d*nn
     const int64_t* slice_ptr;
     const int32_t* slice_T;
     const int32_t* slice_inst;
@@ -125,8 +138,8 @@ struct DamageArgs {
     const uint16_t* ent;
 };
 
-// sliced mapping (FP64)
-hipError_t launch_step(const StepArgs& a, int lanes, int mode, bool stiff, hipStream_t s);
+// sliced mapping (FP64); nofail: some slot carries the no-failure bit
+hipError_t launch_step(const StepArgs& a, int lanes, int mode, bool stiff, bool nofail, hipStream_t s);
 
 // velocity-Verlet drift of every node (fp32: master displacement and f32 records)
 hipError_t launch_drift(const StepArgs& a, bool fp32, hipStream_t s);
@@ -134,7 +147,14 @@ hipError_t launch_drift(const StepArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s);
 
 // staged mapping, FP64 or FP32 bond arithmetic, `split` wavefronts per slice
-hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, int split, hipStream_t s);
+hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, int split, bool nofail, hipStream_t s);
+hipError_t launch_step_staged_f64(const StepArgs& a, int mode, int split, bool nofail, hipStream_t s);
+hipError_t launch_step_staged_f32(const StepArgs& a, int mode, int split, bool nofail, hipStream_t s);
+
+// out[0..2] = sum over the m device nodes idx[] of V_i force_i (force: SoA, stride nn;
+// V_i from vol, or `volume` when vol is nullptr), summed in a fixed order
+hipError_t launch_resultant(const double* force, int64_t nn, const double* vol, double volume, const int64_t* idx,
+                            int64_t m, double* out, hipStream_t s);
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
 

@@ -1,0 +1,572 @@
+// pdmi_step.h -- the step kernels of the bond-based PMB peridynamics library (templates;
+// each launcher file instantiates its share of them).
+//
+// One fused kernel per time step (paper Sec. 3: the bond force, the critical-stretch
+// check and the per-node reduction are fused, Algorithm 2; here the time integration
+// is fused too).  It reads displacement level k from one node-record buffer and writes
+// level k+1 into the other, so no wavefront can observe a half-updated field (the race
+// that forces the paper to keep integration in a separate kernel, Sec. 3.3).
+//
+// Mapping: a wavefront serves one slice of W = 64/G nodes; each node's bonds are split
+// over G lanes, each lane sums its bonds sequentially, and the G partial sums meet in a
+// butterfly of cross-lane shuffles.  No atomics and no LDS: a node's force is owned by
+// its slice and the result is deterministic.
+//
+// Bond arithmetic (per slot b = (i, j), Eqs. microelastic and simpleBond):
+//   xi = x_j - x_i,  eta = u_j - u_i,  y = xi + eta
+//   q  = |y|^2/|xi|^2 - 1 = (2 xi.eta + eta.eta) / |xi|^2      (no cancellation)
+//   break when q >= (1 + s0)^2 - 1, i.e. s >= s0
+//   f  = c s V_j y/|y| = c V_j (1/|xi|) (1 - (1+q)^(-1/2)) y
+// 1 - (1+q)^(-1/2) is summed as its binomial series for |q| < 4e-3, so small stretches
+// keep full relative precision instead of losing digits in |y| - |xi|.
+//
+// Every kernel also has a force-evaluation mode (kModeForce): the same gather at the
+// current level, no breaking, the bond force density written out (the reaction-force
+// readout of the quasi-static examples, Sec. 6).
+#pragma once
+
+#include "pdmi_device.h"
+
+namespace pdmi {
+namespace {
+
+// Contribution of one slot.  live: the slot holds an intact bond; breakable: the bond may
+// break in this pass (intact, outside the no-failure zones, not a force evaluation).
+// (X, U) are the owner's position and displacement, p0..p2 the neighbour's node record,
+// kv = stiffness times neighbour volume.  Adds the force density to F; returns true when
+// the bond breaks in this pass.
+__device__ __forceinline__ bool slot_force(bool live, bool breakable, const double2 p0, const double2 p1, const double2 p2,
+                                           double X0, double X1, double X2, double U0, double U1, double U2,
+                                           double kv, double q0, double& F0, double& F1, double& F2,
+                                           const SeriesCoef& sk = SeriesCoef())
+{
+    const double xi0 = p0.x - X0, xi1 = p0.y - X1, xi2 = p1.x - X2;
+    const double e0 = p1.y - U0, e1 = p2.x - U1, e2 = p2.y - U2;
+    const double y0 = xi0 + e0, y1 = xi1 + e1, y2 = xi2 + e2;
+    // |y|^2 - |xi|^2 = eta . (xi + y)
+    const double z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
+    const double tq = __builtin_fma(e2, z2, __builtin_fma(e1, z1, e0 * z0));
+    const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
+    const double iL = rsq64<1>(L2);
+    const double q = tq * (iL * iL);
+    const bool brk = breakable && q >= q0;
+    const bool alive = live && !brk;
+    // broken and padding slots evaluate g(0) = 0 and add nothing
+    const double coef = (kv * iL) * one_minus_rsqrt1p(alive ? q : 0.0, sk);
+    F0 = __builtin_fma(coef, y0, F0);
+    F1 = __builtin_fma(coef, y1, F1);
+    F2 = __builtin_fma(coef, y2, F2);
+    return brk;
+}
+
+// FP32 bond arithmetic (same formulas): the bond vector is formed in f64 from the f64
+// coordinates and rounded once, displacements are the f32 values of the records.
+// 1 - (1+q)^(-1/2) uses four series terms (below 1.3e-10 relative for |q| < 4e-3).
+__device__ __forceinline__ bool slot_force32(bool live, bool breakable, const double2 p0, const double2 p1, const double2 p2,
+                                             double X0, double X1, double X2, float U0, float U1, float U2,
+                                             float kv, float q0, float& F0, float& F1, float& F2)
+{
+    const float xi0 = static_cast<float>(p0.x - X0), xi1 = static_cast<float>(p0.y - X1),
+                xi2 = static_cast<float>(p1.x - X2);
+    const uint64_t b1 = __double_as_longlong(p1.y), b2 = __double_as_longlong(p2.x);
+    const float uj0 = __uint_as_float(static_cast<uint32_t>(b1)), uj1 = __uint_as_float(static_cast<uint32_t>(b1 >> 32)),
+                uj2 = __uint_as_float(static_cast<uint32_t>(b2));
+    const float e0 = uj0 - U0, e1 = uj1 - U1, e2 = uj2 - U2;
+    const float y0 = xi0 + e0, y1 = xi1 + e1, y2 = xi2 + e2;
+    const float z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
+    const float tq = __builtin_fmaf(e2, z2, __builtin_fmaf(e1, z1, e0 * z0));
+    const float L2 = __builtin_fmaf(xi2, xi2, __builtin_fmaf(xi1, xi1, xi0 * xi0));
+    const float iL = __builtin_amdgcn_rsqf(L2);
+    const float q = tq * (iL * iL);
+    const bool brk = breakable && q >= q0;
+    const bool alive = live && !brk;
+    const float qa = alive ? q : 0.0f;
+    float g;
+    if (fabsf(qa) < 4.0e-3f) {
+        float p = -35.0f / 128.0f;
+        p = __builtin_fmaf(p, qa, 5.0f / 16.0f);
+        p = __builtin_fmaf(p, qa, -3.0f / 8.0f);
+        p = __builtin_fmaf(p, qa, 0.5f);
+        g = qa * p;
+    } else {
+        g = 1.0f - __builtin_amdgcn_rsqf(1.0f + qa);
+    }
+    const float coef = (kv * iL) * g;
+    F0 = __builtin_fmaf(coef, y0, F0);
+    F1 = __builtin_fmaf(coef, y1, F1);
+    F2 = __builtin_fmaf(coef, y2, F2);
+    return brk;
+}
+
+// Integration and boundary conditions of one node given its force density F (the tail
+// of every step kernel).  U is the node's displacement at the level the forces used.
+template <int MODE, bool FP32 = false>
+__device__ __forceinline__ void node_update(const StepArgs& A, const InstParams& P, int64_t node,
+                                            double U0, double U1, double U2, double F0, double F1, double F2)
+{
+    const int32_t bcid = A.bc_id[node];
+    if (bcid == kNodePad) return;
+
+    const int64_t nn = A.nn;
+    if (MODE == kModeForce) {  // bond force density of the current level, nothing else
+        A.force[node] = F0;
+        A.force[nn + node] = F1;
+        A.force[2 * nn + node] = F2;
+        return;
+    }
+    const double dt = A.dt;
+    const int64_t k = *A.step_base + A.step_local;
+    double F[3] = {F0, F1, F2};
+    if (P.has_body)
+        for (int d = 0; d < 3; ++d) F[d] += P.bmag * A.bhat[d * nn + node];
+    double u[3] = {U0, U1, U2};
+    if (FP32)  // the integrator advances the f64 master displacement
+        for (int d = 0; d < 3; ++d) u[d] = A.um_in[d * nn + node];
+    double vv[3], un[3], vn[3], an[3];
+    for (int d = 0; d < 3; ++d) vv[d] = A.v[d * nn + node];
+    BCRec bc;
+    bc.code = 0;
+    if (bcid >= 0) bc = A.bc[bcid];
+
+    if (MODE == kModeEC || MODE == kModeFE) {
+        const double t1 = static_cast<double>(k + 1) * dt;
+        for (int d = 0; d < 3; ++d) {
+            const double acc = (F[d] - P.eta * vv[d]) / P.rho;
+            if (MODE == kModeEC) {
+                vn[d] = vv[d] + dt * acc;
+                un[d] = u[d] + dt * vn[d];
+            } else {
+                un[d] = u[d] + dt * vv[d];
+                vn[d] = vv[d] + dt * acc;
+            }
+            if (constrained(bc, d)) {
+                vn[d] = bc_vel(bc, d, t1);
+                un[d] = bc_disp(bc, d, t1, u[d], dt);
+            }
+        }
+    } else if (MODE == kModeVV) {
+        // u holds level k+1; v, a hold level k.  Finish step k -> k+1, then move the
+        // displacement on to level k+2 (Eq. Velocity_Verlet1) for the next launch.
+        const double t1 = static_cast<double>(k + 1) * dt, t2 = static_cast<double>(k + 2) * dt;
+        const double hdt = 0.5 * dt, hdt2 = 0.5 * dt * dt;
+        for (int d = 0; d < 3; ++d) {
+            const double aa = A.a[d * nn + node];
+            const double vh = vv[d] + hdt * aa;
+            an[d] = (F[d] - P.eta * vh) / P.rho;
+            vn[d] = vv[d] + hdt * (aa + an[d]);
+            if (constrained(bc, d)) {
+                vn[d] = bc_vel(bc, d, t1);
+                an[d] = 0.0;
+            }
+            un[d] = (u[d] + dt * vn[d]) + hdt2 * an[d];
+            if (constrained(bc, d)) un[d] = bc_disp(bc, d, t2, u[d], dt);
+        }
+    } else {  // kModeVVInit: u holds level k; acceleration of level k, then u of level k+1
+        const double t1 = static_cast<double>(k + 1) * dt;
+        const double hdt2 = 0.5 * dt * dt;
+        for (int d = 0; d < 3; ++d) {
+            an[d] = constrained(bc, d) ? 0.0 : (F[d] - P.eta * vv[d]) / P.rho;
+            un[d] = (u[d] + dt * vv[d]) + hdt2 * an[d];
+            if (constrained(bc, d)) un[d] = bc_disp(bc, d, t1, u[d], dt);
+            vn[d] = vv[d];
+        }
+    }
+
+    bool finite = true;
+    for (int d = 0; d < 3; ++d) finite = finite && __builtin_isfinite(un[d]) && __builtin_isfinite(vn[d]);
+    if (!finite) atomicOr(A.status, 1);
+    double* ro = A.rec_out + 6 * node;
+    if (FP32) {
+        float* rf = reinterpret_cast<float*>(ro + 3);
+        for (int d = 0; d < 3; ++d) {
+            rf[d] = static_cast<float>(un[d]);
+            A.um_out[d * nn + node] = un[d];
+        }
+    } else {
+        ro[3] = un[0];
+        ro[4] = un[1];
+        ro[5] = un[2];
+    }
+    if (MODE != kModeVVInit)
+        for (int d = 0; d < 3; ++d) A.v[d * nn + node] = vn[d];
+    if (MODE == kModeVV || MODE == kModeVVInit)
+        for (int d = 0; d < 3; ++d) A.a[d * nn + node] = an[d];
+}
+
+template <int G, int MODE, bool STIFF, bool VOLN, bool KNODE, bool NOFAIL>
+__global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
+{
+    constexpr int W = kWave / G;
+    constexpr int U = kRowUnroll;  // slot rows in flight per iteration
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t slice =
+        wave_uniform(xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + (threadIdx.x >> 6));
+    if (slice >= A.nslices) return;
+    const int32_t* __restrict__ slice_inst = A.slice_inst;
+    const InstParams* __restrict__ params = A.params;
+    const int64_t* __restrict__ slice_ptr = A.slice_ptr;
+    const int32_t* __restrict__ slice_T = A.slice_T;
+    const InstParams P = params[slice_inst[slice]];
+    const int w = lane / G, g = lane % G;
+    const int64_t node = slice * W + w;
+
+    const double2* __restrict__ rin = reinterpret_cast<const double2*>(A.rec_in);
+    const double2 o0 = rin[3 * node], o1 = rin[3 * node + 1], o2 = rin[3 * node + 2];
+    const double X0 = o0.x, X1 = o0.y, X2 = o1.x;
+    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;
+    // 32-bit byte offsets from wave-uniform bases (the host keeps every offset below 2^32)
+    const char* __restrict__ recb = reinterpret_cast<const char*>(A.rec_in);
+    const int64_t base = slice_ptr[slice];
+    const int T = slice_T[slice];
+    const char* __restrict__ colb = reinterpret_cast<const char*>(A.col + base);
+    const char* __restrict__ kb = STIFF ? reinterpret_cast<const char*>(A.kslot + base) : nullptr;
+    const double* __restrict__ volp = A.vol;
+    const double* __restrict__ nwp = A.nw;
+    const double ai = KNODE ? A.na[node] : 0.0;  // own stiffness factor
+    const uint32_t lane4 = static_cast<uint32_t>(lane) * 4u;
+    const double cv = P.c * P.volume;
+
+    // Rows are fetched one iteration ahead.  T is a multiple of kRowUnroll and the slot
+    // arrays end with kRowUnroll spare rows, so every prefetch is in bounds and no load
+    // sits behind a branch (rows prefetched past T belong to the next slice; unused).
+    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+    const SeriesCoef sk = series_coef_regs();
+    if (T > 0) {
+        auto col_at = [&](int t) -> int32_t {
+            const uint32_t off = static_cast<uint32_t>(t) * (kWave * 4u) + lane4;
+            return __builtin_nontemporal_load(reinterpret_cast<const int32_t*>(colb + off));
+        };
+        int32_t cn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cn[u] = col_at(u);
+        for (int t = 0; t < T; t += U) {
+            int32_t c[U];
+            double2 p[U][3];
+            double kv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c[u] = cn[u];
+                const uint32_t j = static_cast<uint32_t>(c[u] ^ (c[u] >> 31)) &
+                                   (NOFAIL ? static_cast<uint32_t>(kColNode) : 0xffffffffu);
+                const char* rj = recb + __umul24(j, 48u);  // full-rate 24-bit multiply: j < 2^24
+                p[u][0] = *reinterpret_cast<const double2*>(rj);
+                p[u][1] = *reinterpret_cast<const double2*>(rj + 16);
+                p[u][2] = *reinterpret_cast<const double2*>(rj + 32);
+                if (KNODE) {
+                    kv[u] = ai * nwp[j];  // sqrt(k_i) sqrt(k_j) V_j
+                } else if (STIFF || VOLN) {
+                    double k = P.c;
+                    if (STIFF) {
+                        const uint32_t off = static_cast<uint32_t>(t + u) * (kWave * 8u) + 2u * lane4;
+                        k = __builtin_nontemporal_load(reinterpret_cast<const double*>(kb + off));
+                    }
+                    kv[u] = k * (VOLN ? volp[j] : P.volume);
+                } else {
+                    kv[u] = cv;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) cn[u] = col_at(t + U + u);
+            bool brk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                // a bond may break unless it is broken, padding or in a no-failure zone
+                const bool breakable = MODE != kModeForce &&
+                                       (NOFAIL ? static_cast<uint32_t>(c[u]) < static_cast<uint32_t>(kColNoFail)
+                                               : c[u] >= 0);
+                brk[u] = slot_force(c[u] >= 0, breakable, p[u][0], p[u][1], p[u][2], X0, X1, X2, U0, U1, U2, kv[u],
+                                    P.q0, F0, F1, F2, sk);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (brk[u]) {
+                    const int64_t ds = base + static_cast<int64_t>(t + u) * kWave + lane;
+                    A.col[ds] = ~c[u];  // irreversible
+                    A.bstep[ds] = static_cast<int32_t>(*A.step_base + A.step_local);
+                }
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) {
+        F0 += __shfl_xor(F0, m);
+        F1 += __shfl_xor(F1, m);
+        F2 += __shfl_xor(F2, m);
+    }
+    if (g != 0) return;
+    node_update<MODE>(A, P, node, U0, U1, U2, F0, F1, F2);
+}
+
+// Orders a wavefront's own LDS writes before its later LDS reads (no workgroup barrier).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Staged step kernel: one workgroup of S wavefronts per 64-node slice, one lane per node.
+// Wavefront w takes the slice's pieces w, w + S, w + 2S, ...  For every piece, the
+// wavefront loads the range's node records and the piece's slot entries straight into
+// its own LDS area (gfx950 global_load_lds_dwordx4, no staging registers, which leaves
+// room for six wavefronts per SIMD to cover the load latency); per-node weights come
+// through registers one piece ahead.  Every slot reads its neighbour from LDS.  Each record crosses the
+// vector-memory path once per piece instead of once per slot.  Per-slot stiffness, when
+// present, streams from global memory (two rows one piece ahead, the rest when the piece
+// starts, which keeps the register count at four wavefronts per SIMD).  Rows are processed in pairs so
+// the LDS reads of one row overlap the arithmetic of the other; an odd last row runs
+// alone.  With S > 1 the partial forces meet in LDS in a fixed order (S > 1 fills the
+// chip on problems with fewer slices than SIMDs).
+template <bool FP32, int MODE, bool STIFF, bool VOLN, bool KNODE, int S, bool NOFAIL>
+__global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2* __restrict__ pieces,
+                                                             const int32_t* __restrict__ slice_piece,
+                                                             const int64_t* __restrict__ slice_ptr)
+{
+    constexpr int kRecChunks = kStageChunks + 3;             // staged records, then the sentinel
+    constexpr int kEntChunks = kPieceRows * kWave * 2 / 16;  // 16-byte chunks of entries
+    constexpr bool WSTAGE = VOLN || KNODE;  // a per-node weight is staged beside the records
+    constexpr int kVolWords = WSTAGE ? (kEntPad / 48 + 2) / 2 * 2 : 0;  // staged weights (doubles), sentinel last
+    constexpr int kLds = kRecChunks + kEntChunks + kVolWords / 2;
+    static_assert(kStageChunks == 4 * kWave && kEntChunks == kWave, "four record loads and one entry load");
+    __shared__ double2 lds[S * kLds];
+    __shared__ double red[S > 1 ? (S - 1) * 3 * kWave : 1];  // partial forces of wavefronts 1..S-1
+    const int wv = S > 1 ? __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave) : 0;
+    double2* const lrec = lds + wv * kLds;
+    const char* const lrecb = reinterpret_cast<const char*>(lrec);
+    uint16_t* const lent = reinterpret_cast<uint16_t*>(lrec + kRecChunks);
+    double* const lvol = reinterpret_cast<double*>(lrec + kRecChunks + kEntChunks);
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
+    if (slice >= A.nslices) return;
+    const int32_t* __restrict__ slice_inst = A.slice_inst;
+    const InstParams* __restrict__ params = A.params;
+    const InstParams P = params[slice_inst[slice]];
+    const int64_t node = slice * kWave + lane;
+    const double2* __restrict__ rin = reinterpret_cast<const double2*>(A.rec_in);
+    const double2 o0 = rin[3 * node], o1 = rin[3 * node + 1], o2 = rin[3 * node + 2];
+    const double X0 = o0.x, X1 = o0.y, X2 = o1.x;
+    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;  // FP64 build
+    const uint64_t ub1 = __double_as_longlong(o1.y), ub2 = __double_as_longlong(o2.x);
+    const float Uf0 = __uint_as_float(static_cast<uint32_t>(ub1)), Uf1 = __uint_as_float(static_cast<uint32_t>(ub1 >> 32)),
+                Uf2 = __uint_as_float(static_cast<uint32_t>(ub2));  // FP32 build
+    const double cv = P.c * P.volume;
+    const float cvf = static_cast<float>(cv), q0f = static_cast<float>(P.q0);
+    uint16_t* __restrict__ entw = A.ent;
+    int32_t* __restrict__ bstep = A.bstep;
+    // the two innermost series coefficients stay in registers
+    const SeriesCoef sk = series_coef_regs();
+    const double2* __restrict__ ent2 = reinterpret_cast<const double2*>(A.ent);
+
+    // sentinel record (padding entries point at it), volume 0
+    if (lane < 3) lrec[kStageChunks + lane] = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
+    if (WSTAGE && lane == 0) lvol[kEntPad / 48] = 0.0;
+    // staged weight: V_j, or sqrt(k_j) V_j with per-node stiffness (times the own sqrt(k_i))
+    const double* __restrict__ wsrc = KNODE ? A.nw : A.vol;
+    const double ai = KNODE ? A.na[node] : 0.0;
+
+    const int p0 = __builtin_amdgcn_readfirstlane(slice_piece[slice]);
+    const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
+    auto rows_of = [&](int p) { return (pieces[__builtin_amdgcn_readfirstlane(p)].y >> 8) & 0xff; };
+    int64_t ent = wave_uniform(slice_ptr[slice]);  // first entry of the current piece
+    const int pa = p0 + wv;                         // this wavefront's first piece
+    for (int q = p0; q < pa && q < p1; ++q) ent += static_cast<int64_t>(rows_of(q)) * kWave;
+    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+    float Ff0 = 0.0f, Ff1 = 0.0f, Ff2 = 0.0f;
+
+    // staging registers of the next piece (weights and stiffness; records and entries go
+    // straight to LDS)
+    double vs0 = 0.0, vs1 = 0.0;
+    int vlen = 0;
+    constexpr int kKPre = 2;  // stiffness rows fetched a piece ahead; the rest when the piece starts
+    double kcur[kPieceRows], knext[kKPre];
+
+    // Loads of piece p (first entry e): a fixed 256-chunk window from the range start
+    // (the record buffers end with kRecPad spare records) and the whole 8-row entry block
+    // (rows >= T are never read); volumes from clamped addresses.
+    auto issue = [&](int p, int64_t e) {
+        const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
+        if (WSTAGE) {
+            const int len = m.y & 0xff;
+            vlen = len;
+            vs0 = wsrc[m.x + min(lane, len - 1)];
+            vs1 = wsrc[m.x + min(lane + kWave, len - 1)];
+        }
+        if (STIFF)
+#pragma unroll
+            for (int t = 0; t < kKPre; ++t) knext[t] = __builtin_nontemporal_load(A.kslot + e + t * kWave + lane);
+    };
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    auto dma = [&](int p, int64_t e) {
+        const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
+        const double2* rs = rin + 3 * static_cast<int64_t>(m.x) + lane;
+        __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs + kWave, (lds_ptr)(lrec + kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs + 2 * kWave, (lds_ptr)(lrec + 2 * kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs + 3 * kWave, (lds_ptr)(lrec + 3 * kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(ent2 + e / 8 + lane, (lds_ptr)(lent), 16, 0, 0);
+    };
+    auto commit = [&]() {
+        if (WSTAGE) {
+            if (lane < vlen) lvol[lane] = vs0;
+            if (lane + kWave < vlen) lvol[lane + kWave] = vs1;
+        }
+    };
+    auto row = [&](uint16_t e, double kst) {
+        const uint32_t off = e & kEntOff;  // byte offset of the neighbour's staged record
+        const double2 q0 = *reinterpret_cast<const double2*>(lrecb + off);
+        const double2 q1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
+        const double2 q2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
+        const bool live = !(e & kEntBroken);
+        const bool breakable = MODE != kModeForce && (NOFAIL ? !(e & (kEntBroken | kEntNoFail)) : live);
+        double kv = cv;
+        const uint32_t widx = (off * 0xAAABu) >> 21;  // off / 48
+        if (KNODE)
+            kv = ai * lvol[widx];
+        else if (STIFF || VOLN)
+            kv = (STIFF ? kst : P.c) * (VOLN ? lvol[widx] : P.volume);
+        if (FP32)
+            return slot_force32(live, breakable, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2,
+                                (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : cvf,
+                                q0f, Ff0, Ff1, Ff2);
+        return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2, sk);
+    };
+    // a slot that broke in this pass: flag it (irreversible) and record the pass
+    auto broke = [&](int64_t ds, uint16_t e) {
+        entw[ds] = static_cast<uint16_t>(e | kEntBroken);
+        bstep[ds] = static_cast<int32_t>(*A.step_base + A.step_local);
+    };
+
+    if (pa < p1) {
+        issue(pa, ent);
+        for (int p = pa; p < p1; p += S) {
+            const int T = rows_of(p);
+            int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;  // first entry of piece p + S
+            for (int q = p + 1; q < p + S && q < p1; ++q) ent_next += static_cast<int64_t>(rows_of(q)) * kWave;
+            wave_sync();  // the previous piece is no longer read
+            dma(p, ent);
+            // s_waitcnt with vmcnt = 0 (expcnt and lgkmcnt at their no-wait maxima): the
+            // piece's direct-to-LDS loads have landed
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            commit();
+            if (STIFF)
+#pragma unroll
+                for (int t = 0; t < kPieceRows; ++t)
+                    kcur[t] = t < kKPre ? knext[t] : __builtin_nontemporal_load(A.kslot + ent + t * kWave + lane);
+            if (p + S < p1) issue(p + S, ent_next);
+            wave_sync();  // the piece's LDS copy is complete
+#pragma unroll
+            for (int t = 0; t < kPieceRows; t += 2) {
+                if (t >= T) break;
+                const uint16_t ea = lent[t * kWave + lane];
+                if (t + 1 < T) {
+                    const uint16_t eb = lent[(t + 1) * kWave + lane];
+                    const bool ba = row(ea, STIFF ? kcur[t] : 0.0);
+                    const bool bb = row(eb, STIFF ? kcur[t + 1] : 0.0);
+                    if (ba) broke(ent + t * kWave + lane, ea);
+                    if (bb) broke(ent + (t + 1) * kWave + lane, eb);
+                } else {
+                    if (row(ea, STIFF ? kcur[t] : 0.0)) broke(ent + t * kWave + lane, ea);
+                }
+            }
+            ent = ent_next;
+        }
+    }
+    if (FP32) {
+        F0 = Ff0;
+        F1 = Ff1;
+        F2 = Ff2;
+    }
+    if (S > 1) {  // wavefront 0 adds the partial forces of 1..S-1 in that order
+        if (wv > 0) {
+            double* r = red + (wv - 1) * 3 * kWave + lane;
+            r[0] = F0;
+            r[kWave] = F1;
+            r[2 * kWave] = F2;
+        }
+        __syncthreads();  // every wavefront of the workgroup reaches this once
+        if (wv > 0) return;
+#pragma unroll
+        for (int w = 1; w < S; ++w) {
+            const double* r = red + (w - 1) * 3 * kWave + lane;
+            F0 += r[0];
+            F1 += r[kWave];
+            F2 += r[2 * kWave];
+        }
+    }
+    node_update<MODE, FP32>(A, P, node, U0, U1, U2, F0, F1, F2);
+}
+
+// ---------------------------------------------------------------- launch templates
+
+template <int G, bool STIFF, bool VOLN, bool KNODE, bool NOFAIL>
+hipError_t launch_step_gsv(const StepArgs& a, int mode, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>((a.nslices + 3) / 4)), block(kBlock);
+    switch (mode) {
+#define PD_L(M) hipLaunchKernelGGL((step_f64<G, M, STIFF, VOLN, KNODE, NOFAIL>), grid, block, 0, s, a)
+    case kModeEC: PD_L(kModeEC); break;
+    case kModeVV: PD_L(kModeVV); break;
+    case kModeVVInit: PD_L(kModeVVInit); break;
+    case kModeFE: PD_L(kModeFE); break;
+    case kModeForce: PD_L(kModeForce); break;
+#undef PD_L
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int G, bool NOFAIL>
+hipError_t launch_step_g(const StepArgs& a, int mode, bool stiff, hipStream_t s)
+{
+    const bool voln = a.vol != nullptr;
+    if (a.nw) return launch_step_gsv<G, false, false, true, NOFAIL>(a, mode, s);  // per-node stiffness
+    if (stiff)
+        return voln ? launch_step_gsv<G, true, true, false, NOFAIL>(a, mode, s)
+                    : launch_step_gsv<G, true, false, false, NOFAIL>(a, mode, s);
+    return voln ? launch_step_gsv<G, false, true, false, NOFAIL>(a, mode, s)
+                : launch_step_gsv<G, false, false, false, NOFAIL>(a, mode, s);
+}
+
+template <bool FP32, bool STIFF, bool VOLN, bool KNODE, int S, bool NOFAIL>
+hipError_t launch_staged_svs(const StepArgs& a, int mode, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>(a.nslices)), block(kWave * S);
+    switch (mode) {
+#define PD_L(M)                                                                                             \
+    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN, KNODE, S, NOFAIL>), grid, block, 0, s, a, a.pieces, \
+                       a.slice_piece, a.slice_ptr)
+    case kModeEC: PD_L(kModeEC); break;
+    case kModeVV: PD_L(kModeVV); break;
+    case kModeVVInit: PD_L(kModeVVInit); break;
+    case kModeFE: PD_L(kModeFE); break;
+    case kModeForce: PD_L(kModeForce); break;
+#undef PD_L
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <bool FP32, bool STIFF, bool VOLN, bool KNODE, bool NOFAIL>
+hipError_t launch_staged_sv(const StepArgs& a, int mode, int split, hipStream_t s)
+{
+    switch (split) {
+    case 1: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 1, NOFAIL>(a, mode, s);
+    case 2: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 2, NOFAIL>(a, mode, s);
+    case 4: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 4, NOFAIL>(a, mode, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool FP32, bool NOFAIL>
+hipError_t launch_staged_n(const StepArgs& a, int mode, int split, hipStream_t s)
+{
+    const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
+    if (a.nw) return launch_staged_sv<FP32, false, false, true, NOFAIL>(a, mode, split, s);  // per-node stiffness
+    if (stiff)
+        return voln ? launch_staged_sv<FP32, true, true, false, NOFAIL>(a, mode, split, s)
+                    : launch_staged_sv<FP32, true, false, false, NOFAIL>(a, mode, split, s);
+    return voln ? launch_staged_sv<FP32, false, true, false, NOFAIL>(a, mode, split, s)
+                : launch_staged_sv<FP32, false, false, false, NOFAIL>(a, mode, split, s);
+}
+
+}  // namespace
+}  // namespace pdmi

@@ -1,0 +1,12 @@
+// pdmi_step_staged_f64.hip -- launcher of the staged-mapping step kernels, FP64 bond arithmetic.
+#include "pdmi_step.h"
+
+namespace pdmi {
+
+hipError_t launch_step_staged_f64(const StepArgs& a, int mode, int split, bool nofail, hipStream_t s)
+{
+    if (a.nslices <= 0) return hipSuccess;
+    return nofail ? launch_staged_n<false, true>(a, mode, split, s) : launch_staged_n<false, false>(a, mode, split, s);
+}
+
+}  // namespace pdmi

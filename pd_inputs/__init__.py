@@ -210,6 +210,9 @@ class Workload:
     notch: Optional[Tuple[int, int]] = None   # (plane2, height2) or None
     body_force: Optional[Tuple[np.ndarray, float]] = None   # (b_hat (n,3), magnitude)
     stiffness_field: Optional[Tuple[float, float, int]] = None  # (sigma, corr_len, seed)
+    eta: float = 0.0                # dynamic-relaxation damping coefficient (kg/(m^3 s))
+    ramp_T: Optional[float] = None  # duration of the SCHED_RAMP5 components
+    nofail: Optional[np.ndarray] = None  # node ids of the no-failure zones
     meta: Dict = field(default_factory=dict)
 
     @property
@@ -256,6 +259,31 @@ def _bcs_beam3pb(ijk, dims):
             BCSpec(load.astype(np.int64), 0b100, BC_VEL, (0.0, 0.0, -1.0e-3), SCHED_CONST)]
 
 
+def qs_beam_sets(ijk, dims):
+    """Support and load node sets of the three-point bend of Sec. 6 (span 125/175 of the
+    length): 2 x 2 node cross-sections (x by z) through the thickness at the supports,
+    3 x 2 at the central load."""
+    mid, top = dims[0] // 2, dims[2] - 1
+    half = int(round(dims[0] * 125.0 / 175.0 / 2.0))
+
+    def box(x0, x1, z0, z1):
+        return np.nonzero((ijk[:, 0] >= x0) & (ijk[:, 0] <= x1) & (ijk[:, 2] >= z0) & (ijk[:, 2] <= z1))[0]
+    left = box(mid - half - 1, mid - half, 0, 1)
+    right = box(mid + half, mid + half + 1, 0, 1)
+    load = box(mid - 1, mid + 1, top - 1, top)
+    return left.astype(np.int64), right.astype(np.int64), load.astype(np.int64)
+
+
+def _bcs_qs_beam(ijk, dims, amp):
+    # left support clamped, right support held in y and z, the load held in y and pushed
+    # down in z by the fifth-order ramp to amplitude amp
+    left, right, load = qs_beam_sets(ijk, dims)
+    return [BCSpec(left, 0b111, BC_DISP, (0.0, 0.0, 0.0), SCHED_CONST),
+            BCSpec(right, 0b110, BC_DISP, (0.0, 0.0, 0.0), SCHED_CONST),
+            BCSpec(load, 0b010, BC_DISP, (0.0, 0.0, 0.0), SCHED_CONST),
+            BCSpec(load, 0b100, BC_DISP, (0.0, 0.0, -amp), SCHED_RAMP5)]
+
+
 def _bcs_tension_x(ijk, dims):
     return [BCSpec(face_nodes(ijk, 0, 0), 0b111, BC_DISP, (0.0, 0.0, 0.0), SCHED_CONST),
             BCSpec(face_nodes(ijk, 0, dims[0] - 1), 0b001, BC_DISP, (0.1, 0.0, 0.0), SCHED_LINEAR)]
@@ -291,6 +319,21 @@ def workload(name: str, **over) -> Workload:
                    _bcs_tension_x_clamp_only, body=_body_tip_down,
                    fld=(0.2, 5.0, 2000), meta={"sensor_seed": 7, "n_sensors": 200,
                                                "target_seed": 2001, "ckpt_every": 100})
+    if name == "qs_beam":
+        # displacement-controlled three-point bend of a notched beam with the quasi-static
+        # toolkit of Secs. 6-7: the Example 2 geometry (175 x 50 x 50 mm, notch 1/5 of the
+        # depth) on a 1 mm lattice, fifth-order ramp, no-failure zones on the support and
+        # load nodes, dynamic-relaxation damping, velocity Verlet
+        dims = over.get("dims", (175, 50, 50))
+        steps = over.get("steps", 4000)
+        amp = over.get("amp", 1.15e-7 * dims[0])  # same bending strain at any scale
+        ramp_T = over.get("ramp_T", 0.75 * steps * 1.0e-7)
+        w = _mk(name, dims, 3.14, over.get("s0", 1.0e-4), steps, "velocity_verlet",
+                lambda ijk, d: _bcs_qs_beam(ijk, d, amp), notch=(2 * (dims[0] // 2) + 1, 2 * (dims[2] // 5)))
+        w.eta = over.get("eta", 2.5e6)
+        w.ramp_T = ramp_T
+        w.nofail = np.unique(np.concatenate(qs_beam_sets(w.ijk, dims)))
+        return w
     raise KeyError(name)
 
 
@@ -298,7 +341,7 @@ def _bcs_tension_x_clamp_only(ijk, dims):
     return [BCSpec(face_nodes(ijk, 0, 0), 0b111, BC_DISP, (0.0, 0.0, 0.0), SCHED_CONST)]
 
 
-WORKLOADS = ("block10", "beam3pb", "cube100", "cube100_wide", "adjoint_beam")
+WORKLOADS = ("block10", "beam3pb", "cube100", "cube100_wide", "adjoint_beam", "qs_beam")
 
 
 def adjoint_sensors(w: Workload, m: Optional[int] = None, seed: Optional[int] = None):
