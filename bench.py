@@ -28,7 +28,7 @@ PEAK_VALU_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # FP64 with six terms, 7 in FP32 with four); the coefficient (2); the force update (6).
 FLOPS_PER_SLOT = {"f64": 50, "f32": 46}
 STEP_SOURCES = [os.path.join(ROOT, "paper_2105_04150_amd", "csrc", f)
-                for f in ("pdmi_kernels.hip", "pdmi_device.h", "pdmi_internal.h")]
+                for f in ("pdmi_step.h", "pdmi_device.h", "pdmi_internal.h")]
 
 
 def kernel_hash() -> str:
@@ -86,6 +86,7 @@ def adjoint_extra(P, pi, sync, steps: int, ckpt: int):
     w = pi.workload("adjoint_beam", steps=steps)
     sim = P.simulation_for(w, lanes=4)
     sim.autotune(trial_steps=10)
+    sim.prepare()
     info = sim.info()
     nnz = info["n_slots"]
     sensors, target = pi.adjoint_sensors(w)
@@ -141,6 +142,7 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
     sim.set_integrator("euler_cromer", ws[0].dt)
     for b, w in enumerate(ws):
         P.apply_workload(sim, w, inst=b, stiffness="node")
+    sim.prepare()
     setup = time.perf_counter() - t0
     info = sim.info()
     nnz = info["n_slots"]
@@ -153,6 +155,7 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
     print(f"# batched: {t_b * 1e3 / steps:.3f} ms/step; sequential sample next", file=sys.stderr, flush=True)
     for b in idx:
         s1 = P.simulation_for(ws[b], lanes=lanes, mapping=mapping, order=order, stiffness="node")
+        s1.prepare()
         s1.step(20)
         s1.sync()
         seq_t += _timed(lambda: (s1.step(steps), s1.sync()), sync)
@@ -168,12 +171,59 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
             "batched_vs_sequential": batched / seq}
 
 
+def quasistatic_extra(P, pi, sync, steps: int, every: int):
+    """The quasi-static toolkit on the notched three-point bend of Sec. 6 (175 x 50 x 50
+    lattice, velocity Verlet with damping, fifth-order load ramp, no-failure zones on the
+    support and load nodes): the step rate with the zones (zone-aware kernels), the same
+    with a load readout (device resultant of the load set) every `every` steps, and the
+    rate once the zones are removed (plain kernels), each over `steps` steps of one
+    continuing run."""
+    w = pi.workload("qs_beam")
+    sim = P.simulation_for(w)
+    sim.autotune(trial_steps=10)
+    sim.prepare()
+    info = sim.info()
+    nnz = info["n_slots"]
+    _, _, load = pi.qs_beam_sets(w.ijk, w.dims)
+    sim.step(20)
+    sim.sync()
+    t_zone = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    dev_ms = sim.last_step_ms() / steps
+    loads = []
+
+    def with_readout():
+        for _ in range(steps // every):
+            sim.step(every)
+            loads.append(float(sim.resultant(load)[2]))
+    t_read = _timed(with_readout, sync)
+    n_read = steps // every
+    sim.set_no_fail(None)
+    sim.prepare()
+    sim.step(5)
+    sim.sync()
+    t_plain = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    mapping = "staged" if info["mapping"] == P.PD_MAP_STAGED else f"sliced-{info['lanes_per_node']}"
+    sim.close()
+    tflops = nnz * FLOPS_PER_SLOT["f64"] / (dev_ms / 1e3) / 1e12
+    return {"config": f"qs_beam {w.dims[0]}x{w.dims[1]}x{w.dims[2]}, velocity Verlet, eta {w.eta:g}, "
+                      f"ramp {w.ramp_T:g} s, {len(w.nofail)} zone nodes, f64",
+            "nodes": info["n_nodes"], "bond_slots": nnz, "mapping": mapping, "steps": steps,
+            "value": nnz * steps / t_zone, "unit": "bond-updates/s", "avg_launch_ms": dev_ms,
+            "alu_frac": tflops / PEAK_VALU_TFLOPS["f64"],
+            "rate_with_load_readout": nnz * n_read * every / t_read, "readout_every": every,
+            "readout_ms": max(t_read - t_zone * n_read * every / steps, 0.0) * 1e3 / max(n_read, 1),
+            "last_load_N": loads[-1] if loads else None,
+            "rate_without_zones": nnz * steps / t_plain,
+            "zones_vs_plain": t_plain / t_zone}
+
+
 def fp32_extra(P, pi, sync, workload: str, steps: int):
     """The FP32 build (f32 bond arithmetic, f64 master displacement) on the headline
     workload with the staged mapping, the only mapping it runs."""
     w = pi.workload(workload)
     w.order = "natural"
     sim = P.simulation_for(w, precision=P.PD_FP32, mapping="staged")
+    sim.prepare()
     info = sim.info()
     sim.step(20)
     sim.sync()
@@ -192,7 +242,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cube100", choices=["cube100", "cube100_wide", "block10", "beam3pb"])
+    ap.add_argument("--workload", default="cube100",
+                    choices=["cube100", "cube100_wide", "block10", "beam3pb", "qs_beam"])
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--lanes", type=int, default=0, help="lanes per node of the sliced mapping")
     ap.add_argument("--mapping", default="auto", choices=["auto", "sliced", "staged"],
@@ -201,7 +252,8 @@ def main():
                     help="device node order (auto: the autotuner tries both)")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batched measurements")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP32, adjoint, batched and quasi-static measurements")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=300)
@@ -238,6 +290,7 @@ def main():
         sim.autotune(trial_steps=10)
     else:
         sim = P.simulation_for(w, precision=prec, lanes=args.lanes, mapping=args.mapping)
+    sim.prepare()  # step graphs built before the warm-up, not inside the timed region
     setup_s = time.perf_counter() - t0
     info = sim.info()
     mapping = "staged" if info["mapping"] == P.PD_MAP_STAGED else "sliced"
@@ -311,6 +364,8 @@ def main():
         out["batched"] = batched_extra(P, pi, torch_sync, args.batch_count, args.batch_steps, 8)
         out["batched"]["batched_vs_headline_step"] = out["batched"]["batched_rate"] / value
         print(f"# batched {out['batched']}", file=sys.stderr, flush=True)
+        out["quasistatic"] = quasistatic_extra(P, pi, torch_sync, args.steps, 50)
+        print(f"# quasistatic {out['quasistatic']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, threads)

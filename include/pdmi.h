@@ -209,6 +209,13 @@ int pd_set_integrator(pd_ctx *ctx, int scheme, double dt);
  * non-finite state is reported by the next synchronising call (PD_ENONFINITE). */
 int pd_step(pd_ctx *ctx, int64_t nsteps);
 
+/* Capture and instantiate now the step graphs that pd_step would otherwise build on
+ * first use (chunks of several steps recorded once and replayed), for the current
+ * integrator, layout and loads, so that a later pd_step spends no host time on them.
+ * Runs nothing on the device and changes no state.  Calls that change the layout,
+ * the integrator, the loads or the no-failure zones discard the graphs again. */
+int pd_prepare(pd_ctx *ctx);
+
 /* Wait for the stream; returns PD_ENONFINITE if any step produced a non-finite
  * displacement or velocity since the state was last set. */
 int pd_sync(pd_ctx *ctx);

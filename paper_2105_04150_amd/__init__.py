@@ -113,6 +113,10 @@ class Simulation:
     def step(self, nsteps):
         B.pd_step(self.ctx, nsteps)
 
+    def prepare(self):
+        """Build the step graphs now rather than inside the first long pd_step."""
+        B.pd_prepare(self.ctx)
+
     def sync(self):
         B.pd_sync(self.ctx)
 

@@ -28,7 +28,7 @@ SYMBOLS = [
     "pd_set_node_stiffness",
     "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_bc_ramp", "pd_set_no_fail", "pd_get_force",
     "pd_get_resultant", "pd_set_body_force", "pd_set_integrator",
-    "pd_step", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
+    "pd_step", "pd_prepare", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
     "pd_get_info", "pd_last_step_ms", "pd_adj_forward", "pd_adj_backward", "pd_get_break_steps",
 ]
@@ -85,6 +85,7 @@ def load() -> C.CDLL:
         "pd_set_body_force": [P, i32, P, d],
         "pd_set_integrator": [P, C.c_int, d],
         "pd_step": [P, i64],
+        "pd_prepare": [P],
         "pd_sync": [P],
         "pd_get_step": [P, P],
         "pd_get_u": [P, i32, P], "pd_get_v": [P, i32, P], "pd_get_a": [P, i32, P],
@@ -247,6 +248,10 @@ def pd_set_integrator(ctx, scheme: int, dt: float) -> None:
 
 def pd_step(ctx, nsteps: int) -> None:
     _check(ctx, load().pd_step(ctx, int(nsteps)))
+
+
+def pd_prepare(ctx) -> None:
+    _check(ctx, load().pd_prepare(ctx))
 
 
 def pd_sync(ctx) -> None:

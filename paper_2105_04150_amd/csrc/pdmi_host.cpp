@@ -1600,6 +1600,18 @@ int pd_step(pd_ctx* ctx, int64_t nsteps)
     });
 }
 
+int pd_prepare(pd_ctx* ctx)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        require_built(ctx);
+        set_device(ctx);
+        if (!ctx->use_graphs) return;
+        const int mode = step_mode(ctx->scheme);
+        for (int parity = 0; parity < 2; ++parity) (void)chunk_graph(ctx, mode, parity);
+    });
+}
+
 int pd_sync(pd_ctx* ctx)
 {
     if (!ctx) return PD_EINVAL;

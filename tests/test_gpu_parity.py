@@ -284,3 +284,25 @@ def test_coincident_nodes_rejected():
     with Simulation() as g:
         with pytest.raises(PdmiError):
             g.build_family(x, 3.015e-3)
+
+
+@pytest.mark.parametrize("scheme", ["euler_cromer", "velocity_verlet"])
+def test_prepare_builds_graphs_without_changing_results(scheme):
+    """pd_prepare captures the step graphs up front; the run that follows is bit-identical
+    to one that builds them on first use, and preparing twice or after a change is safe."""
+    from paper_2105_04150_amd import simulation_for
+    w = pi.workload("qs_beam", dims=(35, 10, 10), steps=300)
+    w.scheme = scheme
+    a = simulation_for(w, lanes=1, mapping="staged")
+    a.prepare()
+    a.prepare()
+    a.step(150)
+    a.set_no_fail(None)
+    a.prepare()
+    a.step(150)
+    b = simulation_for(w, lanes=1, mapping="staged")
+    b.step(150)
+    b.set_no_fail(None)
+    b.step(150)
+    assert np.array_equal(a.u(), b.u()) and np.array_equal(a.v(), b.v())
+    assert np.array_equal(a.broken(), b.broken())
