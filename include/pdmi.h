@@ -251,6 +251,12 @@ int pd_get_force(pd_ctx *ctx, int32_t inst, double *out);
  * Errors: PD_EINVAL (node id out of range, m < 1). */
 int pd_get_resultant(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes, double out[3]);
 
+/* Mean displacement of a node set: out[0..2] = (1/m) sum over the m nodes (host ids,
+ * user order) of u_i at the current level, summed on the device in a fixed order (the
+ * mid-span deflection of Sec. 7, "the average deflection of the nodes at the top of the
+ * beam at the midspan").  Errors: PD_EINVAL (node id out of range, m < 1). */
+int pd_get_mean_displacement(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes, double out[3]);
+
 /* Overwrite the state of instance `inst` (checkpoint / restart, Sec. 3.6 "initiating
  * a simulation from an intermediate state").  Any of u, v, a (host n x 3) or broken
  * (host nnz; replaces the broken set exactly, un-breaking included) may be NULL to

@@ -91,6 +91,10 @@ class Simulation:
         """sum of V_i F_i over the given nodes (the reaction measured at a loaded set)."""
         return B.pd_get_resultant(self.ctx, inst, nodes)
 
+    def mean_displacement(self, nodes, inst=0):
+        """Mean u over the given nodes (e.g. the mid-span deflection of a beam)."""
+        return B.pd_get_mean_displacement(self.ctx, inst, nodes)
+
     def set_body_force(self, b_hat, magnitude, inst=0):
         B.pd_set_body_force(self.ctx, inst, b_hat, magnitude)
 

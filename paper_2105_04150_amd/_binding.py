@@ -27,7 +27,7 @@ SYMBOLS = [
     "pd_num_instances", "pd_instance_size", "pd_get_family", "pd_set_material", "pd_set_bond_stiffness",
     "pd_set_node_stiffness",
     "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_bc_ramp", "pd_set_no_fail", "pd_get_force",
-    "pd_get_resultant", "pd_set_body_force", "pd_set_integrator",
+    "pd_get_resultant", "pd_get_mean_displacement", "pd_set_body_force", "pd_set_integrator",
     "pd_step", "pd_prepare", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
     "pd_get_info", "pd_last_step_ms", "pd_adj_forward", "pd_adj_backward", "pd_get_break_steps",
@@ -82,6 +82,7 @@ def load() -> C.CDLL:
         "pd_set_no_fail": [P, i32, i64, P],
         "pd_get_force": [P, i32, P],
         "pd_get_resultant": [P, i32, i64, P, P],
+        "pd_get_mean_displacement": [P, i32, i64, P, P],
         "pd_set_body_force": [P, i32, P, d],
         "pd_set_integrator": [P, C.c_int, d],
         "pd_step": [P, i64],
@@ -234,6 +235,13 @@ def pd_get_resultant(ctx, inst: int, nodes) -> np.ndarray:
     nd = np.ascontiguousarray(nodes, dtype=np.int64)
     out = np.zeros(3)
     _check(ctx, load().pd_get_resultant(ctx, inst, nd.shape[0], _p(nd) if nd.shape[0] else None, _p(out)))
+    return out
+
+
+def pd_get_mean_displacement(ctx, inst: int, nodes) -> np.ndarray:
+    nd = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros(3)
+    _check(ctx, load().pd_get_mean_displacement(ctx, inst, nd.shape[0], _p(nd) if nd.shape[0] else None, _p(out)))
     return out
 
 

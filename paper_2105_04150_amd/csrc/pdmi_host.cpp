@@ -1724,28 +1724,59 @@ int pd_get_force(pd_ctx* ctx, int32_t inst, double* out)
     });
 }
 
+// Device indices of a host node list of one instance (validated).
+std::vector<int64_t> device_nodes(const Inst& I, int64_t m, const int64_t* nodes)
+{
+    if (m < 1 || !nodes) fail(PD_EINVAL, "need at least one node");
+    std::vector<int64_t> idx(static_cast<size_t>(m));
+    for (int64_t i = 0; i < m; ++i) {
+        if (nodes[i] < 0 || nodes[i] >= I.n) fail(PD_EINVAL, "node id out of range");
+        idx[i] = I.node_off + I.iperm[nodes[i]];
+    }
+    return idx;
+}
+
+// out = sum over the listed device nodes of w_i field(i, .) (see launch_set_sum).
+void set_sum(pd_ctx* ctx, const std::vector<int64_t>& idx, const double* field, int64_t snode, int64_t scomp,
+             const double* wv, double w, double out[3])
+{
+    ctx->rset.alloc(idx.size() * sizeof(int64_t));
+    if (!ctx->rsum.p) ctx->rsum.alloc(3 * sizeof(double));
+    upload(ctx->rset, idx.data(), idx.size() * sizeof(int64_t), 0, ctx->stream);
+    hip_check(launch_set_sum(field, snode, scomp, wv, w, ctx->rset.as<int64_t>(), static_cast<int64_t>(idx.size()),
+                             ctx->rsum.as<double>(), ctx->stream),
+              "set-sum launch");
+    download(out, ctx->rsum, 3 * sizeof(double), 0, ctx->stream);
+    sync(ctx);
+}
+
 int pd_get_resultant(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t* nodes, double out[3])
 {
     if (!ctx) return PD_EINVAL;
     return guarded(ctx, [&] {
         const Inst& I = instance(ctx, inst);
-        if (m < 1 || !nodes) fail(PD_EINVAL, "need at least one node");
         if (!out) fail(PD_EINVAL, "out is NULL");
-        std::vector<int64_t> idx(static_cast<size_t>(m));
-        for (int64_t i = 0; i < m; ++i) {
-            if (nodes[i] < 0 || nodes[i] >= I.n) fail(PD_EINVAL, "node id out of range");
-            idx[i] = I.node_off + I.iperm[nodes[i]];
-        }
+        const std::vector<int64_t> idx = device_nodes(I, m, nodes);
         set_device(ctx);
         eval_force(ctx);
-        ctx->rset.alloc(idx.size() * sizeof(int64_t));
-        if (!ctx->rsum.p) ctx->rsum.alloc(3 * sizeof(double));
-        upload(ctx->rset, idx.data(), idx.size() * sizeof(int64_t), 0, ctx->stream);
-        hip_check(launch_resultant(ctx->force.as<double>(), ctx->nn, ctx->has_vol ? ctx->vol.as<double>() : nullptr,
-                                   I.volume, ctx->rset.as<int64_t>(), m, ctx->rsum.as<double>(), ctx->stream),
-                  "resultant launch");
-        download(out, ctx->rsum, 3 * sizeof(double), 0, ctx->stream);
-        sync(ctx);
+        set_sum(ctx, idx, ctx->force.as<double>(), 1, ctx->nn, ctx->has_vol ? ctx->vol.as<double>() : nullptr,
+                I.volume, out);
+    });
+}
+
+int pd_get_mean_displacement(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t* nodes, double out[3])
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        const std::vector<int64_t> idx = device_nodes(I, m, nodes);
+        set_device(ctx);
+        const double w = 1.0 / static_cast<double>(m);
+        if (fp32(ctx))  // the f64 master displacement, structure of arrays
+            set_sum(ctx, idx, ctx->um[ctx->cur].as<double>(), 1, ctx->nn, nullptr, w, out);
+        else            // the node records: x then u, 6 doubles per node
+            set_sum(ctx, idx, ctx->rec[ctx->cur].as<double>() + 3, 6, 1, nullptr, w, out);
     });
 }
 

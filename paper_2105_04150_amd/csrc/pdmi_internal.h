@@ -151,10 +151,10 @@ hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, int split,
 hipError_t launch_step_staged_f64(const StepArgs& a, int mode, int split, bool nofail, hipStream_t s);
 hipError_t launch_step_staged_f32(const StepArgs& a, int mode, int split, bool nofail, hipStream_t s);
 
-// out[0..2] = sum over the m device nodes idx[] of V_i force_i (force: SoA, stride nn;
-// V_i from vol, or `volume` when vol is nullptr), summed in a fixed order
-hipError_t launch_resultant(const double* force, int64_t nn, const double* vol, double volume, const int64_t* idx,
-                            int64_t m, double* out, hipStream_t s);
+// out[d] = sum over the m device nodes idx[] of w_i field[i * snode + d * scomp], w_i = wv[i]
+// or w when wv is nullptr, summed in a fixed order (force resultants, set means)
+hipError_t launch_set_sum(const double* field, int64_t snode, int64_t scomp, const double* wv, double w,
+                          const int64_t* idx, int64_t m, double* out, hipStream_t s);
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
 

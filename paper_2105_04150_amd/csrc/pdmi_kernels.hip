@@ -1,5 +1,5 @@
 // pdmi_kernels.hip -- gfx950 kernels around the step: local damage, the velocity-Verlet
-// drift, the step counter and the force resultant of a node set; the launchers that
+// drift, the step counter and weighted sums over node sets; the launchers that
 // dispatch to the step-kernel launcher files.
 #include "pdmi_device.h"
 
@@ -100,21 +100,24 @@ __global__ void advance_kernel(int64_t* step_base, int64_t by)
     if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += by;
 }
 
-// Force resultant of a node set: out = sum over idx[0..m) of V_i F_i, one workgroup, each
-// thread sums a strided subsequence, then a fixed-shape tree in LDS (deterministic).
-__global__ __launch_bounds__(kBlock) void resultant_kernel(const double* __restrict__ force, int64_t nn,
-                                                          const double* __restrict__ vol, double volume,
-                                                          const int64_t* __restrict__ idx, int64_t m,
-                                                          double* __restrict__ out)
+// Weighted sum over a node set: out[d] = sum over idx[0..m) of w_i field(i, d), with
+// field(i, d) = field[i * snode + d * scomp] and w_i = wv[i], or w when wv is nullptr.
+// One workgroup; each thread sums a strided subsequence, then a fixed-shape tree in
+// LDS (deterministic).
+__global__ __launch_bounds__(kBlock) void set_sum_kernel(const double* __restrict__ field, int64_t snode,
+                                                        int64_t scomp, const double* __restrict__ wv, double w,
+                                                        const int64_t* __restrict__ idx, int64_t m,
+                                                        double* __restrict__ out)
 {
     __shared__ double red[3][kBlock];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int64_t r = threadIdx.x; r < m; r += kBlock) {
         const int64_t i = idx[r];
-        const double w = vol ? vol[i] : volume;
-        s0 += w * force[i];
-        s1 += w * force[nn + i];
-        s2 += w * force[2 * nn + i];
+        const double wi = wv ? wv[i] : w;
+        const double* f = field + i * snode;
+        s0 += wi * f[0];
+        s1 += wi * f[scomp];
+        s2 += wi * f[2 * scomp];
     }
     red[0][threadIdx.x] = s0;
     red[1][threadIdx.x] = s1;
@@ -171,10 +174,10 @@ hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_resultant(const double* force, int64_t nn, const double* vol, double volume, const int64_t* idx,
-                            int64_t m, double* out, hipStream_t s)
+hipError_t launch_set_sum(const double* field, int64_t snode, int64_t scomp, const double* wv, double w,
+                          const int64_t* idx, int64_t m, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(resultant_kernel, dim3(1), dim3(kBlock), 0, s, force, nn, vol, volume, idx, m, out);
+    hipLaunchKernelGGL(set_sum_kernel, dim3(1), dim3(kBlock), 0, s, field, snode, scomp, wv, w, idx, m, out);
     return hipGetLastError();
 }
 

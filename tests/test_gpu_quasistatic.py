@@ -184,6 +184,26 @@ def test_resultant(qs_oracle):
     assert np.abs(g2.resultant(load) - R_ref).max() <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_mean_displacement(qs_oracle, precision):
+    """Mid-span deflection: the mean u of the top nodes at mid-span (and of the load set)
+    after the run, against the oracle's displacement."""
+    from paper_2105_04150_amd import PD_FP32, PD_FP64, simulation_for
+    w, o = qs_oracle
+    g = simulation_for(w, mapping="staged", precision=PD_FP64 if precision == "f64" else PD_FP32)
+    g.step(w.steps)
+    mid = np.nonzero((w.ijk[:, 0] == w.dims[0] // 2) & (w.ijk[:, 2] == w.dims[2] - 1))[0]
+    _, _, load = pi.qs_beam_sets(w.ijk, w.dims)
+    tol = TOL_FP64 if precision == "f64" else TOL_FP32
+    scale = np.abs(o.u).max()
+    for nodes in (mid, load, np.arange(w.n)):
+        got = g.mean_displacement(nodes)
+        want = o.u[nodes].mean(0)
+        assert np.abs(got - want).max() <= tol * scale, (len(nodes), got, want)
+    # the ramp holds the load set exactly at its end value
+    assert g.mean_displacement(load)[2] == pytest.approx(-1.15e-7 * w.dims[0], rel=1e-14)
+
+
 def test_zone_changes_keep_state_and_break_steps():
     """Removing a zone mid-run keeps the broken set and the recorded break steps, and the
     run goes on as the oracle's with the same history (zone for 1200 steps, none after)."""
@@ -224,6 +244,10 @@ def test_arguments():
         g.resultant([])
     with pytest.raises(PdmiError):
         g.resultant([w.n])
+    with pytest.raises(PdmiError):
+        g.mean_displacement([])
+    with pytest.raises(PdmiError):
+        g.mean_displacement([-3])
     g.step(10)
 
 
