@@ -45,7 +45,7 @@ def _load():
         _lib.pdo_run.restype = C.c_int
         _lib.pdo_run.argtypes = [P, P, i64]
         _lib.pdo_damage.restype = None
-        _lib.pdo_damage.argtypes = [P, P, P]
+        _lib.pdo_damage.argtypes = [P, P, P, P]
         _lib.pdo_apply_jt.restype = None
         _lib.pdo_apply_jt.argtypes = [P, P, P, i64, P, P]
         _lib.pdo_adjoint_ec.restype = C.c_int
@@ -60,13 +60,15 @@ class _Problem(C.Structure):
                 ("eta", C.c_double), ("dt", C.c_double), ("bhat", C.c_void_p),
                 ("bmag", C.c_double), ("bc_kind", C.c_void_p), ("bc_sched", C.c_void_p),
                 ("bc_val", C.c_void_p), ("scheme", C.c_int32), ("nthreads", C.c_int32),
-                ("ramp_T", C.c_double), ("nofail", C.c_void_p)]
+                ("ramp_T", C.c_double), ("nofail", C.c_void_p),
+                ("ncls", C.c_int32), ("pad2_", C.c_int32), ("cls_nb", C.c_void_p), ("cls_s", C.c_void_p),
+                ("cls_r", C.c_void_p), ("slot_cls", C.c_void_p)]
 
 
 class _State(C.Structure):
     _fields_ = [("u", C.c_void_p), ("v", C.c_void_p), ("a", C.c_void_p),
                 ("broken", C.c_void_p), ("break_step", C.c_void_p), ("frozen", C.c_void_p),
-                ("step", C.c_int64), ("a_valid", C.c_int32), ("pad_", C.c_int32)]
+                ("step", C.c_int64), ("a_valid", C.c_int32), ("pad_", C.c_int32), ("smax", C.c_void_p)]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -105,7 +107,8 @@ class OracleSim:
 
     def __init__(self, coords, row_ptr, col, *, c, s0, rho, dt, vol, scheme="euler_cromer",
                  eta=0.0, kslot=None, bhat=None, bmag=0.0, bcs=(), nthreads=0,
-                 record_breaks=False, frozen=None, broken=None, ramp_T=1.0, nofail=None):
+                 record_breaks=False, frozen=None, broken=None, ramp_T=1.0, nofail=None,
+                 laws=None, slot_cls=None, smax=None):
         lib = _load()
         self._lib = lib
         self.x = np.ascontiguousarray(coords, dtype=np.float64)
@@ -122,11 +125,27 @@ class OracleSim:
         self.nofail = None if nofail is None else np.ascontiguousarray(nofail, dtype=np.uint8)
         if self.nofail is not None and self.nofail.shape != (n,):
             raise ValueError("nofail needs one flag per node")
+        # damage laws: a list of (stretch breakpoints, force ratios) per bond class
+        MAXB = 8
+        self.laws = None if not laws else list(laws)
+        ncls = 0 if self.laws is None else len(self.laws)
+        self.cls_nb = np.zeros(max(ncls, 1), dtype=np.int32)
+        self.cls_s = np.zeros(max(ncls, 1) * MAXB)
+        self.cls_r = np.zeros(max(ncls, 1) * MAXB)
+        for k, (sb, rb) in enumerate(self.laws or []):
+            sb, rb = np.asarray(sb, dtype=np.float64), np.asarray(rb, dtype=np.float64)
+            if not (1 <= sb.shape[0] <= MAXB and sb.shape == rb.shape):
+                raise ValueError("a damage law needs 1..8 breakpoints and as many ratios")
+            self.cls_nb[k] = sb.shape[0]
+            self.cls_s[k * MAXB: k * MAXB + sb.shape[0]] = sb
+            self.cls_r[k * MAXB: k * MAXB + sb.shape[0]] = rb
+        self.slot_cls = None if slot_cls is None else np.ascontiguousarray(slot_cls, dtype=np.uint8)
         self.P = _Problem(n, _ptr(self.x), _ptr(self.vol), _ptr(self.row_ptr), _ptr(self.col),
                           _ptr(self.kslot), float(c), float(s0), float(rho), float(eta), float(dt),
                           _ptr(self.bhat), float(bmag), _ptr(self.bc_kind), _ptr(self.bc_sched),
                           _ptr(self.bc_val), SCHEMES[scheme], int(nthreads), float(ramp_T),
-                          _ptr(self.nofail))
+                          _ptr(self.nofail), ncls, 0, _ptr(self.cls_nb), _ptr(self.cls_s), _ptr(self.cls_r),
+                          _ptr(self.slot_cls))
         self.u = np.zeros((n, 3))
         self.v = np.zeros((n, 3))
         self.a = np.zeros((n, 3))
@@ -136,8 +155,13 @@ class OracleSim:
         self.break_step = (np.full(max(self.nnz, 1), np.iinfo(np.int32).max, dtype=np.int32)
                            if record_breaks else None)
         self.frozen = None if frozen is None else np.ascontiguousarray(frozen, dtype=np.int32)
+        self.smax = None
+        if ncls:
+            self.smax = np.zeros(max(self.nnz, 1))
+            if smax is not None:
+                self.smax[: self.nnz] = smax
         self.S = _State(_ptr(self.u), _ptr(self.v), _ptr(self.a), _ptr(self.broken),
-                        _ptr(self.break_step), _ptr(self.frozen), 0, 0, 0)
+                        _ptr(self.break_step), _ptr(self.frozen), 0, 0, 0, _ptr(self.smax))
 
     @property
     def step(self) -> int:
@@ -168,7 +192,7 @@ class OracleSim:
 
     def damage(self) -> np.ndarray:
         phi = np.zeros(self.n)
-        self._lib.pdo_damage(C.byref(self.P), _ptr(self.broken), _ptr(phi))
+        self._lib.pdo_damage(C.byref(self.P), _ptr(self.broken), _ptr(self.smax), _ptr(phi))
         return phi
 
     @property

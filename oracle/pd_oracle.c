@@ -23,6 +23,10 @@
  *   damage          phi_i = 1 - sum_j mu_ij V_j / sum_j V_j            (Sec. 2.2, local damage)
  *   integrators     velocity Verlet (Eqs. Velocity_Verlet1-3), Euler-Cromer and forward Euler
  *                   (the integrator classes listed in Sec. 3.6; their update rules are not printed).
+ *   damage laws     n-linear softening laws (the "arbitrary number of linear splines" of
+ *                   Sec. 3.7; trilinear in Sec. 6, bilinear in Sec. 7) per bond class, with
+ *                   irreversibility through the largest stretch a bond has reached (Sec. 2.2
+ *                   reading: the bond follows the secant to the origin once it has softened)
  *   quasi-static    prescribed displacements ramped by a fifth-order polynomial in time with
  *   loading         zero initial velocity and acceleration (Examples 2 and 3, Secs. 6-7), and
  *                   'no-failure zones': bonds of flagged nodes never break (Secs. 5.1, 6, 7).
@@ -41,6 +45,8 @@
 #define PDO_EC 0
 #define PDO_VV 1
 #define PDO_FE 2
+
+#define PDO_MAXB 8  /* breakpoints per damage law */
 
 #define PDO_FREE 0
 #define PDO_DISP 1
@@ -66,7 +72,19 @@ typedef struct pdo_problem {
     int32_t scheme;          /* PDO_EC / PDO_VV / PDO_FE */
     int32_t nthreads;        /* <= 0: library default */
     double ramp_T;           /* duration of the fifth-order ramp (schedule 2) */
-    const uint8_t *nofail;   /* n or NULL: 1 = no-failure zone, bonds touching the node never break */
+    const uint8_t *nofail;   /* n or NULL: 1 = no-failure zone, bonds touching the node never break
+                                nor soften */
+    /* Damage laws.  ncls = 0: the brittle law with s0 above.  Otherwise class k has
+     * cls_nb[k] breakpoints s_0 < s_1 < ... < s_last (cls_s[k * PDO_MAXB + .]) with force
+     * ratios r_0 = 1, ..., r_last = 0 (cls_r): the bond force of a monotonic pull is
+     * c s up to s_0, then c s_0 times the linear interpolation of the ratios, and the
+     * bond is broken from s_last on (one breakpoint: the brittle law with s0 = s_0). */
+    int32_t ncls;
+    int32_t pad2_;
+    const int32_t *cls_nb;
+    const double *cls_s;
+    const double *cls_r;
+    const uint8_t *slot_cls; /* nnz class of each slot, or NULL: class 0 */
 } pdo_problem;
 
 typedef struct pdo_state {
@@ -79,6 +97,8 @@ typedef struct pdo_state {
     int64_t step;            /* number of completed time steps */
     int32_t a_valid;         /* velocity Verlet: a holds the acceleration of the current u */
     int32_t pad_;
+    double *smax;            /* nnz (with damage laws): the largest stretch a slot has reached
+                                beyond its elastic limit, 0 while it has not */
 } pdo_state;
 
 static void set_threads(const pdo_problem *P)
@@ -219,6 +239,28 @@ int64_t pdo_family_cells(int64_t n, const double *x, double delta, int64_t *row_
 
 /* ------------------------------------------------------------------ bond forces */
 
+/* Secant ratio of damage law k at a stretch sm beyond its elastic limit s_0 (and below
+ * s_last): the law's force c s_0 rho(sm), rho interpolated linearly between breakpoints,
+ * divided by the elastic force c sm. */
+static double law_ratio(const pdo_problem *P, int k, double sm)
+{
+    const double *sb = P->cls_s + k * PDO_MAXB, *rb = P->cls_r + k * PDO_MAXB;
+    int seg = 0;
+    while (seg + 2 < P->cls_nb[k] && sm >= sb[seg + 1]) ++seg;
+    double rho = rb[seg] + (rb[seg + 1] - rb[seg]) * ((sm - sb[seg]) / (sb[seg + 1] - sb[seg]));
+    return (sb[0] * rho) / sm;
+}
+
+static int slot_class(const pdo_problem *P, int64_t b) { return P->slot_cls ? P->slot_cls[b] : 0; }
+
+/* Damage of a slot under the damage laws: 1 broken, 1 - secant ratio once softened. */
+static double slot_damage(const pdo_problem *P, const uint8_t *broken, const double *smax, int64_t b)
+{
+    if (broken[b]) return 1.0;
+    if (P->ncls > 0 && smax && smax[b] > 0.0) return 1.0 - law_ratio(P, slot_class(P, b), smax[b]);
+    return 0.0;
+}
+
 /* Force density of every node for displacement u, in pass k (the index of the time
  * level u belongs to).  Without a frozen schedule, a slot whose stretch reaches s0
  * is marked broken (and its pass recorded) and contributes nothing; with a frozen
@@ -247,13 +289,32 @@ void pdo_force(const pdo_problem *P, pdo_state *S, const double *u, int64_t k, d
             double L = sqrt((xi0 * xi0 + xi1 * xi1) + xi2 * xi2);
             double s = (r - L) / L;
             const int unbreakable = P->nofail && (P->nofail[i] || P->nofail[j]);
-            if (!S->frozen && !unbreakable && s >= P->s0) {
+            double w = 1.0;  /* secant ratio of a softened bond */
+            if (P->ncls > 0) {
+                const int cl = slot_class(P, b);
+                const double s_first = P->cls_s[cl * PDO_MAXB];
+                const double s_last = P->cls_s[cl * PDO_MAXB + P->cls_nb[cl] - 1];
+                if (S->frozen) {
+                    if (S->smax[b] > 0.0) w = law_ratio(P, cl, S->smax[b]);
+                } else if (!unbreakable) {
+                    double sm = s > S->smax[b] ? s : S->smax[b];
+                    if (sm >= s_last) {
+                        S->broken[b] = 1;
+                        if (S->break_step) S->break_step[b] = (int32_t)k;
+                        continue;
+                    }
+                    if (sm > s_first) {
+                        S->smax[b] = sm;
+                        w = law_ratio(P, cl, sm);
+                    }
+                }
+            } else if (!S->frozen && !unbreakable && s >= P->s0) {
                 S->broken[b] = 1;
                 if (S->break_step) S->break_step[b] = (int32_t)k;
                 continue;
             }
             double kb = P->kslot ? P->kslot[b] : P->c;
-            double scal = ((kb * s) * P->vol[j]) / r;
+            double scal = (((kb * s) * w) * P->vol[j]) / r;
             f0 += scal * y0;
             f1 += scal * y1;
             f2 += scal * y2;
@@ -418,14 +479,21 @@ int pdo_run(const pdo_problem *P, pdo_state *S, int64_t nsteps)
 
 /* ------------------------------------------------------------------ damage */
 
-void pdo_damage(const pdo_problem *P, const uint8_t *broken, double *phi)
+/* phi_i = 1 - sum_j (1 - d_ij) V_j / sum_j V_j over the initial family: d = 1 for a
+ * broken bond, 1 - secant ratio for a softened one (smax may be NULL: brittle), 0
+ * otherwise.  With the brittle law this is 1 - sum_j mu_ij V_j / sum_j V_j. */
+void pdo_damage(const pdo_problem *P, const uint8_t *broken, const double *smax, double *phi)
 {
     for (int64_t i = 0; i < P->n; ++i) {
         double num = 0.0, den = 0.0;
         for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
             double vj = P->vol[P->col[b]];
             den += vj;
-            if (!broken[b]) num += vj;
+            const double d = slot_damage(P, broken, smax, b);
+            if (d == 0.0)
+                num += vj;
+            else if (d < 1.0)
+                num += (1.0 - d) * vj;
         }
         phi[i] = den > 0.0 ? 1.0 - num / den : 0.0;
     }
