@@ -188,9 +188,34 @@ int pd_set_bc_ramp(pd_ctx *ctx, int32_t inst, double ramp_time);
 
 /* No-failure zones (Secs. 5.1, 6, 7): the m nodes (host ids, user order) of instance
  * `inst` become the zone, replacing any earlier one; a bond with either end in the zone
- * never breaks from now on (bonds already broken stay broken, recorded break steps are
- * kept).  m = 0 removes the zone.  Errors: PD_EINVAL (node id out of range). */
+ * never breaks and keeps its damage state from now on (bonds already broken stay broken,
+ * softened ones keep their secant ratio, recorded break steps are kept).  m = 0 removes the zone.  Errors: PD_EINVAL (node id out of range). */
 int pd_set_no_fail(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes);
+
+/* Damage law of bond class `cls` (0..7) of instance `inst` (Sec. 3.6: laws made of
+ * linear splines; the trilinear law of Sec. 6, the bilinear law of Sec. 7).  nb (1..8)
+ * stretch breakpoints s_break[0] < ... < s_break[nb-1], all > 0, with force ratios
+ * ratio[nb] >= 0, ratio[0] = 1 and ratio[nb-1] = 0 when nb > 1.  Under a monotonic pull
+ * a bond carries c s up to s_break[0], then c s_break[0] times the ratio interpolated
+ * linearly between breakpoints, and breaks for good at s_break[nb-1]; nb = 1 is the
+ * brittle law with s0 = s_break[0].  Damage is irreversible: a bond that has softened
+ * to a largest stretch s_m carries (c s_break[0] rho(s_m) / s_m) s, the secant to the
+ * origin, in tension and compression.  Once an instance has laws, they replace the s0
+ * of pd_set_material.  Classes are defined in order (cls <= number defined); setting a
+ * law again replaces it.  Every change of laws or classes clears the softening state
+ * (broken flags and recorded break steps are kept).  Host arrays are copied.
+ * Errors: PD_EINVAL (class out of range or out of order, bad breakpoints or ratios). */
+int pd_set_damage_law(pd_ctx *ctx, int32_t inst, int32_t cls, int32_t nb, const double *s_break,
+                      const double *ratio);
+
+/* Bond class of every slot: cls[nnz] (host, user CSR order), each below the number of
+ * laws defined; both slots of a bond must be in the same class (Sec. 2.2: bond classes
+ * as a function of the two end points).  NULL puts every slot in class 0.
+ * Errors: PD_EINVAL (no laws, class without a law, asymmetric classes). */
+int pd_set_bond_classes(pd_ctx *ctx, int32_t inst, const uint8_t *cls);
+
+/* Back to the brittle law with the s0 of pd_set_material (laws and classes removed). */
+int pd_clear_damage_laws(pd_ctx *ctx, int32_t inst);
 
 /* Body force density b_i = magnitude * b_hat_i (N/m^3) of instance `inst`;
  * b_hat: host n x 3, user order; NULL removes it. */
@@ -231,17 +256,29 @@ int pd_get_u(pd_ctx *ctx, int32_t inst, double *out);
 int pd_get_v(pd_ctx *ctx, int32_t inst, double *out);
 int pd_get_a(pd_ctx *ctx, int32_t inst, double *out);
 
-/* Local damage phi_i = 1 - sum_j mu_ij V_j / sum_j V_j over the initial family
- * (Sec. 2.2), as of the last completed step; 0 for a node without bonds.
+/* Local damage phi_i = 1 - sum_j (1 - d_ij) V_j / sum_j V_j over the initial family
+ * (Sec. 2.2; d = 1 broken, d = 1 - secant ratio for a bond softened under a damage law,
+ * 0 intact: with the brittle law this is 1 - sum_j mu_ij V_j / sum_j V_j), as of the
+ * last completed step; 0 for a node without bonds.
  * out: host, n doubles, user order. */
 int pd_get_damage(pd_ctx *ctx, int32_t inst, double *out);
 
 /* Broken flags of every slot: out[nnz] (host, user CSR order), 1 = broken. */
 int pd_get_broken(pd_ctx *ctx, int32_t inst, uint8_t *out);
 
+/* Largest stretch each slot has reached beyond its damage law's elastic limit, 0 while
+ * it has not (and without damage laws): out[nnz] (host, user CSR order). */
+int pd_get_max_stretch(pd_ctx *ctx, int32_t inst, double *out);
+
+/* Overwrite the stretch state (checkpoint / restart with damage laws): smax[nnz] (host,
+ * user CSR order) as pd_get_max_stretch returns it; a slot with smax > 0 counts as
+ * softened.  Errors: PD_ESTATE (no damage laws), PD_EINVAL (negative or non-finite). */
+int pd_set_max_stretch(pd_ctx *ctx, int32_t inst, const double *smax);
+
 /* Bond force density F_i = sum_j f_ij V_j (Eq. discrete EOM without the body force) at
- * the current displacement, over the bonds intact now; no bond breaks and the state is
- * not changed.  Evaluated on the device for every instance by the step kernel in a
+ * the current displacement, over the bonds intact now, each with its damage state as it
+ * stands (a softened bond with its secant ratio); no bond breaks or softens and the state
+ * is not changed.  Evaluated on the device for every instance by the step kernel in a
  * force-only mode.  out: host, n x 3 doubles, user order. */
 int pd_get_force(pd_ctx *ctx, int32_t inst, double *out);
 

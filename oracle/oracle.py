@@ -252,6 +252,10 @@ def from_workload(w, nthreads: int = 0, record_breaks: bool = False, method: str
         sig, ell, seed = w.stiffness_field
         kslot = slot_stiffness(w.c, gaussian_node_field(w.dims, sig, ell, seed), row_ptr, col)
     bhat, bmag = (None, 0.0) if w.body_force is None else w.body_force
+    slot_cls = None
+    if w.laws and w.class_spec is not None:
+        from pd_inputs import bond_classes
+        slot_cls = bond_classes(row_ptr, col, *w.class_spec)
     nofail = None
     if w.nofail is not None:
         nofail = np.zeros(w.n, dtype=np.uint8)
@@ -259,4 +263,5 @@ def from_workload(w, nthreads: int = 0, record_breaks: bool = False, method: str
     return OracleSim(w.coords, row_ptr, col, c=w.c, s0=w.s0, rho=w.rho, dt=w.dt, vol=w.volume,
                      scheme=w.scheme, eta=w.eta, kslot=kslot, bhat=bhat, bmag=bmag, bcs=w.bcs,
                      nthreads=nthreads, record_breaks=record_breaks, broken=broken,
-                     ramp_T=1.0 if w.ramp_T is None else w.ramp_T, nofail=nofail, frozen=frozen)
+                     ramp_T=1.0 if w.ramp_T is None else w.ramp_T, nofail=nofail, frozen=frozen,
+                     laws=w.laws, slot_cls=slot_cls)

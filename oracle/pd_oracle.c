@@ -24,7 +24,7 @@
  *   integrators     velocity Verlet (Eqs. Velocity_Verlet1-3), Euler-Cromer and forward Euler
  *                   (the integrator classes listed in Sec. 3.6; their update rules are not printed).
  *   damage laws     n-linear softening laws (the "arbitrary number of linear splines" of
- *                   Sec. 3.7; trilinear in Sec. 6, bilinear in Sec. 7) per bond class, with
+ *                   Sec. 3.6; trilinear in Sec. 6, bilinear in Sec. 7) per bond class, with
  *                   irreversibility through the largest stretch a bond has reached (Sec. 2.2
  *                   reading: the bond follows the secant to the origin once it has softened)
  *   quasi-static    prescribed displacements ramped by a fifth-order polynomial in time with
@@ -73,7 +73,7 @@ typedef struct pdo_problem {
     int32_t nthreads;        /* <= 0: library default */
     double ramp_T;           /* duration of the fifth-order ramp (schedule 2) */
     const uint8_t *nofail;   /* n or NULL: 1 = no-failure zone, bonds touching the node never break
-                                nor soften */
+                                and their damage state does not change */
     /* Damage laws.  ncls = 0: the brittle law with s0 above.  Otherwise class k has
      * cls_nb[k] breakpoints s_0 < s_1 < ... < s_last (cls_s[k * PDO_MAXB + .]) with force
      * ratios r_0 = 1, ..., r_last = 0 (cls_r): the bond force of a monotonic pull is
@@ -294,9 +294,9 @@ void pdo_force(const pdo_problem *P, pdo_state *S, const double *u, int64_t k, d
                 const int cl = slot_class(P, b);
                 const double s_first = P->cls_s[cl * PDO_MAXB];
                 const double s_last = P->cls_s[cl * PDO_MAXB + P->cls_nb[cl] - 1];
-                if (S->frozen) {
+                if (S->frozen || unbreakable) {  /* damage state as it stands */
                     if (S->smax[b] > 0.0) w = law_ratio(P, cl, S->smax[b]);
-                } else if (!unbreakable) {
+                } else {
                     double sm = s > S->smax[b] ? s : S->smax[b];
                     if (sm >= s_last) {
                         S->broken[b] = 1;

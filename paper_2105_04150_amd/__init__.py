@@ -91,6 +91,24 @@ class Simulation:
         """sum of V_i F_i over the given nodes (the reaction measured at a loaded set)."""
         return B.pd_get_resultant(self.ctx, inst, nodes)
 
+    def set_damage_law(self, cls, s_break, ratio, inst=0):
+        """Damage law of bond class cls: stretch breakpoints and force ratios (1 ... 0)."""
+        B.pd_set_damage_law(self.ctx, inst, cls, s_break, ratio)
+
+    def set_bond_classes(self, cls, inst=0):
+        """Bond class of every slot (user CSR order, symmetric per bond); None: class 0."""
+        B.pd_set_bond_classes(self.ctx, inst, cls)
+
+    def clear_damage_laws(self, inst=0):
+        B.pd_clear_damage_laws(self.ctx, inst)
+
+    def max_stretch(self, inst=0):
+        """Largest stretch of every slot beyond its law's elastic limit (0 if none)."""
+        return B.pd_get_max_stretch(self.ctx, inst)
+
+    def set_max_stretch(self, smax, inst=0):
+        B.pd_set_max_stretch(self.ctx, inst, smax)
+
     def mean_displacement(self, nodes, inst=0):
         """Mean u over the given nodes (e.g. the mid-span deflection of a beam)."""
         return B.pd_get_mean_displacement(self.ctx, inst, nodes)
@@ -184,6 +202,11 @@ def apply_workload(sim: Simulation, w, inst: int = 0, row_ptr=None, col=None, st
         sim.set_bcs(bc.nodes, bc.comp_mask, bc.kind, bc.value, bc.sched, inst=inst)
     if w.ramp_T is not None:
         sim.set_bc_ramp(w.ramp_T, inst=inst)
+    if w.laws:
+        for k, (sb, rb) in enumerate(w.laws):
+            sim.set_damage_law(k, sb, rb, inst=inst)
+        if w.class_spec is not None:
+            sim.set_bond_classes(pi.bond_classes(row_ptr, col, *w.class_spec), inst=inst)
     if w.nofail is not None:
         sim.set_no_fail(w.nofail, inst=inst)
     if w.notch is not None:

@@ -27,7 +27,8 @@ SYMBOLS = [
     "pd_num_instances", "pd_instance_size", "pd_get_family", "pd_set_material", "pd_set_bond_stiffness",
     "pd_set_node_stiffness",
     "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_bc_ramp", "pd_set_no_fail", "pd_get_force",
-    "pd_get_resultant", "pd_get_mean_displacement", "pd_set_body_force", "pd_set_integrator",
+    "pd_get_resultant", "pd_get_mean_displacement", "pd_set_damage_law", "pd_set_bond_classes",
+    "pd_clear_damage_laws", "pd_get_max_stretch", "pd_set_max_stretch", "pd_set_body_force", "pd_set_integrator",
     "pd_step", "pd_prepare", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
     "pd_get_info", "pd_last_step_ms", "pd_adj_forward", "pd_adj_backward", "pd_get_break_steps",
@@ -83,6 +84,11 @@ def load() -> C.CDLL:
         "pd_get_force": [P, i32, P],
         "pd_get_resultant": [P, i32, i64, P, P],
         "pd_get_mean_displacement": [P, i32, i64, P, P],
+        "pd_set_damage_law": [P, i32, i32, i32, P, P],
+        "pd_set_bond_classes": [P, i32, P],
+        "pd_clear_damage_laws": [P, i32],
+        "pd_get_max_stretch": [P, i32, P],
+        "pd_set_max_stretch": [P, i32, P],
         "pd_set_body_force": [P, i32, P, d],
         "pd_set_integrator": [P, C.c_int, d],
         "pd_step": [P, i64],
@@ -243,6 +249,44 @@ def pd_get_mean_displacement(ctx, inst: int, nodes) -> np.ndarray:
     out = np.zeros(3)
     _check(ctx, load().pd_get_mean_displacement(ctx, inst, nd.shape[0], _p(nd) if nd.shape[0] else None, _p(out)))
     return out
+
+
+def pd_set_damage_law(ctx, inst: int, cls: int, s_break, ratio) -> None:
+    sb = np.ascontiguousarray(s_break, dtype=np.float64).ravel()
+    rb = np.ascontiguousarray(ratio, dtype=np.float64).ravel()
+    if sb.shape != rb.shape:
+        raise ValueError("s_break and ratio need the same length")
+    _check(ctx, load().pd_set_damage_law(ctx, inst, int(cls), sb.shape[0], _p(sb), _p(rb)))
+
+
+def pd_set_bond_classes(ctx, inst: int, cls) -> None:
+    if cls is None:
+        _check(ctx, load().pd_set_bond_classes(ctx, inst, None))
+        return
+    nnz = pd_instance_size(ctx, inst)[1]
+    c = np.ascontiguousarray(cls, dtype=np.uint8)
+    if c.shape != (nnz,):
+        raise ValueError(f"bond classes need shape ({nnz},)")
+    _check(ctx, load().pd_set_bond_classes(ctx, inst, _p(c)))
+
+
+def pd_clear_damage_laws(ctx, inst: int = 0) -> None:
+    _check(ctx, load().pd_clear_damage_laws(ctx, inst))
+
+
+def pd_get_max_stretch(ctx, inst: int = 0) -> np.ndarray:
+    nnz = pd_instance_size(ctx, inst)[1]
+    out = np.zeros(max(nnz, 1))
+    _check(ctx, load().pd_get_max_stretch(ctx, inst, _p(out)))
+    return out[:nnz]
+
+
+def pd_set_max_stretch(ctx, inst: int, smax) -> None:
+    nnz = pd_instance_size(ctx, inst)[1]
+    sm = np.ascontiguousarray(smax, dtype=np.float64)
+    if sm.shape != (nnz,):
+        raise ValueError(f"stretch state needs shape ({nnz},)")
+    _check(ctx, load().pd_set_max_stretch(ctx, inst, _p(sm)))
 
 
 def pd_set_body_force(ctx, inst: int, b_hat, magnitude: float) -> None:

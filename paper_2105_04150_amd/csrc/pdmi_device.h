@@ -106,6 +106,21 @@ __device__ __forceinline__ double bc_disp(const BCRec& r, int d, double t, doubl
 
 __device__ __forceinline__ bool constrained(const BCRec& r, int d) { return ((r.code >> (2 * d)) & 3) != 0; }
 
+// Secant ratio of a bond softened to stretch sm under law L (s[0] < sm < s[nb-1]): the
+// law's force c s[0] rho(sm), rho interpolated linearly between breakpoints, over the
+// elastic force c sm.  The bond force is this ratio times c s (unloading and reloading
+// follow the secant to the origin).
+__device__ __forceinline__ double law_secant(const LawRec& L, double sm)
+{
+    int seg = 0;
+    while (seg + 2 < L.nb && sm >= L.s[seg + 1]) ++seg;
+    const double rho = L.r[seg] + (L.r[seg + 1] - L.r[seg]) * ((sm - L.s[seg]) / (L.s[seg + 1] - L.s[seg]));
+    return (L.s[0] * rho) / sm;
+}
+
+// Damage of a softened slot from its stored largest stretch.
+__device__ __forceinline__ double law_damage(const LawRec& L, double sm) { return 1.0 - law_secant(L, sm); }
+
 // Neighbour device index of a sliced slot word (intact or broken, no-failure bit dropped).
 __device__ __forceinline__ uint32_t col_node(int32_t c)
 {

@@ -92,6 +92,8 @@ struct Inst {
     std::vector<double> bc_val;              // n*3
     double ramp_T = 1.0;                     // duration of the fifth-order ramp schedule
     std::vector<uint8_t> nofail;             // user order, no-failure zone flags; empty = none
+    std::vector<LawRec> laws;                // damage laws (bond classes); empty = the brittle law with s0
+    std::vector<uint8_t> cls;                // user CSR order: law of every slot; empty = law 0
     // device layout
     std::vector<int64_t> perm;       // device-local node -> user node, -1 = padding
     std::vector<int64_t> iperm;      // user node -> device-local node
@@ -133,9 +135,11 @@ struct pd_ctx {
     int64_t nn = 0, ns = 0, nslices = 0;
     bool has_stiff = false, has_vol = false, has_body = false, has_knode = false;
     bool has_nofail = false;         // some slot carries the no-failure bit
+    bool has_laws = false;           // some instance has damage laws (smax, laws allocated)
     DevBuf rec[2], um[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc,
         step_base, status, phi, pieces, slice_piece, ent;
     DevBuf force, rset, rsum;        // force readout: F (SoA), node list and sum of a resultant
+    DevBuf laws, cls, smax;          // damage laws, per-slot law (several per instance), stretch state
 
     // adjoint: per-slot break steps (recorded by every step while allocated) and the
     // (u, v) checkpoints of the last recorded forward run
@@ -194,6 +198,9 @@ int guarded(pd_ctx* ctx, F&& f)
 }
 
 void set_device(pd_ctx* ctx) { hip_check(hipSetDevice(ctx->device), "hipSetDevice"); }
+
+// The step kernels with the bond-model branch: no-failure zones or damage laws present.
+bool ext_kernels(const pd_ctx* ctx) { return ctx->has_nofail || ctx->has_laws; }
 
 void require_built(const pd_ctx* ctx)
 {
@@ -405,11 +412,20 @@ std::vector<int32_t> slot_ranks(const Inst& I, double h)
     return order;
 }
 
-InstParams make_params(const Inst& I)
+InstParams make_params(const Inst& I, int32_t law_off)
 {
     InstParams p{};
     p.c = I.c;
     p.q0 = I.s0 * (2.0 + I.s0);
+    p.nlaw = static_cast<int32_t>(I.laws.size());
+    p.law_off = law_off;
+    if (!I.laws.empty()) {
+        // the kernels' threshold for the bond-model branch: just below every law's
+        // elastic limit (the branch itself decides in stretch)
+        double qmin = std::numeric_limits<double>::infinity();
+        for (const LawRec& L : I.laws) qmin = std::min(qmin, L.s[0] * (2.0 + L.s[0]));
+        p.q0 = qmin * (1.0 - 1e-9);
+    }
     p.rho = I.rho;
     p.eta = I.eta;
     p.volume = I.volume;
@@ -448,13 +464,18 @@ size_t rec_bytes(int64_t nn) { return static_cast<size_t>(nn + 1 + kRecPad) * 48
 struct HostState {
     std::vector<std::vector<double>> u, v, a;   // per instance, n*3
     std::vector<std::vector<uint8_t>> broken;   // per instance, nnz
+    std::vector<std::vector<double>> smax;      // per instance, nnz (empty without damage laws)
 };
 
 void upload_params(pd_ctx* ctx)
 {
     ctx->tape_valid = false;
     std::vector<InstParams> p;
-    for (auto& I : ctx->inst) p.push_back(make_params(I));
+    int32_t law_off = 0;
+    for (auto& I : ctx->inst) {
+        p.push_back(make_params(I, law_off));
+        law_off += static_cast<int32_t>(I.laws.size());
+    }
     upload(ctx->params, p.data(), p.size() * sizeof(InstParams), 0, ctx->stream);
 }
 
@@ -694,6 +715,59 @@ void init_break_steps(pd_ctx* ctx, const Inst& I)
               "break-step init launch");
 }
 
+// Damage-law table of every instance, the per-slot law index (instances with several
+// laws) and a zeroed stretch state; without laws all three are released.
+void upload_laws(pd_ctx* ctx)
+{
+    ctx->tape_valid = false;
+    std::vector<LawRec> all;
+    bool many = false;
+    for (auto& I : ctx->inst) {
+        all.insert(all.end(), I.laws.begin(), I.laws.end());
+        many |= I.laws.size() > 1;
+    }
+    ctx->has_laws = !all.empty();
+    if (!ctx->has_laws) {
+        ctx->laws.release();
+        ctx->cls.release();
+        ctx->smax.release();
+        return;
+    }
+    ctx->laws.alloc(all.size() * sizeof(LawRec));
+    upload(ctx->laws, all.data(), all.size() * sizeof(LawRec), 0, ctx->stream);
+    const size_t nslot = static_cast<size_t>(ctx->ns) + kSpareRows * kWave;
+    ctx->smax.alloc(nslot * sizeof(double));
+    hip_check(hipMemsetAsync(ctx->smax.p, 0, ctx->smax.bytes, ctx->stream), "hipMemsetAsync");
+    if (many) {
+        std::vector<uint8_t> c(nslot, 0);
+        for (auto& I : ctx->inst) {
+            if (I.cls.empty()) continue;
+            for (int64_t d = 0; d < I.n_dslots; ++d) {
+                const int32_t b = I.dslot_user[d];
+                if (b >= 0) c[I.dslot_off + d] = I.cls[b];
+            }
+        }
+        ctx->cls.alloc(nslot);
+        upload(ctx->cls, c.data(), nslot, 0, ctx->stream);
+    } else {
+        ctx->cls.release();
+    }
+    sync(ctx);
+}
+
+// One instance's stretch state in user CSR order (zeros without damage laws).
+std::vector<double> smax_of(pd_ctx* ctx, const Inst& I)
+{
+    std::vector<double> out(static_cast<size_t>(I.nnz), 0.0);
+    if (!ctx->has_laws) return out;
+    std::vector<double> d(static_cast<size_t>(I.n_dslots));
+    download(d.data(), ctx->smax, d.size() * sizeof(double), I.dslot_off * sizeof(double), ctx->stream);
+    sync(ctx);
+    for (int64_t k = 0; k < I.n_dslots; ++k)
+        if (I.dslot_user[k] >= 0) out[I.dslot_user[k]] = d[k];
+    return out;
+}
+
 // Per user slot: the bond touches a no-failure zone (empty without flags).
 std::vector<uint8_t> nofail_slots(const Inst& I)
 {
@@ -707,14 +781,24 @@ std::vector<uint8_t> nofail_slots(const Inst& I)
     return nf;
 }
 
-// Slot words of one instance from its broken flags and no-failure zones.  The recorded
-// break steps restart from the flags unless keep_bsteps (only the zones changed).
-void upload_col(pd_ctx* ctx, Inst& I, const uint8_t* broken, bool keep_bsteps = false)
+// Slot words of one instance from its broken flags, no-failure zones and stretch state
+// (smax in user CSR order, nullptr: no bond softened; a slot with smax > 0 is marked
+// softened).  The recorded break steps restart from the flags unless keep_bsteps.
+void upload_col(pd_ctx* ctx, Inst& I, const uint8_t* broken, bool keep_bsteps = false,
+                const double* smax = nullptr)
 {
     ctx->tape_valid = false;
     I.br_sym = bond_symmetric(I, broken);
     const std::vector<uint8_t> nf = nofail_slots(I);
     const bool any_nf = !nf.empty();
+    if (ctx->has_laws) {
+        std::vector<double> d(static_cast<size_t>(I.n_dslots), 0.0);
+        if (smax)
+            for (int64_t k = 0; k < I.n_dslots; ++k)
+                if (I.dslot_user[k] >= 0) d[k] = smax[I.dslot_user[k]];
+        upload(ctx->smax, d.data(), d.size() * sizeof(double), I.dslot_off * sizeof(double), ctx->stream);
+    }
+    auto soft = [&](int32_t b) { return ctx->has_laws && smax && smax[b] > 0.0; };
     if (ctx->mapping == PD_MAP_STAGED) {
         std::vector<uint16_t> e(static_cast<size_t>(I.n_dslots));
         parallel_for(I.n_dslots, [&](int64_t s0, int64_t s1) {
@@ -724,7 +808,7 @@ void upload_col(pd_ctx* ctx, Inst& I, const uint8_t* broken, bool keep_bsteps = 
                     e[d] = static_cast<uint16_t>(kEntBroken | kEntPad);
                 else
                     e[d] = static_cast<uint16_t>((48 * I.ent_idx[d]) | ((broken && broken[b]) ? kEntBroken : 0) |
-                                                 ((any_nf && nf[b]) ? kEntNoFail : 0));
+                                                 ((any_nf && nf[b]) ? kEntNoFail : 0) | (soft(b) ? kEntSoft : 0));
             }
         });
         upload(ctx->ent, e.data(), e.size() * sizeof(uint16_t), I.dslot_off * sizeof(uint16_t), ctx->stream);
@@ -743,7 +827,7 @@ void upload_col(pd_ctx* ctx, Inst& I, const uint8_t* broken, bool keep_bsteps = 
                         colv[ds] = ~static_cast<int32_t>(ctx->nn);  // padding: the sentinel record
                     } else {
                         const int32_t j = static_cast<int32_t>(I.node_off + I.iperm[I.col[b]]) |
-                                          ((any_nf && nf[b]) ? kColNoFail : 0);
+                                          ((any_nf && nf[b]) ? kColNoFail : 0) | (soft(b) ? kColSoft : 0);
                         colv[ds] = (broken && broken[b]) ? ~j : j;
                     }
                 }
@@ -815,6 +899,7 @@ HostState snapshot(pd_ctx* ctx)
         S.v.push_back(soa_of(ctx, I, ctx->v));
         S.a.push_back(soa_of(ctx, I, ctx->a));
         S.broken.push_back(broken_of(ctx, I));
+        S.smax.push_back(ctx->has_laws ? smax_of(ctx, I) : std::vector<double>());
     }
     return S;
 }
@@ -1037,12 +1122,14 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     upload_volumes(ctx);
     upload_node_weights(ctx);
     upload_body(ctx);
+    upload_laws(ctx);
     for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
         Inst& I = ctx->inst[ii];
         std::vector<double> zeros(static_cast<size_t>(3 * I.n), 0.0);
         upload_state(ctx, I, S ? S->u[ii].data() : zeros.data(), S ? S->v[ii].data() : nullptr,
                      S ? S->a[ii].data() : nullptr);
-        upload_col(ctx, I, S ? S->broken[ii].data() : nullptr);
+        const double* sm = (S && !S->smax[ii].empty()) ? S->smax[ii].data() : nullptr;
+        upload_col(ctx, I, S ? S->broken[ii].data() : nullptr, false, sm);
     }
     ctx->cur = 0;
     ctx->vv_ahead = false;
@@ -1087,6 +1174,7 @@ void new_problem(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* con
     ctx->order = order == PD_ORDER_AUTO ? PD_ORDER_NATURAL : order;
     ctx->order_auto = order == PD_ORDER_AUTO;
     ctx->has_nofail = false;
+    ctx->has_laws = false;
     ctx->step = 0;
     ctx->a_valid = false;
     ctx->vv_ahead = false;
@@ -1111,6 +1199,9 @@ StepArgs step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
     A.nw = ctx->has_knode ? ctx->nw.as<double>() : nullptr;
     A.bhat = ctx->has_body ? ctx->bhat.as<double>() : nullptr;
     A.force = ctx->force.p ? ctx->force.as<double>() : nullptr;
+    A.laws = ctx->has_laws ? ctx->laws.as<LawRec>() : nullptr;
+    A.cls = ctx->cls.p ? ctx->cls.as<uint8_t>() : nullptr;
+    A.smax = ctx->has_laws ? ctx->smax.as<double>() : nullptr;
     A.slice_ptr = ctx->slice_ptr.as<int64_t>();
     A.slice_T = ctx->slice_T.as<int32_t>();
     A.slice_inst = ctx->slice_inst.as<int32_t>();
@@ -1139,10 +1230,10 @@ void launch_one(pd_ctx* ctx, int mode, int in, int out, int64_t step_local)
 {
     const StepArgs A = step_args(ctx, in, out, step_local);
     if (ctx->mapping == PD_MAP_STAGED)
-        hip_check(launch_step_staged(A, mode, fp32(ctx), ctx->lanes, ctx->has_nofail, ctx->stream),
+        hip_check(launch_step_staged(A, mode, fp32(ctx), ctx->lanes, ext_kernels(ctx), ctx->stream),
                   "step kernel launch");
     else
-        hip_check(launch_step(A, ctx->lanes, mode, ctx->has_stiff, ctx->has_nofail, ctx->stream),
+        hip_check(launch_step(A, ctx->lanes, mode, ctx->has_stiff, ext_kernels(ctx), ctx->stream),
                   "step kernel launch");
 }
 
@@ -1248,6 +1339,8 @@ void adjoint_checks(pd_ctx* ctx)
     if (fp32(ctx)) fail(PD_EINVAL, "the adjoint runs in the FP64 build only");
     if (ctx->scheme != PD_EULER_CROMER) fail(PD_EINVAL, "the adjoint differentiates the Euler-Cromer scheme only");
     if (ctx->inst.size() != 1) fail(PD_EINVAL, "the adjoint needs a single-instance problem");
+    for (const LawRec& L : ctx->inst[0].laws)
+        if (L.nb > 1) fail(PD_EINVAL, "the adjoint differentiates brittle damage laws only");
 }
 
 // The reverse pass gathers the transposed tangent over each node's own family, which
@@ -1262,10 +1355,10 @@ void check_symmetric(const Inst& I)
 void launch_ec(pd_ctx* ctx, const StepArgs& A)
 {
     if (ctx->mapping == PD_MAP_STAGED)
-        hip_check(launch_step_staged(A, kModeEC, false, ctx->lanes, ctx->has_nofail, ctx->stream),
+        hip_check(launch_step_staged(A, kModeEC, false, ctx->lanes, ext_kernels(ctx), ctx->stream),
                   "step kernel launch");
     else
-        hip_check(launch_step(A, ctx->lanes, kModeEC, ctx->has_stiff, ctx->has_nofail, ctx->stream),
+        hip_check(launch_step(A, ctx->lanes, kModeEC, ctx->has_stiff, ext_kernels(ctx), ctx->stream),
                   "step kernel launch");
 }
 
@@ -1459,7 +1552,8 @@ int pd_break_bonds(pd_ctx* ctx, int32_t inst, const uint8_t* broken)
         set_device(ctx);
         std::vector<uint8_t> cur = broken_of(ctx, I);
         for (int64_t b = 0; b < I.nnz; ++b) cur[b] = cur[b] || broken[b];
-        upload_col(ctx, I, cur.data());
+        const std::vector<double> sm = smax_of(ctx, I);
+        upload_col(ctx, I, cur.data(), false, sm.data());
         ctx->a_valid = false;
         ctx->vv_ahead = false;
     });
@@ -1534,6 +1628,7 @@ int pd_set_no_fail(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t* nodes)
             if (nodes[i] < 0 || nodes[i] >= I.n) fail(PD_EINVAL, "no-failure node id out of range");
         set_device(ctx);
         const std::vector<uint8_t> br = broken_of(ctx, I);
+        const std::vector<double> sm = smax_of(ctx, I);
         I.nofail.clear();
         if (m > 0) {
             I.nofail.assign(static_cast<size_t>(I.n), 0);
@@ -1541,8 +1636,81 @@ int pd_set_no_fail(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t* nodes)
         }
         ctx->has_nofail = false;
         for (auto& J : ctx->inst) ctx->has_nofail |= !J.nofail.empty();
-        upload_col(ctx, I, br.data(), /*keep_bsteps=*/true);
+        upload_col(ctx, I, br.data(), /*keep_bsteps=*/true, sm.data());
         ctx->drop_graphs();
+    });
+}
+
+// After a change of damage laws or bond classes: new tables, softening state cleared
+// (broken flags and recorded break steps kept).
+void reset_laws(pd_ctx* ctx)
+{
+    std::vector<std::vector<uint8_t>> br;
+    for (auto& I : ctx->inst) br.push_back(broken_of(ctx, I));
+    upload_params(ctx);
+    upload_laws(ctx);
+    for (size_t ii = 0; ii < ctx->inst.size(); ++ii) upload_col(ctx, ctx->inst[ii], br[ii].data(), true, nullptr);
+    ctx->drop_graphs();
+}
+
+int pd_set_damage_law(pd_ctx* ctx, int32_t inst, int32_t cls, int32_t nb, const double* s_break, const double* ratio)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (cls < 0 || cls >= kLawMaxClasses) fail(PD_EINVAL, "bond class out of range 0..7");
+        if (cls > static_cast<int32_t>(I.laws.size())) fail(PD_EINVAL, "bond classes must be defined in order");
+        if (nb < 1 || nb > kLawMaxB) fail(PD_EINVAL, "a damage law has 1..8 breakpoints");
+        if (!s_break || !ratio) fail(PD_EINVAL, "s_break or ratio is NULL");
+        LawRec L{};
+        L.nb = nb;
+        for (int k = 0; k < nb; ++k) {
+            if (!std::isfinite(s_break[k]) || !(s_break[k] > 0.0)) fail(PD_EINVAL, "breakpoints must be positive");
+            if (k > 0 && !(s_break[k] > s_break[k - 1])) fail(PD_EINVAL, "breakpoints must increase");
+            if (!std::isfinite(ratio[k]) || ratio[k] < 0.0) fail(PD_EINVAL, "force ratios must be >= 0");
+            L.s[k] = s_break[k];
+            L.r[k] = ratio[k];
+        }
+        if (nb > 1 && (ratio[0] != 1.0 || ratio[nb - 1] != 0.0))
+            fail(PD_EINVAL, "a softening law starts at ratio 1 and ends at ratio 0");
+        set_device(ctx);
+        if (cls == static_cast<int32_t>(I.laws.size()))
+            I.laws.push_back(L);
+        else
+            I.laws[cls] = L;
+        reset_laws(ctx);
+    });
+}
+
+int pd_set_bond_classes(pd_ctx* ctx, int32_t inst, const uint8_t* cls)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (cls) {
+            if (I.laws.empty()) fail(PD_EINVAL, "define the damage laws first");
+            for (int64_t b = 0; b < I.nnz; ++b)
+                if (cls[b] >= I.laws.size()) fail(PD_EINVAL, "bond class without a damage law");
+            if (!bond_symmetric(I, cls)) fail(PD_EINVAL, "both slots of a bond must be in the same class");
+        }
+        set_device(ctx);
+        if (cls)
+            I.cls.assign(cls, cls + I.nnz);
+        else
+            I.cls.clear();
+        reset_laws(ctx);
+    });
+}
+
+int pd_clear_damage_laws(pd_ctx* ctx, int32_t inst)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        set_device(ctx);
+        I.laws.clear();
+        I.cls.clear();
+        reset_laws(ctx);
     });
 }
 
@@ -1687,6 +1855,9 @@ int pd_get_damage(pd_ctx* ctx, int32_t inst, double* out)
         D.pieces = ctx->pieces.as<int2>();
         D.slice_piece = ctx->slice_piece.as<int32_t>();
         D.ent = ctx->ent.as<uint16_t>();
+        D.laws = ctx->has_laws ? ctx->laws.as<LawRec>() : nullptr;
+        D.cls = ctx->cls.p ? ctx->cls.as<uint8_t>() : nullptr;
+        D.smax = ctx->has_laws ? ctx->smax.as<double>() : nullptr;
         if (ctx->mapping == PD_MAP_STAGED)
             hip_check(launch_damage_staged(D, ctx->stream), "damage launch");
         else
@@ -1708,6 +1879,34 @@ int pd_get_broken(pd_ctx* ctx, int32_t inst, uint8_t* out)
         set_device(ctx);
         auto b = broken_of(ctx, I);
         std::memcpy(out, b.data(), b.size());
+    });
+}
+
+int pd_get_max_stretch(pd_ctx* ctx, int32_t inst, double* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        set_device(ctx);
+        const std::vector<double> sm = smax_of(ctx, I);
+        std::memcpy(out, sm.data(), sm.size() * sizeof(double));
+    });
+}
+
+int pd_set_max_stretch(pd_ctx* ctx, int32_t inst, const double* smax)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (!smax) fail(PD_EINVAL, "smax is NULL");
+        if (!ctx->has_laws) fail(PD_ESTATE, "no damage laws");
+        for (int64_t b = 0; b < I.nnz; ++b)
+            if (!std::isfinite(smax[b]) || smax[b] < 0.0) fail(PD_EINVAL, "stretch state must be finite and >= 0");
+        set_device(ctx);
+        const std::vector<uint8_t> br = broken_of(ctx, I);
+        upload_col(ctx, I, br.data(), true, smax);
+        ctx->drop_graphs();
     });
 }
 
@@ -1796,7 +1995,10 @@ int pd_set_state(pd_ctx* ctx, int32_t inst, const double* u, const double* v, co
             upload_state(ctx, I, u, nullptr, nullptr);
         }
         upload_state(ctx, I, nullptr, v, a);
-        if (broken) upload_col(ctx, I, broken);
+        if (broken) {
+            const std::vector<double> sm = smax_of(ctx, I);
+            upload_col(ctx, I, broken, false, sm.data());
+        }
         reset_flags_after_state_change(ctx, a != nullptr);
     });
 }

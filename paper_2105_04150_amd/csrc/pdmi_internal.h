@@ -18,8 +18,9 @@
 //                                 T rows of 64 entries, entry (t, w*G + g) = slot t*G + g of the
 //                                 slice's node w.  col >= 0: intact bond to device node
 //                                 col & kColNode, bit 30 (kColNoFail) set when the bond
-//                                 touches a no-failure zone; col < 0: ~col is the word of a
-//                                 broken bond, or the sentinel nn for padding.
+//                                 touches a no-failure zone, bit 29 (kColSoft) once it has
+//                                 softened under a damage law; col < 0: ~col is the word of
+//                                 a broken bond, or the sentinel nn for padding.
 //   stiffness     kslot[ns]       f64 per slot, same layout (only with a per-slot stiffness field)
 //   node stiffness na[nn+1], nw[nn+1]  f64 per node (only with a per-node stiffness field,
 //                                 bond stiffness sqrt(k_i k_j)): na = sqrt(k_i), nw = sqrt(k_j) V_j;
@@ -32,10 +33,13 @@
 // copies a piece's node records and entries into LDS, then reads neighbours from there.
 //   pieces        int2 {first node of the range, len | T << 8} per piece
 //   slice_piece   first piece of every slice (+ one past the last)
-//   ent[ns]       uint16 per slot: bits 0..13 = byte offset of the neighbour's record in the
+//   ent[ns]       uint16 per slot: bits 0..12 = byte offset of the neighbour's record in the
 //                 staged copy (48 x index into the range; kEntPad for padding, the LDS
-//                 sentinel record), bit 14 = no-failure zone, bit 15 = broken; slice_ptr
-//                 gives each slice's first entry.
+//                 sentinel record), bit 13 = softened, bit 14 = no-failure zone, bit 15 =
+//                 broken; slice_ptr gives each slice's first entry.
+//   smax[ns]      f64 per slot (with damage laws): the largest stretch the slot reached
+//                 beyond its law's elastic limit (0 while it has not); cls[ns] uint8: the
+//                 slot's law (bond class) when an instance has several
 //                 The entry array ends with kPieceRows spare rows (whole 8-row blocks are
 //                 loaded).
 #pragma once
@@ -56,24 +60,42 @@ constexpr int kStageChunks = 4 * 64;    // 16-byte record chunks one staged rang
 constexpr int kEntPad = kStageChunks * 16;  // entry byte offset of the LDS sentinel record
 constexpr int kRecPad = kStageChunks / 3 + 2;  // zero records after the sentinel
 // slot flags: a bond touching a no-failure zone never breaks (Secs. 5.1, 6, 7)
+// and a bond that has softened under a damage law is marked so its state is read
 constexpr int32_t kColNoFail = 0x40000000;  // sliced word: no-failure bit
-constexpr int32_t kColNode = 0x3fffffff;    // sliced word: neighbour index bits
-constexpr uint32_t kEntOff = 0x3fff;        // staged entry: record byte offset bits
+constexpr int32_t kColSoft = 0x20000000;    // sliced word: softened bit
+constexpr int32_t kColNode = 0x1fffffff;    // sliced word: neighbour index bits
+constexpr uint32_t kEntOff = 0x1fff;        // staged entry: record byte offset bits
+constexpr uint32_t kEntSoft = 0x2000;       // staged entry: softened bit
 constexpr uint32_t kEntNoFail = 0x4000;     // staged entry: no-failure bit
 constexpr uint32_t kEntBroken = 0x8000;     // staged entry: broken bit
+
+// One damage law (bond class): stretch breakpoints s[0] < ... < s[nb-1] with force ratios
+// r[0] = 1, ..., r[nb-1] = 0.  A monotonic pull follows c s up to s[0], then c s[0] times
+// the interpolated ratio; the bond is broken from s[nb-1] on (nb = 1: the brittle law).
+constexpr int kLawMaxB = 8;
+constexpr int kLawMaxClasses = 8;
+struct LawRec {
+    double s[kLawMaxB];
+    double r[kLawMaxB];
+    int32_t nb;
+    int32_t pad_;
+};
 static_assert(3 * kSegMax <= kStageChunks, "a range fits the staged record loads");
-static_assert(kEntPad <= kEntOff, "entry offsets fit 14 bits");
+static_assert(kEntPad <= kEntOff, "entry offsets fit 13 bits");
 constexpr int32_t kNodeFree = -1;       // bc_id of an unconstrained node
 constexpr int32_t kNodePad = -2;        // bc_id of a padding node (never updated)
 
 struct InstParams {
     double c;        // micromodulus without a stiffness field
-    double q0;       // break threshold on q = r^2/L^2 - 1: (1 + s0)^2 - 1
+    double q0;       // break threshold on q = r^2/L^2 - 1: (1 + s0)^2 - 1; with damage
+                     // laws, a threshold just below every law's elastic limit
     double rho;
     double eta;
     double volume;   // uniform node volume without a volume array
     double bmag;     // body-force magnitude
     int32_t has_body;
+    int32_t nlaw;    // damage laws of the instance (0: the brittle law with q0)
+    int32_t law_off; // first law of the instance in StepArgs::laws
     int32_t pad_;
 };
 
@@ -105,6 +127,9 @@ struct StepArgs {
     const double* nw;
     const double* bhat;         // bhat + d*nn, nullptr without body forces
     double* force;              // kModeForce: bond force density out, force + d*nn
+    const LawRec* laws;         // damage laws of every instance (nullptr without)
+    const uint8_t* cls;         // per slot: law index within the instance (nullptr: 0)
+    double* smax;               // per slot: largest stretch beyond the elastic limit
     const int64_t* slice_ptr;
     const int32_t* slice_T;
     const int32_t* slice_inst;
@@ -136,10 +161,14 @@ struct DamageArgs {
     const int2* pieces;         // staged layout only
     const int32_t* slice_piece;
     const uint16_t* ent;
+    const LawRec* laws;         // damage laws (nullptr without)
+    const uint8_t* cls;
+    const double* smax;
 };
 
-// sliced mapping (FP64); nofail: some slot carries the no-failure bit
-hipError_t launch_step(const StepArgs& a, int lanes, int mode, bool stiff, bool nofail, hipStream_t s);
+// sliced mapping (FP64); ext: some slot may carry the no-failure bit or a damage law
+// (the kernels with the bond-model branch)
+hipError_t launch_step(const StepArgs& a, int lanes, int mode, bool stiff, bool ext, hipStream_t s);
 
 // velocity-Verlet drift of every node (fp32: master displacement and f32 records)
 hipError_t launch_drift(const StepArgs& a, bool fp32, hipStream_t s);
@@ -147,9 +176,9 @@ hipError_t launch_drift(const StepArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s);
 
 // staged mapping, FP64 or FP32 bond arithmetic, `split` wavefronts per slice
-hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, int split, bool nofail, hipStream_t s);
-hipError_t launch_step_staged_f64(const StepArgs& a, int mode, int split, bool nofail, hipStream_t s);
-hipError_t launch_step_staged_f32(const StepArgs& a, int mode, int split, bool nofail, hipStream_t s);
+hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, int split, bool ext, hipStream_t s);
+hipError_t launch_step_staged_f64(const StepArgs& a, int mode, int split, bool ext, hipStream_t s);
+hipError_t launch_step_staged_f32(const StepArgs& a, int mode, int split, bool ext, hipStream_t s);
 
 // out[d] = sum over the m device nodes idx[] of w_i field[i * snode + d * scomp], w_i = wv[i]
 // or w when wv is nullptr, summed in a fixed order (force resultants, set means)

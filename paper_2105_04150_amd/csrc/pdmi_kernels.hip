@@ -6,6 +6,17 @@
 namespace pdmi {
 namespace {
 
+// 1 - d of a slot: 0 broken, the secant ratio of its law once softened, 1 otherwise
+// (local damage is 1 - sum (1 - d) V_j / sum V_j; with the brittle law d is 0 or 1).
+__device__ __forceinline__ double intact_share(const DamageArgs& A, const InstParams& P, int64_t ds, bool broken,
+                                               bool soft)
+{
+    if (broken) return 0.0;
+    if (!soft || P.nlaw == 0) return 1.0;
+    const LawRec& L = A.laws[P.law_off + (P.nlaw > 1 ? A.cls[ds] : 0)];
+    return 1.0 - law_damage(L, A.smax[ds]);
+}
+
 // Local damage on the staged layout.
 __global__ __launch_bounds__(kWave) void damage_staged(DamageArgs A)
 {
@@ -21,12 +32,13 @@ __global__ __launch_bounds__(kWave) void damage_staged(DamageArgs A)
         const int2 m = A.pieces[p];
         const int T = (m.y >> 8) & 0xff;
         for (int t = 0; t < T; ++t) {
-            const uint16_t e = A.ent[ent + t * kWave + lane];
+            const int64_t ds = ent + t * kWave + lane;
+            const uint16_t e = A.ent[ds];
             const int off = e & kEntOff;
             if (off == kEntPad) continue;  // padding
             const double vj = A.vol ? A.vol[m.x + off / 48] : P.volume;
             den += vj;
-            if (!(e & kEntBroken)) num += vj;
+            num += intact_share(A, P, ds, (e & kEntBroken) != 0, (e & kEntSoft) != 0) * vj;
         }
         ent += static_cast<int64_t>(T) * kWave;
     }
@@ -80,12 +92,13 @@ __global__ __launch_bounds__(kBlock) void damage_kernel(DamageArgs A)
     const int T = A.slice_T[slice];
     double num = 0.0, den = 0.0;
     for (int t = 0; t < T; ++t) {
-        const int32_t c = A.col[base + static_cast<int64_t>(t) * kWave + lane];
+        const int64_t ds = base + static_cast<int64_t>(t) * kWave + lane;
+        const int32_t c = A.col[ds];
         const int32_t j = static_cast<int32_t>(col_node(c));
         if (j == A.sentinel) continue;  // padding
         const double vj = A.vol ? A.vol[j] : P.volume;
         den += vj;
-        if (c >= 0) num += vj;
+        num += intact_share(A, P, ds, c < 0, (c & kColSoft) != 0) * vj;
     }
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) {
@@ -162,9 +175,9 @@ hipError_t launch_damage(const DamageArgs& a, int lanes, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, int split, bool nofail, hipStream_t s)
+hipError_t launch_step_staged(const StepArgs& a, int mode, bool fp32, int split, bool ext, hipStream_t s)
 {
-    return fp32 ? launch_step_staged_f32(a, mode, split, nofail, s) : launch_step_staged_f64(a, mode, split, nofail, s);
+    return fp32 ? launch_step_staged_f32(a, mode, split, ext, s) : launch_step_staged_f64(a, mode, split, ext, s);
 }
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s)

@@ -23,12 +23,28 @@
 // Every kernel also has a force-evaluation mode (kModeForce): the same gather at the
 // current level, no breaking, the bond force density written out (the reaction-force
 // readout of the quasi-static examples, Sec. 6).
+//
+// EXT variants carry the bond-model branch: no-failure zones and n-linear damage laws
+// per bond class.  Their common path adds every live bond's elastic contribution; a slot
+// over the instance's threshold (or already softened) then takes a rare branch that asks
+// its damage state for a weight w and moves its contribution from 1 to w (breaking:
+// w = 0).  Problems without zones or laws run the plain kernels.
 #pragma once
 
 #include "pdmi_device.h"
 
 namespace pdmi {
 namespace {
+
+// What the bond-model branch needs of a slot: its q and its elastic contribution
+// coef * y to the force density (FP64 and FP32 builds).
+struct SlotTerm {
+    double q, coef, y0, y1, y2;
+};
+struct SlotTerm32 {
+    double q;
+    float coef, y0, y1, y2;
+};
 
 // Contribution of one slot.  live: the slot holds an intact bond; breakable: the bond may
 // break in this pass (intact, outside the no-failure zones, not a force evaluation).
@@ -37,7 +53,7 @@ namespace {
 // the bond breaks in this pass.
 __device__ __forceinline__ bool slot_force(bool live, bool breakable, const double2 p0, const double2 p1, const double2 p2,
                                            double X0, double X1, double X2, double U0, double U1, double U2,
-                                           double kv, double q0, double& F0, double& F1, double& F2,
+                                           double kv, double q0, double& F0, double& F1, double& F2, SlotTerm& st,
                                            const SeriesCoef& sk = SeriesCoef())
 {
     const double xi0 = p0.x - X0, xi1 = p0.y - X1, xi2 = p1.x - X2;
@@ -53,6 +69,7 @@ __device__ __forceinline__ bool slot_force(bool live, bool breakable, const doub
     const bool alive = live && !brk;
     // broken and padding slots evaluate g(0) = 0 and add nothing
     const double coef = (kv * iL) * one_minus_rsqrt1p(alive ? q : 0.0, sk);
+    st = SlotTerm{q, coef, y0, y1, y2};
     F0 = __builtin_fma(coef, y0, F0);
     F1 = __builtin_fma(coef, y1, F1);
     F2 = __builtin_fma(coef, y2, F2);
@@ -64,7 +81,7 @@ __device__ __forceinline__ bool slot_force(bool live, bool breakable, const doub
 // 1 - (1+q)^(-1/2) uses four series terms (below 1.3e-10 relative for |q| < 4e-3).
 __device__ __forceinline__ bool slot_force32(bool live, bool breakable, const double2 p0, const double2 p1, const double2 p2,
                                              double X0, double X1, double X2, float U0, float U1, float U2,
-                                             float kv, float q0, float& F0, float& F1, float& F2)
+                                             float kv, float q0, float& F0, float& F1, float& F2, SlotTerm32& st)
 {
     const float xi0 = static_cast<float>(p0.x - X0), xi1 = static_cast<float>(p0.y - X1),
                 xi2 = static_cast<float>(p1.x - X2);
@@ -92,10 +109,42 @@ __device__ __forceinline__ bool slot_force32(bool live, bool breakable, const do
         g = 1.0f - __builtin_amdgcn_rsqf(1.0f + qa);
     }
     const float coef = (kv * iL) * g;
+    st = SlotTerm32{q, coef, y0, y1, y2};
     F0 = __builtin_fmaf(coef, y0, F0);
     F1 = __builtin_fmaf(coef, y1, F1);
     F2 = __builtin_fmaf(coef, y2, F2);
     return brk;
+}
+
+// Weight of a slot in the bond-model branch (EXT kernels): the slot is live and either at
+// or over the instance's threshold q0, or softened.  q is its q of this pass, nofail /
+// soft its word's flags.  Returns w (the bond adds w times its elastic force); sets broke
+// when it breaks now and newly_soft when it softens for the first time.  A zone bond, and
+// every bond in a force evaluation, keeps its damage state as it stands.
+template <int MODE, bool FP32>
+__device__ double bond_weight(const StepArgs& A, const InstParams& P, int64_t ds, double q, bool nofail, bool soft,
+                              bool& broke, bool& newly_soft)
+{
+    broke = false;
+    newly_soft = false;
+    if (P.nlaw == 0) {  // the brittle law with the instance's s0
+        if (nofail || MODE == kModeForce) return 1.0;
+        broke = FP32 ? static_cast<float>(q) >= static_cast<float>(P.q0) : q >= P.q0;
+        return broke ? 0.0 : 1.0;
+    }
+    const LawRec& L = A.laws[P.law_off + (P.nlaw > 1 ? A.cls[ds] : 0)];
+    const double sold = soft ? A.smax[ds] : 0.0;
+    if (nofail || MODE == kModeForce) return soft ? law_secant(L, sold) : 1.0;
+    const double s = q / (1.0 + __builtin_sqrt(1.0 + q));  // stretch from q without cancellation
+    const double sm = s > sold ? s : sold;
+    if (sm >= L.s[L.nb - 1]) {
+        broke = true;
+        return 0.0;
+    }
+    if (!(sm > L.s[0])) return 1.0;
+    if (sm > sold) A.smax[ds] = sm;
+    newly_soft = !soft;
+    return law_secant(L, sm);
 }
 
 // Integration and boundary conditions of one node given its force density F (the tail
@@ -193,7 +242,7 @@ __device__ __forceinline__ void node_update(const StepArgs& A, const InstParams&
         for (int d = 0; d < 3; ++d) A.a[d * nn + node] = an[d];
 }
 
-template <int G, int MODE, bool STIFF, bool VOLN, bool KNODE, bool NOFAIL>
+template <int G, int MODE, bool STIFF, bool VOLN, bool KNODE, bool EXT>
 __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
 {
     constexpr int W = kWave / G;
@@ -247,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
             for (int u = 0; u < U; ++u) {
                 c[u] = cn[u];
                 const uint32_t j = static_cast<uint32_t>(c[u] ^ (c[u] >> 31)) &
-                                   (NOFAIL ? static_cast<uint32_t>(kColNode) : 0xffffffffu);
+                                   (EXT ? static_cast<uint32_t>(kColNode) : 0xffffffffu);
                 const char* rj = recb + __umul24(j, 48u);  // full-rate 24-bit multiply: j < 2^24
                 p[u][0] = *reinterpret_cast<const double2*>(rj);
                 p[u][1] = *reinterpret_cast<const double2*>(rj + 16);
@@ -267,22 +316,46 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) cn[u] = col_at(t + U + u);
-            bool brk[U];
+            bool flag[U];  // plain: breaks now; EXT: takes the bond-model branch
+            SlotTerm st[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                // a bond may break unless it is broken, padding or in a no-failure zone
-                const bool breakable = MODE != kModeForce &&
-                                       (NOFAIL ? static_cast<uint32_t>(c[u]) < static_cast<uint32_t>(kColNoFail)
-                                               : c[u] >= 0);
-                brk[u] = slot_force(c[u] >= 0, breakable, p[u][0], p[u][1], p[u][2], X0, X1, X2, U0, U1, U2, kv[u],
-                                    P.q0, F0, F1, F2, sk);
+                if constexpr (EXT) {
+                    slot_force(c[u] >= 0, false, p[u][0], p[u][1], p[u][2], X0, X1, X2, U0, U1, U2, kv[u], P.q0, F0,
+                               F1, F2, st[u], sk);
+                    const bool soft = (c[u] & kColSoft) != 0;
+                    flag[u] = c[u] >= 0 && (MODE == kModeForce ? soft : (st[u].q >= P.q0 || soft));
+                } else {
+                    flag[u] = slot_force(c[u] >= 0, MODE != kModeForce && c[u] >= 0, p[u][0], p[u][1], p[u][2], X0,
+                                         X1, X2, U0, U1, U2, kv[u], P.q0, F0, F1, F2, st[u], sk);
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (brk[u]) {
+                if (flag[u]) {
                     const int64_t ds = base + static_cast<int64_t>(t + u) * kWave + lane;
-                    A.col[ds] = ~c[u];  // irreversible
-                    A.bstep[ds] = static_cast<int32_t>(*A.step_base + A.step_local);
+                    const int32_t step = static_cast<int32_t>(*A.step_base + A.step_local);
+                    if constexpr (EXT) {
+                        // move the slot's elastic contribution from weight 1 to w
+                        bool brk, newly;
+                        const double wt = bond_weight<MODE, false>(A, P, ds, st[u].q, (c[u] & kColNoFail) != 0,
+                                                                   (c[u] & kColSoft) != 0, brk, newly);
+                        if (brk) {
+                            A.col[ds] = ~c[u];
+                            A.bstep[ds] = step;
+                        } else if (newly) {
+                            A.col[ds] = c[u] | kColSoft;
+                        }
+                        if (wt != 1.0) {
+                            const double m = (wt - 1.0) * st[u].coef;
+                            F0 = __builtin_fma(m, st[u].y0, F0);
+                            F1 = __builtin_fma(m, st[u].y1, F1);
+                            F2 = __builtin_fma(m, st[u].y2, F2);
+                        }
+                    } else {
+                        A.col[ds] = ~c[u];  // irreversible
+                        A.bstep[ds] = step;
+                    }
                 }
         }
     }
@@ -315,7 +388,7 @@ __device__ __forceinline__ void wave_sync()
 // the LDS reads of one row overlap the arithmetic of the other; an odd last row runs
 // alone.  With S > 1 the partial forces meet in LDS in a fixed order (S > 1 fills the
 // chip on problems with fewer slices than SIMDs).
-template <bool FP32, int MODE, bool STIFF, bool VOLN, bool KNODE, int S, bool NOFAIL>
+template <bool FP32, int MODE, bool STIFF, bool VOLN, bool KNODE, int S, bool EXT>
 __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2* __restrict__ pieces,
                                                              const int32_t* __restrict__ slice_piece,
                                                              const int64_t* __restrict__ slice_ptr)
@@ -410,13 +483,13 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             if (lane + kWave < vlen) lvol[lane + kWave] = vs1;
         }
     };
-    auto row = [&](uint16_t e, double kst) {
+    // One slot from its staged record into the force accumulators; returns true when it
+    // breaks now (plain kernels) and what the bond-model branch needs in st / st32.
+    auto eval = [&](uint16_t e, double kst, bool live, bool breakable, SlotTerm& st, SlotTerm32& st32) {
         const uint32_t off = e & kEntOff;  // byte offset of the neighbour's staged record
         const double2 q0 = *reinterpret_cast<const double2*>(lrecb + off);
         const double2 q1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
         const double2 q2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
-        const bool live = !(e & kEntBroken);
-        const bool breakable = MODE != kModeForce && (NOFAIL ? !(e & (kEntBroken | kEntNoFail)) : live);
         double kv = cv;
         const uint32_t widx = (off * 0xAAABu) >> 21;  // off / 48
         if (KNODE)
@@ -426,13 +499,56 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
         if (FP32)
             return slot_force32(live, breakable, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2,
                                 (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : cvf,
-                                q0f, Ff0, Ff1, Ff2);
-        return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2, sk);
+                                q0f, Ff0, Ff1, Ff2, st32);
+        return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2, st, sk);
+    };
+    // Plain kernels: true when the slot breaks now.  EXT kernels: true when it takes the
+    // bond-model branch.
+    auto row = [&](uint16_t e, double kst, SlotTerm& st, SlotTerm32& st32) {
+        const bool live = !(e & kEntBroken);
+        if constexpr (EXT) {
+            eval(e, kst, live, false, st, st32);
+            const bool soft = (e & kEntSoft) != 0;
+            const bool over = FP32 ? static_cast<float>(st32.q) >= q0f : st.q >= P.q0;
+            return live && (MODE == kModeForce ? soft : (over || soft));
+        } else {
+            return eval(e, kst, live, MODE != kModeForce && live, st, st32);
+        }
     };
     // a slot that broke in this pass: flag it (irreversible) and record the pass
     auto broke = [&](int64_t ds, uint16_t e) {
         entw[ds] = static_cast<uint16_t>(e | kEntBroken);
         bstep[ds] = static_cast<int32_t>(*A.step_base + A.step_local);
+    };
+    // bond-model branch (EXT): move the slot's elastic contribution from weight 1 to the
+    // weight its damage state gives
+    auto model = [&](int64_t ds, uint16_t e, const SlotTerm& st, const SlotTerm32& st32) {
+        bool brk, newly;
+        const double wt = bond_weight<MODE, FP32>(A, P, ds, FP32 ? st32.q : st.q, (e & kEntNoFail) != 0,
+                                                  (e & kEntSoft) != 0, brk, newly);
+        if (brk)
+            broke(ds, e);
+        else if (newly)
+            entw[ds] = static_cast<uint16_t>(e | kEntSoft);
+        if (wt != 1.0) {
+            if (FP32) {
+                const float m = static_cast<float>(wt - 1.0) * st32.coef;
+                Ff0 = __builtin_fmaf(m, st32.y0, Ff0);
+                Ff1 = __builtin_fmaf(m, st32.y1, Ff1);
+                Ff2 = __builtin_fmaf(m, st32.y2, Ff2);
+            } else {
+                const double m = (wt - 1.0) * st.coef;
+                F0 = __builtin_fma(m, st.y0, F0);
+                F1 = __builtin_fma(m, st.y1, F1);
+                F2 = __builtin_fma(m, st.y2, F2);
+            }
+        }
+    };
+    auto flagged = [&](int64_t ds, uint16_t e, const SlotTerm& st, const SlotTerm32& st32) {
+        if constexpr (EXT)
+            model(ds, e, st, st32);
+        else
+            broke(ds, e);
     };
 
     if (pa < p1) {
@@ -459,12 +575,16 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                 const uint16_t ea = lent[t * kWave + lane];
                 if (t + 1 < T) {
                     const uint16_t eb = lent[(t + 1) * kWave + lane];
-                    const bool ba = row(ea, STIFF ? kcur[t] : 0.0);
-                    const bool bb = row(eb, STIFF ? kcur[t + 1] : 0.0);
-                    if (ba) broke(ent + t * kWave + lane, ea);
-                    if (bb) broke(ent + (t + 1) * kWave + lane, eb);
+                    SlotTerm sa, sb;
+                    SlotTerm32 sa32, sb32;
+                    const bool ba = row(ea, STIFF ? kcur[t] : 0.0, sa, sa32);
+                    const bool bb = row(eb, STIFF ? kcur[t + 1] : 0.0, sb, sb32);
+                    if (ba) flagged(ent + t * kWave + lane, ea, sa, sa32);
+                    if (bb) flagged(ent + (t + 1) * kWave + lane, eb, sb, sb32);
                 } else {
-                    if (row(ea, STIFF ? kcur[t] : 0.0)) broke(ent + t * kWave + lane, ea);
+                    SlotTerm sa;
+                    SlotTerm32 sa32;
+                    if (row(ea, STIFF ? kcur[t] : 0.0, sa, sa32)) flagged(ent + t * kWave + lane, ea, sa, sa32);
                 }
             }
             ent = ent_next;
@@ -497,12 +617,12 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
 
 // ---------------------------------------------------------------- launch templates
 
-template <int G, bool STIFF, bool VOLN, bool KNODE, bool NOFAIL>
+template <int G, bool STIFF, bool VOLN, bool KNODE, bool EXT>
 hipError_t launch_step_gsv(const StepArgs& a, int mode, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>((a.nslices + 3) / 4)), block(kBlock);
     switch (mode) {
-#define PD_L(M) hipLaunchKernelGGL((step_f64<G, M, STIFF, VOLN, KNODE, NOFAIL>), grid, block, 0, s, a)
+#define PD_L(M) hipLaunchKernelGGL((step_f64<G, M, STIFF, VOLN, KNODE, EXT>), grid, block, 0, s, a)
     case kModeEC: PD_L(kModeEC); break;
     case kModeVV: PD_L(kModeVV); break;
     case kModeVVInit: PD_L(kModeVVInit); break;
@@ -514,25 +634,25 @@ hipError_t launch_step_gsv(const StepArgs& a, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int G, bool NOFAIL>
+template <int G, bool EXT>
 hipError_t launch_step_g(const StepArgs& a, int mode, bool stiff, hipStream_t s)
 {
     const bool voln = a.vol != nullptr;
-    if (a.nw) return launch_step_gsv<G, false, false, true, NOFAIL>(a, mode, s);  // per-node stiffness
+    if (a.nw) return launch_step_gsv<G, false, false, true, EXT>(a, mode, s);  // per-node stiffness
     if (stiff)
-        return voln ? launch_step_gsv<G, true, true, false, NOFAIL>(a, mode, s)
-                    : launch_step_gsv<G, true, false, false, NOFAIL>(a, mode, s);
-    return voln ? launch_step_gsv<G, false, true, false, NOFAIL>(a, mode, s)
-                : launch_step_gsv<G, false, false, false, NOFAIL>(a, mode, s);
+        return voln ? launch_step_gsv<G, true, true, false, EXT>(a, mode, s)
+                    : launch_step_gsv<G, true, false, false, EXT>(a, mode, s);
+    return voln ? launch_step_gsv<G, false, true, false, EXT>(a, mode, s)
+                : launch_step_gsv<G, false, false, false, EXT>(a, mode, s);
 }
 
-template <bool FP32, bool STIFF, bool VOLN, bool KNODE, int S, bool NOFAIL>
+template <bool FP32, bool STIFF, bool VOLN, bool KNODE, int S, bool EXT>
 hipError_t launch_staged_svs(const StepArgs& a, int mode, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>(a.nslices)), block(kWave * S);
     switch (mode) {
 #define PD_L(M)                                                                                             \
-    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN, KNODE, S, NOFAIL>), grid, block, 0, s, a, a.pieces, \
+    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN, KNODE, S, EXT>), grid, block, 0, s, a, a.pieces, \
                        a.slice_piece, a.slice_ptr)
     case kModeEC: PD_L(kModeEC); break;
     case kModeVV: PD_L(kModeVV); break;
@@ -545,27 +665,27 @@ hipError_t launch_staged_svs(const StepArgs& a, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool FP32, bool STIFF, bool VOLN, bool KNODE, bool NOFAIL>
+template <bool FP32, bool STIFF, bool VOLN, bool KNODE, bool EXT>
 hipError_t launch_staged_sv(const StepArgs& a, int mode, int split, hipStream_t s)
 {
     switch (split) {
-    case 1: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 1, NOFAIL>(a, mode, s);
-    case 2: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 2, NOFAIL>(a, mode, s);
-    case 4: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 4, NOFAIL>(a, mode, s);
+    case 1: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 1, EXT>(a, mode, s);
+    case 2: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 2, EXT>(a, mode, s);
+    case 4: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 4, EXT>(a, mode, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <bool FP32, bool NOFAIL>
+template <bool FP32, bool EXT>
 hipError_t launch_staged_n(const StepArgs& a, int mode, int split, hipStream_t s)
 {
     const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
-    if (a.nw) return launch_staged_sv<FP32, false, false, true, NOFAIL>(a, mode, split, s);  // per-node stiffness
+    if (a.nw) return launch_staged_sv<FP32, false, false, true, EXT>(a, mode, split, s);  // per-node stiffness
     if (stiff)
-        return voln ? launch_staged_sv<FP32, true, true, false, NOFAIL>(a, mode, split, s)
-                    : launch_staged_sv<FP32, true, false, false, NOFAIL>(a, mode, split, s);
-    return voln ? launch_staged_sv<FP32, false, true, false, NOFAIL>(a, mode, split, s)
-                : launch_staged_sv<FP32, false, false, false, NOFAIL>(a, mode, split, s);
+        return voln ? launch_staged_sv<FP32, true, true, false, EXT>(a, mode, split, s)
+                    : launch_staged_sv<FP32, true, false, false, EXT>(a, mode, split, s);
+    return voln ? launch_staged_sv<FP32, false, true, false, EXT>(a, mode, split, s)
+                : launch_staged_sv<FP32, false, false, false, EXT>(a, mode, split, s);
 }
 
 }  // namespace

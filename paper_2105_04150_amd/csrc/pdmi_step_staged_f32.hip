@@ -3,10 +3,10 @@
 
 namespace pdmi {
 
-hipError_t launch_step_staged_f32(const StepArgs& a, int mode, int split, bool nofail, hipStream_t s)
+hipError_t launch_step_staged_f32(const StepArgs& a, int mode, int split, bool ext, hipStream_t s)
 {
     if (a.nslices <= 0) return hipSuccess;
-    return nofail ? launch_staged_n<true, true>(a, mode, split, s) : launch_staged_n<true, false>(a, mode, split, s);
+    return ext ? launch_staged_n<true, true>(a, mode, split, s) : launch_staged_n<true, false>(a, mode, split, s);
 }
 
 }  // namespace pdmi

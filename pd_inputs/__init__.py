@@ -145,6 +145,27 @@ def notch_mask(ijk: np.ndarray, row_ptr: np.ndarray, col: np.ndarray,
     return (crosses & below).astype(np.uint8)
 
 
+def bond_classes(row_ptr: np.ndarray, col: np.ndarray, fractions: Sequence[float], seed: int) -> np.ndarray:
+    """Per-slot bond class drawn at random with the given class fractions, the same for
+    both slots of a bond (a SplitMix64 uniform keyed on the unordered pair).  Returns
+    uint8 in CSR order."""
+    n = row_ptr.shape[0] - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr)).astype(np.uint64)
+    cols = np.asarray(col, dtype=np.int64).astype(np.uint64)
+    key = np.minimum(rows, cols) * np.uint64(n) + np.maximum(rows, cols)
+    u = uniform01(seed, key)
+    edges = np.cumsum(np.asarray(fractions, dtype=np.float64))[:-1]
+    return np.searchsorted(edges, u, side="right").astype(np.uint8)
+
+
+# Damage laws as (stretch breakpoints, force ratios).  The trilinear law uses the
+# calibrated point estimate 1 of the trilinear parameters (Sec. 6, table of optimised
+# parameters: s0 = 2.3e-4, s1 = 2.42e-4, sc = 1.45e-3) with the kink ratio 1/4; the
+# fibre law of the composite variant is a bilinear law twice as strong in stretch.
+LAW_TRILINEAR = ((2.3e-4, 2.42e-4, 1.45e-3), (1.0, 0.25, 0.0))
+LAW_FIBRE = ((4.6e-4, 2.9e-3), (1.0, 0.0))
+
+
 def _gauss_kernel(std: float) -> np.ndarray:
     r = int(math.ceil(4.0 * std))
     t = np.arange(-r, r + 1, dtype=np.float64)
@@ -213,6 +234,8 @@ class Workload:
     eta: float = 0.0                # dynamic-relaxation damping coefficient (kg/(m^3 s))
     ramp_T: Optional[float] = None  # duration of the SCHED_RAMP5 components
     nofail: Optional[np.ndarray] = None  # node ids of the no-failure zones
+    laws: Optional[List[Tuple[Tuple[float, ...], Tuple[float, ...]]]] = None  # damage law per bond class
+    class_spec: Optional[Tuple[Tuple[float, ...], int]] = None  # (class fractions, seed) for bond_classes
     meta: Dict = field(default_factory=dict)
 
     @property
@@ -326,13 +349,24 @@ def workload(name: str, **over) -> Workload:
         # load nodes, dynamic-relaxation damping, velocity Verlet
         dims = over.get("dims", (175, 50, 50))
         steps = over.get("steps", 4000)
-        amp = over.get("amp", 1.15e-7 * dims[0])  # same bending strain at any scale
+        law = over.get("law", "brittle")
+        # same bending strain at any scale; three times more with the softening laws,
+        # whose bonds break at a larger stretch
+        amp = over.get("amp", (1.15e-7 if law == "brittle" else 3.45e-7) * dims[0])
         ramp_T = over.get("ramp_T", 0.75 * steps * 1.0e-7)
         w = _mk(name, dims, 3.14, over.get("s0", 1.0e-4), steps, "velocity_verlet",
                 lambda ijk, d: _bcs_qs_beam(ijk, d, amp), notch=(2 * (dims[0] // 2) + 1, 2 * (dims[2] // 5)))
         w.eta = over.get("eta", 2.5e6)
         w.ramp_T = ramp_T
         w.nofail = np.unique(np.concatenate(qs_beam_sets(w.ijk, dims)))
+        if law == "trilinear":
+            w.laws = [LAW_TRILINEAR]
+        elif law == "composite":
+            # matrix (70%, trilinear) and fibre (30%, bilinear) bonds mixed at random
+            w.laws = [LAW_TRILINEAR, LAW_FIBRE]
+            w.class_spec = ((0.7, 0.3), 4242)
+        elif law != "brittle":
+            raise KeyError(law)
         return w
     raise KeyError(name)
 
