@@ -202,7 +202,8 @@ def quasistatic_extra(P, pi, sync, steps: int, every: int):
     sim.step(5)
     sim.sync()
     t_plain = _timed(lambda: (sim.step(steps), sim.sync()), sync)
-    mapping = "staged" if info["mapping"] == P.PD_MAP_STAGED else f"sliced-{info['lanes_per_node']}"
+    mapping = (f"staged-{info['waves_per_slice']}" if info["mapping"] == P.PD_MAP_STAGED
+               else f"sliced-{info['lanes_per_node']}")
     sim.close()
     tflops = nnz * FLOPS_PER_SLOT["f64"] / (dev_ms / 1e3) / 1e12
     return {"config": f"qs_beam {w.dims[0]}x{w.dims[1]}x{w.dims[2]}, velocity Verlet, eta {w.eta:g}, "
@@ -215,6 +216,52 @@ def quasistatic_extra(P, pi, sync, steps: int, every: int):
             "last_load_N": loads[-1] if loads else None,
             "rate_without_zones": nnz * steps / t_plain,
             "zones_vs_plain": t_plain / t_zone}
+
+
+def damage_law_extra(P, pi, sync, steps: int):
+    """The trilinear damage law of Sec. 6 on the full-size notched bend (the qs_beam
+    workload with its zones, ramp and damping): K steps from the start of loading, then
+    K steps with every slot marked softened (each slot takes the bond-model branch every
+    step: the worst case), both against the rate of the same problem with the brittle law."""
+    w = pi.workload("qs_beam", law="trilinear")
+    sim = P.simulation_for(w)
+    sim.autotune(trial_steps=10)
+    sim.prepare()
+    info = sim.info()
+    nnz = info["n_slots"]
+    sim.step(20)
+    sim.sync()
+    t_law = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    dev_ms = sim.last_step_ms() / steps
+    soft = float((sim.max_stretch() > 0).mean())
+    # a fracture process zone: every bond of the nodes within 3 spacings of the notch
+    # plane softened to the middle of the second branch; then the worst case, every slot
+    s_mid = 0.5 * (pi.LAW_TRILINEAR[0][1] + pi.LAW_TRILINEAR[0][2])
+    rp, _ = sim.family()
+    band_nodes = np.abs(w.ijk[:, 0] - w.dims[0] // 2) <= 3
+    band = np.repeat(band_nodes, np.diff(rp))
+    sim.set_max_stretch(np.where(band, s_mid, 0.0))
+    sim.prepare()
+    sim.step(5)
+    sim.sync()
+    t_band = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    sim.set_max_stretch(np.full(nnz, s_mid))
+    sim.prepare()
+    sim.step(5)
+    sim.sync()
+    t_all = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    mapping = (f"staged-{info['waves_per_slice']}" if info["mapping"] == P.PD_MAP_STAGED
+               else f"sliced-{info['lanes_per_node']}")
+    sim.close()
+    tflops = nnz * FLOPS_PER_SLOT["f64"] / (dev_ms / 1e3) / 1e12
+    return {"config": f"qs_beam {w.dims[0]}x{w.dims[1]}x{w.dims[2]}, trilinear law {pi.LAW_TRILINEAR}, velocity "
+                      f"Verlet, zones, f64",
+            "bond_slots": nnz, "mapping": mapping, "steps": steps,
+            "value": nnz * steps / t_law, "unit": "bond-updates/s", "avg_launch_ms": dev_ms,
+            "alu_frac": tflops / PEAK_VALU_TFLOPS["f64"], "softened_fraction_after": soft,
+            "band_softened_fraction": float(band.mean()), "rate_band_softened": nnz * steps / t_band,
+            "band_softened_vs_start": t_law / t_band,
+            "rate_all_softened": nnz * steps / t_all, "all_softened_vs_start": t_law / t_all}
 
 
 def fp32_extra(P, pi, sync, workload: str, steps: int):
@@ -366,6 +413,9 @@ def main():
         print(f"# batched {out['batched']}", file=sys.stderr, flush=True)
         out["quasistatic"] = quasistatic_extra(P, pi, torch_sync, args.steps, 50)
         print(f"# quasistatic {out['quasistatic']}", file=sys.stderr, flush=True)
+        out["damage_law"] = damage_law_extra(P, pi, torch_sync, args.steps)
+        out["damage_law"]["vs_brittle_zones"] = out["damage_law"]["value"] / out["quasistatic"]["value"]
+        print(f"# damage_law {out['damage_law']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, threads)

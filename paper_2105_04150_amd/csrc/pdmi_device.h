@@ -106,16 +106,32 @@ __device__ __forceinline__ double bc_disp(const BCRec& r, int d, double t, doubl
 
 __device__ __forceinline__ bool constrained(const BCRec& r, int d) { return ((r.code >> (2 * d)) & 3) != 0; }
 
+// 1/x: hardware estimate and two Newton steps (within a few ulps; x > 0, normal).
+__device__ __forceinline__ double rcp64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = __builtin_fma(__builtin_fma(-x, y, 1.0), y, y);
+    y = __builtin_fma(__builtin_fma(-x, y, 1.0), y, y);
+    return y;
+}
+
 // Secant ratio of a bond softened to stretch sm under law L (s[0] < sm < s[nb-1]): the
 // law's force c s[0] rho(sm), rho interpolated linearly between breakpoints, over the
 // elastic force c sm.  The bond force is this ratio times c s (unloading and reloading
 // follow the secant to the origin).
 __device__ __forceinline__ double law_secant(const LawRec& L, double sm)
 {
-    int seg = 0;
-    while (seg + 2 < L.nb && sm >= L.s[seg + 1]) ++seg;
-    const double rho = L.r[seg] + (L.r[seg + 1] - L.r[seg]) * ((sm - L.s[seg]) / (L.s[seg + 1] - L.s[seg]));
-    return (L.s[0] * rho) / sm;
+    // segment of sm, chosen by selects (no indexed loads: a law shared by the wavefront
+    // stays in scalar registers)
+    double s_lo = L.s[0], r_lo = L.r[0], sl = L.slope[0];
+    for (int k = 1; k + 1 < L.nb; ++k)
+        if (sm >= L.s[k]) {
+            s_lo = L.s[k];
+            r_lo = L.r[k];
+            sl = L.slope[k];
+        }
+    const double rho = __builtin_fma(sl, sm - s_lo, r_lo);
+    return (L.s[0] * rho) * rcp64(sm);
 }
 
 // Damage of a softened slot from its stored largest stretch.

@@ -1673,6 +1673,7 @@ int pd_set_damage_law(pd_ctx* ctx, int32_t inst, int32_t cls, int32_t nb, const 
         }
         if (nb > 1 && (ratio[0] != 1.0 || ratio[nb - 1] != 0.0))
             fail(PD_EINVAL, "a softening law starts at ratio 1 and ends at ratio 0");
+        for (int k = 0; k + 1 < nb; ++k) L.slope[k] = (L.r[k + 1] - L.r[k]) / (L.s[k + 1] - L.s[k]);
         set_device(ctx);
         if (cls == static_cast<int32_t>(I.laws.size()))
             I.laws.push_back(L);

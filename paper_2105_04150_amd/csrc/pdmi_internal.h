@@ -77,6 +77,7 @@ constexpr int kLawMaxClasses = 8;
 struct LawRec {
     double s[kLawMaxB];
     double r[kLawMaxB];
+    double slope[kLawMaxB];  // (r[k+1] - r[k]) / (s[k+1] - s[k]) of segment k
     int32_t nb;
     int32_t pad_;
 };

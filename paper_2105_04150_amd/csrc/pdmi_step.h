@@ -118,12 +118,13 @@ __device__ __forceinline__ bool slot_force32(bool live, bool breakable, const do
 
 // Weight of a slot in the bond-model branch (EXT kernels): the slot is live and either at
 // or over the instance's threshold q0, or softened.  q is its q of this pass, nofail /
-// soft its word's flags.  Returns w (the bond adds w times its elastic force); sets broke
-// when it breaks now and newly_soft when it softens for the first time.  A zone bond, and
-// every bond in a force evaluation, keeps its damage state as it stands.
+// soft its word's flags, sold its stored largest stretch (prefetched by the caller when
+// soft).  Returns w (the bond adds w times its elastic force); sets broke when it breaks
+// now and newly_soft when it softens for the first time.  A zone bond, and every bond in
+// a force evaluation, keeps its damage state as it stands.
 template <int MODE, bool FP32>
 __device__ double bond_weight(const StepArgs& A, const InstParams& P, int64_t ds, double q, bool nofail, bool soft,
-                              bool& broke, bool& newly_soft)
+                              double sold, bool& broke, bool& newly_soft)
 {
     broke = false;
     newly_soft = false;
@@ -132,10 +133,13 @@ __device__ double bond_weight(const StepArgs& A, const InstParams& P, int64_t ds
         broke = FP32 ? static_cast<float>(q) >= static_cast<float>(P.q0) : q >= P.q0;
         return broke ? 0.0 : 1.0;
     }
-    const LawRec& L = A.laws[P.law_off + (P.nlaw > 1 ? A.cls[ds] : 0)];
-    const double sold = soft ? A.smax[ds] : 0.0;
+    // a single law per instance is the same for the whole wavefront (scalar loads)
+    const LawRec& L = P.nlaw == 1 ? A.laws[P.law_off] : A.laws[P.law_off + A.cls[ds]];
+    if (!soft) sold = 0.0;
     if (nofail || MODE == kModeForce) return soft ? law_secant(L, sold) : 1.0;
-    const double s = q / (1.0 + __builtin_sqrt(1.0 + q));  // stretch from q without cancellation
+    // stretch from q without cancellation: s = q / (1 + sqrt(1 + q))
+    const double r = rsq64<2>(1.0 + q);
+    const double s = q * rcp64(__builtin_fma(1.0 + q, r, 1.0));
     const double sm = s > sold ? s : sold;
     if (sm >= L.s[L.nb - 1]) {
         broke = true;
@@ -285,16 +289,26 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
             const uint32_t off = static_cast<uint32_t>(t) * (kWave * 4u) + lane4;
             return __builtin_nontemporal_load(reinterpret_cast<const int32_t*>(colb + off));
         };
+        // stored stretch of softened slots, fetched with their words (EXT with damage laws)
+        auto smax_at = [&](int t, int32_t cw) -> double {
+            if (!EXT || P.nlaw == 0 || cw < 0 || !(cw & kColSoft)) return 0.0;
+            return A.smax[base + static_cast<int64_t>(t) * kWave + lane];
+        };
         int32_t cn[U];
+        double smn[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) cn[u] = col_at(u);
+        for (int u = 0; u < U; ++u) {
+            cn[u] = col_at(u);
+            smn[u] = smax_at(u, cn[u]);
+        }
         for (int t = 0; t < T; t += U) {
             int32_t c[U];
             double2 p[U][3];
-            double kv[U];
+            double kv[U], smc[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 c[u] = cn[u];
+                smc[u] = smn[u];
                 const uint32_t j = static_cast<uint32_t>(c[u] ^ (c[u] >> 31)) &
                                    (EXT ? static_cast<uint32_t>(kColNode) : 0xffffffffu);
                 const char* rj = recb + __umul24(j, 48u);  // full-rate 24-bit multiply: j < 2^24
@@ -316,6 +330,8 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) cn[u] = col_at(t + U + u);
+#pragma unroll
+            for (int u = 0; u < U; ++u) smn[u] = smax_at(t + U + u, cn[u]);
             bool flag[U];  // plain: breaks now; EXT: takes the bond-model branch
             SlotTerm st[U];
 #pragma unroll
@@ -339,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
                         // move the slot's elastic contribution from weight 1 to w
                         bool brk, newly;
                         const double wt = bond_weight<MODE, false>(A, P, ds, st[u].q, (c[u] & kColNoFail) != 0,
-                                                                   (c[u] & kColSoft) != 0, brk, newly);
+                                                                   (c[u] & kColSoft) != 0, smc[u], brk, newly);
                         if (brk) {
                             A.col[ds] = ~c[u];
                             A.bstep[ds] = step;
@@ -524,8 +540,10 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     // weight its damage state gives
     auto model = [&](int64_t ds, uint16_t e, const SlotTerm& st, const SlotTerm32& st32) {
         bool brk, newly;
-        const double wt = bond_weight<MODE, FP32>(A, P, ds, FP32 ? st32.q : st.q, (e & kEntNoFail) != 0,
-                                                  (e & kEntSoft) != 0, brk, newly);
+        const bool soft = (e & kEntSoft) != 0;
+        const double sold = soft ? A.smax[ds] : 0.0;
+        const double wt = bond_weight<MODE, FP32>(A, P, ds, FP32 ? st32.q : st.q, (e & kEntNoFail) != 0, soft,
+                                                  sold, brk, newly);
         if (brk)
             broke(ds, e);
         else if (newly)
