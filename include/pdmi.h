@@ -284,18 +284,18 @@ int pd_get_force(pd_ctx *ctx, int32_t inst, double *out);
 
 /* Resultant force of a node set: out[0..2] = sum over the m nodes (host ids, user order)
  * of V_i F_i with F as pd_get_force, summed on the device in a fixed order (the load
- * measured "in the bonds of the displacement-controlled particles", Sec. 6).
+ * measured as the resultant of the bond forces on the displacement-controlled nodes, Sec. 6).
  * Errors: PD_EINVAL (node id out of range, m < 1). */
 int pd_get_resultant(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes, double out[3]);
 
 /* Mean displacement of a node set: out[0..2] = (1/m) sum over the m nodes (host ids,
  * user order) of u_i at the current level, summed on the device in a fixed order (the
- * mid-span deflection of Sec. 7, "the average deflection of the nodes at the top of the
- * beam at the midspan").  Errors: PD_EINVAL (node id out of range, m < 1). */
+ * mid-span deflection of Sec. 7: the mean deflection of the top nodes at mid-span).
+ * Errors: PD_EINVAL (node id out of range, m < 1). */
 int pd_get_mean_displacement(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes, double out[3]);
 
-/* Overwrite the state of instance `inst` (checkpoint / restart, Sec. 3.6 "initiating
- * a simulation from an intermediate state").  Any of u, v, a (host n x 3) or broken
+/* Overwrite the state of instance `inst` (checkpoint / restart: Sec. 3.6 lets a run
+ * start from an intermediate state).  Any of u, v, a (host n x 3) or broken
  * (host nnz; replaces the broken set exactly, un-breaking included) may be NULL to
  * keep the current value.  pd_set_step sets the step counter of all instances. */
 int pd_set_state(pd_ctx *ctx, int32_t inst, const double *u, const double *v, const double *a,

@@ -23,7 +23,7 @@
  *   damage          phi_i = 1 - sum_j mu_ij V_j / sum_j V_j            (Sec. 2.2, local damage)
  *   integrators     velocity Verlet (Eqs. Velocity_Verlet1-3), Euler-Cromer and forward Euler
  *                   (the integrator classes listed in Sec. 3.6; their update rules are not printed).
- *   damage laws     n-linear softening laws (the "arbitrary number of linear splines" of
+ *   damage laws     n-linear softening laws (the laws made of linear spline pieces of
  *                   Sec. 3.6; trilinear in Sec. 6, bilinear in Sec. 7) per bond class, with
  *                   irreversibility through the largest stretch a bond has reached (Sec. 2.2
  *                   reading: the bond follows the secant to the origin once it has softened)
@@ -341,7 +341,7 @@ static int bc_kind(const pdo_problem *P, int64_t i, int d)
  *   0: g = 1;   1: g = t;
  *   2: the fifth-order ramp from 0 to 1 over [0, T] whose first and second derivatives
  *      vanish at both ends, g = tau^3 (10 - 15 tau + 6 tau^2) with tau = t / T, and g = 1
- *      from T on (displacements ramped smoothly by a fifth-order polynomial, Secs. 6-7). */
+ *      from T on (the boundary displacement ramp of Secs. 6-7). */
 static double sched_g(const pdo_problem *P, int sched, double t)
 {
     if (sched == 1) return t;
