@@ -44,6 +44,8 @@ def _load():
         _lib.pdo_force.argtypes = [P, P, P, i64, P]
         _lib.pdo_run.restype = C.c_int
         _lib.pdo_run.argtypes = [P, P, i64]
+        _lib.pdo_family_volumes.restype = C.c_double
+        _lib.pdo_family_volumes.argtypes = [P, P]
         _lib.pdo_damage.restype = None
         _lib.pdo_damage.argtypes = [P, P, P, P]
         _lib.pdo_apply_jt.restype = None
@@ -62,7 +64,9 @@ class _Problem(C.Structure):
                 ("bc_val", C.c_void_p), ("scheme", C.c_int32), ("nthreads", C.c_int32),
                 ("ramp_T", C.c_double), ("nofail", C.c_void_p),
                 ("ncls", C.c_int32), ("pad2_", C.c_int32), ("cls_nb", C.c_void_p), ("cls_s", C.c_void_p),
-                ("cls_r", C.c_void_p), ("slot_cls", C.c_void_p)]
+                ("cls_r", C.c_void_p), ("slot_cls", C.c_void_p),
+                ("micro", C.c_int32), ("pvol", C.c_int32), ("delta", C.c_double), ("pv_dx", C.c_double),
+                ("surf", C.c_int32), ("pad3_", C.c_int32), ("famvol", C.c_void_p), ("v0", C.c_double)]
 
 
 class _State(C.Structure):
@@ -108,7 +112,7 @@ class OracleSim:
     def __init__(self, coords, row_ptr, col, *, c, s0, rho, dt, vol, scheme="euler_cromer",
                  eta=0.0, kslot=None, bhat=None, bmag=0.0, bcs=(), nthreads=0,
                  record_breaks=False, frozen=None, broken=None, ramp_T=1.0, nofail=None,
-                 laws=None, slot_cls=None, smax=None):
+                 laws=None, slot_cls=None, smax=None, corrections=None):
         lib = _load()
         self._lib = lib
         self.x = np.ascontiguousarray(coords, dtype=np.float64)
@@ -155,6 +159,18 @@ class OracleSim:
         self.break_step = (np.full(max(self.nnz, 1), np.iinfo(np.int32).max, dtype=np.int32)
                            if record_breaks else None)
         self.frozen = None if frozen is None else np.ascontiguousarray(frozen, dtype=np.int32)
+        # stiffness corrections: dict(micro="constant"|"conical", partial_volumes=bool,
+        # surface=bool, delta=horizon of the profile / partial volumes, dx=lattice spacing)
+        corr = dict(corrections or {})
+        self.P.micro = 1 if corr.get("micro", "constant") == "conical" else 0
+        self.P.pvol = 1 if corr.get("partial_volumes") else 0
+        self.P.delta = float(corr.get("delta", 0.0))
+        self.P.pv_dx = float(corr.get("dx", 0.0))
+        self.P.surf = 1 if corr.get("surface") else 0
+        self.famvol = np.zeros(n)
+        self.P.famvol = _ptr(self.famvol)
+        if self.P.surf or self.P.pvol:
+            self.P.v0 = lib.pdo_family_volumes(C.byref(self.P), _ptr(self.famvol))
         self.smax = None
         if ncls:
             self.smax = np.zeros(max(self.nnz, 1))

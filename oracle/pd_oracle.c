@@ -27,6 +27,9 @@
  *                   Sec. 3.6; trilinear in Sec. 6, bilinear in Sec. 7) per bond class, with
  *                   irreversibility through the largest stretch a bond has reached (Sec. 2.2
  *                   reading: the bond follows the secant to the origin once it has softened)
+ *   corrections     a conical micromodulus c (1 - |xi|/delta), partial volumes beta(|xi|) of
+ *                   neighbours cut by the horizon, and the volume-method surface correction
+ *                   lambda_ij = 2 V0 / (V_i + V_j) over family volumes (Secs. 2.2-2.3)
  *   quasi-static    prescribed displacements ramped by a fifth-order polynomial in time with
  *   loading         zero initial velocity and acceleration (Examples 2 and 3, Secs. 6-7), and
  *                   'no-failure zones': bonds of flagged nodes never break (Secs. 5.1, 6, 7).
@@ -85,6 +88,19 @@ typedef struct pdo_problem {
     const double *cls_s;
     const double *cls_r;
     const uint8_t *slot_cls; /* nnz class of each slot, or NULL: class 0 */
+    /* Stiffness corrections, each a factor on the slot's stiffness, applied in this order:
+     * micro = 1: conical micromodulus max(0, 1 - |xi|/delta); pvol = 1: partial volume
+     * beta(|xi|) = 1 up to delta - dx/2, linear down to 0 at delta + dx/2; surf = 1:
+     * lambda_ij = 2 V0 / (V_i + V_j) with famvol[] the family volumes and v0 their maximum
+     * (pdo_family_volumes). */
+    int32_t micro;
+    int32_t pvol;
+    double delta;
+    double pv_dx;
+    int32_t surf;
+    int32_t pad3_;
+    const double *famvol;
+    double v0;
 } pdo_problem;
 
 typedef struct pdo_state {
@@ -253,6 +269,42 @@ static double law_ratio(const pdo_problem *P, int k, double sm)
 
 static int slot_class(const pdo_problem *P, int64_t b) { return P->slot_cls ? P->slot_cls[b] : 0; }
 
+/* Partial volume of a neighbour at reference distance L: the share of its cubic cell
+ * (side dx, centred on it) inside the horizon, approximated linearly across the shell
+ * delta - dx/2 .. delta + dx/2. */
+static double partial_volume(const pdo_problem *P, double L)
+{
+    const double h = 0.5 * P->pv_dx;
+    if (L <= P->delta - h) return 1.0;
+    if (L >= P->delta + h) return 0.0;
+    return (P->delta + h - L) / P->pv_dx;
+}
+
+static double bond_length(const double *x, int64_t i, int64_t j)
+{
+    double a = x[3 * j + 0] - x[3 * i + 0];
+    double b = x[3 * j + 1] - x[3 * i + 1];
+    double c = x[3 * j + 2] - x[3 * i + 2];
+    return sqrt((a * a + b * b) + c * c);
+}
+
+/* Family volumes V_i = sum over H_i of beta_ij V_j (beta = 1 without partial volumes);
+ * returns their maximum, the volume of a complete family. */
+double pdo_family_volumes(const pdo_problem *P, double *famvol)
+{
+    double vmax = 0.0;
+    for (int64_t i = 0; i < P->n; ++i) {
+        double v = 0.0;
+        for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
+            const int64_t j = P->col[b];
+            v += (P->pvol ? partial_volume(P, bond_length(P->x, i, j)) : 1.0) * P->vol[j];
+        }
+        famvol[i] = v;
+        if (v > vmax) vmax = v;
+    }
+    return vmax;
+}
+
 /* Damage of a slot under the damage laws: 1 broken, 1 - secant ratio once softened. */
 static double slot_damage(const pdo_problem *P, const uint8_t *broken, const double *smax, int64_t b)
 {
@@ -314,6 +366,12 @@ void pdo_force(const pdo_problem *P, pdo_state *S, const double *u, int64_t k, d
                 continue;
             }
             double kb = P->kslot ? P->kslot[b] : P->c;
+            if (P->micro == 1) {
+                const double m = 1.0 - L / P->delta;
+                kb = kb * (m > 0.0 ? m : 0.0);
+            }
+            if (P->pvol) kb = kb * partial_volume(P, L);
+            if (P->surf) kb = kb * ((2.0 * P->v0) / (P->famvol[i] + P->famvol[j]));
             double scal = (((kb * s) * w) * P->vol[j]) / r;
             f0 += scal * y0;
             f1 += scal * y1;
