@@ -217,6 +217,33 @@ int pd_set_bond_classes(pd_ctx *ctx, int32_t inst, const uint8_t *cls);
 /* Back to the brittle law with the s0 of pd_set_material (laws and classes removed). */
 int pd_clear_damage_laws(pd_ctx *ctx, int32_t inst);
 
+#define PD_MICRO_CONSTANT 0  /* c(|xi|) = c */
+#define PD_MICRO_CONICAL 1   /* c(|xi|) = c max(0, 1 - |xi|/delta): c is the peak value (5 times the
+                                constant micromodulus for the same bulk stiffness) */
+
+/* Stiffness corrections of one instance (Secs. 2.2-2.3), each a factor on every slot's
+ * stiffness, applied in this order: the micromodulus profile; partial volumes, beta = 1
+ * for |xi| <= delta - dx/2, falling linearly to 0 at delta + dx/2 (the share of a
+ * neighbour's cell inside the horizon; build the family with horizon delta + dx/2 to
+ * include the cut cells); the volume-method surface correction lambda_ij = 2 V0 /
+ * (V_i + V_j), V_i = sum over node i's family of beta_ij V_j and V0 the largest V_i (a
+ * complete family).  The factors are formed once on the host and the step reads the
+ * corrected stiffness per slot. */
+typedef struct pd_corrections {
+    int32_t micromodulus;      /* PD_MICRO_CONSTANT or PD_MICRO_CONICAL */
+    int32_t partial_volumes;   /* nonzero: partial volumes */
+    int32_t surface;           /* nonzero: volume-method surface correction */
+    int32_t reserved_;
+    double delta;              /* horizon of the profile and the partial volumes (> 0 when used) */
+    double dx;                 /* lattice spacing of the partial volumes (> 0 when used) */
+} pd_corrections;
+
+/* Stiffness corrections of instance `inst`; NULL removes them.  They multiply whatever
+ * stiffness the instance has (c, per-slot or per-node field).  The adjoint rejects
+ * problems with corrections.  Errors: PD_EINVAL (unknown profile, delta or dx not
+ * positive where needed). */
+int pd_set_corrections(pd_ctx *ctx, int32_t inst, const pd_corrections *corr);
+
 /* Body force density b_i = magnitude * b_hat_i (N/m^3) of instance `inst`;
  * b_hat: host n x 3, user order; NULL removes it. */
 int pd_set_body_force(pd_ctx *ctx, int32_t inst, const double *b_hat, double magnitude);

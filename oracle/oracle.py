@@ -280,4 +280,4 @@ def from_workload(w, nthreads: int = 0, record_breaks: bool = False, method: str
                      scheme=w.scheme, eta=w.eta, kslot=kslot, bhat=bhat, bmag=bmag, bcs=w.bcs,
                      nthreads=nthreads, record_breaks=record_breaks, broken=broken,
                      ramp_T=1.0 if w.ramp_T is None else w.ramp_T, nofail=nofail, frozen=frozen,
-                     laws=w.laws, slot_cls=slot_cls)
+                     laws=w.laws, slot_cls=slot_cls, corrections=w.corrections)

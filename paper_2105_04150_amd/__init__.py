@@ -102,6 +102,14 @@ class Simulation:
     def clear_damage_laws(self, inst=0):
         B.pd_clear_damage_laws(self.ctx, inst)
 
+    def set_corrections(self, corrections=None, inst=0):
+        """Stiffness corrections: a dict with micro ("constant"/"conical"), partial_volumes,
+        surface, delta, dx; None removes them."""
+        if corrections is None:
+            B.pd_set_corrections(self.ctx, inst, clear=True)
+        else:
+            B.pd_set_corrections(self.ctx, inst, **corrections)
+
     def max_stretch(self, inst=0):
         """Largest stretch of every slot beyond its law's elastic limit (0 if none)."""
         return B.pd_get_max_stretch(self.ctx, inst)
@@ -202,6 +210,8 @@ def apply_workload(sim: Simulation, w, inst: int = 0, row_ptr=None, col=None, st
         sim.set_bcs(bc.nodes, bc.comp_mask, bc.kind, bc.value, bc.sched, inst=inst)
     if w.ramp_T is not None:
         sim.set_bc_ramp(w.ramp_T, inst=inst)
+    if w.corrections:
+        sim.set_corrections(w.corrections, inst=inst)
     if w.laws:
         for k, (sb, rb) in enumerate(w.laws):
             sim.set_damage_law(k, sb, rb, inst=inst)

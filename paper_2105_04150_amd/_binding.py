@@ -28,7 +28,7 @@ SYMBOLS = [
     "pd_set_node_stiffness",
     "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_bc_ramp", "pd_set_no_fail", "pd_get_force",
     "pd_get_resultant", "pd_get_mean_displacement", "pd_set_damage_law", "pd_set_bond_classes",
-    "pd_clear_damage_laws", "pd_get_max_stretch", "pd_set_max_stretch", "pd_set_body_force", "pd_set_integrator",
+    "pd_clear_damage_laws", "pd_get_max_stretch", "pd_set_max_stretch", "pd_set_corrections", "pd_set_body_force", "pd_set_integrator",
     "pd_step", "pd_prepare", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
     "pd_get_info", "pd_last_step_ms", "pd_adj_forward", "pd_adj_backward", "pd_get_break_steps",
@@ -89,6 +89,7 @@ def load() -> C.CDLL:
         "pd_clear_damage_laws": [P, i32],
         "pd_get_max_stretch": [P, i32, P],
         "pd_set_max_stretch": [P, i32, P],
+        "pd_set_corrections": [P, i32, P],
         "pd_set_body_force": [P, i32, P, d],
         "pd_set_integrator": [P, C.c_int, d],
         "pd_step": [P, i64],
@@ -287,6 +288,26 @@ def pd_set_max_stretch(ctx, inst: int, smax) -> None:
     if sm.shape != (nnz,):
         raise ValueError(f"stretch state needs shape ({nnz},)")
     _check(ctx, load().pd_set_max_stretch(ctx, inst, _p(sm)))
+
+
+PD_MICRO_CONSTANT, PD_MICRO_CONICAL = 0, 1
+
+
+class pd_corrections(C.Structure):
+    _fields_ = [("micromodulus", C.c_int32), ("partial_volumes", C.c_int32), ("surface", C.c_int32),
+                ("reserved_", C.c_int32), ("delta", C.c_double), ("dx", C.c_double)]
+
+
+def pd_set_corrections(ctx, inst: int, micro: str = "constant", partial_volumes: bool = False,
+                       surface: bool = False, delta: float = 0.0, dx: float = 0.0, clear: bool = False) -> None:
+    if clear:
+        _check(ctx, load().pd_set_corrections(ctx, inst, None))
+        return
+    kinds = {"constant": PD_MICRO_CONSTANT, "conical": PD_MICRO_CONICAL}
+    if micro not in kinds:
+        raise ValueError(f"unknown micromodulus profile {micro!r}")
+    c = pd_corrections(kinds[micro], int(bool(partial_volumes)), int(bool(surface)), 0, float(delta), float(dx))
+    _check(ctx, load().pd_set_corrections(ctx, inst, C.byref(c)))
 
 
 def pd_set_body_force(ctx, inst: int, b_hat, magnitude: float) -> None:

@@ -93,6 +93,8 @@ struct Inst {
     double ramp_T = 1.0;                     // duration of the fifth-order ramp schedule
     std::vector<uint8_t> nofail;             // user order, no-failure zone flags; empty = none
     std::vector<LawRec> laws;                // damage laws (bond classes); empty = the brittle law with s0
+    pd_corrections corr{};                   // stiffness corrections
+    bool has_corr = false;
     std::vector<uint8_t> cls;                // user CSR order: law of every slot; empty = law 0
     // device layout
     std::vector<int64_t> perm;       // device-local node -> user node, -1 = padding
@@ -516,11 +518,64 @@ void upload_bcs(pd_ctx* ctx)
 
 // Per-slot stiffness of every instance (instances without a field get their c), or only
 // of instance `only` when the array already exists.
+// Correction factors of one instance applied to a slot stiffness k (user CSR order b of
+// row i): micromodulus profile, partial volume, surface correction, in that order.
+struct CorrectionTable {
+    std::vector<double> famvol;  // per node (surface correction)
+    double v0 = 0.0;
+};
+
+double partial_volume(const pd_corrections& c, double L)
+{
+    const double h = 0.5 * c.dx;
+    if (L <= c.delta - h) return 1.0;
+    if (L >= c.delta + h) return 0.0;
+    return (c.delta + h - L) / c.dx;
+}
+
+double ref_length(const Inst& I, int64_t i, int64_t j)
+{
+    const double a = I.x[3 * j] - I.x[3 * i], b = I.x[3 * j + 1] - I.x[3 * i + 1], c = I.x[3 * j + 2] - I.x[3 * i + 2];
+    return std::sqrt((a * a + b * b) + c * c);
+}
+
+CorrectionTable correction_table(const Inst& I)
+{
+    CorrectionTable T;
+    if (!I.has_corr || !I.corr.surface) return T;
+    T.famvol.assign(static_cast<size_t>(I.n), 0.0);
+    parallel_for(I.n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            double v = 0.0;
+            for (int64_t b = I.row_ptr[i]; b < I.row_ptr[i + 1]; ++b) {
+                const int64_t j = I.col[b];
+                const double vj = I.vols.empty() ? I.volume : I.vols[j];
+                v += (I.corr.partial_volumes ? partial_volume(I.corr, ref_length(I, i, j)) : 1.0) * vj;
+            }
+            T.famvol[i] = v;
+        }
+    });
+    for (double v : T.famvol) T.v0 = std::max(T.v0, v);
+    return T;
+}
+
+double corrected(const Inst& I, const CorrectionTable& T, int64_t i, int64_t j, double k)
+{
+    const double L = ref_length(I, i, j);
+    if (I.corr.micromodulus == PD_MICRO_CONICAL) {
+        const double m = 1.0 - L / I.corr.delta;
+        k = k * (m > 0.0 ? m : 0.0);
+    }
+    if (I.corr.partial_volumes) k = k * partial_volume(I.corr, L);
+    if (I.corr.surface) k = k * ((2.0 * T.v0) / (T.famvol[i] + T.famvol[j]));
+    return k;
+}
+
 void upload_stiffness(pd_ctx* ctx, int32_t only = -1)
 {
     ctx->tape_valid = false;
     bool any = false;
-    for (auto& I : ctx->inst) any |= !I.kslot.empty();
+    for (auto& I : ctx->inst) any |= !I.kslot.empty() || I.has_corr;
     if (!any) {
         ctx->has_stiff = false;
         ctx->kslot.release();
@@ -538,18 +593,25 @@ void upload_stiffness(pd_ctx* ctx, int32_t only = -1)
         std::vector<double> k(static_cast<size_t>(I.n_dslots), 0.0);
         std::vector<double> sq;  // a per-node field in per-slot mode: sqrt(k_i) sqrt(k_j)
         std::vector<int32_t> row;
-        if (I.kslot.empty() && !I.knode.empty()) {
-            sq.resize(static_cast<size_t>(I.n));
-            for (int64_t i = 0; i < I.n; ++i) sq[i] = std::sqrt(I.knode[i]);
+        if ((I.kslot.empty() && !I.knode.empty()) || I.has_corr) {
+            if (!I.knode.empty()) {
+                sq.resize(static_cast<size_t>(I.n));
+                for (int64_t i = 0; i < I.n; ++i) sq[i] = std::sqrt(I.knode[i]);
+            }
             row.resize(static_cast<size_t>(I.nnz));
             for (int64_t i = 0; i < I.n; ++i)
                 for (int64_t b = I.row_ptr[i]; b < I.row_ptr[i + 1]; ++b) row[b] = static_cast<int32_t>(i);
         }
-        for (int64_t s = 0; s < I.n_dslots; ++s) {
-            const int32_t b = I.dslot_user[s];
-            if (b < 0) continue;
-            k[s] = !I.kslot.empty() ? I.kslot[b] : !sq.empty() ? sq[row[b]] * sq[I.col[b]] : I.c;
-        }
+        const CorrectionTable T = correction_table(I);
+        parallel_for(I.n_dslots, [&](int64_t s0, int64_t s1) {
+            for (int64_t s = s0; s < s1; ++s) {
+                const int32_t b = I.dslot_user[s];
+                if (b < 0) continue;
+                double kb = !I.kslot.empty() ? I.kslot[b] : !sq.empty() ? sq[row[b]] * sq[I.col[b]] : I.c;
+                if (I.has_corr) kb = corrected(I, T, row[b], I.col[b], kb);
+                k[s] = kb;
+            }
+        });
         upload(ctx->kslot, k.data(), k.size() * sizeof(double), I.dslot_off * sizeof(double), ctx->stream);
         sync(ctx);
     }
@@ -1341,6 +1403,7 @@ void adjoint_checks(pd_ctx* ctx)
     if (ctx->inst.size() != 1) fail(PD_EINVAL, "the adjoint needs a single-instance problem");
     for (const LawRec& L : ctx->inst[0].laws)
         if (L.nb > 1) fail(PD_EINVAL, "the adjoint differentiates brittle damage laws only");
+    if (ctx->inst[0].has_corr) fail(PD_EINVAL, "the adjoint does not take stiffness corrections");
 }
 
 // The reverse pass gathers the transposed tangent over each node's own family, which
@@ -1712,6 +1775,29 @@ int pd_clear_damage_laws(pd_ctx* ctx, int32_t inst)
         I.laws.clear();
         I.cls.clear();
         reset_laws(ctx);
+    });
+}
+
+int pd_set_corrections(pd_ctx* ctx, int32_t inst, const pd_corrections* corr)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (corr) {
+            if (corr->micromodulus != PD_MICRO_CONSTANT && corr->micromodulus != PD_MICRO_CONICAL)
+                fail(PD_EINVAL, "unknown micromodulus profile");
+            const bool need_delta = corr->micromodulus == PD_MICRO_CONICAL || corr->partial_volumes;
+            if (need_delta && (!(corr->delta > 0.0) || !std::isfinite(corr->delta)))
+                fail(PD_EINVAL, "delta must be positive and finite");
+            if (corr->partial_volumes && (!(corr->dx > 0.0) || !std::isfinite(corr->dx)))
+                fail(PD_EINVAL, "dx must be positive and finite");
+        }
+        set_device(ctx);
+        I.has_corr = corr && (corr->micromodulus != PD_MICRO_CONSTANT || corr->partial_volumes || corr->surface);
+        I.corr = corr ? *corr : pd_corrections{};
+        upload_stiffness(ctx);
+        upload_node_weights(ctx);
+        ctx->drop_graphs();
     });
 }
 

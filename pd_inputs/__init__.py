@@ -236,6 +236,7 @@ class Workload:
     nofail: Optional[np.ndarray] = None  # node ids of the no-failure zones
     laws: Optional[List[Tuple[Tuple[float, ...], Tuple[float, ...]]]] = None  # damage law per bond class
     class_spec: Optional[Tuple[Tuple[float, ...], int]] = None  # (class fractions, seed) for bond_classes
+    corrections: Optional[Dict] = None  # stiffness corrections: micro, partial_volumes, surface, delta, dx
     meta: Dict = field(default_factory=dict)
 
     @property
