@@ -264,6 +264,30 @@ def damage_law_extra(P, pi, sync, steps: int):
             "rate_all_softened": nnz * steps / t_all, "all_softened_vs_start": t_law / t_all}
 
 
+def corrections_extra(P, pi, sync, workload: str, steps: int, plain_ms: float):
+    """The headline workload with the conical micromodulus and the volume-method surface
+    correction (peak 5c for the same bulk stiffness): the corrected stiffness streams per
+    slot, 8 more bytes per slot than the plain step."""
+    w = pi.workload(workload)
+    w.order = "natural"
+    w.c = 5.0 * w.c
+    w.corrections = dict(micro="conical", surface=True, delta=w.horizon, dx=w.dx)
+    sim = P.simulation_for(w, mapping="staged")
+    sim.prepare()
+    info = sim.info()
+    sim.step(20)
+    sim.sync()
+    t = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    dev_ms = sim.last_step_ms() / steps
+    sim.close()
+    nnz = info["n_slots"]
+    return {"config": f"{workload}, conical micromodulus + surface correction, staged mapping, natural order",
+            "steps": steps, "value": nnz * steps / t, "unit": "bond-updates/s", "avg_launch_ms": dev_ms,
+            "model_bytes_per_step": info["model_bytes_per_step"],
+            "hbm_frac": info["model_bytes_per_step"] / (dev_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
+            "vs_plain_step": plain_ms / dev_ms}
+
+
 def fp32_extra(P, pi, sync, workload: str, steps: int):
     """The FP32 build (f32 bond arithmetic, f64 master displacement) on the headline
     workload with the staged mapping, the only mapping it runs."""
@@ -405,6 +429,8 @@ def main():
             out["fp32"] = fp32_extra(P, pi, torch_sync, args.workload, args.steps)
             out["fp32"]["vs_fp64"] = out["fp32"]["value"] / value
             print(f"# fp32 {out['fp32']}", file=sys.stderr, flush=True)
+        out["corrections"] = corrections_extra(P, pi, torch_sync, args.workload, args.steps, per_launch_s * 1e3)
+        print(f"# corrections {out['corrections']}", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_extra(P, pi, torch_sync, args.adjoint_steps, 100)
         out["adjoint"]["adjoint_vs_headline_step"] = out["adjoint"]["adjoint_rate"] / value
         print(f"# adjoint {out['adjoint']}", file=sys.stderr, flush=True)
