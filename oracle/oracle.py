@@ -46,6 +46,8 @@ def _load():
         _lib.pdo_run.argtypes = [P, P, i64]
         _lib.pdo_family_volumes.restype = C.c_double
         _lib.pdo_family_volumes.argtypes = [P, P]
+        _lib.pdo_weighted_volumes.restype = None
+        _lib.pdo_weighted_volumes.argtypes = [P, P]
         _lib.pdo_damage.restype = None
         _lib.pdo_damage.argtypes = [P, P, P, P]
         _lib.pdo_apply_jt.restype = None
@@ -66,7 +68,9 @@ class _Problem(C.Structure):
                 ("ncls", C.c_int32), ("pad2_", C.c_int32), ("cls_nb", C.c_void_p), ("cls_s", C.c_void_p),
                 ("cls_r", C.c_void_p), ("slot_cls", C.c_void_p),
                 ("micro", C.c_int32), ("pvol", C.c_int32), ("delta", C.c_double), ("pv_dx", C.c_double),
-                ("surf", C.c_int32), ("pad3_", C.c_int32), ("famvol", C.c_void_p), ("v0", C.c_double)]
+                ("surf", C.c_int32), ("pad3_", C.c_int32), ("famvol", C.c_void_p), ("v0", C.c_double),
+                ("model", C.c_int32), ("pad4_", C.c_int32), ("K", C.c_double), ("G", C.c_double),
+                ("m", C.c_void_p), ("theta", C.c_void_p)]
 
 
 class _State(C.Structure):
@@ -112,7 +116,7 @@ class OracleSim:
     def __init__(self, coords, row_ptr, col, *, c, s0, rho, dt, vol, scheme="euler_cromer",
                  eta=0.0, kslot=None, bhat=None, bmag=0.0, bcs=(), nthreads=0,
                  record_breaks=False, frozen=None, broken=None, ramp_T=1.0, nofail=None,
-                 laws=None, slot_cls=None, smax=None, corrections=None):
+                 laws=None, slot_cls=None, smax=None, corrections=None, state_based=None):
         lib = _load()
         self._lib = lib
         self.x = np.ascontiguousarray(coords, dtype=np.float64)
@@ -171,6 +175,17 @@ class OracleSim:
         self.P.famvol = _ptr(self.famvol)
         if self.P.surf or self.P.pvol:
             self.P.v0 = lib.pdo_family_volumes(C.byref(self.P), _ptr(self.famvol))
+        # state-based linear solid: state_based = (K, G); c, kslot, laws and corrections unused
+        self.m = np.zeros(n)
+        self.theta = np.zeros(n)
+        self.P.m = _ptr(self.m)
+        self.P.theta = _ptr(self.theta)
+        if state_based is not None:
+            if ncls or self.kslot is not None or self.P.micro or self.P.pvol or self.P.surf:
+                raise ValueError("the state-based model takes no stiffness field, damage law or correction")
+            self.P.model = 1
+            self.P.K, self.P.G = (float(v) for v in state_based)
+            lib.pdo_weighted_volumes(C.byref(self.P), _ptr(self.m))
         self.smax = None
         if ncls:
             self.smax = np.zeros(max(self.nnz, 1))
@@ -280,4 +295,5 @@ def from_workload(w, nthreads: int = 0, record_breaks: bool = False, method: str
                      scheme=w.scheme, eta=w.eta, kslot=kslot, bhat=bhat, bmag=bmag, bcs=w.bcs,
                      nthreads=nthreads, record_breaks=record_breaks, broken=broken,
                      ramp_T=1.0 if w.ramp_T is None else w.ramp_T, nofail=nofail, frozen=frozen,
-                     laws=w.laws, slot_cls=slot_cls, corrections=w.corrections)
+                     laws=w.laws, slot_cls=slot_cls, corrections=w.corrections,
+                     state_based=w.state_based)

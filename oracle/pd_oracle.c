@@ -35,6 +35,13 @@
  *                   'no-failure zones': bonds of flagged nodes never break (Secs. 5.1, 6, 7).
  *   adjoint         reverse-mode derivative of an Euler-Cromer run with the break schedule
  *                   frozen, w.r.t. per-slot stiffness and body-force magnitude.
+ *   state-based     the ordinary state-based linear peridynamic solid (Sec. 8.2, after Silling
+ *                   et al. 2007): weighted volume m_i = sum_j omega |xi|^2 V_j, dilation
+ *                   theta_i = (3/m_i) sum_j omega |xi| e_ij V_j over intact bonds, extension
+ *                   e = |xi + eta| - |xi|, scalar force state t_ij = (3 K theta_i / m_i) omega |xi|
+ *                   + (15 G / m_i) omega (e - theta_i |xi| / 3), node force sum_j (t_ij + t_ji)
+ *                   M_ij V_j with M = (xi + eta)/|xi + eta|; influence function omega = 1.  Two
+ *                   passes per force evaluation: breaking and dilation, then the force.
  */
 #include <math.h>
 #include <stdint.h>
@@ -101,6 +108,16 @@ typedef struct pdo_problem {
     int32_t pad3_;
     const double *famvol;
     double v0;
+    /* model = 1: the ordinary state-based linear solid with bulk modulus K and shear
+     * modulus G in place of the PMB bond force (c, kslot, damage laws and corrections are
+     * not used); m[] the weighted volumes (pdo_weighted_volumes); theta[] (n) receives the
+     * dilation of every node in each force evaluation. */
+    int32_t model;
+    int32_t pad4_;
+    double K;
+    double G;
+    const double *m;
+    double *theta;
 } pdo_problem;
 
 typedef struct pdo_state {
@@ -305,6 +322,20 @@ double pdo_family_volumes(const pdo_problem *P, double *famvol)
     return vmax;
 }
 
+/* Weighted volumes of the state-based model, m_i = sum over the whole family H_i of
+ * omega |xi|^2 V_j with omega = 1 (reference configuration, bonds broken or not). */
+void pdo_weighted_volumes(const pdo_problem *P, double *m)
+{
+    for (int64_t i = 0; i < P->n; ++i) {
+        double acc = 0.0;
+        for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
+            const double L = bond_length(P->x, i, P->col[b]);
+            acc += L * L * P->vol[P->col[b]];
+        }
+        m[i] = acc;
+    }
+}
+
 /* Damage of a slot under the damage laws: 1 broken, 1 - secant ratio once softened. */
 static double slot_damage(const pdo_problem *P, const uint8_t *broken, const double *smax, int64_t b)
 {
@@ -317,10 +348,16 @@ static double slot_damage(const pdo_problem *P, const uint8_t *broken, const dou
  * level u belongs to).  Without a frozen schedule, a slot whose stretch reaches s0
  * is marked broken (and its pass recorded) and contributes nothing; with a frozen
  * schedule, the slot is alive in pass k iff k < frozen[b]. */
+static void lps_force(const pdo_problem *P, pdo_state *S, const double *u, int64_t k, double *F);
+
 void pdo_force(const pdo_problem *P, pdo_state *S, const double *u, int64_t k, double *F)
 {
     const double *x = P->x;
     set_threads(P);
+    if (P->model == 1) {
+        lps_force(P, S, u, k, F);
+        return;
+    }
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < P->n; ++i) {
         double f0 = 0.0, f1 = 0.0, f2 = 0.0;
@@ -385,6 +422,75 @@ void pdo_force(const pdo_problem *P, pdo_state *S, const double *u, int64_t k, d
         F[3 * i + 0] = f0;
         F[3 * i + 1] = f1;
         F[3 * i + 2] = f2;
+    }
+}
+
+/* Deformed bond of slot (i, j): y = xi + eta, its length r and the reference length L. */
+static void deformed_bond(const double *x, const double *u, int64_t i, int64_t j, double y[3], double *r, double *L)
+{
+    double xi[3];
+    for (int d = 0; d < 3; ++d) {
+        xi[d] = x[3 * j + d] - x[3 * i + d];
+        y[d] = xi[d] + (u[3 * j + d] - u[3 * i + d]);
+    }
+    *r = sqrt((y[0] * y[0] + y[1] * y[1]) + y[2] * y[2]);
+    *L = sqrt((xi[0] * xi[0] + xi[1] * xi[1]) + xi[2] * xi[2]);
+}
+
+/* The state-based force density (see the header), in pass k.  First pass: a slot whose
+ * stretch e / |xi| reaches s0 breaks (as in the bond-based model: outside no-failure
+ * zones, never with a frozen schedule), then the dilation of every node sums the bonds
+ * still intact.  Second pass: every intact bond adds (t_ij + t_ji) M_ij V_j, t_ji formed
+ * with node j's dilation and weighted volume. */
+static void lps_force(const pdo_problem *P, pdo_state *S, const double *u, int64_t k, double *F)
+{
+    const double *x = P->x;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < P->n; ++i) {
+        double acc = 0.0;
+        for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
+            if (S->frozen) {
+                if (!(k < (int64_t)S->frozen[b])) continue;
+            } else if (S->broken[b]) {
+                continue;
+            }
+            const int64_t j = P->col[b];
+            double y[3], r, L;
+            deformed_bond(x, u, i, j, y, &r, &L);
+            const double e = r - L;
+            const int unbreakable = P->nofail && (P->nofail[i] || P->nofail[j]);
+            if (!S->frozen && !unbreakable && e / L >= P->s0) {
+                S->broken[b] = 1;
+                if (S->break_step) S->break_step[b] = (int32_t)k;
+                continue;
+            }
+            acc += L * e * P->vol[j];  /* omega = 1 */
+        }
+        P->theta[i] = 3.0 * acc / P->m[i];
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < P->n; ++i) {
+        double f[3] = {0.0, 0.0, 0.0};
+        for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
+            if (S->frozen) {
+                if (!(k < (int64_t)S->frozen[b])) continue;
+            } else if (S->broken[b]) {
+                continue;
+            }
+            const int64_t j = P->col[b];
+            double y[3], r, L;
+            deformed_bond(x, u, i, j, y, &r, &L);
+            const double e = r - L;
+            const double th_i = P->theta[i], th_j = P->theta[j];
+            const double t_ij = (3.0 * P->K * th_i / P->m[i]) * L + (15.0 * P->G / P->m[i]) * (e - th_i * L / 3.0);
+            const double t_ji = (3.0 * P->K * th_j / P->m[j]) * L + (15.0 * P->G / P->m[j]) * (e - th_j * L / 3.0);
+            const double scal = (t_ij + t_ji) * P->vol[j] / r;
+            for (int d = 0; d < 3; ++d) f[d] += scal * y[d];
+        }
+        for (int d = 0; d < 3; ++d) {
+            if (P->bhat) f[d] += P->bmag * P->bhat[3 * i + d];
+            F[3 * i + d] = f[d];
+        }
     }
 }
 

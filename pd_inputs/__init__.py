@@ -237,6 +237,7 @@ class Workload:
     laws: Optional[List[Tuple[Tuple[float, ...], Tuple[float, ...]]]] = None  # damage law per bond class
     class_spec: Optional[Tuple[Tuple[float, ...], int]] = None  # (class fractions, seed) for bond_classes
     corrections: Optional[Dict] = None  # stiffness corrections: micro, partial_volumes, surface, delta, dx
+    state_based: Optional[Tuple[float, float]] = None  # (K, G): the state-based linear solid
     meta: Dict = field(default_factory=dict)
 
     @property
@@ -322,8 +323,29 @@ def _body_tip_down(ijk, dims):
 ADJOINT_LOAD = 5.0e8      # body-force density magnitude on the loaded face (N/m^3)
 
 
+def shear_modulus(K: float, poisson: float) -> float:
+    """Isotropic shear modulus from the bulk modulus and Poisson's ratio."""
+    return 3.0 * K * (1.0 - 2.0 * poisson) / (2.0 * (1.0 + poisson))
+
+
+POISSON_CONCRETE = 0.2   # Poisson's ratio of the state-based workloads (the PMB fixes 1/4)
+
+
 def workload(name: str, **over) -> Workload:
-    """Build one named workload.  Keyword overrides replace dims/steps for scaled-down tests."""
+    """Build one named workload.  Keyword overrides replace dims/steps for scaled-down tests;
+    model="state_based" swaps the PMB bond force for the state-based linear solid with the
+    same bulk modulus and Poisson's ratio ``poisson`` (default 0.2)."""
+    model = over.pop("model", "pmb")
+    poisson = over.pop("poisson", POISSON_CONCRETE)
+    w = _workload(name, **over)
+    if model == "state_based":
+        w.state_based = (K_CONCRETE, shear_modulus(K_CONCRETE, poisson))
+    elif model != "pmb":
+        raise KeyError(model)
+    return w
+
+
+def _workload(name: str, **over) -> Workload:
     if name == "block10":
         dims = over.get("dims", (10, 10, 10))
         return _mk(name, dims, 3.015, 1.0e-3, over.get("steps", 1000), "euler_cromer", _bcs_block)
