@@ -288,6 +288,28 @@ def corrections_extra(P, pi, sync, workload: str, steps: int, plain_ms: float):
             "vs_plain_step": plain_ms / dev_ms}
 
 
+def state_based_extra(P, pi, sync, workload: str, steps: int, plain_ms: float):
+    """The headline workload on the ordinary state-based linear solid (same bulk modulus,
+    Poisson ratio 0.2): two kernels per step, the dilation pass then the force pass, each
+    gathering the whole family; one bond update per slot and step as for the PMB."""
+    w = pi.workload(workload, model="state_based")
+    w.order = "natural"
+    sim = P.simulation_for(w, mapping="staged")
+    sim.prepare()
+    info = sim.info()
+    sim.step(20)
+    sim.sync()
+    t = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    dev_ms = sim.last_step_ms() / steps
+    sim.close()
+    nnz = info["n_slots"]
+    return {"config": f"{workload}, state-based linear solid (K, nu = 0.2), staged mapping, natural order",
+            "steps": steps, "value": nnz * steps / t, "unit": "bond-updates/s", "step_ms": dev_ms,
+            "model_bytes_per_step": info["model_bytes_per_step"],
+            "hbm_frac": info["model_bytes_per_step"] / (dev_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
+            "vs_plain_step": plain_ms / dev_ms}
+
+
 def fp32_extra(P, pi, sync, workload: str, steps: int):
     """The FP32 build (f32 bond arithmetic, f64 master displacement) on the headline
     workload with the staged mapping, the only mapping it runs."""
@@ -431,6 +453,8 @@ def main():
             print(f"# fp32 {out['fp32']}", file=sys.stderr, flush=True)
         out["corrections"] = corrections_extra(P, pi, torch_sync, args.workload, args.steps, per_launch_s * 1e3)
         print(f"# corrections {out['corrections']}", file=sys.stderr, flush=True)
+        out["state_based"] = state_based_extra(P, pi, torch_sync, args.workload, args.steps, per_launch_s * 1e3)
+        print(f"# state_based {out['state_based']}", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_extra(P, pi, torch_sync, args.adjoint_steps, 100)
         out["adjoint"]["adjoint_vs_headline_step"] = out["adjoint"]["adjoint_rate"] / value
         print(f"# adjoint {out['adjoint']}", file=sys.stderr, flush=True)

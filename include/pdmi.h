@@ -244,6 +244,26 @@ typedef struct pd_corrections {
  * positive where needed). */
 int pd_set_corrections(pd_ctx *ctx, int32_t inst, const pd_corrections *corr);
 
+#define PD_MODEL_PMB 0          /* bond-based prototype microelastic brittle model (Sec. 2.2) */
+#define PD_MODEL_STATE_BASED 1  /* ordinary state-based linear peridynamic solid (Sec. 8.2) */
+
+/* Constitutive model of instance `inst`.  PD_MODEL_STATE_BASED replaces the PMB bond force
+ * by the ordinary state-based linear solid of Sec. 8.2 (after Silling et al. 2007) with
+ * bulk modulus K > 0 and shear modulus G >= 0 (so any Poisson ratio, where the PMB fixes
+ * it at 1/4, Sec. 2.2), influence function 1:
+ *   weighted volume  m_i = sum over the whole family of |xi|^2 V (reference configuration)
+ *   dilation         theta_i = (3 / m_i) sum over intact bonds of |xi| e V, e = |y| - |xi|
+ *   bond force       (t_ij + t_ji) y/|y| V,  t_ij = (3 K theta_i / m_i) |xi|
+ *                    + (15 G / m_i) (e - theta_i |xi| / 3)
+ * Bonds break at the critical stretch s0 of pd_set_material (irreversibly, on both
+ * slots, not in no-failure zones), before the dilation of the same step.  Each step runs
+ * two kernels (dilation, then force and integration).  The model needs the staged
+ * mapping, the FP64 build and a uniform node volume; it takes no stiffness field, damage
+ * law or correction, the adjoint rejects it, and every instance of a context must run
+ * the same model (checked here and when stepping; c of pd_set_material is unused).
+ * PD_MODEL_PMB (K, G ignored) returns to the bond-based model.  Errors: PD_EINVAL. */
+int pd_set_model(pd_ctx *ctx, int32_t inst, int model, double K, double G);
+
 /* Body force density b_i = magnitude * b_hat_i (N/m^3) of instance `inst`;
  * b_hat: host n x 3, user order; NULL removes it. */
 int pd_set_body_force(pd_ctx *ctx, int32_t inst, const double *b_hat, double magnitude);
@@ -289,6 +309,11 @@ int pd_get_a(pd_ctx *ctx, int32_t inst, double *out);
  * last completed step; 0 for a node without bonds.
  * out: host, n doubles, user order. */
 int pd_get_damage(pd_ctx *ctx, int32_t inst, double *out);
+
+/* State-based model: dilation theta_i of every node at the current displacement over
+ * the bonds intact now (Sec. 8.2; breaks nothing).  out: host, n doubles, user order.
+ * Errors: PD_EINVAL if the instance runs the PMB model. */
+int pd_get_dilation(pd_ctx *ctx, int32_t inst, double *out);
 
 /* Broken flags of every slot: out[nnz] (host, user CSR order), 1 = broken. */
 int pd_get_broken(pd_ctx *ctx, int32_t inst, uint8_t *out);

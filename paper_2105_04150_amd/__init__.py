@@ -110,6 +110,13 @@ class Simulation:
         else:
             B.pd_set_corrections(self.ctx, inst, **corrections)
 
+    def set_model(self, model, K=0.0, G=0.0, inst=0):
+        """Constitutive model: "pmb" or "state_based" (bulk modulus K, shear modulus G)."""
+        B.pd_set_model(self.ctx, inst, model, K, G)
+
+    def dilation(self, inst=0):
+        return B.pd_get_dilation(self.ctx, inst)
+
     def max_stretch(self, inst=0):
         """Largest stretch of every slot beyond its law's elastic limit (0 if none)."""
         return B.pd_get_max_stretch(self.ctx, inst)
@@ -210,6 +217,8 @@ def apply_workload(sim: Simulation, w, inst: int = 0, row_ptr=None, col=None, st
         sim.set_bcs(bc.nodes, bc.comp_mask, bc.kind, bc.value, bc.sched, inst=inst)
     if w.ramp_T is not None:
         sim.set_bc_ramp(w.ramp_T, inst=inst)
+    if w.state_based is not None:
+        sim.set_model("state_based", *w.state_based, inst=inst)
     if w.corrections:
         sim.set_corrections(w.corrections, inst=inst)
     if w.laws:
@@ -237,6 +246,8 @@ def simulation_for(w, precision: int = PD_FP64, lanes: int = 0, device: int = 0,
                    mapping="sliced", stiffness: str = "slot") -> Simulation:
     """A single-instance Simulation set up for workload ``w`` (family built on the host)."""
     sim = Simulation(device, precision)
+    if w.state_based is not None and mapping == "sliced":
+        mapping = "staged"  # the state-based kernels run on the staged layout
     if lanes or mapping != "sliced":
         sim.set_mapping(mapping, lanes)
     sim.build_family(w.coords, w.horizon, order or w.order)

@@ -21,6 +21,7 @@ PD_EULER_CROMER, PD_VELOCITY_VERLET, PD_EULER_FORWARD = 0, 1, 2
 PD_BC_DISP, PD_BC_VEL = 1, 2
 PD_SCHED_CONST, PD_SCHED_LINEAR, PD_SCHED_RAMP5 = 0, 1, 2
 PD_MAP_SLICED, PD_MAP_STAGED = 0, 1
+PD_MODEL_PMB, PD_MODEL_STATE_BASED = 0, 1
 
 SYMBOLS = [
     "pd_create", "pd_destroy", "pd_last_error", "pd_build_family", "pd_build_family_batch",
@@ -28,7 +29,8 @@ SYMBOLS = [
     "pd_set_node_stiffness",
     "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_bc_ramp", "pd_set_no_fail", "pd_get_force",
     "pd_get_resultant", "pd_get_mean_displacement", "pd_set_damage_law", "pd_set_bond_classes",
-    "pd_clear_damage_laws", "pd_get_max_stretch", "pd_set_max_stretch", "pd_set_corrections", "pd_set_body_force", "pd_set_integrator",
+    "pd_clear_damage_laws", "pd_get_max_stretch", "pd_set_max_stretch", "pd_set_corrections", "pd_set_model", "pd_get_dilation",
+    "pd_set_body_force", "pd_set_integrator",
     "pd_step", "pd_prepare", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
     "pd_get_info", "pd_last_step_ms", "pd_adj_forward", "pd_adj_backward", "pd_get_break_steps",
@@ -90,6 +92,8 @@ def load() -> C.CDLL:
         "pd_get_max_stretch": [P, i32, P],
         "pd_set_max_stretch": [P, i32, P],
         "pd_set_corrections": [P, i32, P],
+        "pd_set_model": [P, i32, C.c_int, d, d],
+        "pd_get_dilation": [P, i32, P],
         "pd_set_body_force": [P, i32, P, d],
         "pd_set_integrator": [P, C.c_int, d],
         "pd_step": [P, i64],
@@ -353,6 +357,19 @@ def pd_get_v(ctx, inst: int = 0) -> np.ndarray:
 
 def pd_get_a(ctx, inst: int = 0) -> np.ndarray:
     return _get3(load().pd_get_a, ctx, inst)
+
+
+def pd_set_model(ctx, inst: int, model: str, K: float = 0.0, G: float = 0.0) -> None:
+    code = {"pmb": PD_MODEL_PMB, "state_based": PD_MODEL_STATE_BASED}.get(model)
+    if code is None:
+        raise ValueError(f"unknown model {model!r}")
+    _check(ctx, load().pd_set_model(ctx, inst, code, float(K), float(G)))
+
+
+def pd_get_dilation(ctx, inst: int = 0) -> np.ndarray:
+    out = np.zeros(_inst_n(ctx, inst))
+    _check(ctx, load().pd_get_dilation(ctx, inst, _p(out)))
+    return out
 
 
 def pd_get_damage(ctx, inst: int = 0) -> np.ndarray:

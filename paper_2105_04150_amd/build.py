@@ -30,7 +30,7 @@ def _run(cmd):
 
 
 KERNEL_SOURCES = ("pdmi_step_sliced.hip", "pdmi_step_staged_f64.hip", "pdmi_step_staged_f32.hip",
-                  "pdmi_kernels.hip", "pdmi_adjoint.hip")
+                  "pdmi_kernels.hip", "pdmi_adjoint.hip", "pdmi_osb.hip")
 
 
 def build(verbose: bool = False) -> str:

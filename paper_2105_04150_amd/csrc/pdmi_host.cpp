@@ -96,6 +96,8 @@ struct Inst {
     pd_corrections corr{};                   // stiffness corrections
     bool has_corr = false;
     std::vector<uint8_t> cls;                // user CSR order: law of every slot; empty = law 0
+    bool osb = false;                        // the state-based linear solid instead of the PMB
+    double osb_K = 0.0, osb_G = 0.0;         // its bulk and shear moduli
     // device layout
     std::vector<int64_t> perm;       // device-local node -> user node, -1 = padding
     std::vector<int64_t> iperm;      // user node -> device-local node
@@ -138,10 +140,12 @@ struct pd_ctx {
     bool has_stiff = false, has_vol = false, has_body = false, has_knode = false;
     bool has_nofail = false;         // some slot carries the no-failure bit
     bool has_laws = false;           // some instance has damage laws (smax, laws allocated)
+    bool has_osb = false;            // the instances run the state-based linear solid
     DevBuf rec[2], um[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc,
         step_base, status, phi, pieces, slice_piece, ent;
     DevBuf force, rset, rsum;        // force readout: F (SoA), node list and sum of a resultant
     DevBuf laws, cls, smax;          // damage laws, per-slot law (several per instance), stretch state
+    DevBuf osb, minv;                // state-based model: node pairs {theta/m, 1/m}, 1/m
 
     // adjoint: per-slot break steps (recorded by every step while allocated) and the
     // (u, v) checkpoints of the last recorded forward run
@@ -433,6 +437,10 @@ InstParams make_params(const Inst& I, int32_t law_off)
     p.volume = I.volume;
     p.bmag = I.bmag;
     p.has_body = I.bhat.empty() ? 0 : 1;
+    if (I.osb) {
+        p.osb_a = 3.0 * I.osb_K - 5.0 * I.osb_G;
+        p.osb_b = 15.0 * I.osb_G;
+    }
     return p;
 }
 
@@ -662,6 +670,66 @@ void upload_volumes(pd_ctx* ctx)
     ctx->vol.alloc(V.size() * sizeof(double));
     upload(ctx->vol, V.data(), V.size() * sizeof(double), 0, ctx->stream);
     sync(ctx);
+}
+
+// State-based model: 1/m_i per device node, m_i = sum over the whole family of |xi|^2 V
+// (influence function 1, reference configuration, uniform volume); padding 0.  The pair
+// buffer {theta/m, 1/m} starts zeroed, with kOsbPad spare pairs.
+void upload_osb(pd_ctx* ctx)
+{
+    ctx->has_osb = false;
+    for (auto& I : ctx->inst) ctx->has_osb |= I.osb;
+    if (!ctx->has_osb) {
+        ctx->osb.release();
+        ctx->minv.release();
+        return;
+    }
+    std::vector<double> b(static_cast<size_t>(ctx->nn) + 1, 0.0);
+    for (auto& I : ctx->inst) {
+        if (!I.osb) continue;
+        std::vector<double> m(static_cast<size_t>(I.n), 0.0);
+        parallel_for(I.n, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                double acc = 0.0;
+                for (int64_t q = I.row_ptr[i]; q < I.row_ptr[i + 1]; ++q) {
+                    const int64_t j = I.col[q];
+                    double L2 = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        const double xi = I.x[3 * j + d] - I.x[3 * i + d];
+                        L2 += xi * xi;
+                    }
+                    acc += L2;
+                }
+                m[i] = acc * I.volume;
+            }
+        });
+        for (int64_t l = 0; l < I.n_pad; ++l) {
+            const int64_t u = I.perm[l];
+            if (u >= 0 && m[u] > 0.0) b[I.node_off + l] = 1.0 / m[u];
+        }
+    }
+    ctx->minv.alloc(b.size() * sizeof(double));
+    upload(ctx->minv, b.data(), b.size() * sizeof(double), 0, ctx->stream);
+    ctx->osb.alloc(static_cast<size_t>(ctx->nn + kOsbPad) * 2 * sizeof(double));
+    hip_check(hipMemsetAsync(ctx->osb.p, 0, ctx->osb.bytes, ctx->stream), "hipMemsetAsync");
+    sync(ctx);
+}
+
+// What the state-based kernels support: every instance on the model, the staged layout,
+// FP64, uniform volumes, the constant micromodulus replaced by (K, G): no stiffness
+// fields, damage laws or corrections.
+void osb_checks(const pd_ctx* ctx)
+{
+    if (!ctx->has_osb) return;
+    for (const Inst& I : ctx->inst) {
+        if (!I.osb) fail(PD_EINVAL, "state-based and bond-based instances cannot share a context");
+        if (!I.laws.empty()) fail(PD_EINVAL, "the state-based model takes the brittle critical stretch only (no damage laws)");
+        if (I.has_corr) fail(PD_EINVAL, "the state-based model takes no stiffness corrections");
+    }
+    if (ctx->mapping != PD_MAP_STAGED) fail(PD_EINVAL, "the state-based model runs in the staged mapping");
+    if (fp32(ctx)) fail(PD_EINVAL, "the state-based model runs in the FP64 build");
+    if (ctx->has_vol) fail(PD_EINVAL, "the state-based model takes a uniform node volume per instance");
+    if (ctx->has_stiff || ctx->has_knode) fail(PD_EINVAL, "the state-based model takes no stiffness field");
 }
 
 void upload_body(pd_ctx* ctx)
@@ -1185,6 +1253,7 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     upload_node_weights(ctx);
     upload_body(ctx);
     upload_laws(ctx);
+    upload_osb(ctx);
     for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
         Inst& I = ctx->inst[ii];
         std::vector<double> zeros(static_cast<size_t>(3 * I.n), 0.0);
@@ -1237,6 +1306,7 @@ void new_problem(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* con
     ctx->order_auto = order == PD_ORDER_AUTO;
     ctx->has_nofail = false;
     ctx->has_laws = false;
+    ctx->has_osb = false;
     ctx->step = 0;
     ctx->a_valid = false;
     ctx->vv_ahead = false;
@@ -1264,6 +1334,8 @@ StepArgs step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
     A.laws = ctx->has_laws ? ctx->laws.as<LawRec>() : nullptr;
     A.cls = ctx->cls.p ? ctx->cls.as<uint8_t>() : nullptr;
     A.smax = ctx->has_laws ? ctx->smax.as<double>() : nullptr;
+    A.osb = ctx->has_osb ? ctx->osb.as<double2>() : nullptr;
+    A.minv = ctx->has_osb ? ctx->minv.as<double>() : nullptr;
     A.slice_ptr = ctx->slice_ptr.as<int64_t>();
     A.slice_T = ctx->slice_T.as<int32_t>();
     A.slice_inst = ctx->slice_inst.as<int32_t>();
@@ -1291,7 +1363,9 @@ int step_mode(int scheme)
 void launch_one(pd_ctx* ctx, int mode, int in, int out, int64_t step_local)
 {
     const StepArgs A = step_args(ctx, in, out, step_local);
-    if (ctx->mapping == PD_MAP_STAGED)
+    if (ctx->has_osb)
+        hip_check(launch_osb_step(A, mode, ctx->lanes, ctx->stream), "state-based step launch");
+    else if (ctx->mapping == PD_MAP_STAGED)
         hip_check(launch_step_staged(A, mode, fp32(ctx), ctx->lanes, ext_kernels(ctx), ctx->stream),
                   "step kernel launch");
     else
@@ -1305,6 +1379,7 @@ void launch_one(pd_ctx* ctx, int mode, int in, int out, int64_t step_local)
 // kernel in its force-only mode, reading the record buffer that holds level `step`.
 void eval_force(pd_ctx* ctx)
 {
+    osb_checks(ctx);
     const size_t bytes = static_cast<size_t>(3 * ctx->nn) * sizeof(double);
     if (!ctx->force.p || ctx->force.bytes < bytes) ctx->force.alloc(bytes);
     launch_one(ctx, kModeForce, ctx->cur, 1 - ctx->cur, 0);
@@ -1343,6 +1418,7 @@ hipGraphExec_t chunk_graph(pd_ctx* ctx, int mode, int parity)
 
 void do_steps(pd_ctx* ctx, int64_t nsteps)
 {
+    osb_checks(ctx);
     const int mode = step_mode(ctx->scheme);
     ctx->tape_valid = false;
     if (!ctx->ev0) {
@@ -1404,6 +1480,7 @@ void adjoint_checks(pd_ctx* ctx)
     for (const LawRec& L : ctx->inst[0].laws)
         if (L.nb > 1) fail(PD_EINVAL, "the adjoint differentiates brittle damage laws only");
     if (ctx->inst[0].has_corr) fail(PD_EINVAL, "the adjoint does not take stiffness corrections");
+    if (ctx->has_osb) fail(PD_EINVAL, "the adjoint differentiates the bond-based model only");
 }
 
 // The reverse pass gathers the transposed tangent over each node's own family, which
@@ -1552,6 +1629,7 @@ int pd_set_material(pd_ctx* ctx, int32_t inst, const pd_material* m)
         upload_volumes(ctx);
         if (ctx->has_stiff) upload_stiffness(ctx, inst);
         upload_node_weights(ctx);
+        if (I.osb) upload_osb(ctx);  // the weighted volumes scale with the node volume
         ctx->a_valid = false;
         ctx->vv_ahead = false;
         ctx->drop_graphs();
@@ -1861,6 +1939,7 @@ int pd_prepare(pd_ctx* ctx)
     return guarded(ctx, [&] {
         require_built(ctx);
         set_device(ctx);
+        osb_checks(ctx);
         if (!ctx->use_graphs) return;
         const int mode = step_mode(ctx->scheme);
         for (int parity = 0; parity < 2; ++parity) (void)chunk_graph(ctx, mode, parity);
@@ -1957,6 +2036,52 @@ int pd_get_damage(pd_ctx* ctx, int32_t inst, double* out)
     });
 }
 
+int pd_set_model(pd_ctx* ctx, int32_t inst, int model, double K, double G)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (model != PD_MODEL_PMB && model != PD_MODEL_STATE_BASED) fail(PD_EINVAL, "unknown model");
+        if (model == PD_MODEL_STATE_BASED) {
+            if (!(K > 0.0) || !std::isfinite(K)) fail(PD_EINVAL, "K must be positive and finite");
+            if (!(G >= 0.0) || !std::isfinite(G)) fail(PD_EINVAL, "G must be >= 0 and finite");
+            if (ctx->mapping != PD_MAP_STAGED)
+                fail(PD_EINVAL, "the state-based model runs in the staged mapping: call pd_set_mapping first");
+            if (fp32(ctx)) fail(PD_EINVAL, "the state-based model runs in the FP64 build");
+        }
+        set_device(ctx);
+        I.osb = model == PD_MODEL_STATE_BASED;
+        I.osb_K = I.osb ? K : 0.0;
+        I.osb_G = I.osb ? G : 0.0;
+        upload_params(ctx);
+        upload_osb(ctx);
+        ctx->a_valid = false;
+        ctx->vv_ahead = false;
+        ctx->drop_graphs();
+        sync(ctx);
+    });
+}
+
+int pd_get_dilation(pd_ctx* ctx, int32_t inst, double* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        if (!I.osb) fail(PD_EINVAL, "the instance does not run the state-based model");
+        osb_checks(ctx);
+        set_device(ctx);
+        // the dilation pass at the current level, breaking nothing
+        hip_check(launch_osb_dilation(step_args(ctx, ctx->cur, 1 - ctx->cur, 0), false, ctx->lanes, ctx->stream),
+                  "dilation launch");
+        std::vector<double> h(static_cast<size_t>(2 * I.n_pad));
+        download(h.data(), ctx->osb, h.size() * 8, I.node_off * 16, ctx->stream);
+        sync(ctx);
+        for (int64_t l = 0; l < I.n_pad; ++l)
+            if (I.perm[l] >= 0) out[I.perm[l]] = h[2 * l + 1] > 0.0 ? h[2 * l] / h[2 * l + 1] : 0.0;
+    });
+}
+
 int pd_get_broken(pd_ctx* ctx, int32_t inst, uint8_t* out)
 {
     if (!ctx) return PD_EINVAL;
@@ -2011,7 +2136,7 @@ int pd_get_force(pd_ctx* ctx, int32_t inst, double* out)
 }
 
 // Device indices of a host node list of one instance (validated).
-std::vector<int64_t> device_nodes(const Inst& I, int64_t m, const int64_t* nodes)
+static std::vector<int64_t> device_nodes(const Inst& I, int64_t m, const int64_t* nodes)
 {
     if (m < 1 || !nodes) fail(PD_EINVAL, "need at least one node");
     std::vector<int64_t> idx(static_cast<size_t>(m));
@@ -2023,7 +2148,7 @@ std::vector<int64_t> device_nodes(const Inst& I, int64_t m, const int64_t* nodes
 }
 
 // out = sum over the listed device nodes of w_i field(i, .) (see launch_set_sum).
-void set_sum(pd_ctx* ctx, const std::vector<int64_t>& idx, const double* field, int64_t snode, int64_t scomp,
+static void set_sum(pd_ctx* ctx, const std::vector<int64_t>& idx, const double* field, int64_t snode, int64_t scomp,
              const double* wv, double w, double out[3])
 {
     ctx->rset.alloc(idx.size() * sizeof(int64_t));
@@ -2111,6 +2236,8 @@ int pd_set_mapping(pd_ctx* ctx, int mapping, int lanes)
     return guarded(ctx, [&] {
         if (mapping != PD_MAP_SLICED && mapping != PD_MAP_STAGED) fail(PD_EINVAL, "unknown mapping");
         if (fp32(ctx) && mapping != PD_MAP_STAGED) fail(PD_EINVAL, "the FP32 build runs the staged mapping only");
+        if (ctx->has_osb && mapping != PD_MAP_STAGED)
+            fail(PD_EINVAL, "the state-based model runs in the staged mapping");
         if (lanes == 0) lanes = mapping == PD_MAP_STAGED ? 1 : kDefaultLanes;
         if (mapping == PD_MAP_STAGED && !split_supported(lanes))
             fail(PD_EINVAL, "unsupported wavefronts per slice (staged mapping: 1, 2 or 4)");
@@ -2156,7 +2283,7 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
         const int orders[] = {PD_ORDER_NATURAL, PD_ORDER_MORTON};
         for (int o : orders) {
             if (!ctx->order_auto && o != ctx->order) continue;
-            if (!fp32(ctx))
+            if (!fp32(ctx) && !ctx->has_osb)
                 for (int L : {1, 4, 16, 64}) cands.push_back({PD_MAP_SLICED, L, o});
             for (int S : {1, 2, 4}) cands.push_back({PD_MAP_STAGED, S, o});
         }
@@ -2406,6 +2533,9 @@ int pd_get_info(const pd_ctx* ctx, pd_info* info)
     per_node += ctx->has_knode ? 16.0 : 0.0;  // per-node stiffness factors (own and neighbour weight)
     info->model_bytes_per_step = static_cast<double>(nnz) * (4.0 + (ctx->has_stiff ? 8.0 : 0.0)) +
                                  static_cast<double>(n) * per_node;
+    if (ctx->has_osb)  // two passes: the neighbour index twice; x and u read again, the node pair
+                       // {theta/m, 1/m} written, then read, with 1/m read by the first pass
+        info->model_bytes_per_step += static_cast<double>(nnz) * 4.0 + static_cast<double>(n) * (48.0 + 16.0 + 16.0 + 8.0);
     return PD_OK;
 }
 

@@ -98,6 +98,8 @@ struct InstParams {
     int32_t nlaw;    // damage laws of the instance (0: the brittle law with q0)
     int32_t law_off; // first law of the instance in StepArgs::laws
     int32_t pad_;
+    double osb_a;    // state-based linear solid: 3K - 5G
+    double osb_b;    // state-based linear solid: 15G
 };
 
 // Constraint of one node: per component d, kind in bits 2d..2d+1 (0 free, 1 displacement,
@@ -131,6 +133,8 @@ struct StepArgs {
     const LawRec* laws;         // damage laws of every instance (nullptr without)
     const uint8_t* cls;         // per slot: law index within the instance (nullptr: 0)
     double* smax;               // per slot: largest stretch beyond the elastic limit
+    double2* osb;               // state-based model: per node {theta / m, 1 / m} (nn + 128 entries)
+    const double* minv;         // state-based model: per node 1 / m (padding 0)
     const int64_t* slice_ptr;
     const int32_t* slice_T;
     const int32_t* slice_inst;
@@ -187,6 +191,13 @@ hipError_t launch_set_sum(const double* field, int64_t snode, int64_t scomp, con
                           const int64_t* idx, int64_t m, double* out, hipStream_t s);
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
+
+// state-based linear solid (staged layout, FP64): the dilation pass alone (breaking or a
+// force evaluation), and a whole step (dilation pass, then the force pass with the
+// integrator of `mode`)
+hipError_t launch_osb_dilation(const StepArgs& a, bool breaking, int split, hipStream_t s);
+hipError_t launch_osb_step(const StepArgs& a, int mode, int split, hipStream_t s);
+constexpr int kOsbPad = 128;    // spare pairs after the last node (the pass-2 range copy)
 
 hipError_t launch_advance(int64_t* step_base, int64_t by, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t value, hipStream_t s);

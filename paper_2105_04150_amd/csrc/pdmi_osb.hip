@@ -1,0 +1,226 @@
+// pdmi_osb.hip -- the ordinary state-based linear solid (Sec. 8.2): two kernels per time
+// step on the staged layout.
+//
+// The bond force of this model depends on the dilation of both end nodes, a sum over each
+// node's whole family, so one pass over the bonds cannot both form and use it (Sec. 8.2:
+// two loops, hence two kernels).
+//
+//   pass 1 (osb_staged<0, ...>): every slot forms its stretch; a slot at or over the
+//     critical stretch breaks (outside no-failure zones, not in a force evaluation); the
+//     node sums |xi| e V over its intact bonds into the dilation theta_i = 3 V / m_i sum and
+//     writes the node pair {theta_i / m_i, 1 / m_i}.
+//   pass 2 (osb_staged<1, ...>): every intact slot adds
+//       (t_ij + t_ji) y / |y| V,   t_ij + t_ji = |xi| [(3K - 5G)(A_i + A_j) + 15 G s (B_i + B_j)]
+//     with A = theta / m, B = 1 / m, s = e / |xi| the stretch, then the node integrates
+//     (the same tail as the bond-based step kernels).
+//
+// Both passes use the staged mapping of the bond-based kernels: a slice of 64 nodes, one
+// lane per node, the node records of each piece's range and its slot entries copied
+// straight into LDS; pass 2 copies the range's node pairs beside them.  Influence function
+// 1, uniform node volume per instance, FP64.
+//
+// Per slot: xi, eta and q = (|y|^2 - |xi|^2)/|xi|^2 as in the bond-based kernels; then
+// g = 1 - (1+q)^(-1/2) (series for small q), |xi| / |y| = 1 - g and s = g / (1 - g), so
+// neither the stretch nor the force loses digits to cancellation.  The force term is
+//   (t_ij + t_ji) V y / |y| = V (1 - g) [(3K - 5G)(A_i + A_j) + 15 G s (B_i + B_j)] y,
+// the |xi| of the scalar state cancelling the 1 / |xi| of y / |y|.
+#include "pdmi_step.h"
+
+namespace pdmi {
+namespace {
+
+template <int PASS, int MODE, int S>
+__global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* __restrict__ pieces,
+                                                        const int32_t* __restrict__ slice_piece,
+                                                        const int64_t* __restrict__ slice_ptr)
+{
+    constexpr int kRecChunks = kStageChunks + 3;             // staged records, then the sentinel
+    constexpr int kEntChunks = kPieceRows * kWave * 2 / 16;  // 16-byte chunks of entries
+    constexpr int kPairChunks = PASS == 1 ? 2 * kWave : 0;   // node pairs of the range (pass 2)
+    constexpr int kLds = kRecChunks + kEntChunks + kPairChunks;
+    constexpr int kRed = PASS == 1 ? 3 : 1;
+    static_assert(kEntPad / 48 < kPairChunks || PASS == 0, "the sentinel's pair index lies in the copy");
+    __shared__ double2 lds[S * kLds];
+    __shared__ double red[S > 1 ? (S - 1) * kRed * kWave : 1];
+    const int wv = S > 1 ? __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave) : 0;
+    double2* const lrec = lds + wv * kLds;
+    const char* const lrecb = reinterpret_cast<const char*>(lrec);
+    uint16_t* const lent = reinterpret_cast<uint16_t*>(lrec + kRecChunks);
+    double2* const lpair = lrec + kRecChunks + kEntChunks;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
+    if (slice >= A.nslices) return;
+    const InstParams P = A.params[A.slice_inst[slice]];
+    const int64_t node = slice * kWave + lane;
+    const double2* __restrict__ rin = reinterpret_cast<const double2*>(A.rec_in);
+    const double2 o0 = rin[3 * node], o1 = rin[3 * node + 1], o2 = rin[3 * node + 2];
+    const double X0 = o0.x, X1 = o0.y, X2 = o1.x;
+    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;
+    const double2* __restrict__ ent2 = reinterpret_cast<const double2*>(A.ent);
+    uint16_t* __restrict__ entw = A.ent;
+    const SeriesCoef sk = series_coef_regs();
+    double2 own = {0.0, 0.0};
+    if (PASS == 1) own = A.osb[node];
+    const double Ai = own.x, Bi = own.y;
+    const double ka = P.osb_a, kb = P.osb_b;
+
+    // sentinel record (padding entries point at it)
+    if (lane < 3) lrec[kStageChunks + lane] = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
+
+    const int p0 = __builtin_amdgcn_readfirstlane(slice_piece[slice]);
+    const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
+    auto rows_of = [&](int p) { return (pieces[__builtin_amdgcn_readfirstlane(p)].y >> 8) & 0xff; };
+    int64_t ent = wave_uniform(slice_ptr[slice]);
+    const int pa = p0 + wv;
+    for (int q = p0; q < pa && q < p1; ++q) ent += static_cast<int64_t>(rows_of(q)) * kWave;
+
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    auto dma = [&](int p, int64_t e) {
+        const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
+        const double2* rs = rin + 3 * static_cast<int64_t>(m.x) + lane;
+        __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs + kWave, (lds_ptr)(lrec + kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs + 2 * kWave, (lds_ptr)(lrec + 2 * kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs + 3 * kWave, (lds_ptr)(lrec + 3 * kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(ent2 + e / 8 + lane, (lds_ptr)(lent), 16, 0, 0);
+        if (PASS == 1) {  // the pair buffer ends with 2 x 64 spare pairs
+            const double2* ps = A.osb + m.x + lane;
+            __builtin_amdgcn_global_load_lds(ps, (lds_ptr)(lpair), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(ps + kWave, (lds_ptr)(lpair + kWave), 16, 0, 0);
+        }
+    };
+
+    double D = 0.0;                    // pass 1: sum of |xi|^2 s over intact bonds
+    double F0 = 0.0, F1 = 0.0, F2 = 0.0;  // pass 2: force density without the factor V
+    constexpr bool BREAK = PASS == 0 && MODE != kModeForce;
+    const int32_t step = static_cast<int32_t>(*A.step_base + A.step_local);
+
+    auto slot = [&](uint16_t e, int64_t ds) {
+        const bool live = !(e & kEntBroken);
+        const uint32_t off = e & kEntOff;
+        const double2 r0 = *reinterpret_cast<const double2*>(lrecb + off);
+        const double2 r1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
+        const double2 r2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
+        const double xi0 = r0.x - X0, xi1 = r0.y - X1, xi2 = r1.x - X2;
+        const double e0 = r1.y - U0, e1 = r2.x - U1, e2 = r2.y - U2;
+        const double y0 = xi0 + e0, y1 = xi1 + e1, y2 = xi2 + e2;
+        const double z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
+        const double tq = __builtin_fma(e2, z2, __builtin_fma(e1, z1, e0 * z0));
+        const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
+        const double iL = rsq64<1>(L2);
+        const double q = tq * (iL * iL);
+        const bool brk = BREAK && live && !(e & kEntNoFail) && q >= P.q0;
+        const bool alive = live && !brk;
+        const double g = one_minus_rsqrt1p(alive ? q : 0.0, sk);
+        const double r = 1.0 - g;  // |xi| / |y|
+        const double s = g * rcp64(r);
+        if (PASS == 0) {
+            D += alive ? L2 * s : 0.0;
+            if (brk) {
+                entw[ds] = static_cast<uint16_t>(e | kEntBroken);
+                A.bstep[ds] = step;
+            }
+        } else {
+            const double2 pj = lpair[(off * 0xAAABu) >> 21];  // off / 48: the neighbour's pair
+            const double t = __builtin_fma(kb * s, Bi + pj.y, ka * (Ai + pj.x));
+            const double coef = alive ? r * t : 0.0;
+            F0 = __builtin_fma(coef, y0, F0);
+            F1 = __builtin_fma(coef, y1, F1);
+            F2 = __builtin_fma(coef, y2, F2);
+        }
+    };
+
+    for (int p = pa; p < p1; p += S) {
+        const int T = rows_of(p);
+        int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;
+        for (int q = p + 1; q < p + S && q < p1; ++q) ent_next += static_cast<int64_t>(rows_of(q)) * kWave;
+        wave_sync();  // the previous piece is no longer read
+        dma(p, ent);
+        // s_waitcnt with vmcnt = 0 (expcnt and lgkmcnt at their no-wait maxima): the
+        // piece's direct-to-LDS loads have landed
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        wave_sync();
+#pragma unroll
+        for (int t = 0; t < kPieceRows; t += 2) {
+            if (t >= T) break;
+            const uint16_t ea = lent[t * kWave + lane];
+            slot(ea, ent + t * kWave + lane);
+            if (t + 1 < T) slot(lent[(t + 1) * kWave + lane], ent + (t + 1) * kWave + lane);
+        }
+        ent = ent_next;
+    }
+
+    if (S > 1) {  // wavefront 0 adds the partial sums of 1..S-1 in that order
+        if (wv > 0) {
+            double* rr = red + (wv - 1) * kRed * kWave + lane;
+            if (PASS == 0) {
+                rr[0] = D;
+            } else {
+                rr[0] = F0;
+                rr[kWave] = F1;
+                rr[2 * kWave] = F2;
+            }
+        }
+        __syncthreads();  // every wavefront of the workgroup reaches this once
+        if (wv > 0) return;
+#pragma unroll
+        for (int w = 1; w < S; ++w) {
+            const double* rr = red + (w - 1) * kRed * kWave + lane;
+            if (PASS == 0) {
+                D += rr[0];
+            } else {
+                F0 += rr[0];
+                F1 += rr[kWave];
+                F2 += rr[2 * kWave];
+            }
+        }
+    }
+    if (PASS == 0) {
+        // theta_i = 3 V D / m_i; padding nodes (1/m = 0) write zeros
+        const double b = A.minv[node];
+        const double theta = (3.0 * P.volume) * D * b;
+        A.osb[node] = double2{theta * b, b};
+        return;
+    }
+    const double V = P.volume;
+    node_update<MODE, false>(A, P, node, U0, U1, U2, V * F0, V * F1, V * F2);
+}
+
+template <int PASS, int MODE>
+hipError_t launch_osb_pm(const StepArgs& a, int split, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>(a.nslices));
+    switch (split) {
+    case 1: hipLaunchKernelGGL((osb_staged<PASS, MODE, 1>), grid, dim3(kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+    case 2: hipLaunchKernelGGL((osb_staged<PASS, MODE, 2>), grid, dim3(2 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+    case 4: hipLaunchKernelGGL((osb_staged<PASS, MODE, 4>), grid, dim3(4 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_osb_dilation(const StepArgs& a, bool breaking, int split, hipStream_t s)
+{
+    if (a.nslices <= 0) return hipSuccess;
+    return breaking ? launch_osb_pm<0, kModeEC>(a, split, s) : launch_osb_pm<0, kModeForce>(a, split, s);
+}
+
+hipError_t launch_osb_step(const StepArgs& a, int mode, int split, hipStream_t s)
+{
+    if (a.nslices <= 0) return hipSuccess;
+    hipError_t e = launch_osb_dilation(a, mode != kModeForce, split, s);
+    if (e != hipSuccess) return e;
+    switch (mode) {
+    case kModeEC: return launch_osb_pm<1, kModeEC>(a, split, s);
+    case kModeVV: return launch_osb_pm<1, kModeVV>(a, split, s);
+    case kModeVVInit: return launch_osb_pm<1, kModeVVInit>(a, split, s);
+    case kModeFE: return launch_osb_pm<1, kModeFE>(a, split, s);
+    case kModeForce: return launch_osb_pm<1, kModeForce>(a, split, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace pdmi
