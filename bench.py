@@ -338,6 +338,9 @@ def main():
     ap.add_argument("--workload", default="cube100",
                     choices=["cube100", "cube100_wide", "block10", "beam3pb", "qs_beam"])
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--model", default="pmb", choices=["pmb", "state_based"],
+                    help="constitutive model of the timed line (state_based: profiling runs of "
+                         "the two-pass step; the state-based extra line covers it otherwise)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per node of the sliced mapping")
     ap.add_argument("--mapping", default="auto", choices=["auto", "sliced", "staged"],
                     help="step-kernel mapping (auto: the library's autotuner picks)")
@@ -374,7 +377,9 @@ def main():
     import pd_inputs as pi
     import paper_2105_04150_amd as P
 
-    w = pi.workload(args.workload)
+    w = pi.workload(args.workload, model=args.model)
+    if args.model == "state_based" and (args.mapping != "staged" or args.precision != "f64"):
+        sys.exit("the state-based model runs with --mapping staged --precision f64")
     w.order = args.order
     prec = P.PD_FP64 if args.precision == "f64" else P.PD_FP32
     t0 = time.perf_counter()
@@ -431,7 +436,8 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"{args.workload} {w.dims[0]}x{w.dims[1]}x{w.dims[2]} lattice, "
-                               f"horizon {w.horizon / w.dx:.3f} dx, {w.scheme}",
+                               f"horizon {w.horizon / w.dx:.3f} dx, {w.scheme}"
+                               + (", state-based linear solid" if args.model == "state_based" else ""),
                    "nodes": info["n_nodes"], "bond_slots": nnz, "mapping": mapping, "lanes_per_node": lanes,
                    "device_node_order": order,
                    "parallelism": "1 GPU"},
@@ -446,7 +452,11 @@ def main():
                              "algorithmic_bytes_per_launch": model_bytes, "measured_bytes_per_launch": traffic}},
     }
     sim.close()
-    if not args.no_extras:
+    if args.model == "state_based":  # a profiling run: the PMB roofline does not apply
+        out["roofline"] = {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": None, "step_ms": per_launch_s * 1e3,
+                           "note": "two kernels per step; step time over the algorithmic bytes of both"}
+    if not args.no_extras and args.model == "pmb":
         if args.precision == "f64":
             out["fp32"] = fp32_extra(P, pi, torch_sync, args.workload, args.steps)
             out["fp32"]["vs_fp64"] = out["fp32"]["value"] / value

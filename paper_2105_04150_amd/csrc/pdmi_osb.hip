@@ -19,15 +19,42 @@
 // straight into LDS; pass 2 copies the range's node pairs beside them.  Influence function
 // 1, uniform node volume per instance, FP64.
 //
-// Per slot: xi, eta and q = (|y|^2 - |xi|^2)/|xi|^2 as in the bond-based kernels; then
-// g = 1 - (1+q)^(-1/2) (series for small q), |xi| / |y| = 1 - g and s = g / (1 - g), so
-// neither the stretch nor the force loses digits to cancellation.  The force term is
-//   (t_ij + t_ji) V y / |y| = V (1 - g) [(3K - 5G)(A_i + A_j) + 15 G s (B_i + B_j)] y,
-// the |xi| of the scalar state cancelling the 1 / |xi| of y / |y|.
+// Per slot: xi, eta and q = (|y|^2 - |xi|^2)/|xi|^2 as in the bond-based kernels.  The
+// dilation pass needs the stretch s = sqrt(1+q) - 1, the force pass g = 1 - (1+q)^(-1/2)
+// = |y| - |xi| over |y|: with |xi| / |y| = 1 - g and s (1 - g) = g the force term is
+//   (t_ij + t_ji) V y / |y| = V [(3K - 5G)(A_i + A_j)(1 - g) + 15 G (B_i + B_j) g] y,
+// the |xi| of the scalar state cancelling the 1 / |xi| of y / |y|.  Both s and g come
+// from their binomial series for small |q| (no division, no cancellation).
 #include "pdmi_step.h"
 
 namespace pdmi {
 namespace {
+
+// sqrt(1+q) - 1.  Series q/2 - q^2/8 + q^3/16 - 5q^4/128 + 7q^5/256 - 21q^6/1024; the first
+// omitted term, 33q^7/2048, is below 2e-16 of the sum for |q| < 4e-3.  Larger |q| takes
+// q / (1 + sqrt(1+q)), which has no cancellation.
+__device__ __forceinline__ double sqrt1p_minus1(double q)
+{
+    if (fabs(q) < 4.0e-3) {
+        double p = __builtin_fma(-21.0 / 1024.0, q, 7.0 / 256.0);
+        p = __builtin_fma(p, q, -5.0 / 128.0);
+        p = __builtin_fma(p, q, 1.0 / 16.0);
+        p = __builtin_fma(p, q, -1.0 / 8.0);
+        p = __builtin_fma(p, q, 0.5);
+        return q * p;
+    }
+    const double r = rsq64<2>(1.0 + q);
+    return q * rcp64(__builtin_fma(1.0 + q, r, 1.0));
+}
+
+// 1/x for the q of a slot: hardware estimate and one Newton step (relative error near
+// 1e-14, the level of the bond-based kernels' one-step 1/sqrt); neither pass needs
+// 1/|xi| itself.
+__device__ __forceinline__ double rcp64_1(double x)
+{
+    const double y = __builtin_amdgcn_rcp(x);
+    return __builtin_fma(__builtin_fma(-x, y, 1.0), y, y);
+}
 
 template <int PASS, int MODE, int S>
 __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* __restrict__ pieces,
@@ -108,23 +135,21 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         const double z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
         const double tq = __builtin_fma(e2, z2, __builtin_fma(e1, z1, e0 * z0));
         const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
-        const double iL = rsq64<1>(L2);
-        const double q = tq * (iL * iL);
+        const double q = tq * rcp64_1(L2);
         const bool brk = BREAK && live && !(e & kEntNoFail) && q >= P.q0;
         const bool alive = live && !brk;
-        const double g = one_minus_rsqrt1p(alive ? q : 0.0, sk);
-        const double r = 1.0 - g;  // |xi| / |y|
-        const double s = g * rcp64(r);
         if (PASS == 0) {
-            D += alive ? L2 * s : 0.0;
+            const double s = sqrt1p_minus1(alive ? q : 0.0);
+            D = __builtin_fma(L2, s, D);  // |xi| e = |xi|^2 s; 0 for broken and padding slots
             if (brk) {
                 entw[ds] = static_cast<uint16_t>(e | kEntBroken);
                 A.bstep[ds] = step;
             }
         } else {
+            const double g = one_minus_rsqrt1p(alive ? q : 0.0, sk);
             const double2 pj = lpair[(off * 0xAAABu) >> 21];  // off / 48: the neighbour's pair
-            const double t = __builtin_fma(kb * s, Bi + pj.y, ka * (Ai + pj.x));
-            const double coef = alive ? r * t : 0.0;
+            const double a = ka * (Ai + pj.x), b = kb * (Bi + pj.y);
+            const double coef = alive ? __builtin_fma(g, b - a, a) : 0.0;
             F0 = __builtin_fma(coef, y0, F0);
             F1 = __builtin_fma(coef, y1, F1);
             F2 = __builtin_fma(coef, y2, F2);
