@@ -115,6 +115,13 @@ __device__ __forceinline__ double rcp64(double x)
     return y;
 }
 
+// 1/x with one Newton step (relative error near 1e-14, the level of rsq64<1>; x > 0, normal).
+__device__ __forceinline__ double rcp64_1(double x)
+{
+    const double y = __builtin_amdgcn_rcp(x);
+    return __builtin_fma(__builtin_fma(-x, y, 1.0), y, y);
+}
+
 // Secant ratio of a bond softened to stretch sm under law L (s[0] < sm < s[nb-1]): the
 // law's force c s[0] rho(sm), rho interpolated linearly between breakpoints, over the
 // elastic force c sm.  The bond force is this ratio times c s (unloading and reloading

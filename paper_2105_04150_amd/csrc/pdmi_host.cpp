@@ -95,6 +95,7 @@ struct Inst {
     std::vector<LawRec> laws;                // damage laws (bond classes); empty = the brittle law with s0
     pd_corrections corr{};                   // stiffness corrections
     bool has_corr = false;
+    double corr_v0 = 0.0;                    // largest family volume (surface correction)
     std::vector<uint8_t> cls;                // user CSR order: law of every slot; empty = law 0
     bool osb = false;                        // the state-based linear solid instead of the PMB
     double osb_K = 0.0, osb_G = 0.0;         // its bulk and shear moduli
@@ -141,11 +142,13 @@ struct pd_ctx {
     bool has_nofail = false;         // some slot carries the no-failure bit
     bool has_laws = false;           // some instance has damage laws (smax, laws allocated)
     bool has_osb = false;            // the instances run the state-based linear solid
+    bool corr_k = false;             // corrections formed per slot in the kernel (no stiffness stream)
     DevBuf rec[2], um[2], v, a, col, kslot, vol, bhat, slice_ptr, slice_T, slice_inst, params, bc_id, bc,
         step_base, status, phi, pieces, slice_piece, ent;
     DevBuf force, rset, rsum;        // force readout: F (SoA), node list and sum of a resultant
     DevBuf laws, cls, smax;          // damage laws, per-slot law (several per instance), stretch state
     DevBuf osb, minv;                // state-based model: node pairs {theta/m, 1/m}, 1/m
+    DevBuf cfv;                      // corrections per slot: family volume per node
 
     // adjoint: per-slot break steps (recorded by every step while allocated) and the
     // (u, v) checkpoints of the last recorded forward run
@@ -441,6 +444,16 @@ InstParams make_params(const Inst& I, int32_t law_off)
         p.osb_a = 3.0 * I.osb_K - 5.0 * I.osb_G;
         p.osb_b = 15.0 * I.osb_G;
     }
+    if (I.has_corr) {
+        p.cr_flags = (I.corr.micromodulus == PD_MICRO_CONICAL ? 1 : 0) | (I.corr.partial_volumes ? 2 : 0) |
+                     (I.corr.surface ? 4 : 0);
+        if (I.corr.delta > 0.0) p.cr_idelta = 1.0 / I.corr.delta;
+        if (I.corr.dx > 0.0) {
+            p.cr_idx = 1.0 / I.corr.dx;
+            p.cr_pvhi = (I.corr.delta + 0.5 * I.corr.dx) / I.corr.dx;
+        }
+        p.cr_2v0 = 2.0 * I.corr_v0;
+    }
     return p;
 }
 
@@ -579,9 +592,52 @@ double corrected(const Inst& I, const CorrectionTable& T, int64_t i, int64_t j, 
     return k;
 }
 
+// Corrections are formed per slot in the step kernel (no per-slot stiffness stream) when
+// the FP64 staged kernels run and no instance has a stiffness field or per-node volumes;
+// otherwise they are folded into the per-slot stiffness.
+bool corrections_in_kernel(const pd_ctx* ctx)
+{
+    if (fp32(ctx) || ctx->mapping != PD_MAP_STAGED) return false;
+    bool any = false;
+    for (const Inst& I : ctx->inst) {
+        if (!I.kslot.empty() || !I.knode.empty() || !I.vols.empty()) return false;
+        any |= I.has_corr;
+    }
+    return any;
+}
+
+// Family volume of every device node for the per-slot corrections (1 for padding, for the
+// spare entries the kernels' fixed copy window reaches past the last node, for nodes
+// without bonds and for instances without the surface correction: every entry is positive,
+// so no slot divides by zero); sets each instance's V0.
+void upload_family_volumes(pd_ctx* ctx)
+{
+    std::vector<double> fv(static_cast<size_t>(ctx->nn) + kCorrPad, 1.0);
+    for (auto& I : ctx->inst) {
+        const CorrectionTable T = correction_table(I);
+        I.corr_v0 = T.v0;
+        if (T.famvol.empty()) continue;
+        for (int64_t l = 0; l < I.n_pad; ++l) {
+            const int64_t u = I.perm[l];
+            if (u >= 0 && T.famvol[u] > 0.0) fv[I.node_off + l] = T.famvol[u];
+        }
+    }
+    ctx->cfv.alloc(fv.size() * sizeof(double));
+    upload(ctx->cfv, fv.data(), fv.size() * sizeof(double), 0, ctx->stream);
+}
+
 void upload_stiffness(pd_ctx* ctx, int32_t only = -1)
 {
     ctx->tape_valid = false;
+    ctx->corr_k = corrections_in_kernel(ctx);
+    if (ctx->corr_k) {
+        ctx->has_stiff = false;
+        ctx->kslot.release();
+        upload_family_volumes(ctx);
+        upload_params(ctx);
+        return;
+    }
+    ctx->cfv.release();
     bool any = false;
     for (auto& I : ctx->inst) any |= !I.kslot.empty() || I.has_corr;
     if (!any) {
@@ -1336,6 +1392,7 @@ StepArgs step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
     A.smax = ctx->has_laws ? ctx->smax.as<double>() : nullptr;
     A.osb = ctx->has_osb ? ctx->osb.as<double2>() : nullptr;
     A.minv = ctx->has_osb ? ctx->minv.as<double>() : nullptr;
+    A.cfv = ctx->corr_k ? ctx->cfv.as<double>() : nullptr;
     A.slice_ptr = ctx->slice_ptr.as<int64_t>();
     A.slice_T = ctx->slice_T.as<int32_t>();
     A.slice_inst = ctx->slice_inst.as<int32_t>();
@@ -1627,7 +1684,9 @@ int pd_set_material(pd_ctx* ctx, int32_t inst, const pd_material* m)
         I.vols = std::move(vols);
         upload_params(ctx);
         upload_volumes(ctx);
-        if (ctx->has_stiff) upload_stiffness(ctx, inst);
+        bool any_corr = false;  // family volumes and the in-kernel choice depend on the volumes
+        for (const Inst& J : ctx->inst) any_corr |= J.has_corr;
+        if (ctx->has_stiff || any_corr) upload_stiffness(ctx, any_corr ? -1 : inst);
         upload_node_weights(ctx);
         if (I.osb) upload_osb(ctx);  // the weighted volumes scale with the node volume
         ctx->a_valid = false;
@@ -2531,6 +2590,7 @@ int pd_get_info(const pd_ctx* ctx, pd_info* info)
     double per_node = 24.0 + 4.0 * 24.0 + (ctx->scheme == PD_VELOCITY_VERLET ? 2.0 * 24.0 : 0.0) +
                       (ctx->precision == PD_FP32 ? 24.0 : 0.0);
     per_node += ctx->has_knode ? 16.0 : 0.0;  // per-node stiffness factors (own and neighbour weight)
+    per_node += ctx->corr_k ? 8.0 : 0.0;      // family volumes of the per-slot corrections
     info->model_bytes_per_step = static_cast<double>(nnz) * (4.0 + (ctx->has_stiff ? 8.0 : 0.0)) +
                                  static_cast<double>(n) * per_node;
     if (ctx->has_osb)  // two passes: the neighbour index twice; x and u read again, the node pair

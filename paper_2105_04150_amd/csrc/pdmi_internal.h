@@ -100,6 +100,15 @@ struct InstParams {
     int32_t pad_;
     double osb_a;    // state-based linear solid: 3K - 5G
     double osb_b;    // state-based linear solid: 15G
+    // stiffness corrections evaluated per slot (kernels with CORR): flags bit 0 conical
+    // profile 1 - |xi|/delta, bit 1 partial volume clamp((delta + dx/2 - |xi|)/dx, 0, 1),
+    // bit 2 surface factor 2 V0 / (V_i + V_j) over family volumes
+    double cr_idelta;  // 1/delta
+    double cr_pvhi;    // (delta + dx/2)/dx
+    double cr_idx;     // 1/dx
+    double cr_2v0;     // 2 V0
+    int32_t cr_flags;
+    int32_t pad2_;
 };
 
 // Constraint of one node: per component d, kind in bits 2d..2d+1 (0 free, 1 displacement,
@@ -135,6 +144,7 @@ struct StepArgs {
     double* smax;               // per slot: largest stretch beyond the elastic limit
     double2* osb;               // state-based model: per node {theta / m, 1 / m} (nn + 128 entries)
     const double* minv;         // state-based model: per node 1 / m (padding 0)
+    const double* cfv;          // corrections per slot: family volume per node (padding and the sentinel 1)
     const int64_t* slice_ptr;
     const int32_t* slice_T;
     const int32_t* slice_inst;
@@ -198,6 +208,7 @@ hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
 hipError_t launch_osb_dilation(const StepArgs& a, bool breaking, int split, hipStream_t s);
 hipError_t launch_osb_step(const StepArgs& a, int mode, int split, hipStream_t s);
 constexpr int kOsbPad = 128;    // spare pairs after the last node (the pass-2 range copy)
+constexpr int kCorrPad = 128;   // spare family volumes after the last node (the step kernels' copy window)
 
 hipError_t launch_advance(int64_t* step_base, int64_t by, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t value, hipStream_t s);

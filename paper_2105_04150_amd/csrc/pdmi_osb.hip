@@ -47,15 +47,6 @@ __device__ __forceinline__ double sqrt1p_minus1(double q)
     return q * rcp64(__builtin_fma(1.0 + q, r, 1.0));
 }
 
-// 1/x for the q of a slot: hardware estimate and one Newton step (relative error near
-// 1e-14, the level of the bond-based kernels' one-step 1/sqrt); neither pass needs
-// 1/|xi| itself.
-__device__ __forceinline__ double rcp64_1(double x)
-{
-    const double y = __builtin_amdgcn_rcp(x);
-    return __builtin_fma(__builtin_fma(-x, y, 1.0), y, y);
-}
-
 template <int PASS, int MODE, int S>
 __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* __restrict__ pieces,
                                                         const int32_t* __restrict__ slice_piece,
@@ -135,7 +126,7 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         const double z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
         const double tq = __builtin_fma(e2, z2, __builtin_fma(e1, z1, e0 * z0));
         const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
-        const double q = tq * rcp64_1(L2);
+        const double q = tq * rcp64_1(L2);  // neither pass needs 1/|xi| itself
         const bool brk = BREAK && live && !(e & kEntNoFail) && q >= P.q0;
         const bool alive = live && !brk;
         if (PASS == 0) {

@@ -151,6 +151,18 @@ __device__ double bond_weight(const StepArgs& A, const InstParams& P, int64_t ds
     return law_secant(L, sm);
 }
 
+// Stiffness-correction factor of a slot of reference length L (CORR kernels), in the
+// order profile, partial volume, surface factor; fvi, fvj the family volumes of the two
+// ends.  The flags are the instance's, the same for the whole wavefront.
+__device__ __forceinline__ double corr_factor(const InstParams& P, double L, double fvi, double fvj)
+{
+    double f = 1.0;
+    if (P.cr_flags & 1) f = fmax(__builtin_fma(-L, P.cr_idelta, 1.0), 0.0);
+    if (P.cr_flags & 2) f *= fmin(fmax(__builtin_fma(-L, P.cr_idx, P.cr_pvhi), 0.0), 1.0);
+    if (P.cr_flags & 4) f *= P.cr_2v0 * rcp64_1(fvi + fvj);
+    return f;
+}
+
 // Integration and boundary conditions of one node given its force density F (the tail
 // of every step kernel).  U is the node's displacement at the level the forces used.
 template <int MODE, bool FP32 = false>
@@ -403,16 +415,25 @@ __device__ __forceinline__ void wave_sync()
 // starts, which keeps the register count at four wavefronts per SIMD).  Rows are processed in pairs so
 // the LDS reads of one row overlap the arithmetic of the other; an odd last row runs
 // alone.  With S > 1 the partial forces meet in LDS in a fixed order (S > 1 fills the
-// chip on problems with fewer slices than SIMDs).
-template <bool FP32, int MODE, bool STIFF, bool VOLN, bool KNODE, int S, bool EXT>
+// chip on problems with fewer slices than SIMDs).  CORR (FP64, uniform volume, no stiffness
+// field): the stiffness corrections are formed per slot from the bond length and the two
+// family volumes (the neighbour's staged beside its record) instead of read from a
+// per-slot stiffness stream.
+template <bool FP32, int MODE, bool STIFF, bool VOLN, bool KNODE, int S, bool EXT, bool CORR = false>
 __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2* __restrict__ pieces,
                                                              const int32_t* __restrict__ slice_piece,
                                                              const int64_t* __restrict__ slice_ptr)
 {
     constexpr int kRecChunks = kStageChunks + 3;             // staged records, then the sentinel
     constexpr int kEntChunks = kPieceRows * kWave * 2 / 16;  // 16-byte chunks of entries
-    constexpr bool WSTAGE = VOLN || KNODE;  // a per-node weight is staged beside the records
-    constexpr int kVolWords = WSTAGE ? (kEntPad / 48 + 2) / 2 * 2 : 0;  // staged weights (doubles), sentinel last
+    // a per-node weight staged beside the records: through registers (VOLN, KNODE), or the
+    // family volumes copied straight to LDS (CORR)
+    constexpr bool WREG = VOLN || KNODE;
+    static_assert(!CORR || (!FP32 && !STIFF && !VOLN && !KNODE), "per-slot corrections: FP64, uniform stiffness and volume");
+    // staged weights (doubles): the range and the sentinel's slot; CORR copies a fixed window
+    // of 3 x 64 dwords (the family-volume buffer ends with spare entries)
+    constexpr int kVolWords = WREG ? (kEntPad / 48 + 2) / 2 * 2 : CORR ? 3 * kWave / 2 : 0;
+    static_assert(!CORR || kEntPad / 48 < kVolWords, "the sentinel's weight index lies in the copy");
     constexpr int kLds = kRecChunks + kEntChunks + kVolWords / 2;
     static_assert(kStageChunks == 4 * kWave && kEntChunks == kWave, "four record loads and one entry load");
     __shared__ double2 lds[S * kLds];
@@ -447,10 +468,14 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
 
     // sentinel record (padding entries point at it), volume 0
     if (lane < 3) lrec[kStageChunks + lane] = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
-    if (WSTAGE && lane == 0) lvol[kEntPad / 48] = 0.0;
-    // staged weight: V_j, or sqrt(k_j) V_j with per-node stiffness (times the own sqrt(k_i))
-    const double* __restrict__ wsrc = KNODE ? A.nw : A.vol;
+    // (CORR: the copied window fills the sentinel's slot with a positive family volume,
+    // which keeps 1/(V_i + V_j) finite on padding slots)
+    if (WREG && lane == 0) lvol[kEntPad / 48] = 0.0;
+    // staged weight: V_j, or sqrt(k_j) V_j with per-node stiffness (times the own sqrt(k_i)),
+    // or the family volume V_j of the surface correction
+    const double* __restrict__ wsrc = KNODE ? A.nw : CORR ? A.cfv : A.vol;
     const double ai = KNODE ? A.na[node] : 0.0;
+    const double fvi = CORR ? A.cfv[node] : 0.0;
 
     const int p0 = __builtin_amdgcn_readfirstlane(slice_piece[slice]);
     const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
@@ -473,7 +498,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     // (rows >= T are never read); volumes from clamped addresses.
     auto issue = [&](int p, int64_t e) {
         const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
-        if (WSTAGE) {
+        if (WREG) {
             const int len = m.y & 0xff;
             vlen = len;
             vs0 = wsrc[m.x + min(lane, len - 1)];
@@ -492,9 +517,16 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
         __builtin_amdgcn_global_load_lds(rs + 2 * kWave, (lds_ptr)(lrec + 2 * kWave), 16, 0, 0);
         __builtin_amdgcn_global_load_lds(rs + 3 * kWave, (lds_ptr)(lrec + 3 * kWave), 16, 0, 0);
         __builtin_amdgcn_global_load_lds(ent2 + e / 8 + lane, (lds_ptr)(lent), 16, 0, 0);
+        if (CORR) {
+            const float* ws = reinterpret_cast<const float*>(A.cfv + m.x) + lane;
+            float* wl = reinterpret_cast<float*>(lvol);
+            __builtin_amdgcn_global_load_lds(ws, (lds_ptr)(wl), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(ws + kWave, (lds_ptr)(wl + kWave), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(ws + 2 * kWave, (lds_ptr)(wl + 2 * kWave), 4, 0, 0);
+        }
     };
     auto commit = [&]() {
-        if (WSTAGE) {
+        if (WREG) {
             if (lane < vlen) lvol[lane] = vs0;
             if (lane + kWave < vlen) lvol[lane + kWave] = vs1;
         }
@@ -508,13 +540,18 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
         const double2 q2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
         double kv = cv;
         const uint32_t widx = (off * 0xAAABu) >> 21;  // off / 48
-        if (KNODE)
+        if (KNODE) {
             kv = ai * lvol[widx];
-        else if (STIFF || VOLN)
+        } else if (STIFF || VOLN) {
             kv = (STIFF ? kst : P.c) * (VOLN ? lvol[widx] : P.volume);
+        } else if (CORR) {  // the bond length as slot_force forms it (the compiler shares the work)
+            const double xa = q0.x - X0, xb = q0.y - X1, xc = q1.x - X2;
+            const double L2 = __builtin_fma(xc, xc, __builtin_fma(xb, xb, xa * xa));
+            kv = cv * corr_factor(P, L2 * rsq64<1>(L2), fvi, lvol[widx]);
+        }
         if (FP32)
             return slot_force32(live, breakable, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2,
-                                (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : cvf,
+                                (STIFF || VOLN || KNODE || CORR) ? static_cast<float>(kv) : cvf,
                                 q0f, Ff0, Ff1, Ff2, st32);
         return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2, st, sk);
     };
@@ -664,13 +701,13 @@ hipError_t launch_step_g(const StepArgs& a, int mode, bool stiff, hipStream_t s)
                 : launch_step_gsv<G, false, false, false, EXT>(a, mode, s);
 }
 
-template <bool FP32, bool STIFF, bool VOLN, bool KNODE, int S, bool EXT>
+template <bool FP32, bool STIFF, bool VOLN, bool KNODE, int S, bool EXT, bool CORR = false>
 hipError_t launch_staged_svs(const StepArgs& a, int mode, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>(a.nslices)), block(kWave * S);
     switch (mode) {
-#define PD_L(M)                                                                                             \
-    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN, KNODE, S, EXT>), grid, block, 0, s, a, a.pieces, \
+#define PD_L(M)                                                                                                   \
+    hipLaunchKernelGGL((step_staged<FP32, M, STIFF, VOLN, KNODE, S, EXT, CORR>), grid, block, 0, s, a, a.pieces, \
                        a.slice_piece, a.slice_ptr)
     case kModeEC: PD_L(kModeEC); break;
     case kModeVV: PD_L(kModeVV); break;
@@ -683,13 +720,13 @@ hipError_t launch_staged_svs(const StepArgs& a, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool FP32, bool STIFF, bool VOLN, bool KNODE, bool EXT>
+template <bool FP32, bool STIFF, bool VOLN, bool KNODE, bool EXT, bool CORR = false>
 hipError_t launch_staged_sv(const StepArgs& a, int mode, int split, hipStream_t s)
 {
     switch (split) {
-    case 1: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 1, EXT>(a, mode, s);
-    case 2: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 2, EXT>(a, mode, s);
-    case 4: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 4, EXT>(a, mode, s);
+    case 1: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 1, EXT, CORR>(a, mode, s);
+    case 2: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 2, EXT, CORR>(a, mode, s);
+    case 4: return launch_staged_svs<FP32, STIFF, VOLN, KNODE, 4, EXT, CORR>(a, mode, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -698,6 +735,8 @@ template <bool FP32, bool EXT>
 hipError_t launch_staged_n(const StepArgs& a, int mode, int split, hipStream_t s)
 {
     const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
+    if constexpr (!FP32)
+        if (a.cfv) return launch_staged_sv<false, false, false, false, EXT, true>(a, mode, split, s);  // corrections per slot
     if (a.nw) return launch_staged_sv<FP32, false, false, true, EXT>(a, mode, split, s);  // per-node stiffness
     if (stiff)
         return voln ? launch_staged_sv<FP32, true, true, false, EXT>(a, mode, split, s)

@@ -207,3 +207,33 @@ def test_cube100_full_size():
     g.step(w.steps)
     eu, ev, mism, ephi = compare(g, o, TOL_FP64, "state-based cube100 full size")
     assert np.abs(o.u).max() > 0 and mism == 0 and eu <= TOL_FP64
+
+
+@pytest.mark.parametrize("n", [1, 2, 65, 130])
+def test_small_and_ragged_problems(n):
+    """A single node (no bonds: m = 0, no dilation, no force), a pair, and node counts just
+    past a 64-node slice, with 1 and 4 wavefronts per slice."""
+    from paper_2105_04150_amd import Simulation
+    rng = np.random.default_rng(100 + n)
+    x = rng.uniform(0, 4e-3, size=(n, 3))
+    delta = 1.6e-3
+    K, G = 1.4e10, pi.shear_modulus(1.4e10, 0.2)
+    from oracle.oracle import family
+    rp, col = family(x, delta)
+    u0 = rng.normal(size=(n, 3)) * 1e-7
+    o = OracleSim(x, rp, col, c=0.0, s0=2e-3, rho=2400.0, dt=1e-7, vol=1e-9, state_based=(K, G))
+    o.set_state(u=u0)
+    o.run(50)
+    say(f"[run] state-based random cloud n={n} nnz={rp[-1]} broken {int(o.broken_mask.sum())}")
+    for split in (1, 4):
+        with Simulation() as g:
+            g.set_mapping("staged", split)
+            g.build_family(x, delta)
+            g.set_material(2400.0, 0.0, 2e-3, 0.0, 1e-9)
+            g.set_model("state_based", K, G)
+            g.set_state(u=u0)
+            g.step(50)
+            assert rel_err(g.u(), o.u) <= TOL_FP64 or np.abs(o.u - u0).max() == 0
+            assert np.array_equal(g.broken().astype(bool), o.broken_mask)
+            if n == 1:
+                assert np.array_equal(g.u(), u0) and g.dilation()[0] == 0.0
