@@ -100,3 +100,38 @@ def test_batch64_full_size_sampled():
             eu, ev, mism, ephi = compare(g, o, TOL_FP64, f"batch64 inst {b} {ws[b].dims}", inst=b)
             assert np.abs(o.u).max() > 0
             assert mism == 0 and eu <= TOL_FP64
+
+
+@pytest.mark.parametrize("law,lanes", [("brittle", 2), ("trilinear", 4)])
+def test_qs_beam_full_size(law, lanes):
+    """The quasi-static bend at the benchmark's size (175 x 50 x 50, 437,500 nodes, 50.6M
+    slots) with zones, damping and velocity Verlet, in the launch configurations of the
+    quasistatic and damage_law lines; a 60-step prefix with the ramp compressed into it so
+    that the load moves the beam by a resolvable amount."""
+    from paper_2105_04150_amd import simulation_for
+    w = pi.workload("qs_beam", steps=60, law=law)
+    say(f"[run] oracle qs_beam {law} full size, {w.steps} steps, {THREADS} threads")
+    o = oracle_run(w, w.steps, nthreads=THREADS)
+    g = simulation_for(w, lanes=lanes, mapping="staged", order="natural")
+    g.step(w.steps)
+    eu, ev, mism, ephi = compare(g, o, TOL_FP64, f"qs_beam {law} full size staged-{lanes}")
+    assert np.abs(o.u).max() > 0
+    assert mism == 0 and eu <= TOL_FP64 and ephi <= 1e-12
+    if law != "brittle":
+        assert np.array_equal(g.max_stretch() > 0, o.smax[: o.nnz] > 0)
+
+
+def test_cube100_corrections_full_size():
+    """The corrections line's problem (the 1M-node cube, conical profile at 5c, surface
+    correction, formed per slot in the kernel) over a short prefix."""
+    from paper_2105_04150_amd import simulation_for
+    w = pi.workload("cube100", steps=8)
+    w.order = "natural"
+    w.c = 5.0 * w.c
+    w.corrections = dict(micro="conical", surface=True, delta=w.horizon, dx=w.dx)
+    say(f"[run] oracle cube100 with corrections, {w.steps} steps, {THREADS} threads")
+    o = oracle_run(w, w.steps, nthreads=THREADS)
+    g = simulation_for(w, mapping="staged", order="natural")
+    g.step(w.steps)
+    eu, ev, mism, ephi = compare(g, o, TOL_FP64, "cube100 corrections full size")
+    assert np.abs(o.u).max() > 0 and mism == 0 and eu <= TOL_FP64
