@@ -132,6 +132,16 @@ int pd_build_family(pd_ctx *ctx, int64_t n, const double *coords, double horizon
 int pd_build_family_batch(pd_ctx *ctx, int32_t ninst, const int64_t *n,
                           const double *const *coords, const double *horizon, int order);
 
+/* A single-instance problem on a family the caller supplies (reuse of a family built
+ * earlier, or any other neighbourhood; Eq. family is the usual one): n nodes at coords
+ * (host, n x 3), CSR row_ptr (n+1 int64, row_ptr[0] = 0) and col (int32), rows strictly
+ * ascending, no self bond, every bond present in both directions (j in row i iff i in row
+ * j), no two nodes at the same place.  Replaces any earlier problem like
+ * pd_build_family; the family is kept as given (pd_get_family returns it).  Errors:
+ * PD_EINVAL (a rule above broken), PD_ERANGE (2^31 or more slots). */
+int pd_set_family(pd_ctx *ctx, int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col,
+                  int order);
+
 /* Number of instances of the current problem. */
 int pd_num_instances(const pd_ctx *ctx, int32_t *ninst);
 
@@ -304,6 +314,16 @@ int pd_get_step(const pd_ctx *ctx, int64_t *step);
 int pd_get_u(pd_ctx *ctx, int32_t inst, double *out);
 int pd_get_v(pd_ctx *ctx, int32_t inst, double *out);
 int pd_get_a(pd_ctx *ctx, int32_t inst, double *out);
+
+/* The same readouts into device memory (for example a torch tensor on this context's
+ * device): out is a device pointer to n x 3 (displacement, velocity) or n (damage)
+ * doubles, written in user order.  Stream-ordered on the context's stream and not
+ * synchronising: the values are there once that stream has reached this point (the
+ * non-finite check is left to pd_sync).  Errors: PD_EINVAL if out is not device memory of
+ * the context's device (the size cannot be checked: out must hold the values). */
+int pd_get_u_dev(pd_ctx *ctx, int32_t inst, double *out);
+int pd_get_v_dev(pd_ctx *ctx, int32_t inst, double *out);
+int pd_get_damage_dev(pd_ctx *ctx, int32_t inst, double *out);
 
 /* Local damage phi_i = 1 - sum_j (1 - d_ij) V_j / sum_j V_j over the initial family
  * (Sec. 2.2; d = 1 broken, d = 1 - secant ratio for a bond softened under a damage law,

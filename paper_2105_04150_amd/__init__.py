@@ -47,6 +47,20 @@ class Simulation:
     def build_family(self, coords, horizon, order="natural"):
         B.pd_build_family(self.ctx, coords, horizon, ORDERS.get(order, order))
 
+    def set_family(self, coords, row_ptr, col, order="natural"):
+        """A problem on the caller's CSR family (see pd_set_family)."""
+        B.pd_set_family(self.ctx, coords, row_ptr, col, ORDERS.get(order, order))
+
+    def u_dev(self, out, inst=0):
+        """Displacement into a float64 CUDA tensor (n x 3), on the library's stream."""
+        B.pd_get_u_dev(self.ctx, inst, out)
+
+    def v_dev(self, out, inst=0):
+        B.pd_get_v_dev(self.ctx, inst, out)
+
+    def damage_dev(self, out, inst=0):
+        B.pd_get_damage_dev(self.ctx, inst, out)
+
     def build_family_batch(self, coords_list, horizons, order="natural"):
         B.pd_build_family_batch(self.ctx, coords_list, horizons, ORDERS.get(order, order))
 

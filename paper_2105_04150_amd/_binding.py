@@ -24,7 +24,8 @@ PD_MAP_SLICED, PD_MAP_STAGED = 0, 1
 PD_MODEL_PMB, PD_MODEL_STATE_BASED = 0, 1
 
 SYMBOLS = [
-    "pd_create", "pd_destroy", "pd_last_error", "pd_build_family", "pd_build_family_batch",
+    "pd_create", "pd_destroy", "pd_last_error", "pd_build_family", "pd_build_family_batch", "pd_set_family",
+    "pd_get_u_dev", "pd_get_v_dev", "pd_get_damage_dev",
     "pd_num_instances", "pd_instance_size", "pd_get_family", "pd_set_material", "pd_set_bond_stiffness",
     "pd_set_node_stiffness",
     "pd_break_bonds", "pd_set_bcs", "pd_clear_bcs", "pd_set_bc_ramp", "pd_set_no_fail", "pd_get_force",
@@ -102,6 +103,8 @@ def load() -> C.CDLL:
         "pd_get_step": [P, P],
         "pd_get_u": [P, i32, P], "pd_get_v": [P, i32, P], "pd_get_a": [P, i32, P],
         "pd_get_damage": [P, i32, P],
+        "pd_set_family": [P, i64, P, P, P, C.c_int],
+        "pd_get_u_dev": [P, i32, P], "pd_get_v_dev": [P, i32, P], "pd_get_damage_dev": [P, i32, P],
         "pd_get_broken": [P, i32, P],
         "pd_set_state": [P, i32, P, P, P, P],
         "pd_set_step": [P, i64],
@@ -370,6 +373,38 @@ def pd_get_dilation(ctx, inst: int = 0) -> np.ndarray:
     out = np.zeros(_inst_n(ctx, inst))
     _check(ctx, load().pd_get_dilation(ctx, inst, _p(out)))
     return out
+
+
+def pd_set_family(ctx, coords, row_ptr, col, order: int = 0) -> None:
+    x = _f64(coords)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    if x.ndim != 2 or x.shape[1] != 3 or rp.shape != (x.shape[0] + 1,):
+        raise ValueError("coords must be n x 3 and row_ptr n + 1 long")
+    if cl.shape[0] < rp[-1]:
+        raise ValueError("col is shorter than row_ptr[n]")
+    _check(ctx, load().pd_set_family(ctx, x.shape[0], _p(x), _p(rp), _p(cl), int(order)))
+
+
+def _dev_out(out, n: int, ncomp: int) -> int:
+    """Device pointer of a contiguous float64 CUDA tensor of at least n * ncomp values."""
+    import torch
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float64 \
+            or not out.is_contiguous() or out.numel() < n * ncomp:
+        raise ValueError(f"out must be a contiguous float64 CUDA tensor of >= {n * ncomp} values")
+    return out.data_ptr()
+
+
+def pd_get_u_dev(ctx, inst: int, out) -> None:
+    _check(ctx, load().pd_get_u_dev(ctx, inst, C.c_void_p(_dev_out(out, _inst_n(ctx, inst), 3))))
+
+
+def pd_get_v_dev(ctx, inst: int, out) -> None:
+    _check(ctx, load().pd_get_v_dev(ctx, inst, C.c_void_p(_dev_out(out, _inst_n(ctx, inst), 3))))
+
+
+def pd_get_damage_dev(ctx, inst: int, out) -> None:
+    _check(ctx, load().pd_get_damage_dev(ctx, inst, C.c_void_p(_dev_out(out, _inst_n(ctx, inst), 1))))
 
 
 def pd_get_damage(ctx, inst: int = 0) -> np.ndarray:

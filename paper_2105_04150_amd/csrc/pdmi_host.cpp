@@ -97,6 +97,7 @@ struct Inst {
     bool has_corr = false;
     double corr_v0 = 0.0;                    // largest family volume (surface correction)
     std::vector<uint8_t> cls;                // user CSR order: law of every slot; empty = law 0
+    int64_t user_off = 0;                    // first entry of the instance in the device node map
     bool osb = false;                        // the state-based linear solid instead of the PMB
     double osb_K = 0.0, osb_G = 0.0;         // its bulk and shear moduli
     // device layout
@@ -149,6 +150,7 @@ struct pd_ctx {
     DevBuf laws, cls, smax;          // damage laws, per-slot law (several per instance), stretch state
     DevBuf osb, minv;                // state-based model: node pairs {theta/m, 1/m}, 1/m
     DevBuf cfv;                      // corrections per slot: family volume per node
+    DevBuf unode;                    // device node of every user node (instances concatenated)
 
     // adjoint: per-slot break steps (recorded by every step while allocated) and the
     // (u, v) checkpoints of the last recorded forward run
@@ -1318,6 +1320,15 @@ void build_layout(pd_ctx* ctx, const HostState* S)
         const double* sm = (S && !S->smax[ii].empty()) ? S->smax[ii].data() : nullptr;
         upload_col(ctx, I, S ? S->broken[ii].data() : nullptr, false, sm);
     }
+    {  // device node of every user node, for readouts into device memory
+        std::vector<int64_t> dn;
+        for (auto& I : ctx->inst) {
+            I.user_off = static_cast<int64_t>(dn.size());
+            for (int64_t u = 0; u < I.n; ++u) dn.push_back(I.node_off + I.iperm[u]);
+        }
+        ctx->unode.alloc(dn.size() * sizeof(int64_t));
+        upload(ctx->unode, dn.data(), dn.size() * sizeof(int64_t), 0, ctx->stream);
+    }
     ctx->cur = 0;
     ctx->vv_ahead = false;
     ctx->built = true;
@@ -1333,8 +1344,47 @@ void validate_coords(int64_t n, const double* coords, double horizon)
         if (!std::isfinite(coords[i])) fail(PD_EINVAL, "coords must be finite");
 }
 
+// A caller's family (pd_set_family): CSR with rows strictly ascending, no self bonds,
+// every bond present in both directions, no zero-length bond.  Returns the longest bond.
+double validate_family(int64_t n, const double* x, const int64_t* row_ptr, const int32_t* col)
+{
+    if (!row_ptr || row_ptr[0] != 0) fail(PD_EINVAL, "row_ptr must start at 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) fail(PD_EINVAL, "row_ptr must be non-decreasing");
+    if (row_ptr[n] >= std::numeric_limits<int32_t>::max()) fail(PD_ERANGE, "family has 2^31 or more slots");
+    if (row_ptr[n] > 0 && !col) fail(PD_EINVAL, "col is NULL");
+    std::atomic<int> bad{0};
+    std::vector<double> longest(static_cast<size_t>(n), 0.0);
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            for (int64_t b = row_ptr[i]; b < row_ptr[i + 1]; ++b) {
+                const int64_t j = col[b];
+                if (j < 0 || j >= n || j == i) { bad = 1; return; }
+                if (b > row_ptr[i] && col[b - 1] >= col[b]) { bad = 2; return; }
+                if (!std::binary_search(col + row_ptr[j], col + row_ptr[j + 1], static_cast<int32_t>(i))) {
+                    bad = 3;
+                    return;
+                }
+                double L2 = 0.0;
+                for (int d = 0; d < 3; ++d) L2 += (x[3 * j + d] - x[3 * i + d]) * (x[3 * j + d] - x[3 * i + d]);
+                if (!(L2 > 0.0)) { bad = 4; return; }
+                longest[i] = std::max(longest[i], std::sqrt(L2));
+            }
+    });
+    switch (bad.load()) {
+    case 1: fail(PD_EINVAL, "family: neighbour id out of range or a self bond");
+    case 2: fail(PD_EINVAL, "family: rows must be strictly ascending");
+    case 3: fail(PD_EINVAL, "family: every bond must appear in both directions");
+    case 4: fail(PD_EINVAL, "family: zero-length bond (coincident nodes)");
+    default: break;
+    }
+    double h = 0.0;
+    for (double v : longest) h = std::max(h, v);
+    return h > 0.0 ? h : 1.0;
+}
+
 void new_problem(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* const* coords, const double* horizon,
-                 int order)
+                 int order, const int64_t* user_row_ptr = nullptr, const int32_t* user_col = nullptr)
 {
     if (order != PD_ORDER_NATURAL && order != PD_ORDER_MORTON && order != PD_ORDER_AUTO)
         fail(PD_EINVAL, "unknown node order");
@@ -1347,7 +1397,12 @@ void new_problem(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* con
         I.n = n[b];
         I.horizon = horizon[b];
         I.x.assign(coords[b], coords[b] + 3 * n[b]);
-        family_search(I.n, I.x.data(), I.horizon, I.row_ptr, I.col);
+        if (user_row_ptr) {  // the caller's family (one instance), validated already
+            I.row_ptr.assign(user_row_ptr, user_row_ptr + n[b] + 1);
+            I.col.assign(user_col, user_col + user_row_ptr[n[b]]);
+        } else {
+            family_search(I.n, I.x.data(), I.horizon, I.row_ptr, I.col);
+        }
         I.nnz = I.row_ptr[I.n];
         I.bc_kind.assign(static_cast<size_t>(3 * I.n), 0);
         I.bc_sched.assign(static_cast<size_t>(3 * I.n), 0);
@@ -1559,6 +1614,71 @@ void launch_ec(pd_ctx* ctx, const StepArgs& A)
                   "step kernel launch");
 }
 
+// Local damage of every device node into ctx->phi (stream-ordered).
+void launch_damage_now(pd_ctx* ctx)
+{
+    DamageArgs D{};
+    D.col = ctx->col.as<int32_t>();
+    D.sentinel = static_cast<int32_t>(ctx->nn);
+    D.vol = ctx->has_vol ? ctx->vol.as<double>() : nullptr;
+    D.slice_ptr = ctx->slice_ptr.as<int64_t>();
+    D.slice_T = ctx->slice_T.as<int32_t>();
+    D.slice_inst = ctx->slice_inst.as<int32_t>();
+    D.params = ctx->params.as<InstParams>();
+    D.phi = ctx->phi.as<double>();
+    D.nslices = ctx->nslices;
+    D.pieces = ctx->pieces.as<int2>();
+    D.slice_piece = ctx->slice_piece.as<int32_t>();
+    D.ent = ctx->ent.as<uint16_t>();
+    D.laws = ctx->has_laws ? ctx->laws.as<LawRec>() : nullptr;
+    D.cls = ctx->cls.p ? ctx->cls.as<uint8_t>() : nullptr;
+    D.smax = ctx->has_laws ? ctx->smax.as<double>() : nullptr;
+    if (ctx->mapping == PD_MAP_STAGED)
+        hip_check(launch_damage_staged(D, ctx->stream), "damage launch");
+    else
+        hip_check(launch_damage(D, ctx->lanes, ctx->stream), "damage launch");
+}
+
+// A caller's device buffer for a readout: device memory of this context's device.
+void require_device_buffer(const pd_ctx* ctx, const void* p)
+{
+    if (!p) fail(PD_EINVAL, "out is NULL");
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();  // clear the error an unknown pointer leaves
+        fail(PD_EINVAL, "out is not device memory");
+    }
+    if (at.type != hipMemoryTypeDevice || at.device != ctx->device)
+        fail(PD_EINVAL, "out is not device memory of the context's device");
+}
+
+// Readouts into device memory (user order, stream-ordered on the context's stream):
+// what = 0 displacement, 1 velocity, 2 damage.
+int get_nodes_dev(pd_ctx* ctx, int32_t inst, double* out, int what)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        require_device_buffer(ctx, out);
+        set_device(ctx);
+        const int64_t* dn = ctx->unode.as<int64_t>() + I.user_off;
+        const int64_t nn = ctx->nn;
+        hipError_t e;
+        if (what == 0) {
+            if (fp32(ctx))  // the f64 master displacement, SoA
+                e = launch_export_nodes(ctx->um[ctx->cur].as<double>(), 1, nn, 0, dn, I.n, 3, out, ctx->stream);
+            else            // records: x then u, 6 doubles per node
+                e = launch_export_nodes(ctx->rec[ctx->cur].as<double>(), 6, 1, 3, dn, I.n, 3, out, ctx->stream);
+        } else if (what == 1) {
+            e = launch_export_nodes(ctx->v.as<double>(), 1, nn, 0, dn, I.n, 3, out, ctx->stream);
+        } else {
+            launch_damage_now(ctx);
+            e = launch_export_nodes(ctx->phi.as<double>(), 1, 0, 0, dn, I.n, 1, out, ctx->stream);
+        }
+        hip_check(e, "readout launch");
+    });
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1619,6 +1739,17 @@ int pd_build_family(pd_ctx* ctx, int64_t n, const double* coords, double horizon
 {
     if (!ctx) return PD_EINVAL;
     return guarded(ctx, [&] { new_problem(ctx, 1, &n, &coords, &horizon, order); });
+}
+
+int pd_set_family(pd_ctx* ctx, int64_t n, const double* coords, const int64_t* row_ptr, const int32_t* col,
+                  int order)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        validate_coords(n, coords, 1.0);
+        const double longest = validate_family(n, coords, row_ptr, col);
+        new_problem(ctx, 1, &n, &coords, &longest, order, row_ptr, col);
+    });
 }
 
 int pd_build_family_batch(pd_ctx* ctx, int32_t ninst, const int64_t* n, const double* const* coords,
@@ -2067,26 +2198,7 @@ int pd_get_damage(pd_ctx* ctx, int32_t inst, double* out)
         const Inst& I = instance(ctx, inst);
         if (!out) fail(PD_EINVAL, "out is NULL");
         set_device(ctx);
-        DamageArgs D{};
-        D.col = ctx->col.as<int32_t>();
-        D.sentinel = static_cast<int32_t>(ctx->nn);
-        D.vol = ctx->has_vol ? ctx->vol.as<double>() : nullptr;
-        D.slice_ptr = ctx->slice_ptr.as<int64_t>();
-        D.slice_T = ctx->slice_T.as<int32_t>();
-        D.slice_inst = ctx->slice_inst.as<int32_t>();
-        D.params = ctx->params.as<InstParams>();
-        D.phi = ctx->phi.as<double>();
-        D.nslices = ctx->nslices;
-        D.pieces = ctx->pieces.as<int2>();
-        D.slice_piece = ctx->slice_piece.as<int32_t>();
-        D.ent = ctx->ent.as<uint16_t>();
-        D.laws = ctx->has_laws ? ctx->laws.as<LawRec>() : nullptr;
-        D.cls = ctx->cls.p ? ctx->cls.as<uint8_t>() : nullptr;
-        D.smax = ctx->has_laws ? ctx->smax.as<double>() : nullptr;
-        if (ctx->mapping == PD_MAP_STAGED)
-            hip_check(launch_damage_staged(D, ctx->stream), "damage launch");
-        else
-            hip_check(launch_damage(D, ctx->lanes, ctx->stream), "damage launch");
+        launch_damage_now(ctx);
         std::vector<double> h(static_cast<size_t>(I.n_pad));
         download(h.data(), ctx->phi, h.size() * 8, I.node_off * 8, ctx->stream);
         sync(ctx);
@@ -2140,6 +2252,10 @@ int pd_get_dilation(pd_ctx* ctx, int32_t inst, double* out)
             if (I.perm[l] >= 0) out[I.perm[l]] = h[2 * l + 1] > 0.0 ? h[2 * l] / h[2 * l + 1] : 0.0;
     });
 }
+
+int pd_get_u_dev(pd_ctx* ctx, int32_t inst, double* out) { return get_nodes_dev(ctx, inst, out, 0); }
+int pd_get_v_dev(pd_ctx* ctx, int32_t inst, double* out) { return get_nodes_dev(ctx, inst, out, 1); }
+int pd_get_damage_dev(pd_ctx* ctx, int32_t inst, double* out) { return get_nodes_dev(ctx, inst, out, 2); }
 
 int pd_get_broken(pd_ctx* ctx, int32_t inst, uint8_t* out)
 {

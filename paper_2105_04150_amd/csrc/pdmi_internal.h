@@ -211,6 +211,9 @@ constexpr int kOsbPad = 128;    // spare pairs after the last node (the pass-2 r
 constexpr int kCorrPad = 128;   // spare family volumes after the last node (the step kernels' copy window)
 
 hipError_t launch_advance(int64_t* step_base, int64_t by, hipStream_t s);
+// out[i * ncomp + d] = src[off + dnode[i] * snode + d * scomp], i < n (readout to device memory)
+hipError_t launch_export_nodes(const double* src, int64_t snode, int64_t scomp, int64_t off, const int64_t* dnode,
+                               int64_t n, int ncomp, double* out, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t value, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint (Euler-Cromer)

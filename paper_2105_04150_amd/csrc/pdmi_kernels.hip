@@ -144,7 +144,29 @@ __global__ __launch_bounds__(kBlock) void set_sum_kernel(const double* __restric
     if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Device-to-device readout in the caller's order: out[i * ncomp + d] =
+// src[off + dnode[i] * snode + d * scomp] for i < n (dnode: device node of user node i).
+__global__ __launch_bounds__(kBlock) void export_nodes_kernel(const double* __restrict__ src, int64_t snode,
+                                                             int64_t scomp, int64_t off,
+                                                             const int64_t* __restrict__ dnode, int64_t n,
+                                                             int ncomp, double* __restrict__ out)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t dn = dnode[i];
+    for (int d = 0; d < ncomp; ++d) out[i * ncomp + d] = src[off + dn * snode + d * scomp];
+}
+
 }  // namespace
+
+hipError_t launch_export_nodes(const double* src, int64_t snode, int64_t scomp, int64_t off, const int64_t* dnode,
+                               int64_t n, int ncomp, double* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(export_nodes_kernel, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, src, snode, scomp, off, dnode, n, ncomp, out);
+    return hipGetLastError();
+}
 
 bool lanes_supported(int lanes) { return lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64; }
 
