@@ -11,7 +11,7 @@ import pytest
 
 import pd_inputs as pi
 from oracle.oracle import from_workload
-from parity import TOL_FP32, TOL_FP64, compare, oracle_run, say
+from parity import TOL_FP32, TOL_FP64, compare, oracle_run, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -170,3 +170,33 @@ def test_correction_arguments():
         g.adj_forward(5, 5)
     g.set_corrections(None)
     g.step(10)
+
+
+@pytest.mark.parametrize("n", [1, 2, 65, 130])
+def test_small_and_ragged_problems(oracle_lib, n):
+    """A single node (no bonds, family volume 0), a pair, and node counts just past a
+    64-node slice, with every correction, per slot (staged) and folded (sliced)."""
+    from paper_2105_04150_amd import Simulation
+    rng = np.random.default_rng(200 + n)
+    x = rng.uniform(0, 4e-3, size=(n, 3))
+    delta, dx = 1.6e-3, 1e-3
+    corr = dict(micro="conical", partial_volumes=True, surface=True, delta=delta - 0.5 * dx, dx=dx)
+    rp, col = oracle_lib.family(x, delta)
+    u0 = rng.normal(size=(n, 3)) * 1e-7
+    o = oracle_lib.OracleSim(x, rp, col, c=5e20, s0=2e-3, rho=2400.0, dt=1e-7, vol=1e-9, corrections=corr)
+    o.set_state(u=u0)
+    o.run(50)
+    for mapping, lanes in (("staged", 1), ("staged", 4), ("sliced", 4)):
+        with Simulation() as g:
+            g.set_mapping(mapping, lanes)
+            g.build_family(x, delta)
+            g.set_material(2400.0, 5e20, 2e-3, 0.0, 1e-9)
+            g.set_corrections(corr)
+            g.set_state(u=u0)
+            g.step(50)
+            assert np.all(np.isfinite(g.u()))
+            if n == 1:
+                assert np.array_equal(g.u(), u0)
+            else:
+                assert rel_err(g.u(), o.u) <= TOL_FP64
+            assert np.array_equal(g.broken().astype(bool), o.broken_mask)
