@@ -101,6 +101,13 @@ def adjoint_extra(P, pi, sync, steps: int, ckpt: int):
     t_fwd = _timed(lambda: (sim.adj_forward(steps, ckpt), sim.sync()), sync)
     dldu = 2.0 * (sim.u()[sensors] - target)
     t_bwd = _timed(lambda: sim.adj_backward(sensors, dldu), sync)
+    # the whole trajectory kept in HBM (a checkpoint at every level: no recompute)
+    sim.set_state(u=z, v=z, a=z, broken=np.zeros(nnz, dtype=np.uint8))
+    sim.set_step(0)
+    t_fwd1 = _timed(lambda: (sim.adj_forward(steps, 1), sim.sync()), sync)
+    dldu1 = 2.0 * (sim.u()[sensors] - target)
+    t_bwd1 = _timed(lambda: sim.adj_backward(sensors, dldu1), sync)
+    traj_bytes = steps * info["n_nodes_dev"] * 48
     mapping = "staged" if info["mapping"] == P.PD_MAP_STAGED else f"sliced-{info['lanes_per_node']}"
     sim.close()
     plain = nnz * steps / t_plain
@@ -111,7 +118,10 @@ def adjoint_extra(P, pi, sync, steps: int, ckpt: int):
             "forward_recording_ms": t_fwd * 1e3, "backward_ms": t_bwd * 1e3,
             "adjoint_rate": nnz * steps / (t_fwd + t_bwd),
             "adjoint_vs_plain": (nnz * steps / (t_fwd + t_bwd)) / plain,
-            "backward_vs_plain_step": t_plain / t_bwd}
+            "backward_vs_plain_step": t_plain / t_bwd,
+            "full_trajectory": {"trajectory_bytes": traj_bytes, "forward_recording_ms": t_fwd1 * 1e3,
+                                "backward_ms": t_bwd1 * 1e3, "adjoint_rate": nnz * steps / (t_fwd1 + t_bwd1),
+                                "adjoint_vs_plain": (nnz * steps / (t_fwd1 + t_bwd1)) / plain}}
 
 
 def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):

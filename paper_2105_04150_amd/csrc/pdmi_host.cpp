@@ -2513,8 +2513,35 @@ int pd_adj_forward(pd_ctx* ctx, int64_t nsteps, int32_t ckpt_every)
         const int64_t C = (nsteps + ckpt_every - 1) / ckpt_every;
         // with a checkpoint at every level nothing is recomputed and v is not needed
         const size_t stride = Rb + (ckpt_every > 1 ? Vb : 0);
-        ctx->ck.alloc(static_cast<size_t>(C) * stride);
         const int64_t step0 = ctx->step;
+        if (ckpt_every == 1) {
+            // the whole trajectory: step k reads level k of the tape and writes level k+1
+            // straight into it (every level first gets the positions, sentinel and spare
+            // records); the last level then becomes the current state
+            ctx->ck.alloc(static_cast<size_t>(nsteps + 1) * Rb);
+            char* tape = ctx->ck.as<char>();
+            for (int64_t k = 0; k <= nsteps; ++k)
+                hip_check(hipMemcpyAsync(tape + static_cast<size_t>(k) * Rb, ctx->rec[ctx->cur].p, Rb,
+                                         hipMemcpyDeviceToDevice, ctx->stream),
+                          "trajectory init");
+            for (int64_t k = 0; k < nsteps; ++k) {
+                StepArgs A = step_args(ctx, ctx->cur, 1 - ctx->cur, k);
+                A.rec_in = reinterpret_cast<const double*>(tape + static_cast<size_t>(k) * Rb);
+                A.rec_out = reinterpret_cast<double*>(tape + static_cast<size_t>(k + 1) * Rb);
+                launch_ec(ctx, A);
+            }
+            hip_check(launch_advance(ctx->step_base.as<int64_t>(), nsteps, ctx->stream), "advance launch");
+            hip_check(hipMemcpyAsync(ctx->rec[ctx->cur].p, tape + static_cast<size_t>(nsteps) * Rb, Rb,
+                                     hipMemcpyDeviceToDevice, ctx->stream),
+                      "trajectory end");
+            ctx->step += nsteps;
+            ctx->tape_valid = true;
+            ctx->tape_step0 = step0;
+            ctx->tape_nsteps = nsteps;
+            ctx->tape_every = 1;
+            return;
+        }
+        ctx->ck.alloc(static_cast<size_t>(C) * stride);
         for (int64_t c = 0; c < C; ++c) {
             char* dst = ctx->ck.as<char>() + static_cast<size_t>(c) * stride;
             hip_check(hipMemcpyAsync(dst, ctx->rec[ctx->cur].p, Rb, hipMemcpyDeviceToDevice, ctx->stream),
