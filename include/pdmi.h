@@ -237,7 +237,7 @@ int pd_clear_damage_laws(pd_ctx *ctx, int32_t inst);
  * neighbour's cell inside the horizon; build the family with horizon delta + dx/2 to
  * include the cut cells); the volume-method surface correction lambda_ij = 2 V0 /
  * (V_i + V_j), V_i = sum over node i's family of beta_ij V_j and V0 the largest V_i (a
- * complete family).  The FP64 build in the staged mapping forms the factors per slot from
+ * complete family).  The staged mapping (FP64 and FP32 builds) forms the factors per slot from
  * the bond length and the two family volumes when no instance has a stiffness field or
  * per-node volumes; otherwise they are formed once on the host and the step reads the
  * corrected stiffness per slot.  Both forms give the same results up to rounding. */

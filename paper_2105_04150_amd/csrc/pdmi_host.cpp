@@ -595,11 +595,11 @@ double corrected(const Inst& I, const CorrectionTable& T, int64_t i, int64_t j, 
 }
 
 // Corrections are formed per slot in the step kernel (no per-slot stiffness stream) when
-// the FP64 staged kernels run and no instance has a stiffness field or per-node volumes;
+// the staged kernels run and no instance has a stiffness field or per-node volumes;
 // otherwise they are folded into the per-slot stiffness.
 bool corrections_in_kernel(const pd_ctx* ctx)
 {
-    if (fp32(ctx) || ctx->mapping != PD_MAP_STAGED) return false;
+    if (ctx->mapping != PD_MAP_STAGED) return false;
     bool any = false;
     for (const Inst& I : ctx->inst) {
         if (!I.kslot.empty() || !I.knode.empty() || !I.vols.empty()) return false;

@@ -415,7 +415,7 @@ __device__ __forceinline__ void wave_sync()
 // starts, which keeps the register count at four wavefronts per SIMD).  Rows are processed in pairs so
 // the LDS reads of one row overlap the arithmetic of the other; an odd last row runs
 // alone.  With S > 1 the partial forces meet in LDS in a fixed order (S > 1 fills the
-// chip on problems with fewer slices than SIMDs).  CORR (FP64, uniform volume, no stiffness
+// chip on problems with fewer slices than SIMDs).  CORR (uniform volume, no stiffness
 // field): the stiffness corrections are formed per slot from the bond length and the two
 // family volumes (the neighbour's staged beside its record) instead of read from a
 // per-slot stiffness stream.
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     // a per-node weight staged beside the records: through registers (VOLN, KNODE), or the
     // family volumes copied straight to LDS (CORR)
     constexpr bool WREG = VOLN || KNODE;
-    static_assert(!CORR || (!FP32 && !STIFF && !VOLN && !KNODE), "per-slot corrections: FP64, uniform stiffness and volume");
+    static_assert(!CORR || (!STIFF && !VOLN && !KNODE), "per-slot corrections: uniform stiffness and volume");
     // staged weights (doubles): the range and the sentinel's slot; CORR copies a fixed window
     // of 3 x 64 dwords (the family-volume buffer ends with spare entries)
     constexpr int kVolWords = WREG ? (kEntPad / 48 + 2) / 2 * 2 : CORR ? 3 * kWave / 2 : 0;
@@ -476,6 +476,9 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     const double* __restrict__ wsrc = KNODE ? A.nw : CORR ? A.cfv : A.vol;
     const double ai = KNODE ? A.na[node] : 0.0;
     const double fvi = CORR ? A.cfv[node] : 0.0;
+    // FP32 build: the correction constants in single precision, once
+    const float cr_id = static_cast<float>(P.cr_idelta), cr_ix = static_cast<float>(P.cr_idx),
+                cr_hi = static_cast<float>(P.cr_pvhi), cr_2v0 = static_cast<float>(P.cr_2v0);
 
     const int p0 = __builtin_amdgcn_readfirstlane(slice_piece[slice]);
     const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
@@ -544,14 +547,26 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             kv = ai * lvol[widx];
         } else if (STIFF || VOLN) {
             kv = (STIFF ? kst : P.c) * (VOLN ? lvol[widx] : P.volume);
-        } else if (CORR) {  // the bond length as slot_force forms it (the compiler shares the work)
+        } else if (CORR && !FP32) {  // the bond length as slot_force forms it (the compiler shares the work)
             const double xa = q0.x - X0, xb = q0.y - X1, xc = q1.x - X2;
             const double L2 = __builtin_fma(xc, xc, __builtin_fma(xb, xb, xa * xa));
             kv = cv * corr_factor(P, L2 * rsq64<1>(L2), fvi, lvol[widx]);
         }
+        float kvf = cvf;
+        if (CORR && FP32) {  // the same factors in single precision, from slot_force32's bond vector
+            const float xa = static_cast<float>(q0.x - X0), xb = static_cast<float>(q0.y - X1),
+                        xc = static_cast<float>(q1.x - X2);
+            const float L2 = __builtin_fmaf(xc, xc, __builtin_fmaf(xb, xb, xa * xa));
+            const float L = L2 * __builtin_amdgcn_rsqf(L2);
+            float f = 1.0f;
+            if (P.cr_flags & 1) f = fmaxf(__builtin_fmaf(-L, cr_id, 1.0f), 0.0f);
+            if (P.cr_flags & 2) f *= fminf(fmaxf(__builtin_fmaf(-L, cr_ix, cr_hi), 0.0f), 1.0f);
+            if (P.cr_flags & 4) f *= cr_2v0 * __builtin_amdgcn_rcpf(static_cast<float>(fvi + lvol[widx]));
+            kvf = cvf * f;
+        }
         if (FP32)
             return slot_force32(live, breakable, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2,
-                                (STIFF || VOLN || KNODE || CORR) ? static_cast<float>(kv) : cvf,
+                                (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : kvf,
                                 q0f, Ff0, Ff1, Ff2, st32);
         return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2, st, sk);
     };
@@ -735,8 +750,7 @@ template <bool FP32, bool EXT>
 hipError_t launch_staged_n(const StepArgs& a, int mode, int split, hipStream_t s)
 {
     const bool stiff = a.kslot != nullptr, voln = a.vol != nullptr;
-    if constexpr (!FP32)
-        if (a.cfv) return launch_staged_sv<false, false, false, false, EXT, true>(a, mode, split, s);  // corrections per slot
+    if (a.cfv) return launch_staged_sv<FP32, false, false, false, EXT, true>(a, mode, split, s);  // corrections per slot
     if (a.nw) return launch_staged_sv<FP32, false, false, true, EXT>(a, mode, split, s);  // per-node stiffness
     if (stiff)
         return voln ? launch_staged_sv<FP32, true, true, false, EXT>(a, mode, split, s)
