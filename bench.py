@@ -313,11 +313,20 @@ def state_based_extra(P, pi, sync, workload: str, steps: int, plain_ms: float):
     dev_ms = sim.last_step_ms() / steps
     sim.close()
     nnz = info["n_slots"]
+    # the FP32 build of the same step
+    sim = P.simulation_for(w, precision=P.PD_FP32, mapping="staged")
+    sim.prepare()
+    sim.step(20)
+    sim.sync()
+    t32 = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    dev32 = sim.last_step_ms() / steps
+    sim.close()
     return {"config": f"{workload}, state-based linear solid (K, nu = 0.2), staged mapping, natural order",
             "steps": steps, "value": nnz * steps / t, "unit": "bond-updates/s", "step_ms": dev_ms,
             "model_bytes_per_step": info["model_bytes_per_step"],
             "hbm_frac": info["model_bytes_per_step"] / (dev_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
-            "vs_plain_step": plain_ms / dev_ms}
+            "vs_plain_step": plain_ms / dev_ms,
+            "fp32": {"value": nnz * steps / t32, "step_ms": dev32, "vs_fp64": dev_ms / dev32}}
 
 
 def fp32_extra(P, pi, sync, workload: str, steps: int):

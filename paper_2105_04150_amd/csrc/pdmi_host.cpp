@@ -774,7 +774,7 @@ void upload_osb(pd_ctx* ctx)
 }
 
 // What the state-based kernels support: every instance on the model, the staged layout,
-// FP64, uniform volumes, the constant micromodulus replaced by (K, G): no stiffness
+// uniform volumes, the constant micromodulus replaced by (K, G): no stiffness
 // fields, damage laws or corrections.
 void osb_checks(const pd_ctx* ctx)
 {
@@ -785,7 +785,6 @@ void osb_checks(const pd_ctx* ctx)
         if (I.has_corr) fail(PD_EINVAL, "the state-based model takes no stiffness corrections");
     }
     if (ctx->mapping != PD_MAP_STAGED) fail(PD_EINVAL, "the state-based model runs in the staged mapping");
-    if (fp32(ctx)) fail(PD_EINVAL, "the state-based model runs in the FP64 build");
     if (ctx->has_vol) fail(PD_EINVAL, "the state-based model takes a uniform node volume per instance");
     if (ctx->has_stiff || ctx->has_knode) fail(PD_EINVAL, "the state-based model takes no stiffness field");
 }
@@ -1476,7 +1475,7 @@ void launch_one(pd_ctx* ctx, int mode, int in, int out, int64_t step_local)
 {
     const StepArgs A = step_args(ctx, in, out, step_local);
     if (ctx->has_osb)
-        hip_check(launch_osb_step(A, mode, ctx->lanes, ctx->stream), "state-based step launch");
+        hip_check(launch_osb_step(A, mode, fp32(ctx), ctx->lanes, ctx->stream), "state-based step launch");
     else if (ctx->mapping == PD_MAP_STAGED)
         hip_check(launch_step_staged(A, mode, fp32(ctx), ctx->lanes, ext_kernels(ctx), ctx->stream),
                   "step kernel launch");
@@ -2218,7 +2217,6 @@ int pd_set_model(pd_ctx* ctx, int32_t inst, int model, double K, double G)
             if (!(G >= 0.0) || !std::isfinite(G)) fail(PD_EINVAL, "G must be >= 0 and finite");
             if (ctx->mapping != PD_MAP_STAGED)
                 fail(PD_EINVAL, "the state-based model runs in the staged mapping: call pd_set_mapping first");
-            if (fp32(ctx)) fail(PD_EINVAL, "the state-based model runs in the FP64 build");
         }
         set_device(ctx);
         I.osb = model == PD_MODEL_STATE_BASED;
@@ -2243,7 +2241,8 @@ int pd_get_dilation(pd_ctx* ctx, int32_t inst, double* out)
         osb_checks(ctx);
         set_device(ctx);
         // the dilation pass at the current level, breaking nothing
-        hip_check(launch_osb_dilation(step_args(ctx, ctx->cur, 1 - ctx->cur, 0), false, ctx->lanes, ctx->stream),
+        hip_check(launch_osb_dilation(step_args(ctx, ctx->cur, 1 - ctx->cur, 0), false, fp32(ctx), ctx->lanes,
+                                      ctx->stream),
                   "dilation launch");
         std::vector<double> h(static_cast<size_t>(2 * I.n_pad));
         download(h.data(), ctx->osb, h.size() * 8, I.node_off * 16, ctx->stream);

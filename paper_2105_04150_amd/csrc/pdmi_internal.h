@@ -202,11 +202,11 @@ hipError_t launch_set_sum(const double* field, int64_t snode, int64_t scomp, con
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
 
-// state-based linear solid (staged layout, FP64): the dilation pass alone (breaking or a
-// force evaluation), and a whole step (dilation pass, then the force pass with the
-// integrator of `mode`)
-hipError_t launch_osb_dilation(const StepArgs& a, bool breaking, int split, hipStream_t s);
-hipError_t launch_osb_step(const StepArgs& a, int mode, int split, hipStream_t s);
+// state-based linear solid (staged layout, FP64 or FP32 bond arithmetic): the dilation
+// pass alone (breaking or a force evaluation), and a whole step (dilation pass, then the
+// force pass with the integrator of `mode`)
+hipError_t launch_osb_dilation(const StepArgs& a, bool breaking, bool fp32, int split, hipStream_t s);
+hipError_t launch_osb_step(const StepArgs& a, int mode, bool fp32, int split, hipStream_t s);
 constexpr int kOsbPad = 128;    // spare pairs after the last node (the pass-2 range copy)
 constexpr int kCorrPad = 128;   // spare family volumes after the last node (the step kernels' copy window)
 

@@ -17,7 +17,9 @@
 // Both passes use the staged mapping of the bond-based kernels: a slice of 64 nodes, one
 // lane per node, the node records of each piece's range and its slot entries copied
 // straight into LDS; pass 2 copies the range's node pairs beside them.  Influence function
-// 1, uniform node volume per instance, FP64.
+// 1, uniform node volume per instance.  FP64, or the FP32 build: bond arithmetic in
+// single precision from the f32 displacements of the records and the f64 coordinates, the
+// node pairs and the integration (f64 master displacement) as in FP64.
 //
 // Per slot: xi, eta and q = (|y|^2 - |xi|^2)/|xi|^2 as in the bond-based kernels.  The
 // dilation pass needs the stretch s = sqrt(1+q) - 1, the force pass g = 1 - (1+q)^(-1/2)
@@ -47,7 +49,32 @@ __device__ __forceinline__ double sqrt1p_minus1(double q)
     return q * rcp64(__builtin_fma(1.0 + q, r, 1.0));
 }
 
-template <int PASS, int MODE, int S>
+// The FP32 build's sqrt(1+q) - 1: series q/2 - q^2/8 + q^3/16 - 5q^4/128 (the next term is
+// below 2e-11 of the sum for |q| < 4e-3), else q / (1 + sqrt(1+q)).
+__device__ __forceinline__ float sqrt1p_minus1_f32(float q)
+{
+    if (fabsf(q) < 4.0e-3f) {
+        float p = __builtin_fmaf(-5.0f / 128.0f, q, 1.0f / 16.0f);
+        p = __builtin_fmaf(p, q, -1.0f / 8.0f);
+        p = __builtin_fmaf(p, q, 0.5f);
+        return q * p;
+    }
+    return q * __builtin_amdgcn_rcpf(1.0f + __builtin_sqrtf(1.0f + q));
+}
+
+// The FP32 build's 1 - (1+q)^(-1/2): four series terms, else the closed form.
+__device__ __forceinline__ float one_minus_rsqrt1p_f32(float q)
+{
+    if (fabsf(q) < 4.0e-3f) {
+        float p = __builtin_fmaf(-35.0f / 128.0f, q, 5.0f / 16.0f);
+        p = __builtin_fmaf(p, q, -3.0f / 8.0f);
+        p = __builtin_fmaf(p, q, 0.5f);
+        return q * p;
+    }
+    return 1.0f - __builtin_amdgcn_rsqf(1.0f + q);
+}
+
+template <bool FP32, int PASS, int MODE, int S>
 __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* __restrict__ pieces,
                                                         const int32_t* __restrict__ slice_piece,
                                                         const int64_t* __restrict__ slice_ptr)
@@ -74,7 +101,10 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
     const double2* __restrict__ rin = reinterpret_cast<const double2*>(A.rec_in);
     const double2 o0 = rin[3 * node], o1 = rin[3 * node + 1], o2 = rin[3 * node + 2];
     const double X0 = o0.x, X1 = o0.y, X2 = o1.x;
-    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;
+    const double U0 = o1.y, U1 = o2.x, U2 = o2.y;  // FP64 build
+    const uint64_t ub1 = __double_as_longlong(o1.y), ub2 = __double_as_longlong(o2.x);
+    const float Uf0 = __uint_as_float(static_cast<uint32_t>(ub1)), Uf1 = __uint_as_float(static_cast<uint32_t>(ub1 >> 32)),
+                Uf2 = __uint_as_float(static_cast<uint32_t>(ub2));  // FP32 build
     const double2* __restrict__ ent2 = reinterpret_cast<const double2*>(A.ent);
     uint16_t* __restrict__ entw = A.ent;
     const SeriesCoef sk = series_coef_regs();
@@ -82,6 +112,8 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
     if (PASS == 1) own = A.osb[node];
     const double Ai = own.x, Bi = own.y;
     const double ka = P.osb_a, kb = P.osb_b;
+    const float Aif = static_cast<float>(Ai), Bif = static_cast<float>(Bi), kaf = static_cast<float>(ka),
+                kbf = static_cast<float>(kb), q0f = static_cast<float>(P.q0);
 
     // sentinel record (padding entries point at it)
     if (lane < 3) lrec[kStageChunks + lane] = lane == 0 ? double2{1e10, 1e10} : lane == 1 ? double2{1e10, 0.0} : double2{0.0, 0.0};
@@ -111,10 +143,53 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
 
     double D = 0.0;                    // pass 1: sum of |xi|^2 s over intact bonds
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;  // pass 2: force density without the factor V
+    float Df = 0.0f, Ff0 = 0.0f, Ff1 = 0.0f, Ff2 = 0.0f;  // the same in the FP32 build
     constexpr bool BREAK = PASS == 0 && MODE != kModeForce;
     const int32_t step = static_cast<int32_t>(*A.step_base + A.step_local);
 
+    // FP32 build: one slot in single precision (the bond vector formed in f64 and rounded
+    // once, the displacements those of the f32 records)
+    auto slot32 = [&](uint16_t e, int64_t ds) {
+        const bool live = !(e & kEntBroken);
+        const uint32_t off = e & kEntOff;
+        const double2 r0 = *reinterpret_cast<const double2*>(lrecb + off);
+        const double2 r1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
+        const double2 r2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
+        const float xi0 = static_cast<float>(r0.x - X0), xi1 = static_cast<float>(r0.y - X1),
+                    xi2 = static_cast<float>(r1.x - X2);
+        const uint64_t b1 = __double_as_longlong(r1.y), b2 = __double_as_longlong(r2.x);
+        const float e0 = __uint_as_float(static_cast<uint32_t>(b1)) - Uf0,
+                    e1 = __uint_as_float(static_cast<uint32_t>(b1 >> 32)) - Uf1,
+                    e2 = __uint_as_float(static_cast<uint32_t>(b2)) - Uf2;
+        const float y0 = xi0 + e0, y1 = xi1 + e1, y2 = xi2 + e2;
+        const float z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
+        const float tq = __builtin_fmaf(e2, z2, __builtin_fmaf(e1, z1, e0 * z0));
+        const float L2 = __builtin_fmaf(xi2, xi2, __builtin_fmaf(xi1, xi1, xi0 * xi0));
+        const float q = tq * __builtin_amdgcn_rcpf(L2);
+        const bool brk = BREAK && live && !(e & kEntNoFail) && q >= q0f;
+        const bool alive = live && !brk;
+        if (PASS == 0) {
+            Df = __builtin_fmaf(L2, sqrt1p_minus1_f32(alive ? q : 0.0f), Df);
+            if (brk) {
+                entw[ds] = static_cast<uint16_t>(e | kEntBroken);
+                A.bstep[ds] = step;
+            }
+        } else {
+            const float g = one_minus_rsqrt1p_f32(alive ? q : 0.0f);
+            const double2 pj = lpair[(off * 0xAAABu) >> 21];
+            const float a = kaf * (Aif + static_cast<float>(pj.x)), b = kbf * (Bif + static_cast<float>(pj.y));
+            const float coef = alive ? __builtin_fmaf(g, b - a, a) : 0.0f;
+            Ff0 = __builtin_fmaf(coef, y0, Ff0);
+            Ff1 = __builtin_fmaf(coef, y1, Ff1);
+            Ff2 = __builtin_fmaf(coef, y2, Ff2);
+        }
+    };
+
     auto slot = [&](uint16_t e, int64_t ds) {
+        if constexpr (FP32) {
+            slot32(e, ds);
+            return;
+        }
         const bool live = !(e & kEntBroken);
         const uint32_t off = e & kEntOff;
         const double2 r0 = *reinterpret_cast<const double2*>(lrecb + off);
@@ -167,6 +242,12 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         ent = ent_next;
     }
 
+    if (FP32) {
+        D = Df;
+        F0 = Ff0;
+        F1 = Ff1;
+        F2 = Ff2;
+    }
     if (S > 1) {  // wavefront 0 adds the partial sums of 1..S-1 in that order
         if (wv > 0) {
             double* rr = red + (wv - 1) * kRed * kWave + lane;
@@ -200,43 +281,52 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         return;
     }
     const double V = P.volume;
-    node_update<MODE, false>(A, P, node, U0, U1, U2, V * F0, V * F1, V * F2);
+    node_update<MODE, FP32>(A, P, node, U0, U1, U2, V * F0, V * F1, V * F2);
 }
 
-template <int PASS, int MODE>
+template <bool FP32, int PASS, int MODE>
 hipError_t launch_osb_pm(const StepArgs& a, int split, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>(a.nslices));
     switch (split) {
-    case 1: hipLaunchKernelGGL((osb_staged<PASS, MODE, 1>), grid, dim3(kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
-    case 2: hipLaunchKernelGGL((osb_staged<PASS, MODE, 2>), grid, dim3(2 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
-    case 4: hipLaunchKernelGGL((osb_staged<PASS, MODE, 4>), grid, dim3(4 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+    case 1: hipLaunchKernelGGL((osb_staged<FP32, PASS, MODE, 1>), grid, dim3(kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+    case 2: hipLaunchKernelGGL((osb_staged<FP32, PASS, MODE, 2>), grid, dim3(2 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+    case 4: hipLaunchKernelGGL((osb_staged<FP32, PASS, MODE, 4>), grid, dim3(4 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_osb_dilation(const StepArgs& a, bool breaking, int split, hipStream_t s)
+template <bool FP32>
+hipError_t launch_osb_step_p(const StepArgs& a, int mode, int split, hipStream_t s)
 {
-    if (a.nslices <= 0) return hipSuccess;
-    return breaking ? launch_osb_pm<0, kModeEC>(a, split, s) : launch_osb_pm<0, kModeForce>(a, split, s);
-}
-
-hipError_t launch_osb_step(const StepArgs& a, int mode, int split, hipStream_t s)
-{
-    if (a.nslices <= 0) return hipSuccess;
-    hipError_t e = launch_osb_dilation(a, mode != kModeForce, split, s);
+    hipError_t e = mode != kModeForce ? launch_osb_pm<FP32, 0, kModeEC>(a, split, s)
+                                      : launch_osb_pm<FP32, 0, kModeForce>(a, split, s);
     if (e != hipSuccess) return e;
     switch (mode) {
-    case kModeEC: return launch_osb_pm<1, kModeEC>(a, split, s);
-    case kModeVV: return launch_osb_pm<1, kModeVV>(a, split, s);
-    case kModeVVInit: return launch_osb_pm<1, kModeVVInit>(a, split, s);
-    case kModeFE: return launch_osb_pm<1, kModeFE>(a, split, s);
-    case kModeForce: return launch_osb_pm<1, kModeForce>(a, split, s);
+    case kModeEC: return launch_osb_pm<FP32, 1, kModeEC>(a, split, s);
+    case kModeVV: return launch_osb_pm<FP32, 1, kModeVV>(a, split, s);
+    case kModeVVInit: return launch_osb_pm<FP32, 1, kModeVVInit>(a, split, s);
+    case kModeFE: return launch_osb_pm<FP32, 1, kModeFE>(a, split, s);
+    case kModeForce: return launch_osb_pm<FP32, 1, kModeForce>(a, split, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+}  // namespace
+
+hipError_t launch_osb_dilation(const StepArgs& a, bool breaking, bool fp32, int split, hipStream_t s)
+{
+    if (a.nslices <= 0) return hipSuccess;
+    if (fp32)
+        return breaking ? launch_osb_pm<true, 0, kModeEC>(a, split, s) : launch_osb_pm<true, 0, kModeForce>(a, split, s);
+    return breaking ? launch_osb_pm<false, 0, kModeEC>(a, split, s) : launch_osb_pm<false, 0, kModeForce>(a, split, s);
+}
+
+hipError_t launch_osb_step(const StepArgs& a, int mode, bool fp32, int split, hipStream_t s)
+{
+    if (a.nslices <= 0) return hipSuccess;
+    return fp32 ? launch_osb_step_p<true>(a, mode, split, s) : launch_osb_step_p<false>(a, mode, split, s);
 }
 
 }  // namespace pdmi

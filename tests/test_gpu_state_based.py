@@ -9,7 +9,7 @@ import pytest
 
 import pd_inputs as pi
 from oracle.oracle import OracleSim, from_workload
-from parity import TOL_FP64, compare, oracle_run, rel_err, say
+from parity import TOL_FP32, TOL_FP64, compare, oracle_run, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -98,6 +98,20 @@ def _frozen_copy(o, w):
     return c
 
 
+@pytest.mark.parametrize("split", [1, 4])
+def test_fp32_build(block_oracle, split):
+    """The FP32 build (single-precision bond arithmetic, f64 master displacement) against
+    the FP64 oracle at the FP32 bar, break mismatches counted (at most 1%)."""
+    from paper_2105_04150_amd import PD_FP32, simulation_for
+    w, o = block_oracle
+    g = simulation_for(w, precision=PD_FP32, lanes=split, mapping="staged")
+    g.step(w.steps)
+    eu, ev, mism, ephi = compare(g, o, TOL_FP32, f"state-based fp32 staged-{split}")
+    assert eu <= TOL_FP32 and mism <= 0.01 * int(o.broken_mask.sum())
+    th = g.dilation()
+    assert np.all(np.isfinite(th))
+
+
 def test_dilation_and_force_readouts(block_oracle):
     from paper_2105_04150_amd import simulation_for
     w, o = block_oracle
@@ -145,7 +159,7 @@ def test_batched_instances():
 
 
 def test_model_switch_and_errors():
-    from paper_2105_04150_amd import PD_FP32, PdmiError, Simulation, simulation_for
+    from paper_2105_04150_amd import PdmiError, simulation_for
     w = _block(steps=50, dims=(8, 7, 6))
     g = simulation_for(w, mapping="staged")
     with pytest.raises(PdmiError):
@@ -169,16 +183,10 @@ def test_model_switch_and_errors():
     assert np.array_equal(g.u(), ref.u())
     with pytest.raises(PdmiError):
         g.dilation()
-    # sliced mapping and the FP32 build refuse the model
+    # the sliced mapping refuses the model
     s = simulation_for(wp, lanes=4)
     with pytest.raises(PdmiError):
         s.set_model("state_based", *w.state_based)
-    f = Simulation(precision=PD_FP32)
-    f.set_mapping("staged", 1)
-    f.build_family(wp.coords, wp.horizon)
-    with pytest.raises(PdmiError):
-        f.set_model("state_based", *w.state_based)
-    f.close()
 
 
 def test_prepare_and_graph_replays():
@@ -195,10 +203,10 @@ def test_prepare_and_graph_replays():
 
 
 def test_cube100_full_size():
-    """The headline cube (1M nodes) on the state-based model, in the launch configuration
-    the benchmark times (staged, one wavefront per slice, natural order), for a short
-    prefix the oracle can follow."""
-    from paper_2105_04150_amd import simulation_for
+    """The headline cube (1M nodes) on the state-based model, in the launch configurations
+    the benchmark times (staged, one wavefront per slice, natural order; FP64 and FP32),
+    for a short prefix the oracle can follow."""
+    from paper_2105_04150_amd import PD_FP32, simulation_for
     w = pi.workload("cube100", steps=8, model="state_based")
     w.order = "natural"
     say(f"[run] oracle cube100 state-based, {w.steps} steps, {THREADS} threads")
@@ -207,6 +215,11 @@ def test_cube100_full_size():
     g.step(w.steps)
     eu, ev, mism, ephi = compare(g, o, TOL_FP64, "state-based cube100 full size")
     assert np.abs(o.u).max() > 0 and mism == 0 and eu <= TOL_FP64
+    g.close()
+    g = simulation_for(w, precision=PD_FP32, mapping="staged", order="natural")
+    g.step(w.steps)
+    eu, ev, mism, ephi = compare(g, o, TOL_FP32, "state-based cube100 full size fp32")
+    assert eu <= TOL_FP32 and mism == 0
 
 
 @pytest.mark.parametrize("n", [1, 2, 65, 130])
