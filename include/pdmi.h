@@ -9,7 +9,9 @@
  *   mu = 0 for ever once s >= s0 (irreversible brittle breaking)       (Eq. mu)
  *   H_i = { j != i : |x_j - x_i| <= delta }                           (Eq. family)
  *
- * with an explicit time integrator (Sec. 2.4) and per-node local damage (Sec. 2.2).
+ * with an explicit time integrator (Sec. 2.4) and per-node local damage (Sec. 2.2); also
+ * n-linear damage laws per bond class, stiffness corrections, quasi-static loading tools,
+ * the ordinary state-based linear solid (Sec. 8.2) and a reverse-mode adjoint.
  * Every time step runs in hand-written HIP kernels on one GPU.
  *
  * Conventions (all entry points):
@@ -289,7 +291,8 @@ int pd_set_integrator(pd_ctx *ctx, int scheme, double dt);
 /* Advance every instance by nsteps >= 0 steps.  Each step reads the current
  * displacement snapshot, gathers neighbours over the family, computes stretches,
  * breaks bonds with s >= s0 (they contribute nothing from that step on), sums the
- * PMB bond forces per node, then integrates and applies the BCs.  Asynchronous: a
+ * PMB bond forces per node (or the state-based forces, pd_set_model), then integrates
+ * and applies the BCs.  Asynchronous: a
  * non-finite state is reported by the next synchronising call (PD_ENONFINITE). */
 int pd_step(pd_ctx *ctx, int64_t nsteps);
 
