@@ -192,3 +192,17 @@ def test_single_bond_breaks_at_s0(oracle_lib):
         assert (np.abs(F).max() == 0.0) == broken
         if broken:  # irreversible: released, the bond stays broken
             assert np.abs(sim.force(0 * u, 1)).max() == 0.0 and sim.broken_mask.all()
+
+
+def test_workload_moduli():
+    """Isotropic elasticity: G = 3K(1 - 2 nu)/(2(1 + nu)); at nu = 1/4 (the PMB's fixed
+    Poisson ratio) G = 3K/5, and E = 9KG/(3K + G) returns 2G(1 + nu)."""
+    assert pi.shear_modulus(K, 0.25) == pytest.approx(0.6 * K, rel=1e-15)
+    for nu in (0.1, 0.2, 0.3, 0.45):
+        g = pi.shear_modulus(K, nu)
+        assert 9 * K * g / (3 * K + g) == pytest.approx(2 * g * (1 + nu), rel=1e-13)
+    w = pi.workload("block10", dims=(5, 5, 5), steps=10, model="state_based", poisson=0.3)
+    assert w.state_based == (pi.K_CONCRETE, pi.shear_modulus(pi.K_CONCRETE, 0.3))
+    assert pi.workload("block10", dims=(5, 5, 5), steps=10).state_based is None
+    with pytest.raises(KeyError):
+        pi.workload("block10", model="cubic")
