@@ -12,7 +12,7 @@ draw is a pure function of (seed, counter) and identical on every machine.
 
 Workloads follow the paper's benchmark setting (Section 4: beams on a regular
 cubic tensor grid, constant micromodulus, simple displacement / velocity control)
-with sizes chosen per workload; every recipe is documented in the design doc.
+with sizes chosen per workload; each workload's recipe is stated in workload() below.
 """
 from __future__ import annotations
 
