@@ -202,6 +202,30 @@ def test_prepare_and_graph_replays():
     assert np.array_equal(a.u(), b.u()) and np.array_equal(a.broken(), b.broken())
 
 
+def test_velocity_verlet_graphs_and_autotune():
+    """Velocity Verlet through captured graphs (two kernels per step, the drift of a
+    restart) equals single launches bit for bit; the autotuner keeps to the staged
+    layout and its choice matches the oracle."""
+    from paper_2105_04150_amd import simulation_for
+    w = pi.workload("qs_beam", dims=(30, 9, 9), steps=300, model="state_based")
+    a = simulation_for(w, mapping="staged")
+    a.prepare()
+    a.step(150)
+    a.u()  # a readout between chunks
+    a.step(150)
+    b = simulation_for(w, mapping="staged")
+    for _ in range(300):
+        b.step(1)
+    assert np.array_equal(a.u(), b.u()) and np.array_equal(a.v(), b.v())
+    o = oracle_run(w, w.steps)
+    t = simulation_for(w, mapping="staged")
+    chosen = t.autotune(trial_steps=3)
+    assert chosen < 0  # a staged choice (negative: wavefronts per slice)
+    t.step(w.steps)
+    eu, ev, mism, ephi = compare(t, o, TOL_FP64, f"state-based after autotune ({chosen})")
+    assert mism == 0 and eu <= TOL_FP64
+
+
 def test_cube100_full_size():
     """The headline cube (1M nodes) on the state-based model, in the launch configurations
     the benchmark times (staged, one wavefront per slice, natural order; FP64 and FP32),
