@@ -272,7 +272,7 @@ int pd_set_corrections(pd_ctx *ctx, int32_t inst, const pd_corrections *corr);
  * Bonds break at the critical stretch s0 of pd_set_material (irreversibly, on both
  * slots, not in no-failure zones), before the dilation of the same step.  Each step runs
  * two kernels (dilation, then force and integration).  The model needs the staged
- * mapping (FP64 or FP32 build) and a uniform node volume; it takes no stiffness field, damage
+ * mapping (FP64 or FP32 build; uniform or per-node volumes); it takes no stiffness field, damage
  * law or correction, the adjoint rejects it, and every instance of a context must run
  * the same model (checked here and when stepping; c of pd_set_material is unused).
  * PD_MODEL_PMB (K, G ignored) returns to the bond-based model.  Errors: PD_EINVAL. */

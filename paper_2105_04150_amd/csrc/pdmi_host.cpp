@@ -719,7 +719,9 @@ void upload_volumes(pd_ctx* ctx)
         ctx->vol.release();
         return;
     }
-    std::vector<double> V(static_cast<size_t>(ctx->nn) + 1, 0.0);  // entry nn: the sentinel record, volume 0
+    // entry nn: the sentinel record, volume 0; then spare zero entries for the state-based
+    // kernels' fixed copy window
+    std::vector<double> V(static_cast<size_t>(ctx->nn) + kCorrPad, 0.0);
     for (auto& I : ctx->inst)
         for (int64_t l = 0; l < I.n_pad; ++l) {
             const int64_t u = I.perm[l];
@@ -730,8 +732,8 @@ void upload_volumes(pd_ctx* ctx)
     sync(ctx);
 }
 
-// State-based model: 1/m_i per device node, m_i = sum over the whole family of |xi|^2 V
-// (influence function 1, reference configuration, uniform volume); padding 0.  The pair
+// State-based model: 1/m_i per device node, m_i = sum over the whole family of |xi|^2 V_j
+// (influence function 1, reference configuration); padding 0.  The pair
 // buffer {theta/m, 1/m} starts zeroed, with kOsbPad spare pairs.
 void upload_osb(pd_ctx* ctx)
 {
@@ -756,9 +758,9 @@ void upload_osb(pd_ctx* ctx)
                         const double xi = I.x[3 * j + d] - I.x[3 * i + d];
                         L2 += xi * xi;
                     }
-                    acc += L2;
+                    acc += L2 * (I.vols.empty() ? I.volume : I.vols[j]);
                 }
-                m[i] = acc * I.volume;
+                m[i] = acc;
             }
         });
         for (int64_t l = 0; l < I.n_pad; ++l) {
@@ -773,8 +775,7 @@ void upload_osb(pd_ctx* ctx)
     sync(ctx);
 }
 
-// What the state-based kernels support: every instance on the model, the staged layout,
-// uniform volumes, the constant micromodulus replaced by (K, G): no stiffness
+// What the state-based kernels support: every instance on the model, the staged layout, the constant micromodulus replaced by (K, G): no stiffness
 // fields, damage laws or corrections.
 void osb_checks(const pd_ctx* ctx)
 {
@@ -785,7 +786,6 @@ void osb_checks(const pd_ctx* ctx)
         if (I.has_corr) fail(PD_EINVAL, "the state-based model takes no stiffness corrections");
     }
     if (ctx->mapping != PD_MAP_STAGED) fail(PD_EINVAL, "the state-based model runs in the staged mapping");
-    if (ctx->has_vol) fail(PD_EINVAL, "the state-based model takes a uniform node volume per instance");
     if (ctx->has_stiff || ctx->has_knode) fail(PD_EINVAL, "the state-based model takes no stiffness field");
 }
 

@@ -17,7 +17,8 @@
 // Both passes use the staged mapping of the bond-based kernels: a slice of 64 nodes, one
 // lane per node, the node records of each piece's range and its slot entries copied
 // straight into LDS; pass 2 copies the range's node pairs beside them.  Influence function
-// 1, uniform node volume per instance.  FP64, or the FP32 build: bond arithmetic in
+// 1; a uniform node volume per instance, or per-node volumes copied into LDS beside the
+// records (V_j enters the dilation sum and the force term).  FP64, or the FP32 build: bond arithmetic in
 // single precision from the f32 displacements of the records and the f64 coordinates, the
 // node pairs and the integration (f64 master displacement) as in FP64.
 //
@@ -74,7 +75,7 @@ __device__ __forceinline__ float one_minus_rsqrt1p_f32(float q)
     return 1.0f - __builtin_amdgcn_rsqf(1.0f + q);
 }
 
-template <bool FP32, int PASS, int MODE, int S>
+template <bool FP32, int PASS, int MODE, int S, bool VOLN>
 __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* __restrict__ pieces,
                                                         const int32_t* __restrict__ slice_piece,
                                                         const int64_t* __restrict__ slice_ptr)
@@ -82,7 +83,9 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
     constexpr int kRecChunks = kStageChunks + 3;             // staged records, then the sentinel
     constexpr int kEntChunks = kPieceRows * kWave * 2 / 16;  // 16-byte chunks of entries
     constexpr int kPairChunks = PASS == 1 ? 2 * kWave : 0;   // node pairs of the range (pass 2)
-    constexpr int kLds = kRecChunks + kEntChunks + kPairChunks;
+    constexpr int kVolChunks = VOLN ? 3 * kWave * 4 / 16 : 0;    // node volumes of the range (3 x 64 dwords)
+    constexpr int kLds = kRecChunks + kEntChunks + kPairChunks + kVolChunks;
+    static_assert(!VOLN || kEntPad / 48 < 3 * kWave / 2, "the sentinel's volume index lies in the copy");
     constexpr int kRed = PASS == 1 ? 3 : 1;
     static_assert(kEntPad / 48 < kPairChunks || PASS == 0, "the sentinel's pair index lies in the copy");
     __shared__ double2 lds[S * kLds];
@@ -92,6 +95,7 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
     const char* const lrecb = reinterpret_cast<const char*>(lrec);
     uint16_t* const lent = reinterpret_cast<uint16_t*>(lrec + kRecChunks);
     double2* const lpair = lrec + kRecChunks + kEntChunks;
+    double* const lvol = reinterpret_cast<double*>(lrec + kRecChunks + kEntChunks + kPairChunks);
 
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
@@ -139,10 +143,17 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
             __builtin_amdgcn_global_load_lds(ps, (lds_ptr)(lpair), 16, 0, 0);
             __builtin_amdgcn_global_load_lds(ps + kWave, (lds_ptr)(lpair + kWave), 16, 0, 0);
         }
+        if (VOLN) {  // per-node volumes: the volume buffer ends with spare entries
+            const float* ws = reinterpret_cast<const float*>(A.vol + m.x) + lane;
+            float* wl = reinterpret_cast<float*>(lvol);
+            __builtin_amdgcn_global_load_lds(ws, (lds_ptr)(wl), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(ws + kWave, (lds_ptr)(wl + kWave), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(ws + 2 * kWave, (lds_ptr)(wl + 2 * kWave), 4, 0, 0);
+        }
     };
 
-    double D = 0.0;                    // pass 1: sum of |xi|^2 s over intact bonds
-    double F0 = 0.0, F1 = 0.0, F2 = 0.0;  // pass 2: force density without the factor V
+    double D = 0.0;                    // pass 1: sum of |xi|^2 s (V_j) over intact bonds
+    double F0 = 0.0, F1 = 0.0, F2 = 0.0;  // pass 2: force density (uniform volume: without the factor V)
     float Df = 0.0f, Ff0 = 0.0f, Ff1 = 0.0f, Ff2 = 0.0f;  // the same in the FP32 build
     constexpr bool BREAK = PASS == 0 && MODE != kModeForce;
     const int32_t step = static_cast<int32_t>(*A.step_base + A.step_local);
@@ -168,8 +179,9 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         const float q = tq * __builtin_amdgcn_rcpf(L2);
         const bool brk = BREAK && live && !(e & kEntNoFail) && q >= q0f;
         const bool alive = live && !brk;
+        const float vj = VOLN ? static_cast<float>(lvol[(off * 0xAAABu) >> 21]) : 1.0f;
         if (PASS == 0) {
-            Df = __builtin_fmaf(L2, sqrt1p_minus1_f32(alive ? q : 0.0f), Df);
+            Df = __builtin_fmaf(VOLN ? L2 * vj : L2, sqrt1p_minus1_f32(alive ? q : 0.0f), Df);
             if (brk) {
                 entw[ds] = static_cast<uint16_t>(e | kEntBroken);
                 A.bstep[ds] = step;
@@ -178,7 +190,8 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
             const float g = one_minus_rsqrt1p_f32(alive ? q : 0.0f);
             const double2 pj = lpair[(off * 0xAAABu) >> 21];
             const float a = kaf * (Aif + static_cast<float>(pj.x)), b = kbf * (Bif + static_cast<float>(pj.y));
-            const float coef = alive ? __builtin_fmaf(g, b - a, a) : 0.0f;
+            const float c = alive ? __builtin_fmaf(g, b - a, a) : 0.0f;
+            const float coef = VOLN ? c * vj : c;
             Ff0 = __builtin_fmaf(coef, y0, Ff0);
             Ff1 = __builtin_fmaf(coef, y1, Ff1);
             Ff2 = __builtin_fmaf(coef, y2, Ff2);
@@ -204,9 +217,10 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         const double q = tq * rcp64_1(L2);  // neither pass needs 1/|xi| itself
         const bool brk = BREAK && live && !(e & kEntNoFail) && q >= P.q0;
         const bool alive = live && !brk;
+        const double vj = VOLN ? lvol[(off * 0xAAABu) >> 21] : 1.0;
         if (PASS == 0) {
             const double s = sqrt1p_minus1(alive ? q : 0.0);
-            D = __builtin_fma(L2, s, D);  // |xi| e = |xi|^2 s; 0 for broken and padding slots
+            D = __builtin_fma(VOLN ? L2 * vj : L2, s, D);  // |xi| e = |xi|^2 s; 0 for broken and padding slots
             if (brk) {
                 entw[ds] = static_cast<uint16_t>(e | kEntBroken);
                 A.bstep[ds] = step;
@@ -215,7 +229,8 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
             const double g = one_minus_rsqrt1p(alive ? q : 0.0, sk);
             const double2 pj = lpair[(off * 0xAAABu) >> 21];  // off / 48: the neighbour's pair
             const double a = ka * (Ai + pj.x), b = kb * (Bi + pj.y);
-            const double coef = alive ? __builtin_fma(g, b - a, a) : 0.0;
+            const double c = alive ? __builtin_fma(g, b - a, a) : 0.0;
+            const double coef = VOLN ? c * vj : c;
             F0 = __builtin_fma(coef, y0, F0);
             F1 = __builtin_fma(coef, y1, F1);
             F2 = __builtin_fma(coef, y2, F2);
@@ -274,27 +289,37 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         }
     }
     if (PASS == 0) {
-        // theta_i = 3 V D / m_i; padding nodes (1/m = 0) write zeros
+        // theta_i = 3 V D / m_i (per-node volumes: inside D); padding nodes (1/m = 0) write zeros
         const double b = A.minv[node];
-        const double theta = (3.0 * P.volume) * D * b;
+        const double theta = VOLN ? 3.0 * D * b : (3.0 * P.volume) * D * b;
         A.osb[node] = double2{theta * b, b};
         return;
     }
-    const double V = P.volume;
-    node_update<MODE, FP32>(A, P, node, U0, U1, U2, V * F0, V * F1, V * F2);
+    if (VOLN) {
+        node_update<MODE, FP32>(A, P, node, U0, U1, U2, F0, F1, F2);
+    } else {
+        const double V = P.volume;
+        node_update<MODE, FP32>(A, P, node, U0, U1, U2, V * F0, V * F1, V * F2);
+    }
+}
+
+template <bool FP32, int PASS, int MODE, bool VOLN>
+hipError_t launch_osb_pmv(const StepArgs& a, int split, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>(a.nslices));
+    switch (split) {
+    case 1: hipLaunchKernelGGL((osb_staged<FP32, PASS, MODE, 1, VOLN>), grid, dim3(kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+    case 2: hipLaunchKernelGGL((osb_staged<FP32, PASS, MODE, 2, VOLN>), grid, dim3(2 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+    case 4: hipLaunchKernelGGL((osb_staged<FP32, PASS, MODE, 4, VOLN>), grid, dim3(4 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <bool FP32, int PASS, int MODE>
 hipError_t launch_osb_pm(const StepArgs& a, int split, hipStream_t s)
 {
-    const dim3 grid(static_cast<unsigned>(a.nslices));
-    switch (split) {
-    case 1: hipLaunchKernelGGL((osb_staged<FP32, PASS, MODE, 1>), grid, dim3(kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
-    case 2: hipLaunchKernelGGL((osb_staged<FP32, PASS, MODE, 2>), grid, dim3(2 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
-    case 4: hipLaunchKernelGGL((osb_staged<FP32, PASS, MODE, 4>), grid, dim3(4 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return a.vol ? launch_osb_pmv<FP32, PASS, MODE, true>(a, split, s) : launch_osb_pmv<FP32, PASS, MODE, false>(a, split, s);
 }
 
 template <bool FP32>

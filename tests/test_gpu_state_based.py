@@ -112,6 +112,26 @@ def test_fp32_build(block_oracle, split):
     assert np.all(np.isfinite(th))
 
 
+@pytest.mark.parametrize("precision,split", [("f64", 1), ("f64", 4), ("f32", 1)])
+def test_per_node_volumes(precision, split):
+    """Uneven node volumes (+-30%): V_j enters the weighted volume, the dilation and the
+    force; the library copies the volumes into LDS beside the records."""
+    from paper_2105_04150_amd import PD_FP32, PD_FP64, simulation_for
+    w = _block(steps=600, dims=(12, 10, 9))
+    vols = w.volume * (0.7 + 0.6 * pi.uniform01(55, np.arange(w.n, dtype=np.uint64)))
+    o = from_workload(w)
+    o = OracleSim(o.x, o.row_ptr, o.col, c=w.c, s0=w.s0, rho=w.rho, dt=w.dt, vol=vols, bcs=w.bcs,
+                  state_based=w.state_based)
+    o.run(w.steps)
+    g = simulation_for(w, precision=PD_FP32 if precision == "f32" else PD_FP64, lanes=split, mapping="staged")
+    g.set_material(w.rho, w.c, w.s0, w.eta, volumes=vols)
+    g.step(w.steps)
+    tol = TOL_FP32 if precision == "f32" else TOL_FP64
+    eu, ev, mism, ephi = compare(g, o, tol, f"state-based per-node volumes {precision} staged-{split}")
+    assert int(o.broken_mask.sum()) > 100
+    assert eu <= tol and mism <= (0.01 * int(o.broken_mask.sum()) if precision == "f32" else 0)
+
+
 def test_dilation_and_force_readouts(block_oracle):
     from paper_2105_04150_amd import simulation_for
     w, o = block_oracle
