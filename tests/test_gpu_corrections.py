@@ -10,7 +10,6 @@ import numpy as np
 import pytest
 
 import pd_inputs as pi
-from oracle.oracle import from_workload
 from parity import TOL_FP32, TOL_FP64, compare, oracle_run, rel_err, say
 
 pytestmark = pytest.mark.gpu
