@@ -4,7 +4,9 @@ Written separately from ``pd_oracle.c`` and vectorised over slots, it accepts co
 inputs so that complex-step derivatives (Squire and Trapp, SIAM Review 40, 1998) of a
 run with respect to the per-slot stiffness or the body-force magnitude can be taken:
 d f/d p = Im f(p + i h) / h, exact to rounding for real-analytic f.  Breaking follows a
-frozen schedule (slot b acts in pass k iff k < frozen[b]); no damping.
+frozen schedule (slot b acts in pass k iff k < frozen[b]).  Damping follows the damped
+equation of motion (Sec. 2.3): the acceleration is (F - eta v)/rho with the velocity of
+the start of the step.
 """
 from __future__ import annotations
 
@@ -12,7 +14,8 @@ import numpy as np
 
 
 def ec_forward(x, row_ptr, col, kslot, vol, rho, dt, frozen, steps, *, bhat=None, bmag=0.0,
-               bc_kind=None, bc_sched=None, bc_val=None, u0=None, v0=None, step0=0, dtype=complex):
+               bc_kind=None, bc_sched=None, bc_val=None, u0=None, v0=None, step0=0, dtype=complex,
+               eta=0.0):
     """Displacement after `steps` Euler-Cromer steps (f = k s V_j y/|y|, Eq. simpleBond)."""
     n = x.shape[0]
     rows = np.repeat(np.arange(n), np.diff(row_ptr))
@@ -35,7 +38,7 @@ def ec_forward(x, row_ptr, col, kslot, vol, rho, dt, frozen, steps, *, bhat=None
         np.add.at(F, rows, f)
         if b is not None:
             F = F + b
-        vn = v + dt * (F / rho)
+        vn = v + dt * ((F - eta * v) / rho)
         un = u + dt * vn
         t1 = (k + 1) * dt
         if bc_kind is not None:

@@ -110,13 +110,17 @@ TOL_FP32_SOFTENING = 5e-5
 
 
 def test_laws_fp32(law_oracle):
+    """The trilinear beam is held to TOL_FP32_SOFTENING (measured 1.9e-5); the composite,
+    whose bonds mostly sit on gentler branches, meets the brittle law's 1e-5 (measured
+    1.5e-6)."""
     from paper_2105_04150_amd import PD_FP32
     w, o = law_oracle
+    bar = TOL_FP32 if w.class_spec is not None else TOL_FP32_SOFTENING
     g = _sim(w, "staged", 1, precision=PD_FP32)
     g.step(w.steps)
-    eu, ev, mism, ephi, smism, es = _compare_state(g, o, TOL_FP32_SOFTENING, "fp32")
+    eu, ev, mism, ephi, smism, es = _compare_state(g, o, bar, "fp32")
     nsoft = int((o.smax[: o.nnz] > 0).sum())
-    assert eu <= TOL_FP32_SOFTENING and mism <= 0.01 * int(o.broken_mask.sum()) and smism <= 0.01 * nsoft
+    assert eu <= bar and mism <= 0.01 * int(o.broken_mask.sum()) and smism <= 0.01 * nsoft
 
 
 def test_force_readout_with_softened_bonds(law_oracle):
@@ -166,33 +170,46 @@ def test_checkpoint_restart_and_layout_change():
     assert mism == 0 and smism == 0 and eu <= TOL_FP64
 
 
+# The batched case runs 1,200 steps with the loads ramped over that run: there the oracle's
+# own rounding spread (every coordinate moved by one ulp) is 1.3e-10 for the trilinear beam
+# and 4.8e-11 for the 30 x 9 x 9 composite; at 1,600 steps the composites soften into an
+# ill-conditioned regime (spreads 2.6e-10 to 6.5e-9), which no fixed bar can hold.
+BATCH_STEPS = 1200
+SPREAD_MAX = 2.5e-10   # the case must be this well conditioned ...
+BAR_CAP = 1e-9         # ... so the bar, four times the spread, never exceeds this
+
+
 def test_batched_mixed_laws():
     """One instance with the trilinear law, one brittle, one composite: each matches its
     oracle (laws are per instance; the kernels see all three in one launch)."""
     from paper_2105_04150_amd import Simulation, apply_workload
-    ws = [_workload("trilinear"), _workload("brittle", dims=(30, 9, 9)), _workload("composite", dims=(32, 9, 9))]
+    n = BATCH_STEPS
+    ws = [_workload("trilinear", steps=n), _workload("brittle", dims=(30, 9, 9), steps=n),
+          _workload("composite", dims=(30, 9, 9), steps=n)]
     with Simulation() as g:
         g.set_mapping("staged", 1)
         g.build_family_batch([w.coords for w in ws], [w.horizon for w in ws])
         g.set_integrator(ws[0].scheme, ws[0].dt)
         for b, w in enumerate(ws):
             apply_workload(g, w, inst=b)
-        g.step(SMALL["steps"])
+        g.step(n)
         for b, w in enumerate(ws):
             o = from_workload(w)
-            o.run(SMALL["steps"])
+            o.run(n)
             # the bar: 1e-10, or four times the run's own rounding spread where softening
-            # has grown it beyond that
+            # has grown it beyond that, never above BAR_CAP
             bar = TOL_FP64
             if w.laws:
-                spread = _oracle_spread(w, SMALL["steps"], o, class_stiffness=False)
-                bar = max(TOL_FP64, 4.0 * spread)
-                say(f"[laws] inst {b}: oracle spread under one-ulp coordinates {spread:.2e}, bar {bar:.2e}")
-                eu, ev, mism, ephi, smism, es = _compare_state(g, o, TOL_FP64, f"mixed laws inst {b}", inst=b)
+                spread = _oracle_spread(w, n, o, class_stiffness=False)
+                say(f"[laws] inst {b}: oracle spread under one-ulp coordinates {spread:.2e}")
+                assert spread <= SPREAD_MAX, "the case is not conditioned well enough for a fixed bar"
+                bar = min(BAR_CAP, max(TOL_FP64, 4.0 * spread))
+                eu, ev, mism, ephi, smism, es = _compare_state(g, o, bar, f"mixed laws inst {b}", inst=b)
                 assert smism == 0 and es <= bar
+                assert int((o.smax[: o.nnz] > 0).sum()) > 1000
             else:
                 eu, ev, mism, ephi = compare(g, o, TOL_FP64, f"mixed laws inst {b}", inst=b)
-            assert mism == 0 and eu <= bar
+            assert mism == 0 and eu <= bar <= BAR_CAP
 
 
 def test_law_arguments_and_reset():

@@ -3,7 +3,9 @@
 The C adjoint (`pdo_adjoint_ec`, a literal transpose-Jacobian scatter over a stored
 trajectory) is checked against complex-step derivatives of an independent NumPy forward
 run, against the transpose identity <J v, w> = <v, J^T w> per pass, and against
-central finite differences of the C forward run.
+central finite differences of the C forward run.  Every check runs without damping and
+with dynamic-relaxation damping (Sec. 2.3's damped equation of motion: the velocity
+factor 1 - dt eta/rho enters every reverse step).
 """
 import numpy as np
 import pytest
@@ -12,9 +14,13 @@ import pd_inputs as pi
 from oracle.cstep import ec_forward, force_cs
 
 RHO, DT = 2400.0, 1e-7
+# damping coefficients of the two cases: none, and eta with eta dt / rho = 1e-3 per step
+# (4% of the velocity over the 40 steps), enough for a dropped or sign-flipped damping
+# factor in the reverse step to miss the complex-step derivative by far more than 1e-9
+ETAS = (0.0, 2.4e7)
 
 
-def _problem(oracle_lib, seed=3, steps=40):
+def _problem(oracle_lib, seed=3, steps=40, eta=0.0):
     dims = (6, 4, 4)
     x, ijk = pi.lattice(dims, 1e-3, 2e-2, seed=seed)
     rp, col = oracle_lib.family(x, 2.0e-3)
@@ -39,20 +45,20 @@ def _problem(oracle_lib, seed=3, steps=40):
     sensors = np.array([5, 17, 40, 71, 95], dtype=np.int64)
     target = rng.normal(size=(sensors.shape[0], 3)) * 1e-7
     return dict(x=x, ijk=ijk, rp=rp, col=col, k=k, vol=vol, frozen=frozen, bcs=bcs, bhat=bhat,
-                bmag=bmag, sensors=sensors, target=target, steps=steps, n=n)
+                bmag=bmag, sensors=sensors, target=target, steps=steps, n=n, eta=eta)
 
 
 def _sim(oracle_lib, P, k=None, bmag=None):
     return oracle_lib.OracleSim(P["x"], P["rp"], P["col"], c=0.0, s0=1.0, rho=RHO, dt=DT,
                                 vol=P["vol"], kslot=P["k"] if k is None else k, bhat=P["bhat"],
                                 bmag=P["bmag"] if bmag is None else bmag, bcs=P["bcs"],
-                                frozen=P["frozen"])
+                                frozen=P["frozen"], eta=P["eta"])
 
 
 def _loss_cs(P, k, bmag):
     kind, sched, val = __import__("oracle").bc_arrays(P["n"], P["bcs"])
     u, _ = ec_forward(P["x"], P["rp"], P["col"], k, P["vol"], RHO, DT, P["frozen"], P["steps"],
-                      bhat=P["bhat"], bmag=bmag, bc_kind=kind, bc_sched=sched, bc_val=val)
+                      bhat=P["bhat"], bmag=bmag, bc_kind=kind, bc_sched=sched, bc_val=val, eta=P["eta"])
     d = u[P["sensors"]] - P["target"]
     return (d * d).sum()
 
@@ -65,19 +71,26 @@ def _adjoint(oracle_lib, P):
     return sim.adjoint_ec(P["frozen"], P["steps"], z, z, 0, P["sensors"], d), sim
 
 
-def test_numpy_forward_matches_c_forward(oracle_lib):
-    P = _problem(oracle_lib)
+@pytest.mark.parametrize("eta", ETAS)
+def test_numpy_forward_matches_c_forward(oracle_lib, eta):
+    P = _problem(oracle_lib, eta=eta)
     sim = _sim(oracle_lib, P)
     sim.run(P["steps"])
     kind, sched, val = oracle_lib.bc_arrays(P["n"], P["bcs"])
     u, v = ec_forward(P["x"], P["rp"], P["col"], P["k"], P["vol"], RHO, DT, P["frozen"], P["steps"],
-                      bhat=P["bhat"], bmag=P["bmag"], bc_kind=kind, bc_sched=sched, bc_val=val, dtype=float)
+                      bhat=P["bhat"], bmag=P["bmag"], bc_kind=kind, bc_sched=sched, bc_val=val, dtype=float,
+                      eta=eta)
     assert np.abs(u - sim.u).max() <= 1e-13 * np.abs(sim.u).max()
     assert np.abs(sim.u).max() > 1e-9
+    if eta:  # the damping visibly changes the run
+        und = _sim(oracle_lib, dict(P, eta=0.0))
+        und.run(P["steps"])
+        assert np.abs(und.u - sim.u).max() > 1e-3 * np.abs(sim.u).max()
 
 
-def test_adjoint_matches_complex_step(oracle_lib):
-    P = _problem(oracle_lib)
+@pytest.mark.parametrize("eta", ETAS)
+def test_adjoint_matches_complex_step(oracle_lib, eta):
+    P = _problem(oracle_lib, eta=eta)
     (gk, gA), _ = _adjoint(oracle_lib, P)
     h = 1e-30
     rng = np.random.default_rng(9)
@@ -105,8 +118,9 @@ def test_transpose_identity_per_pass(oracle_lib):
         assert lhs == pytest.approx(rhs, rel=1e-11)
 
 
-def test_adjoint_central_differences(oracle_lib):
-    P = _problem(oracle_lib)
+@pytest.mark.parametrize("eta", ETAS)
+def test_adjoint_central_differences(oracle_lib, eta):
+    P = _problem(oracle_lib, eta=eta)
     (gk, gA), _ = _adjoint(oracle_lib, P)
 
     def loss(k, bmag):

@@ -171,3 +171,37 @@ def test_softening_irreversible_and_symmetric(oracle_lib):
     zone[w.nofail] = True
     touch = zone[rows] | zone[o2.col]
     assert not (sm[touch] > 0).any() and not o2.broken_mask[touch & ~o.broken_mask].any()
+
+
+@pytest.mark.parametrize("law", [TRI, BI])
+def test_zone_on_a_softened_bond_keeps_its_secant(oracle_lib, law):
+    """A bond softened to s_m and then made a no-failure zone (Secs. 5.1, 6, 7: the zones
+    keep the loaded and supported nodes' bonds from failing) keeps its damage state as it
+    stands: at any later stretch s, unloading, reloading past s_m or stretched far beyond
+    s_last, it carries the secant force (envelope(s_m)/s_m) s and neither softens further
+    nor breaks.  The expected force is formed here from the law's breakpoints."""
+    sb, rb = law
+    x = np.array([[0.0, 0.0, 0.0], [L, 0.0, 0.0]])
+    rp, col = oracle_lib.family(x, 1.5 * L)
+    sim = oracle_lib.OracleSim(x, rp, col, c=C, s0=1.0, rho=RHO, dt=1e-7, vol=V, laws=[law],
+                               nofail=np.zeros(2, dtype=np.uint8))
+    s_m = 0.5 * (sb[0] + sb[1])                       # on the first softening branch
+    f = _pull(sim, [0.5 * s_m, s_m])
+    assert f[1] == pytest.approx(_envelope(law, s_m), rel=1e-11)
+    secant = _envelope(law, s_m) / s_m
+    stored = sim.smax[:2].copy()
+    assert stored == pytest.approx([s_m, s_m], rel=1e-11)
+    sim.nofail[1] = 1                                 # node 1 joins a zone
+    later = [0.25 * s_m, s_m, 1.5 * s_m, 0.5 * (sb[-2] + sb[-1]), 3.0 * sb[-1], 0.5 * s_m]
+    for k, s in enumerate(later):
+        u = np.zeros((2, 3))
+        u[1, 0] = s * L
+        fs = sim.force(u=u, k=2 + k)[0, 0] / (C * V)
+        assert fs == pytest.approx(secant * s, rel=1e-11), s
+    assert not sim.broken[:2].any()
+    assert np.all(sim.smax[:2] == stored)             # the stored stretch did not move
+    sim.nofail[1] = 0                                 # zone removed: the law applies again
+    u = np.zeros((2, 3))
+    u[1, 0] = 3.0 * sb[-1] * L
+    assert sim.force(u=u, k=10)[0, 0] == 0.0
+    assert sim.broken[:2].all()
