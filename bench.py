@@ -3,9 +3,10 @@
 
 Default workload: the 100 x 100 x 100 simple-cubic cube (1,000,000 nodes, horizon
 3.015 dx, 117,844,248 directed bond slots), FP64, Euler-Cromer, face z = 0 clamped and
-face z = 99 pulled at 1e-8 m per step, Morton node order.  One "step" is one full
-time step of every node (gather, stretch, break check, PMB force, per-node sum,
-integration, boundary conditions).  Prints one JSON line.
+face z = 99 pulled at 1e-8 m per step; the library's autotuner picks the mapping and the
+device node order (natural or Morton).  One "step" is one full time step of every node
+(gather, stretch, break check, PMB force, per-node sum, integration, boundary
+conditions).  Prints one JSON line.
 """
 import argparse
 import hashlib
@@ -22,11 +23,14 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # MI355X vector peaks (256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz)
 PEAK_VALU_TFLOPS = {"f64": 78.6, "f32": 157.3}
-# Algorithmic flops of one slot update as the step kernel evaluates it (an FMA counts 2):
-# bond vector, displacement difference, y and xi + y (12); |y|^2 - |xi|^2 and |xi|^2 (5 + 5);
-# 1/|xi| by rsqrt and one Newton step (7); q (2); the series for 1 - (1+q)^(-1/2) (11 in
-# FP64 with six terms, 7 in FP32 with four); the coefficient (2); the force update (6).
-FLOPS_PER_SLOT = {"f64": 50, "f32": 46}
+# Algorithmic flops of one slot update, the method's own arithmetic in its direct form
+# (Eqs. microelastic and simpleBond, Algorithm 2; a square root counts one): bond vector,
+# displacement difference and deformed bond (9), |y|^2 and |xi|^2 (10), the two square
+# roots (2), s = (r - L)/L (2), the coefficient c s V_j / r (3), the force update (6).
+ALGO_FLOPS_PER_SLOT = 32
+# the committed rocprofv3 counter summary of the headline kernel (VALU instructions per
+# slot row), used when it was taken on the current kernel source
+COUNTERS = os.path.join(ROOT, "profiles", "counters_step_cube100_f64.txt")
 STEP_SOURCES = [os.path.join(ROOT, "paper_2105_04150_amd", "csrc", f)
                 for f in ("pdmi_step.h", "pdmi_device.h", "pdmi_internal.h")]
 
@@ -37,6 +41,19 @@ def kernel_hash() -> str:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def profile_values(path: str) -> dict:
+    """key: value lines of a committed profile summary, or {} if it was taken on another
+    kernel source than the current one."""
+    if not os.path.exists(path):
+        return {}
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    return vals if vals.get("kernel_source_sha256_16") == kernel_hash() else {}
 
 
 def measured_traffic(workload: str, precision: str):
@@ -58,17 +75,39 @@ def measured_traffic(workload: str, precision: str):
         return None
 
 
-def cpu_baseline(w, steps: int, threads: int):
-    """The FP64 oracle as it stands, on the host cores, over a bounded prefix."""
-    from oracle.oracle import from_workload
-    sim = from_workload(w, nthreads=threads)
-    sim.run(1)  # first step outside the timing (page-in)
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, steps: int, threads: int, single_steps: int):
+    """The FP64 oracle as it stands, on the host cores, over bounded prefixes of the same
+    workload: all `threads` cores (the reported value) and one core; the oracle's family
+    build (cell list) is timed on its own."""
+    import oracle.oracle as O
     t0 = time.perf_counter()
-    sim.run(steps)
-    dt = time.perf_counter() - t0
-    return {"value": sim.nnz * steps / dt, "unit": "bond-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} Euler-Cromer steps of the same {w.n}-node workload after one untimed step "
-                      f"(family built by the oracle, not timed)"}
+    O.family(w.coords, w.horizon)
+    family_s = time.perf_counter() - t0
+    rates = {}
+    for nt, k in ((threads, steps), (1, single_steps)):
+        sim = O.from_workload(w, nthreads=nt)
+        sim.run(1)  # first step outside the timing (page-in)
+        t0 = time.perf_counter()
+        sim.run(k)
+        rates[nt] = sim.nnz * k / (time.perf_counter() - t0)
+        nnz = sim.nnz
+        del sim
+    return {"value": rates[threads], "unit": "bond-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} Euler-Cromer steps of the same {w.n}-node, {nnz}-slot workload on {threads} "
+                      f"threads and {single_steps} on one, each after one untimed step; the family build "
+                      f"timed separately",
+            "single_core": {"value": rates[1], "unit": "bond-updates/s", "cores": 1},
+            "family_build_s": family_s, "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def _timed(fn, sync):
@@ -201,6 +240,8 @@ def quasistatic_extra(P, pi, sync, steps: int, every: int):
     dev_ms = sim.last_step_ms() / steps
     loads = []
 
+    every = max(1, min(every, steps // 4))  # at least four readouts in the timed steps
+
     def with_readout():
         for _ in range(steps // every):
             sim.step(every)
@@ -215,12 +256,11 @@ def quasistatic_extra(P, pi, sync, steps: int, every: int):
     mapping = (f"staged-{info['waves_per_slice']}" if info["mapping"] == P.PD_MAP_STAGED
                else f"sliced-{info['lanes_per_node']}")
     sim.close()
-    tflops = nnz * FLOPS_PER_SLOT["f64"] / (dev_ms / 1e3) / 1e12
     return {"config": f"qs_beam {w.dims[0]}x{w.dims[1]}x{w.dims[2]}, velocity Verlet, eta {w.eta:g}, "
                       f"ramp {w.ramp_T:g} s, {len(w.nofail)} zone nodes, f64",
             "nodes": info["n_nodes"], "bond_slots": nnz, "mapping": mapping, "steps": steps,
             "value": nnz * steps / t_zone, "unit": "bond-updates/s", "avg_launch_ms": dev_ms,
-            "alu_frac": tflops / PEAK_VALU_TFLOPS["f64"],
+            "hbm_frac": info["model_bytes_per_step"] / (dev_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
             "rate_with_load_readout": nnz * n_read * every / t_read, "readout_every": every,
             "readout_ms": max(t_read - t_zone * n_read * every / steps, 0.0) * 1e3 / max(n_read, 1),
             "last_load_N": loads[-1] if loads else None,
@@ -263,12 +303,11 @@ def damage_law_extra(P, pi, sync, steps: int):
     mapping = (f"staged-{info['waves_per_slice']}" if info["mapping"] == P.PD_MAP_STAGED
                else f"sliced-{info['lanes_per_node']}")
     sim.close()
-    tflops = nnz * FLOPS_PER_SLOT["f64"] / (dev_ms / 1e3) / 1e12
     return {"config": f"qs_beam {w.dims[0]}x{w.dims[1]}x{w.dims[2]}, trilinear law {pi.LAW_TRILINEAR}, velocity "
                       f"Verlet, zones, f64",
             "bond_slots": nnz, "mapping": mapping, "steps": steps,
             "value": nnz * steps / t_law, "unit": "bond-updates/s", "avg_launch_ms": dev_ms,
-            "alu_frac": tflops / PEAK_VALU_TFLOPS["f64"], "softened_fraction_after": soft,
+            "softened_fraction_after": soft,
             "band_softened_fraction": float(band.mean()), "rate_band_softened": nnz * steps / t_band,
             "band_softened_vs_start": t_law / t_band,
             "rate_all_softened": nnz * steps / t_all, "all_softened_vs_start": t_law / t_all}
@@ -329,6 +368,30 @@ def state_based_extra(P, pi, sync, workload: str, steps: int, plain_ms: float):
             "fp32": {"value": nnz * steps / t32, "step_ms": dev32, "vs_fp64": dev_ms / dev32}}
 
 
+def wide_extra(P, pi, sync, steps: int):
+    """The 1M-node cube at the wider horizon 5.015 dx (514 neighbours per node, 485,972,824
+    slots), FP64, Euler-Cromer, one wavefront per slice of the staged mapping, natural
+    order (the headline's choice on the 3.015 dx cube)."""
+    w = pi.workload("cube100_wide")
+    w.order = "natural"
+    t0 = time.perf_counter()
+    sim = P.simulation_for(w, mapping="staged")
+    sim.prepare()
+    setup = time.perf_counter() - t0
+    info = sim.info()
+    sim.step(5)
+    sim.sync()
+    t = _timed(lambda: (sim.step(steps), sim.sync()), sync)
+    dev_ms = sim.last_step_ms() / steps
+    sim.close()
+    nnz = info["n_slots"]
+    return {"config": "cube100_wide 100x100x100 lattice, horizon 5.015 dx, euler_cromer, staged-1, natural order, f64",
+            "bond_slots": nnz, "steps": steps, "setup_s": setup, "value": nnz * steps / t, "unit": "bond-updates/s",
+            "ms_per_step": t * 1e3 / steps, "avg_launch_ms": dev_ms,
+            "model_bytes_per_step": info["model_bytes_per_step"],
+            "hbm_frac": info["model_bytes_per_step"] / (dev_ms / 1e3) / 1e9 / PEAK_HBM_GBS}
+
+
 def fp32_extra(P, pi, sync, workload: str, steps: int):
     """The FP32 build (f32 bond arithmetic, f64 master displacement) on the headline
     workload with the staged mapping, the only mapping it runs."""
@@ -366,6 +429,7 @@ def main():
     ap.add_argument("--order", default="auto", choices=["auto", "natural", "morton"],
                     help="device node order (auto: the autotuner tries both)")
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-single-steps", type=int, default=2, help="oracle steps timed on one core")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32, adjoint, batched and quasi-static measurements")
@@ -439,8 +503,9 @@ def main():
     model_bytes = info["model_bytes_per_step"]
     achieved_gbs = model_bytes / per_launch_s / 1e9
     traffic = measured_traffic(args.workload, args.precision)
-    tflops = nnz * FLOPS_PER_SLOT[args.precision] / per_launch_s / 1e12
+    tflops = nnz * ALGO_FLOPS_PER_SLOT / per_launch_s / 1e12
     peak = PEAK_VALU_TFLOPS[args.precision]
+    counters = profile_values(COUNTERS) if (args.workload, args.precision) == ("cube100", "f64") else {}
     out = {
         "metric": "bond-updates/s (bonds*steps/s) & % HBM peak; batched/adjoint vs plain step",
         "value": value,
@@ -460,15 +525,17 @@ def main():
                    "nodes": info["n_nodes"], "bond_slots": nnz, "mapping": mapping, "lanes_per_node": lanes,
                    "device_node_order": order,
                    "parallelism": "1 GPU"},
-        # the step kernel issues FP64 (or FP32) vector arithmetic faster than HBM can feed
-        # it only at a fraction of the HBM rate: it is bound by vector ALU issue
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
-                     "frac": tflops / peak, "traffic": traffic,
-                     "algorithmic_flops_per_slot": FLOPS_PER_SLOT[args.precision],
-                     "avg_launch_ms": per_launch_s * 1e3,
-                     "hbm": {"achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                             "frac": achieved_gbs / PEAK_HBM_GBS,
-                             "algorithmic_bytes_per_launch": model_bytes, "measured_bytes_per_launch": traffic}},
+        # the method's roofline is HBM bandwidth over its compulsory bytes per step (4 B
+        # per slot, node state read and written); beside it the method's own FP64
+        # arithmetic against the vector peak and the instructions the kernel issues
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": model_bytes, "avg_launch_ms": per_launch_s * 1e3,
+                     "alu": {"achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
+                             "algorithmic_flops_per_slot": ALGO_FLOPS_PER_SLOT,
+                             "valu_instructions_per_slot_row":
+                                 float(counters["valu_wave_instructions_per_slot_row"])
+                                 if "valu_wave_instructions_per_slot_row" in counters else None}},
     }
     sim.close()
     if args.model == "state_based":  # a profiling run: the PMB roofline does not apply
@@ -495,9 +562,13 @@ def main():
         out["damage_law"] = damage_law_extra(P, pi, torch_sync, args.steps)
         out["damage_law"]["vs_brittle_zones"] = out["damage_law"]["value"] / out["quasistatic"]["value"]
         print(f"# damage_law {out['damage_law']}", file=sys.stderr, flush=True)
+        if args.workload == "cube100" and args.precision == "f64":
+            out["cube100_wide"] = wide_extra(P, pi, torch_sync, args.steps)
+            print(f"# cube100_wide {out['cube100_wide']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
+        # the oracle on the box's share of host cores (16 on the GPU machine) and on one
         threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, threads)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, threads, args.cpu_single_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -233,7 +233,7 @@ int pd_clear_damage_laws(pd_ctx *ctx, int32_t inst);
 #define PD_MICRO_CONICAL 1   /* c(|xi|) = c max(0, 1 - |xi|/delta): c is the peak value (5 times the
                                 constant micromodulus for the same bulk stiffness) */
 
-/* Stiffness corrections of one instance (Secs. 2.2-2.3), each a factor on every slot's
+/* Stiffness corrections of one instance (Secs. 2.2, 2.3 and 2.5), each a factor on every slot's
  * stiffness, applied in this order: the micromodulus profile; partial volumes, beta = 1
  * for |xi| <= delta - dx/2, falling linearly to 0 at delta + dx/2 (the share of a
  * neighbour's cell inside the horizon; build the family with horizon delta + dx/2 to
@@ -379,6 +379,40 @@ int pd_set_state(pd_ctx *ctx, int32_t inst, const double *u, const double *v, co
                  const uint8_t *broken);
 int pd_set_step(pd_ctx *ctx, int64_t step);
 
+/* The whole state of one instance, for checkpoint and restart (Sec. 3.6: a run may
+ * continue from a saved step).  Arrays are host memory owned by the caller, in the
+ * caller's node and slot order; a NULL array is skipped. */
+typedef struct pd_state {
+    double *u;            /* n x 3: displacement of the current level (FP32 build: the
+                             f64 master displacement the integrator advances) */
+    double *v;            /* n x 3: velocity */
+    double *a;            /* n x 3: acceleration (velocity Verlet; otherwise whatever the
+                             problem holds, zeros for a fresh one) */
+    uint8_t *broken;      /* nnz: 1 = broken */
+    int32_t *break_step;  /* nnz: pass in which the slot broke, INT32_MAX intact,
+                             INT32_MIN broken before recording started (pd_get_break_steps) */
+    double *max_stretch;  /* nnz: damage-law stretch state (pd_get_max_stretch; zeros
+                             without damage laws) */
+    int64_t step;         /* step counter (shared by every instance) */
+    int32_t a_valid;      /* 1 when a holds the acceleration of the current level */
+    int32_t pad_;
+} pd_state;
+
+/* Export the state of instance `inst` into the caller's arrays (each NULL array is
+ * skipped) and set out->step and out->a_valid.  Synchronising. */
+int pd_get_state(pd_ctx *ctx, int32_t inst, pd_state *out);
+
+/* Restore a state exported by pd_get_state, possibly into another context holding the
+ * same problem (same family, material and boundary conditions): stepping on from it gives
+ * bit for bit what the exporting context gives.  NULL arrays keep the current values;
+ * u replaces both displacement levels; broken replaces the broken set exactly (the
+ * break steps then restart from it, unless break_step is given too); a max_stretch with
+ * a non-zero entry needs damage laws (PD_ESTATE otherwise; all zeros, as exported for a
+ * problem without laws, is ignored); step sets the step counter of every instance;
+ * a_valid is honoured only together with a.  Discards any adjoint recording.  Errors: PD_EINVAL (non-finite u, v, a or max_stretch, negative
+ * max_stretch, step out of [0, 2^31 - 1)). */
+int pd_load_state(pd_ctx *ctx, int32_t inst, const pd_state *in);
+
 /* ---------------------------------------------------------------- adjoint */
 
 /* Reverse-mode gradients of a displacement misfit after an Euler-Cromer run with the
@@ -392,8 +426,10 @@ int pd_set_step(pd_ctx *ctx, int64_t step);
  * every ckpt_every >= 1 steps ((nn + 89) * 48 + nn * 24 bytes each, nn = padded node
  * count; with ckpt_every = 1 every level is kept, v is not, and the reverse pass
  * recomputes nothing).  Any later change to the problem or state (pd_step included)
- * discards the recording.  Asynchronous like pd_step. */
-int pd_adj_forward(pd_ctx *ctx, int64_t nsteps, int32_t ckpt_every);
+ * discards the recording.  Asynchronous like pd_step.  *recording (may be NULL)
+ * receives an id of this recording, unique in the process and > 0 (0 on error), which
+ * pd_adj_backward takes to make sure its gradient belongs to this run. */
+int pd_adj_forward(pd_ctx *ctx, int64_t nsteps, int32_t ckpt_every, int64_t *recording);
 
 /* Gradient of a loss L(u^T) at the end of the recorded run.  The caller passes
  * dL/du^T for m >= 0 sensor nodes: sensors (host, m user node ids, repeats add up) and
@@ -403,9 +439,11 @@ int pd_adj_forward(pd_ctx *ctx, int64_t nsteps, int32_t ckpt_every);
  * Each segment between checkpoints is recomputed with the forward kernel (same
  * results bit for bit) into a trajectory buffer of min(ckpt_every, nsteps) levels,
  * then the reverse passes run last to first.  The problem state is left unchanged.
- * Synchronising; PD_ESTATE if there is no valid recording. */
-int pd_adj_backward(pd_ctx *ctx, int64_t m, const int64_t *sensors, const double *dL_du, double *grad_k,
-                    double *grad_A);
+ * recording: the id pd_adj_forward returned, or 0 for whichever recording is current.
+ * Synchronising; PD_ESTATE if there is no valid recording or it is not `recording`
+ * (another pd_adj_forward ran since, or the problem or state changed). */
+int pd_adj_backward(pd_ctx *ctx, int64_t recording, int64_t m, const int64_t *sensors, const double *dL_du,
+                    double *grad_k, double *grad_A);
 
 /* Pass index in which each slot broke (host out[nnz], user CSR order): INT32_MAX =
  * intact, INT32_MIN = already broken when the broken set was last established (problem
@@ -438,6 +476,15 @@ int pd_get_info(const pd_ctx *ctx, pd_info *info);
 /* Device time of the last pd_step call in milliseconds (HIP events recorded on the
  * context's stream around that call's kernels); synchronising. */
 int pd_last_step_ms(pd_ctx *ctx, double *ms);
+
+/* The exact stretch the FP64 step kernels decide near the break threshold (Eq. mu:
+ * s = (|y| - |xi|)/|xi|, squares summed as (a^2 + b^2) + c^2, every operation rounded
+ * once, no fused multiply-add, correctly rounded square roots and division), evaluated
+ * on `device` for m bonds: xi and y host m x 3 (row-major), s host m doubles.  For
+ * checking that the device arithmetic agrees bit for bit with an IEEE host evaluation.
+ * Synchronising; allocates and frees its own device buffers.  Errors: PD_EINVAL (m < 0,
+ * NULL arrays with m > 0, bad device), PD_EHIP. */
+int pd_stretch_exact(int device, int64_t m, const double *xi, const double *y, double *s);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,7 @@
  *                   reading: the bond follows the secant to the origin once it has softened)
  *   corrections     a conical micromodulus c (1 - |xi|/delta), partial volumes beta(|xi|) of
  *                   neighbours cut by the horizon, and the volume-method surface correction
- *                   lambda_ij = 2 V0 / (V_i + V_j) over family volumes (Secs. 2.2-2.3)
+ *                   lambda_ij = 2 V0 / (V_i + V_j) over family volumes (Sec. 2.5)
  *   quasi-static    prescribed displacements ramped by a fifth-order polynomial in time with
  *   loading         zero initial velocity and acceleration (Examples 2 and 3, Secs. 6-7), and
  *                   'no-failure zones': bonds of flagged nodes never break (Secs. 5.1, 6, 7).

@@ -196,13 +196,24 @@ class Simulation:
     def set_step(self, step):
         B.pd_set_step(self.ctx, step)
 
+    def get_state(self, inst=0):
+        """The whole state (checkpoint): a dict of u, v, a, broken, break_step,
+        max_stretch, step and a_valid."""
+        return B.pd_get_state(self.ctx, inst)
+
+    def load_state(self, state, inst=0):
+        """Restore a state from get_state (this or another context on the same problem)."""
+        B.pd_load_state(self.ctx, inst, state)
+
     # adjoint (Euler-Cromer, frozen break schedule)
     def adj_forward(self, nsteps, ckpt_every=100):
-        B.pd_adj_forward(self.ctx, nsteps, ckpt_every)
+        """Records a forward run; returns the recording's id."""
+        return B.pd_adj_forward(self.ctx, nsteps, ckpt_every)
 
-    def adj_backward(self, sensors, dL_du):
-        """(grad_k[nnz], grad_A) of a loss whose gradient at the sensors is dL_du (m x 3)."""
-        return B.pd_adj_backward(self.ctx, sensors, dL_du)
+    def adj_backward(self, sensors, dL_du, recording=0):
+        """(grad_k[nnz], grad_A) of a loss whose gradient at the sensors is dL_du (m x 3),
+        for the recording with id `recording` (0: the current one)."""
+        return B.pd_adj_backward(self.ctx, sensors, dL_du, recording)
 
     def break_steps(self, inst=0):
         return B.pd_get_break_steps(self.ctx, inst)

@@ -35,6 +35,7 @@ SYMBOLS = [
     "pd_step", "pd_prepare", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
     "pd_get_info", "pd_last_step_ms", "pd_adj_forward", "pd_adj_backward", "pd_get_break_steps",
+    "pd_get_state", "pd_load_state", "pd_stretch_exact",
 ]
 
 
@@ -47,6 +48,12 @@ class PdmiError(RuntimeError):
 class pd_material(C.Structure):
     _fields_ = [("rho", C.c_double), ("c", C.c_double), ("s0", C.c_double), ("eta", C.c_double),
                 ("volume", C.c_double), ("volumes", C.c_void_p)]
+
+
+class pd_state(C.Structure):
+    _fields_ = [("u", C.c_void_p), ("v", C.c_void_p), ("a", C.c_void_p), ("broken", C.c_void_p),
+                ("break_step", C.c_void_p), ("max_stretch", C.c_void_p), ("step", C.c_int64),
+                ("a_valid", C.c_int32), ("pad_", C.c_int32)]
 
 
 class pd_info(C.Structure):
@@ -113,9 +120,12 @@ def load() -> C.CDLL:
         "pd_autotune": [P, i64, P],
         "pd_get_info": [P, P],
         "pd_last_step_ms": [P, P],
-        "pd_adj_forward": [P, i64, i32],
-        "pd_adj_backward": [P, i64, P, P, P, P],
+        "pd_adj_forward": [P, i64, i32, P],
+        "pd_adj_backward": [P, i64, i64, P, P, P, P],
         "pd_get_break_steps": [P, i32, P],
+        "pd_get_state": [P, i32, P],
+        "pd_load_state": [P, i32, P],
+        "pd_stretch_exact": [C.c_int, i64, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -456,19 +466,61 @@ def pd_last_step_ms(ctx) -> float:
     return v.value
 
 
-def pd_adj_forward(ctx, nsteps: int, ckpt_every: int) -> None:
-    _check(ctx, load().pd_adj_forward(ctx, int(nsteps), int(ckpt_every)))
+def pd_adj_forward(ctx, nsteps: int, ckpt_every: int) -> int:
+    """Returns the id of the recording."""
+    rec = C.c_int64()
+    _check(ctx, load().pd_adj_forward(ctx, int(nsteps), int(ckpt_every), C.byref(rec)))
+    return rec.value
 
 
-def pd_adj_backward(ctx, sensors, dL_du):
-    """Returns (grad_k[nnz], grad_A) for dL/du^T given at the sensor nodes (m x 3)."""
+def pd_adj_backward(ctx, sensors, dL_du, recording: int = 0):
+    """Returns (grad_k[nnz], grad_A) for dL/du^T given at the sensor nodes (m x 3) of the
+    recording `recording` (0: the current one)."""
     sn = np.ascontiguousarray(sensors, dtype=np.int64).reshape(-1)
     dl = _f64(dL_du, (sn.shape[0], 3))
     nnz = pd_instance_size(ctx, 0)[1]
     gk = np.zeros(max(nnz, 1))
     gA = C.c_double()
-    _check(ctx, load().pd_adj_backward(ctx, sn.shape[0], _p(sn), _p(dl), _p(gk), C.byref(gA)))
+    _check(ctx, load().pd_adj_backward(ctx, int(recording), sn.shape[0], _p(sn), _p(dl), _p(gk), C.byref(gA)))
     return gk[:nnz], gA.value
+
+
+def pd_get_state(ctx, inst: int = 0) -> dict:
+    """The whole state of an instance: u, v, a, broken, break_step, max_stretch (arrays
+    in user order), step and a_valid."""
+    n, nnz = pd_instance_size(ctx, inst)
+    arr = {"u": np.zeros((n, 3)), "v": np.zeros((n, 3)), "a": np.zeros((n, 3)),
+           "broken": np.zeros(max(nnz, 1), dtype=np.uint8), "break_step": np.zeros(max(nnz, 1), dtype=np.int32),
+           "max_stretch": np.zeros(max(nnz, 1))}
+    st = pd_state(*(_p(arr[k]) for k in ("u", "v", "a", "broken", "break_step", "max_stretch")), 0, 0, 0)
+    _check(ctx, load().pd_get_state(ctx, inst, C.byref(st)))
+    for k in ("broken", "break_step", "max_stretch"):
+        arr[k] = arr[k][:nnz]
+    arr["step"], arr["a_valid"] = int(st.step), int(st.a_valid)
+    return arr
+
+
+def pd_load_state(ctx, inst: int, state: dict) -> None:
+    """Restore a state as pd_get_state returns it (missing or None entries are kept)."""
+    def get(k, dt):
+        v = state.get(k)
+        return None if v is None else np.ascontiguousarray(v, dtype=dt)
+    u, v, a = get("u", np.float64), get("v", np.float64), get("a", np.float64)
+    br, bs, sm = get("broken", np.uint8), get("break_step", np.int32), get("max_stretch", np.float64)
+    st = pd_state(_p(u), _p(v), _p(a), _p(br), _p(bs), _p(sm), int(state.get("step", 0)),
+                  int(state.get("a_valid", 0)), 0)
+    _check(ctx, load().pd_load_state(ctx, inst, C.byref(st)))
+
+
+def pd_stretch_exact(xi, y, device: int = 0) -> np.ndarray:
+    """The device's exact stretch (m bonds; xi, y m x 3)."""
+    xx = _f64(xi).reshape(-1, 3)
+    yy = _f64(y, xx.shape)
+    s = np.zeros(max(xx.shape[0], 1))
+    rc = load().pd_stretch_exact(int(device), xx.shape[0], _p(xx), _p(yy), _p(s))
+    if rc != PD_OK:
+        raise PdmiError(rc, "pd_stretch_exact failed")
+    return s[: xx.shape[0]]
 
 
 def pd_get_break_steps(ctx, inst: int = 0) -> np.ndarray:

@@ -4,7 +4,9 @@
 initial state with slot stiffness ``k`` (nnz) and body-force magnitude ``A`` and returns
 the displacement of the sensor nodes after ``problem.nsteps`` steps (m x 3).  Its
 backward calls the library's reverse pass (break schedule of the forward run frozen,
-checkpoints every ``problem.ckpt_every`` steps).  Torch only carries the tensors: the
+checkpoints every ``problem.ckpt_every`` steps) on that forward run's recording; a
+backward after another forward on the same simulation raises instead of returning the
+later run's gradient.  Torch only carries the tensors: the
 forward and reverse passes run in the HIP library.
 """
 from __future__ import annotations
@@ -43,7 +45,7 @@ class SensorDisplacement(torch.autograd.Function):
     def forward(ctx, k: torch.Tensor, A: torch.Tensor, problem: AdjointProblem):
         kk = k.detach().to("cpu", torch.float64).numpy()
         problem.reset(kk, float(A))
-        problem.sim.adj_forward(problem.nsteps, problem.ckpt_every)
+        ctx.recording = problem.sim.adj_forward(problem.nsteps, problem.ckpt_every)
         u = problem.sim.u()[problem.sensors]
         ctx.problem = problem
         return torch.from_numpy(u).to(k.device)
@@ -51,7 +53,9 @@ class SensorDisplacement(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_u: torch.Tensor):
         g = grad_u.detach().to("cpu", torch.float64).numpy()
-        gk, gA = ctx.problem.sim.adj_backward(ctx.problem.sensors, g)
+        # the library refuses (PdmiError, PD_ESTATE) if the problem's simulation has
+        # recorded another forward run since this one: its tape no longer holds this run
+        gk, gA = ctx.problem.sim.adj_backward(ctx.problem.sensors, g, ctx.recording)
         dev = grad_u.device
         return torch.from_numpy(gk).to(dev), torch.tensor(gA, dtype=torch.float64, device=dev), None
 

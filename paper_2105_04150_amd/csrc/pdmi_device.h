@@ -43,6 +43,33 @@ __device__ __forceinline__ double one_minus_rsqrt1p(double q, const SeriesCoef& 
     return 1.0 - rsq64<2>(1.0 + q);
 }
 
+// The critical-stretch decision made exactly as the oracle makes it (Eq. mu; the bond
+// kernel keeps a bond only while s < s0): s = (|y| - |xi|)/|xi| with the squares summed
+// as (a^2 + b^2) + c^2, every product and sum rounded once (no fused multiply-add), and
+// the square roots and the division correctly rounded (the device's IEEE sequences).  The
+// step kernels decide on the cancellation-free q almost always; a slot whose q lies
+// within the instance's margin of the threshold (or a law's breakpoint) is decided here,
+// so that two implementations reading the same x and u break the same bonds.
+__device__ __forceinline__ double stretch_exact(double xi0, double xi1, double xi2, double y0, double y1, double y2)
+{
+#pragma clang fp contract(off)
+    const double r = __builtin_sqrt((y0 * y0 + y1 * y1) + y2 * y2);
+    const double L = __builtin_sqrt((xi0 * xi0 + xi1 * xi1) + xi2 * xi2);
+    return (r - L) / L;
+}
+
+// The same from a neighbour record {x_j, u_j} (6 doubles) and the owner's (X, U): the
+// bond vector and the deformed bond formed as the oracle forms them,
+// xi = x_j - x_i and y = xi + (u_j - u_i).
+__device__ __forceinline__ double stretch_exact_rec(const double2 p0, const double2 p1, const double2 p2, double X0,
+                                                    double X1, double X2, double U0, double U1, double U2)
+{
+#pragma clang fp contract(off)
+    const double xi0 = p0.x - X0, xi1 = p0.y - X1, xi2 = p1.x - X2;
+    const double y0 = xi0 + (p1.y - U0), y1 = xi1 + (p2.x - U1), y2 = xi2 + (p2.y - U2);
+    return stretch_exact(xi0, xi1, xi2, y0, y1, y2);
+}
+
 // Series coefficients as opaque registers: the outer ones in scalar registers (each FMA
 // of the Horner chain reads one), the innermost in a vector register (the first FMA
 // reads two constants).

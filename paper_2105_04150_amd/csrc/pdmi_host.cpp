@@ -158,6 +158,7 @@ struct pd_ctx {
     DevBuf na, nw;                   // per-node stiffness: sqrt(k_i) and sqrt(k_j) V_j (entry nn: 0)
     bool tape_valid = false;
     int64_t tape_step0 = 0, tape_nsteps = 0, tape_every = 0;
+    int64_t tape_id = 0;             // id of the last recording (unique in the process, > 0)
 
     // graphs: [parity][mode] for chunks of kGraphChunk steps
     hipGraphExec_t graph[2][4] = {{nullptr}};
@@ -427,7 +428,9 @@ InstParams make_params(const Inst& I, int32_t law_off)
 {
     InstParams p{};
     p.c = I.c;
-    p.q0 = I.s0 * (2.0 + I.s0);
+    const double qt = I.s0 * (2.0 + I.s0);  // (1 + s0)^2 - 1
+    p.q0 = qt - decision_margin(qt);
+    p.s0 = I.s0;
     p.nlaw = static_cast<int32_t>(I.laws.size());
     p.law_off = law_off;
     if (!I.laws.empty()) {
@@ -435,7 +438,7 @@ InstParams make_params(const Inst& I, int32_t law_off)
         // elastic limit (the branch itself decides in stretch)
         double qmin = std::numeric_limits<double>::infinity();
         for (const LawRec& L : I.laws) qmin = std::min(qmin, L.s[0] * (2.0 + L.s[0]));
-        p.q0 = qmin * (1.0 - 1e-9);
+        p.q0 = qmin - decision_margin(qmin);
     }
     p.rho = I.rho;
     p.eta = I.eta;
@@ -2404,6 +2407,105 @@ int pd_set_step(pd_ctx* ctx, int64_t step)
     });
 }
 
+int pd_get_state(pd_ctx* ctx, int32_t inst, pd_state* out)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out) fail(PD_EINVAL, "out is NULL");
+        require_built(ctx);
+        set_device(ctx);
+        auto put = [](auto* dst, const auto& src) { std::memcpy(dst, src.data(), src.size() * sizeof(src[0])); };
+        if (out->u) put(out->u, u_of(ctx, I));
+        if (out->v) put(out->v, soa_of(ctx, I, ctx->v));
+        if (out->a) put(out->a, soa_of(ctx, I, ctx->a));
+        if (out->broken) put(out->broken, broken_of(ctx, I));
+        if (out->max_stretch) put(out->max_stretch, smax_of(ctx, I));
+        if (out->break_step) {
+            std::vector<int32_t> h(static_cast<size_t>(I.n_dslots));
+            download(h.data(), ctx->bstep, h.size() * sizeof(int32_t), static_cast<size_t>(I.dslot_off) * sizeof(int32_t),
+                     ctx->stream);
+            sync(ctx);
+            for (int64_t d = 0; d < I.n_dslots; ++d)
+                if (I.dslot_user[d] >= 0) out->break_step[I.dslot_user[d]] = h[d];
+        }
+        out->step = ctx->step;
+        out->a_valid = ctx->a_valid ? 1 : 0;
+        check_status(ctx);
+    });
+}
+
+int pd_load_state(pd_ctx* ctx, int32_t inst, const pd_state* in)
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        Inst& I = instance(ctx, inst);
+        if (!in) fail(PD_EINVAL, "in is NULL");
+        require_built(ctx);
+        for (const double* p : {static_cast<const double*>(in->u), static_cast<const double*>(in->v), static_cast<const double*>(in->a)})
+            if (p)
+                for (int64_t q = 0; q < 3 * I.n; ++q)
+                    if (!std::isfinite(p[q])) fail(PD_EINVAL, "state must be finite");
+        // a stretch state: needs damage laws unless it is all zeros (what pd_get_state
+        // exports for a problem without laws), which is then ignored
+        const double* smax_in = in->max_stretch;
+        if (smax_in) {
+            bool zero = true;
+            for (int64_t b = 0; b < I.nnz; ++b) {
+                if (!std::isfinite(smax_in[b]) || smax_in[b] < 0.0) fail(PD_EINVAL, "stretch state must be finite and >= 0");
+                zero = zero && smax_in[b] == 0.0;
+            }
+            if (!ctx->has_laws) {
+                if (!zero) fail(PD_ESTATE, "a non-zero max_stretch given without damage laws");
+                smax_in = nullptr;
+            }
+        }
+        if (in->step < 0 || in->step >= std::numeric_limits<int32_t>::max()) fail(PD_EINVAL, "step out of range");
+        set_device(ctx);
+        if (in->u) upload_state(ctx, I, in->u, nullptr, nullptr);  // both displacement levels
+        upload_state(ctx, I, nullptr, in->v, in->a);
+        if (in->broken || smax_in) {
+            const std::vector<uint8_t> br = in->broken ? std::vector<uint8_t>() : broken_of(ctx, I);
+            const std::vector<double> sm = smax_in ? std::vector<double>() : smax_of(ctx, I);
+            upload_col(ctx, I, in->broken ? in->broken : br.data(), !in->broken, smax_in ? smax_in : sm.data());
+        }
+        if (in->break_step) {
+            std::vector<int32_t> h(static_cast<size_t>(I.n_dslots), kBrokeBefore);  // padding counts as broken
+            for (int64_t d = 0; d < I.n_dslots; ++d)
+                if (I.dslot_user[d] >= 0) h[d] = in->break_step[I.dslot_user[d]];
+            upload(ctx->bstep, h.data(), h.size() * sizeof(int32_t), static_cast<size_t>(I.dslot_off) * sizeof(int32_t),
+                   ctx->stream);
+        }
+        ctx->tape_valid = false;
+        ctx->step = in->step;
+        upload(ctx->step_base, &in->step, sizeof in->step, 0, ctx->stream);
+        ctx->drop_graphs();
+        reset_flags_after_state_change(ctx, in->a && in->a_valid);
+    });
+}
+
+int pd_stretch_exact(int device, int64_t m, const double* xi, const double* y, double* s)
+{
+    if (m < 0 || (m > 0 && (!xi || !y || !s))) return PD_EINVAL;
+    if (m == 0) return PD_OK;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) return PD_EHIP;
+    if (device < 0 || device >= count) return PD_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return PD_EHIP;
+    const size_t v3 = static_cast<size_t>(3 * m) * sizeof(double), v1 = static_cast<size_t>(m) * sizeof(double);
+    void* d = nullptr;
+    if (hipMalloc(&d, 2 * v3 + v1) != hipSuccess) return PD_ENOMEM;
+    char* b = static_cast<char*>(d);
+    hipError_t e = hipMemcpy(b, xi, v3, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b + v3, y, v3, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_stretch_exact(reinterpret_cast<const double*>(b), reinterpret_cast<const double*>(b + v3),
+                                 reinterpret_cast<double*>(b + 2 * v3), m, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(s, b + 2 * v3, v1, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return e == hipSuccess ? PD_OK : PD_EHIP;
+}
+
 int pd_set_mapping(pd_ctx* ctx, int mapping, int lanes)
 {
     if (!ctx) return PD_EINVAL;
@@ -2494,9 +2596,14 @@ int pd_autotune(pd_ctx* ctx, int64_t trial_steps, int32_t* chosen)
     });
 }
 
-int pd_adj_forward(pd_ctx* ctx, int64_t nsteps, int32_t ckpt_every)
+namespace {
+std::atomic<int64_t> g_recordings{0};  // recording ids handed out in this process
+}
+
+int pd_adj_forward(pd_ctx* ctx, int64_t nsteps, int32_t ckpt_every, int64_t* recording)
 {
     if (!ctx) return PD_EINVAL;
+    if (recording) *recording = 0;
     return guarded(ctx, [&] {
         adjoint_checks(ctx);
         if (nsteps < 1) fail(PD_EINVAL, "nsteps must be >= 1");
@@ -2538,6 +2645,8 @@ int pd_adj_forward(pd_ctx* ctx, int64_t nsteps, int32_t ckpt_every)
             ctx->tape_step0 = step0;
             ctx->tape_nsteps = nsteps;
             ctx->tape_every = 1;
+            ctx->tape_id = ++g_recordings;
+            if (recording) *recording = ctx->tape_id;
             return;
         }
         ctx->ck.alloc(static_cast<size_t>(C) * stride);
@@ -2554,16 +2663,20 @@ int pd_adj_forward(pd_ctx* ctx, int64_t nsteps, int32_t ckpt_every)
         ctx->tape_step0 = step0;
         ctx->tape_nsteps = nsteps;
         ctx->tape_every = ckpt_every;
+        ctx->tape_id = ++g_recordings;
+        if (recording) *recording = ctx->tape_id;
     });
 }
 
-int pd_adj_backward(pd_ctx* ctx, int64_t m, const int64_t* sensors, const double* dL_du, double* grad_k,
-                    double* grad_A)
+int pd_adj_backward(pd_ctx* ctx, int64_t recording, int64_t m, const int64_t* sensors, const double* dL_du,
+                    double* grad_k, double* grad_A)
 {
     if (!ctx) return PD_EINVAL;
     return guarded(ctx, [&] {
         adjoint_checks(ctx);
         if (!ctx->tape_valid) fail(PD_ESTATE, "no recorded forward run (pd_adj_forward) for the current problem");
+        if (recording != 0 && recording != ctx->tape_id)
+            fail(PD_ESTATE, "the recording asked for has been replaced by a later pd_adj_forward or discarded");
         if (m < 0 || (m > 0 && (!sensors || !dL_du))) fail(PD_EINVAL, "bad sensor arguments");
         if (!grad_k || !grad_A) fail(PD_EINVAL, "gradient outputs are NULL");
         const Inst& I = ctx->inst[0];

@@ -86,10 +86,20 @@ static_assert(kEntPad <= kEntOff, "entry offsets fit 13 bits");
 constexpr int32_t kNodeFree = -1;       // bc_id of an unconstrained node
 constexpr int32_t kNodePad = -2;        // bc_id of a padding node (never updated)
 
+// Margin of the fast break decisions: a q (or a stretch) within this distance of a
+// threshold t is decided on the exact stretch (stretch_exact).  The fast q carries a
+// relative error near 1e-14 (one Newton step on the reciprocal length), the oracle's
+// stretch an absolute error near 1e-16; the margin is far wider than both and so narrow
+// that slots rarely land inside it.
+__host__ __device__ inline double decision_margin(double t) { return 1e-9 * (t < 0.0 ? -t : t) + 1e-15; }
+
 struct InstParams {
     double c;        // micromodulus without a stiffness field
-    double q0;       // break threshold on q = r^2/L^2 - 1: (1 + s0)^2 - 1; with damage
-                     // laws, a threshold just below every law's elastic limit
+    double q0;       // lower edge of the break decision on q = r^2/L^2 - 1: the threshold
+                     // (1 + s0)^2 - 1 minus its margin (a slot at or above it takes the
+                     // rare branch, which decides on the exact stretch); with damage laws,
+                     // just below every law's elastic limit
+    double s0;       // critical stretch of the brittle law
     double rho;
     double eta;
     double volume;   // uniform node volume without a volume array
@@ -215,6 +225,8 @@ hipError_t launch_advance(int64_t* step_base, int64_t by, hipStream_t s);
 hipError_t launch_export_nodes(const double* src, int64_t snode, int64_t scomp, int64_t off, const int64_t* dnode,
                                int64_t n, int ncomp, double* out, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t value, hipStream_t s);
+// s[b] = the exact stretch (stretch_exact) of bond b, xi and y m x 3 row-major
+hipError_t launch_stretch_exact(const double* xi, const double* y, double* s, int64_t m, hipStream_t st);
 
 // ---------------------------------------------------------------- adjoint (Euler-Cromer)
 //

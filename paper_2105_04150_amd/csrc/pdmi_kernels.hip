@@ -216,6 +216,22 @@ hipError_t launch_set_sum(const double* field, int64_t snode, int64_t scomp, con
     return hipGetLastError();
 }
 
+// Exact stretch of m bonds (xi, y: m x 3 row-major), one work-item per bond.
+__global__ __launch_bounds__(kBlock) void stretch_exact_kernel(const double* xi, const double* y, double* s, int64_t m)
+{
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (b >= m) return;
+    s[b] = stretch_exact(xi[3 * b], xi[3 * b + 1], xi[3 * b + 2], y[3 * b], y[3 * b + 1], y[3 * b + 2]);
+}
+
+hipError_t launch_stretch_exact(const double* xi, const double* y, double* s, int64_t m, hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stretch_exact_kernel, dim3(static_cast<unsigned>((m + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       st, xi, y, s, m);
+    return hipGetLastError();
+}
+
 hipError_t launch_advance(int64_t* step_base, int64_t by, hipStream_t s)
 {
     hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, step_base, by);

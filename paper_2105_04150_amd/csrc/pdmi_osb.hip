@@ -215,15 +215,21 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         const double tq = __builtin_fma(e2, z2, __builtin_fma(e1, z1, e0 * z0));
         const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
         const double q = tq * rcp64_1(L2);  // neither pass needs 1/|xi| itself
-        const bool brk = BREAK && live && !(e & kEntNoFail) && q >= P.q0;
-        const bool alive = live && !brk;
+        // a break candidate: q at or above the lower edge of the decision (the rare branch
+        // below decides, on the exact stretch within the margin)
+        const bool cand = BREAK && live && !(e & kEntNoFail) && q >= P.q0;
+        const bool alive = live && !cand;
         const double vj = VOLN ? lvol[(off * 0xAAABu) >> 21] : 1.0;
         if (PASS == 0) {
             const double s = sqrt1p_minus1(alive ? q : 0.0);
             D = __builtin_fma(VOLN ? L2 * vj : L2, s, D);  // |xi| e = |xi|^2 s; 0 for broken and padding slots
-            if (brk) {
-                entw[ds] = static_cast<uint16_t>(e | kEntBroken);
-                A.bstep[ds] = step;
+            if (cand) {
+                if (stretch_exact(xi0, xi1, xi2, y0, y1, y2) >= P.s0) {
+                    entw[ds] = static_cast<uint16_t>(e | kEntBroken);
+                    A.bstep[ds] = step;
+                } else {  // holds: the term the common path left out
+                    D = __builtin_fma(VOLN ? L2 * vj : L2, sqrt1p_minus1(q), D);
+                }
             }
         } else {
             const double g = one_minus_rsqrt1p(alive ? q : 0.0, sk);
@@ -242,6 +248,7 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;
         for (int q = p + 1; q < p + S && q < p1; ++q) ent_next += static_cast<int64_t>(rows_of(q)) * kWave;
         wave_sync();  // the previous piece is no longer read
+        lds_reads_done();
         dma(p, ent);
         // s_waitcnt with vmcnt = 0 (expcnt and lgkmcnt at their no-wait maxima): the
         // piece's direct-to-LDS loads have landed

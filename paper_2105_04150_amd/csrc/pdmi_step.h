@@ -15,10 +15,14 @@
 // Bond arithmetic (per slot b = (i, j), Eqs. microelastic and simpleBond):
 //   xi = x_j - x_i,  eta = u_j - u_i,  y = xi + eta
 //   q  = |y|^2/|xi|^2 - 1 = (2 xi.eta + eta.eta) / |xi|^2      (no cancellation)
-//   break when q >= (1 + s0)^2 - 1, i.e. s >= s0
+//   break when s >= s0, i.e. q >= (1 + s0)^2 - 1
 //   f  = c s V_j y/|y| = c V_j (1/|xi|) (1 - (1+q)^(-1/2)) y
 // 1 - (1+q)^(-1/2) is summed as its binomial series for |q| < 4e-3, so small stretches
 // keep full relative precision instead of losing digits in |y| - |xi|.
+// The break decision is made on q except within a narrow margin around the threshold,
+// where a rare branch recomputes s = (|y| - |xi|)/|xi| in the oracle's exact order of
+// operations (stretch_exact): in the FP64 build, the same x and u break the same bonds
+// whatever the rounding of the fast form.
 //
 // Every kernel also has a force-evaluation mode (kModeForce): the same gather at the
 // current level, no breaking, the bond force density written out (the reaction-force
@@ -49,8 +53,10 @@ struct SlotTerm32 {
 // Contribution of one slot.  live: the slot holds an intact bond; breakable: the bond may
 // break in this pass (intact, outside the no-failure zones, not a force evaluation).
 // (X, U) are the owner's position and displacement, p0..p2 the neighbour's node record,
-// kv = stiffness times neighbour volume.  Adds the force density to F; returns true when
-// the bond breaks in this pass.
+// kv = stiffness times neighbour volume, q0 the lower edge of the break decision.  Adds
+// the force density to F, except for a breakable slot at or above q0: for such a
+// candidate the function returns true and leaves the decision (and, if the bond holds,
+// its contribution) to the caller's rare branch.
 __device__ __forceinline__ bool slot_force(bool live, bool breakable, const double2 p0, const double2 p1, const double2 p2,
                                            double X0, double X1, double X2, double U0, double U1, double U2,
                                            double kv, double q0, double& F0, double& F1, double& F2, SlotTerm& st,
@@ -65,15 +71,15 @@ __device__ __forceinline__ bool slot_force(bool live, bool breakable, const doub
     const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
     const double iL = rsq64<1>(L2);
     const double q = tq * (iL * iL);
-    const bool brk = breakable && q >= q0;
-    const bool alive = live && !brk;
-    // broken and padding slots evaluate g(0) = 0 and add nothing
+    const bool cand = breakable && q >= q0;
+    const bool alive = live && !cand;
+    // broken and padding slots (and candidates) evaluate g(0) = 0 and add nothing
     const double coef = (kv * iL) * one_minus_rsqrt1p(alive ? q : 0.0, sk);
     st = SlotTerm{q, coef, y0, y1, y2};
     F0 = __builtin_fma(coef, y0, F0);
     F1 = __builtin_fma(coef, y1, F1);
     F2 = __builtin_fma(coef, y2, F2);
-    return brk;
+    return cand;
 }
 
 // FP32 bond arithmetic (same formulas): the bond vector is formed in f64 from the f64
@@ -117,20 +123,25 @@ __device__ __forceinline__ bool slot_force32(bool live, bool breakable, const do
 }
 
 // Weight of a slot in the bond-model branch (EXT kernels): the slot is live and either at
-// or over the instance's threshold q0, or softened.  q is its q of this pass, nofail /
-// soft its word's flags, sold its stored largest stretch (prefetched by the caller when
-// soft).  Returns w (the bond adds w times its elastic force); sets broke when it breaks
-// now and newly_soft when it softens for the first time.  A zone bond, and every bond in
-// a force evaluation, keeps its damage state as it stands.
-template <int MODE, bool FP32>
+// or over the instance's lower decision edge q0, or softened.  q is its q of this pass,
+// nofail / soft its word's flags, sold its stored largest stretch (prefetched by the
+// caller when soft), exact_s() the slot's exact stretch (stretch_exact; the FP64 build
+// decides on it near every threshold and stores it as a new maximum, the FP32 build
+// decides on q).  Returns w (the bond adds w times its elastic force); sets broke when it
+// breaks now and newly_soft when it softens for the first time.  A zone bond, and every
+// bond in a force evaluation, keeps its damage state as it stands.
+template <int MODE, bool FP32, typename ExactS>
 __device__ double bond_weight(const StepArgs& A, const InstParams& P, int64_t ds, double q, bool nofail, bool soft,
-                              double sold, bool& broke, bool& newly_soft)
+                              double sold, bool& broke, bool& newly_soft, ExactS exact_s)
 {
     broke = false;
     newly_soft = false;
     if (P.nlaw == 0) {  // the brittle law with the instance's s0
         if (nofail || MODE == kModeForce) return 1.0;
-        broke = FP32 ? static_cast<float>(q) >= static_cast<float>(P.q0) : q >= P.q0;
+        if (FP32)
+            broke = static_cast<float>(q) >= static_cast<float>(P.q0);
+        else
+            broke = q >= P.q0 && exact_s() >= P.s0;
         return broke ? 0.0 : 1.0;
     }
     // a single law per instance is the same for the whole wavefront (scalar loads)
@@ -139,13 +150,19 @@ __device__ double bond_weight(const StepArgs& A, const InstParams& P, int64_t ds
     if (nofail || MODE == kModeForce) return soft ? law_secant(L, sold) : 1.0;
     // stretch from q without cancellation: s = q / (1 + sqrt(1 + q))
     const double r = rsq64<2>(1.0 + q);
-    const double s = q * rcp64(__builtin_fma(1.0 + q, r, 1.0));
+    double s = q * rcp64(__builtin_fma(1.0 + q, r, 1.0));
+    // the exact stretch wherever rounding could decide: at or near the stored maximum (a
+    // new maximum is stored exact) or near the law's elastic limit or last breakpoint
+    const double s_first = L.s[0], s_last = L.s[L.nb - 1];
+    if (!FP32 && (s >= sold - decision_margin(sold) || fabs(s - s_first) <= decision_margin(s_first) ||
+                  fabs(s - s_last) <= decision_margin(s_last)))
+        s = exact_s();
     const double sm = s > sold ? s : sold;
-    if (sm >= L.s[L.nb - 1]) {
+    if (sm >= s_last) {
         broke = true;
         return 0.0;
     }
-    if (!(sm > L.s[0])) return 1.0;
+    if (!(sm > s_first)) return 1.0;
     if (sm > sold) A.smax[ds] = sm;
     newly_soft = !soft;
     return law_secant(L, sm);
@@ -301,90 +318,111 @@ __global__ __launch_bounds__(kBlock) void step_f64(StepArgs A)
             const uint32_t off = static_cast<uint32_t>(t) * (kWave * 4u) + lane4;
             return __builtin_nontemporal_load(reinterpret_cast<const int32_t*>(colb + off));
         };
+        // stiffness times neighbour volume of row t's slot with neighbour j
+        auto kv_of = [&](int t, uint32_t j) -> double {
+            if (KNODE) return ai * nwp[j];  // sqrt(k_i) sqrt(k_j) V_j
+            if (STIFF || VOLN) {
+                double k = P.c;
+                if (STIFF) {
+                    const uint32_t off = static_cast<uint32_t>(t) * (kWave * 8u) + 2u * lane4;
+                    k = __builtin_nontemporal_load(reinterpret_cast<const double*>(kb + off));
+                }
+                return k * (VOLN ? volp[j] : P.volume);
+            }
+            return cv;
+        };
         // stored stretch of softened slots, fetched with their words (EXT with damage laws)
         auto smax_at = [&](int t, int32_t cw) -> double {
             if (!EXT || P.nlaw == 0 || cw < 0 || !(cw & kColSoft)) return 0.0;
             return A.smax[base + static_cast<int64_t>(t) * kWave + lane];
         };
+        // Rare branch of a flagged slot in row t (plain: a break candidate, decided on the
+        // exact stretch; EXT: the bond-model branch).  It runs after a block of 32 rows, from
+        // the slot's word and neighbour record read again, so the common path keeps its
+        // registers.
+        auto flagged = [&](int t) {
+            const int64_t ds = base + static_cast<int64_t>(t) * kWave + lane;
+            const int32_t step = static_cast<int32_t>(*A.step_base + A.step_local);
+            const int32_t cw = col_at(t);
+            const uint32_t j = col_node(cw);
+            const char* rj = recb + __umul24(j, 48u);
+            const double2 r0 = *reinterpret_cast<const double2*>(rj), r1 = *reinterpret_cast<const double2*>(rj + 16),
+                          r2 = *reinterpret_cast<const double2*>(rj + 32);
+            auto exact = [&]() { return stretch_exact_rec(r0, r1, r2, X0, X1, X2, U0, U1, U2); };
+            if constexpr (EXT) {
+                // the slot's terms as the common path formed them (into scratch accumulators),
+                // then move its elastic contribution from weight 1 to w
+                SlotTerm st;
+                double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+                slot_force(true, false, r0, r1, r2, X0, X1, X2, U0, U1, U2, kv_of(t, j), P.q0, d0, d1, d2, st, sk);
+                bool brk, newly;
+                const double wt = bond_weight<MODE, false>(A, P, ds, st.q, (cw & kColNoFail) != 0, (cw & kColSoft) != 0,
+                                                           smax_at(t, cw), brk, newly, exact);
+                if (brk) {
+                    A.col[ds] = ~cw;
+                    A.bstep[ds] = step;
+                } else if (newly) {
+                    A.col[ds] = cw | kColSoft;
+                }
+                if (wt != 1.0) {
+                    const double m = (wt - 1.0) * st.coef;
+                    F0 = __builtin_fma(m, st.y0, F0);
+                    F1 = __builtin_fma(m, st.y1, F1);
+                    F2 = __builtin_fma(m, st.y2, F2);
+                }
+            } else if (exact() >= P.s0) {
+                A.col[ds] = ~cw;  // irreversible
+                A.bstep[ds] = step;
+            } else {  // it holds: the contribution the common path left out
+                SlotTerm sh;
+                slot_force(true, false, r0, r1, r2, X0, X1, X2, U0, U1, U2, kv_of(t, j), P.q0, F0, F1, F2, sh, sk);
+            }
+        };
         int32_t cn[U];
-        double smn[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            cn[u] = col_at(u);
-            smn[u] = smax_at(u, cn[u]);
-        }
+        for (int u = 0; u < U; ++u) cn[u] = col_at(u);
+        uint32_t flags = 0;  // flagged rows of the current block of 32 (from row tb)
+        int tb = 0;
         for (int t = 0; t < T; t += U) {
             int32_t c[U];
             double2 p[U][3];
-            double kv[U], smc[U];
+            double kv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 c[u] = cn[u];
-                smc[u] = smn[u];
                 const uint32_t j = static_cast<uint32_t>(c[u] ^ (c[u] >> 31)) &
                                    (EXT ? static_cast<uint32_t>(kColNode) : 0xffffffffu);
                 const char* rj = recb + __umul24(j, 48u);  // full-rate 24-bit multiply: j < 2^24
                 p[u][0] = *reinterpret_cast<const double2*>(rj);
                 p[u][1] = *reinterpret_cast<const double2*>(rj + 16);
                 p[u][2] = *reinterpret_cast<const double2*>(rj + 32);
-                if (KNODE) {
-                    kv[u] = ai * nwp[j];  // sqrt(k_i) sqrt(k_j) V_j
-                } else if (STIFF || VOLN) {
-                    double k = P.c;
-                    if (STIFF) {
-                        const uint32_t off = static_cast<uint32_t>(t + u) * (kWave * 8u) + 2u * lane4;
-                        k = __builtin_nontemporal_load(reinterpret_cast<const double*>(kb + off));
-                    }
-                    kv[u] = k * (VOLN ? volp[j] : P.volume);
-                } else {
-                    kv[u] = cv;
-                }
+                kv[u] = kv_of(t + u, j);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) cn[u] = col_at(t + U + u);
 #pragma unroll
-            for (int u = 0; u < U; ++u) smn[u] = smax_at(t + U + u, cn[u]);
-            bool flag[U];  // plain: breaks now; EXT: takes the bond-model branch
-            SlotTerm st[U];
-#pragma unroll
             for (int u = 0; u < U; ++u) {
+                SlotTerm st;
+                bool flag;  // plain: a break candidate; EXT: takes the bond-model branch
                 if constexpr (EXT) {
                     slot_force(c[u] >= 0, false, p[u][0], p[u][1], p[u][2], X0, X1, X2, U0, U1, U2, kv[u], P.q0, F0,
-                               F1, F2, st[u], sk);
+                               F1, F2, st, sk);
                     const bool soft = (c[u] & kColSoft) != 0;
-                    flag[u] = c[u] >= 0 && (MODE == kModeForce ? soft : (st[u].q >= P.q0 || soft));
+                    flag = c[u] >= 0 && (MODE == kModeForce ? soft : (st.q >= P.q0 || soft));
                 } else {
-                    flag[u] = slot_force(c[u] >= 0, MODE != kModeForce && c[u] >= 0, p[u][0], p[u][1], p[u][2], X0,
-                                         X1, X2, U0, U1, U2, kv[u], P.q0, F0, F1, F2, st[u], sk);
+                    flag = slot_force(c[u] >= 0, MODE != kModeForce && c[u] >= 0, p[u][0], p[u][1], p[u][2], X0, X1,
+                                      X2, U0, U1, U2, kv[u], P.q0, F0, F1, F2, st, sk);
                 }
+                flags |= flag ? 1u << (t + u - tb) : 0u;
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (flag[u]) {
-                    const int64_t ds = base + static_cast<int64_t>(t + u) * kWave + lane;
-                    const int32_t step = static_cast<int32_t>(*A.step_base + A.step_local);
-                    if constexpr (EXT) {
-                        // move the slot's elastic contribution from weight 1 to w
-                        bool brk, newly;
-                        const double wt = bond_weight<MODE, false>(A, P, ds, st[u].q, (c[u] & kColNoFail) != 0,
-                                                                   (c[u] & kColSoft) != 0, smc[u], brk, newly);
-                        if (brk) {
-                            A.col[ds] = ~c[u];
-                            A.bstep[ds] = step;
-                        } else if (newly) {
-                            A.col[ds] = c[u] | kColSoft;
-                        }
-                        if (wt != 1.0) {
-                            const double m = (wt - 1.0) * st[u].coef;
-                            F0 = __builtin_fma(m, st[u].y0, F0);
-                            F1 = __builtin_fma(m, st[u].y1, F1);
-                            F2 = __builtin_fma(m, st[u].y2, F2);
-                        }
-                    } else {
-                        A.col[ds] = ~c[u];  // irreversible
-                        A.bstep[ds] = step;
-                    }
-                }
+            if (t + U - tb == 32 || t + U >= T) {  // end of a block: its rare branches
+                if (__builtin_amdgcn_ballot_w64(flags != 0) != 0)
+#pragma unroll 1
+                    for (int k = 0; k < 32; ++k)
+                        if (flags & (1u << k)) flagged(tb + k);
+                flags = 0;
+                tb = t + U;
+            }
         }
     }
 #pragma unroll
@@ -403,6 +441,13 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
+
+// Before a wavefront refills its LDS area with direct global-to-LDS loads: every LDS read
+// it issued earlier has returned its data (s_waitcnt lgkmcnt = 0, vmcnt and expcnt at
+// their no-wait maxima).  The direct loads write LDS through the vector-memory path, which
+// is not ordered behind the wavefront's pending LDS reads, so without this wait a read of
+// the previous piece still queued in the LDS unit could return the next piece's data.
+__device__ __forceinline__ void lds_reads_done() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // Staged step kernel: one workgroup of S wavefronts per 64-node slice, one lane per node.
 // Wavefront w takes the slice's pieces w, w + S, w + 2S, ...  For every piece, the
@@ -534,9 +579,10 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             if (lane + kWave < vlen) lvol[lane + kWave] = vs1;
         }
     };
-    // One slot from its staged record into the force accumulators; returns true when it
-    // breaks now (plain kernels) and what the bond-model branch needs in st / st32.
-    auto eval = [&](uint16_t e, double kst, bool live, bool breakable, SlotTerm& st, SlotTerm32& st32) {
+    // One slot from its staged record into the force accumulators; returns true for a
+    // break candidate (plain kernels) and what the rare branches need in st / st32.
+    auto eval_into = [&](uint16_t e, double kst, bool live, bool breakable, SlotTerm& st, SlotTerm32& st32,
+                         double& G0, double& G1, double& G2, float& Gf0, float& Gf1, float& Gf2) {
         const uint32_t off = e & kEntOff;  // byte offset of the neighbour's staged record
         const double2 q0 = *reinterpret_cast<const double2*>(lrecb + off);
         const double2 q1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
@@ -567,11 +613,14 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
         if (FP32)
             return slot_force32(live, breakable, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2,
                                 (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : kvf,
-                                q0f, Ff0, Ff1, Ff2, st32);
-        return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, F0, F1, F2, st, sk);
+                                q0f, Gf0, Gf1, Gf2, st32);
+        return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, G0, G1, G2, st, sk);
     };
-    // Plain kernels: true when the slot breaks now.  EXT kernels: true when it takes the
-    // bond-model branch.
+    auto eval = [&](uint16_t e, double kst, bool live, bool breakable, SlotTerm& st, SlotTerm32& st32) {
+        return eval_into(e, kst, live, breakable, st, st32, F0, F1, F2, Ff0, Ff1, Ff2);
+    };
+    // Plain kernels: true for a break candidate (FP32: a slot that breaks now).  EXT
+    // kernels: true when it takes the bond-model branch.
     auto row = [&](uint16_t e, double kst, SlotTerm& st, SlotTerm32& st32) {
         const bool live = !(e & kEntBroken);
         if constexpr (EXT) {
@@ -588,6 +637,16 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
         entw[ds] = static_cast<uint16_t>(e | kEntBroken);
         bstep[ds] = static_cast<int32_t>(*A.step_base + A.step_local);
     };
+    // the exact stretch of a slot from its staged record (FP64 build; the piece is still
+    // in LDS: the rare branches run before the next piece is loaded)
+    auto exact_of = [&](uint16_t e) {
+        return [&, e]() {
+            const uint32_t off = e & kEntOff;
+            return stretch_exact_rec(*reinterpret_cast<const double2*>(lrecb + off),
+                                     *reinterpret_cast<const double2*>(lrecb + off + 16),
+                                     *reinterpret_cast<const double2*>(lrecb + off + 32), X0, X1, X2, U0, U1, U2);
+        };
+    };
     // bond-model branch (EXT): move the slot's elastic contribution from weight 1 to the
     // weight its damage state gives
     auto model = [&](int64_t ds, uint16_t e, const SlotTerm& st, const SlotTerm32& st32) {
@@ -595,7 +654,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
         const bool soft = (e & kEntSoft) != 0;
         const double sold = soft ? A.smax[ds] : 0.0;
         const double wt = bond_weight<MODE, FP32>(A, P, ds, FP32 ? st32.q : st.q, (e & kEntNoFail) != 0, soft,
-                                                  sold, brk, newly);
+                                                  sold, brk, newly, exact_of(e));
         if (brk)
             broke(ds, e);
         else if (newly)
@@ -614,11 +673,23 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             }
         }
     };
-    auto flagged = [&](int64_t ds, uint16_t e, const SlotTerm& st, const SlotTerm32& st32) {
-        if constexpr (EXT)
+    // rare branch of a flagged slot (kst: its per-slot stiffness), run once the piece's rows
+    // are done (the piece is still staged)
+    auto flagged = [&](int64_t ds, uint16_t e, double kst) {
+        SlotTerm st;
+        SlotTerm32 st32;
+        if constexpr (EXT) {
+            // the slot's terms as the common path formed them (evaluated again, into
+            // scratch accumulators), then its damage state's weight
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+            float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+            eval_into(e, kst, true, false, st, st32, d0, d1, d2, f0, f1, f2);
             model(ds, e, st, st32);
-        else
+        } else if (FP32 || exact_of(e)() >= P.s0) {  // FP64: a candidate decided on the exact stretch
             broke(ds, e);
+        } else {  // it holds: the contribution the common path left out, evaluated again
+            eval(e, kst, true, false, st, st32);
+        }
     };
 
     if (pa < p1) {
@@ -628,6 +699,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             int64_t ent_next = ent + static_cast<int64_t>(T) * kWave;  // first entry of piece p + S
             for (int q = p + 1; q < p + S && q < p1; ++q) ent_next += static_cast<int64_t>(rows_of(q)) * kWave;
             wave_sync();  // the previous piece is no longer read
+            lds_reads_done();
             dma(p, ent);
             // s_waitcnt with vmcnt = 0 (expcnt and lgkmcnt at their no-wait maxima): the
             // piece's direct-to-LDS loads have landed
@@ -639,6 +711,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                     kcur[t] = t < kKPre ? knext[t] : __builtin_nontemporal_load(A.kslot + ent + t * kWave + lane);
             if (p + S < p1) issue(p + S, ent_next);
             wave_sync();  // the piece's LDS copy is complete
+            uint32_t flags = 0;  // rows of this piece whose slot takes the rare branch
 #pragma unroll
             for (int t = 0; t < kPieceRows; t += 2) {
                 if (t >= T) break;
@@ -649,13 +722,17 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                     SlotTerm32 sa32, sb32;
                     const bool ba = row(ea, STIFF ? kcur[t] : 0.0, sa, sa32);
                     const bool bb = row(eb, STIFF ? kcur[t + 1] : 0.0, sb, sb32);
-                    if (ba) flagged(ent + t * kWave + lane, ea, sa, sa32);
-                    if (bb) flagged(ent + (t + 1) * kWave + lane, eb, sb, sb32);
+                    flags |= (ba ? 1u << t : 0u) | (bb ? 2u << t : 0u);
                 } else {
                     SlotTerm sa;
                     SlotTerm32 sa32;
-                    if (row(ea, STIFF ? kcur[t] : 0.0, sa, sa32)) flagged(ent + t * kWave + lane, ea, sa, sa32);
+                    flags |= row(ea, STIFF ? kcur[t] : 0.0, sa, sa32) ? 1u << t : 0u;
                 }
+            }
+            if (__builtin_amdgcn_ballot_w64(flags != 0) != 0) {
+#pragma unroll
+                for (int t = 0; t < kPieceRows; ++t)
+                    if (flags & (1u << t)) flagged(ent + t * kWave + lane, lent[t * kWave + lane], STIFF ? kcur[t] : 0.0);
             }
             ent = ent_next;
         }

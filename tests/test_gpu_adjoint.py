@@ -253,3 +253,41 @@ def test_autograd_function_and_central_differences():
     fdA = (plain_loss(k0, bmag + hA) - plain_loss(k0, bmag - hA)) / (2 * hA)
     say(f"[adjoint] FD load: adjoint {gA:.6e} FD {fdA:.6e}")
     assert gA == pytest.approx(fdA, rel=1e-6)
+
+
+def test_backward_refuses_a_replaced_recording():
+    """Each pd_adj_forward hands out a recording id; a backward asked for an earlier
+    recording than the one the simulation holds raises instead of returning the later
+    run's gradient, through the C ABI and through the autograd Function."""
+    import torch
+    from paper_2105_04150_amd import PdmiError, simulation_for
+    from paper_2105_04150_amd.adjoint import AdjointProblem, sensor_displacement
+    w = pi.workload("adjoint_beam", dims=(20, 8, 6), steps=60)
+    sim = simulation_for(w, lanes=4)
+    rp, col = sim.family()
+    k0 = pi.slot_stiffness(w.c, pi.gaussian_node_field(w.dims, *w.stiffness_field), rp, col)
+    bhat, bmag = w.body_force
+    sensors, target = pi.adjoint_sensors(w, m=10)
+    prob = AdjointProblem(sim, bhat, sensors, w.steps, ckpt_every=16)
+    prob.reset(k0, bmag)
+    r1 = sim.adj_forward(w.steps, 16)
+    dl = np.ones((len(sensors), 3))
+    g1 = sim.adj_backward(sensors, dl, r1)
+    prob.reset(k0 * 1.01, bmag)
+    r2 = sim.adj_forward(w.steps, 16)
+    assert r1 > 0 and r2 > r1
+    with pytest.raises(PdmiError):
+        sim.adj_backward(sensors, dl, r1)
+    g2 = sim.adj_backward(sensors, dl, r2)
+    g0 = sim.adj_backward(sensors, dl)  # 0: the current recording
+    assert np.array_equal(g2[0], g0[0]) and not np.array_equal(g1[0], g2[0])
+    # two forwards of the autograd Function on one problem, then the first one's backward
+    k = torch.tensor(k0, dtype=torch.float64, requires_grad=True)
+    A = torch.tensor(bmag, dtype=torch.float64, requires_grad=True)
+    u1 = sensor_displacement(k, A, prob)
+    u2 = sensor_displacement(k * 1.01, A, prob)
+    with pytest.raises(PdmiError):
+        u1.sum().backward()
+    u2.sum().backward()
+    assert k.grad is not None and np.isfinite(k.grad.numpy()).all()
+    say("[adjoint] a replaced recording is refused; the current one differentiates")

@@ -1,0 +1,191 @@
+"""The stated workload configurations at their full sizes and, where the oracle can follow
+them, their full lengths, in the launch configurations bench.py times.
+
+- the 1M-node cube at the wide horizon 5.015 dx (485,972,824 slots) over a 10-step
+  prefix, FP64 and FP32;
+- the notched three-point-bend beam (200 x 25 x 25, 13.8M slots) for its full 10,000
+  velocity-Verlet steps, FP64 and FP32;
+- the adjoint beam (100 x 25 x 20) for its full 2,000 steps with checkpoints every 100
+  steps against the oracle's reverse pass, and central differences (h = 1e-6 k_b) on 50
+  slots drawn from the top decile of |dL/dk_b|, each printed beside its predicted
+  rounding floor;
+- the 64-beam batch in one launch per step: four instances (smallest to largest)
+  end to end for the full 5,000 steps, and all 64 over a 100-step prefix.
+
+Bars: FP64 displacement 1e-10 norm-wise with identical broken sets, FP32 1e-5 with
+broken-set mismatches counted (at most 1% of the broken slots), adjoint gradients 1e-10.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import pd_inputs as pi
+from parity import TOL_FP32, TOL_FP64, compare, oracle_run, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2105_04150_amd import _binding as B
+    B.load()
+
+
+@pytest.fixture(scope="module")
+def wide_cube_oracle():
+    w = pi.workload("cube100_wide", steps=10)
+    w.order = "natural"
+    say(f"[run] oracle cube100_wide 1M nodes, {w.steps} steps, {THREADS} threads")
+    return w, oracle_run(w, w.steps, nthreads=THREADS)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_cube100_wide_full_size(wide_cube_oracle, precision):
+    from paper_2105_04150_amd import PD_FP32, PD_FP64, simulation_for
+    w, o = wide_cube_oracle
+    g = simulation_for(w, precision=PD_FP32 if precision == "f32" else PD_FP64, mapping="staged", order="natural")
+    assert g.info()["n_slots"] == 485_972_824
+    g.step(w.steps)
+    tol = TOL_FP32 if precision == "f32" else TOL_FP64
+    eu, ev, mism, ephi = compare(g, o, tol, f"cube100_wide full size {precision}")
+    g.close()
+    assert np.abs(o.u).max() > 0 and eu <= tol
+    assert mism == 0 if precision == "f64" else mism <= 0.01 * max(int(o.broken_mask.sum()), 1)
+
+
+@pytest.fixture(scope="module")
+def beam_oracle():
+    w = pi.workload("beam3pb")  # 200 x 25 x 25, 10,000 velocity-Verlet steps
+    say(f"[run] oracle beam3pb full size, {w.steps} steps, {THREADS} threads")
+    return w, oracle_run(w, w.steps, nthreads=THREADS)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_notched_beam_full_length(beam_oracle, precision):
+    from paper_2105_04150_amd import PD_FP32, PD_FP64, simulation_for
+    w, o = beam_oracle
+    g = simulation_for(w, precision=PD_FP32 if precision == "f32" else PD_FP64, mapping="staged")
+    g.autotune(trial_steps=10)
+    g.step(w.steps)
+    tol = TOL_FP32 if precision == "f32" else TOL_FP64
+    eu, ev, mism, ephi = compare(g, o, tol, f"beam3pb 200x25x25 {w.steps} VV steps {precision}")
+    info = g.info()
+    g.close()
+    assert info["n_slots"] == 13_799_348
+    assert o.broken_mask.sum() >= 2 * 7228  # the notch, both slots of each bond
+    assert np.abs(o.u).max() > 0 and eu <= tol
+    assert mism == 0 if precision == "f64" else mism <= 0.01 * max(int(o.broken_mask.sum()), 1)
+
+
+def test_adjoint_beam_full_length():
+    """2,000 Euler-Cromer steps, checkpoints every 100 steps, 200 sensors: the GPU reverse
+    pass against the oracle's, then central differences of the GPU forward run."""
+    from paper_2105_04150_amd import simulation_for
+    from paper_2105_04150_amd.adjoint import AdjointProblem
+    w = pi.workload("adjoint_beam")
+    say(f"[run] oracle adjoint beam full length, {w.steps} steps")
+    o = oracle_run(w, w.steps, nthreads=THREADS, record_breaks=True)
+    sensors, target = pi.adjoint_sensors(w)
+    dldu = 2.0 * (o.u[sensors] - target)
+    z = np.zeros((w.n, 3))
+    gk_o, gA_o = o.adjoint_ec(o.break_step[: o.nnz].copy(), w.steps, z, z, 0, sensors, dldu)
+    g = simulation_for(w, lanes=4)
+    g.autotune(trial_steps=10)
+    rec = g.adj_forward(w.steps, 100)
+    g_sched = g.break_steps()
+    gk, gA = g.adj_backward(sensors, dldu, rec)
+    ek, eA = rel_err(gk, gk_o), abs(gA - gA_o) / abs(gA_o)
+    say(f"[adjoint] full length: grad_k rel {ek:.3e} grad_A rel {eA:.3e}")
+    assert ek <= TOL_FP64 and eA <= TOL_FP64
+
+    # central differences of the loss on 50 slots from the top decile of |g_b|
+    rp, col = g.family()
+    k0 = pi.slot_stiffness(w.c, pi.gaussian_node_field(w.dims, *w.stiffness_field), rp, col)
+    bhat, bmag = w.body_force
+    prob = AdjointProblem(g, bhat, sensors, w.steps, ckpt_every=100)
+
+    def loss(k):
+        prob.reset(k, bmag)
+        g.step(w.steps)
+        d = g.u()[sensors] - target
+        return float((d * d).sum())
+
+    L0 = loss(k0)
+    sched0 = g.break_steps()
+    assert np.array_equal(sched0, g_sched)  # the plain run breaks as the recorded one
+    top = np.argsort(-np.abs(gk))[: max(50, gk.size // 10)]
+    order = top[pi.sample_nodes(top.size, min(top.size, 80), 77)]
+    worst, done, moved = 0.0, 0, 0
+    for b in order:
+        if done == 50:
+            break
+        h = 1e-6 * k0[b]
+        kp, km = k0.copy(), k0.copy()
+        kp[b] += h
+        km[b] -= h
+        lp = loss(kp)
+        same = np.array_equal(g.break_steps(), sched0)
+        lm = loss(km)
+        same = same and np.array_equal(g.break_steps(), sched0)
+        if not same:  # a break moved by a step: the difference quotient is not the frozen-schedule derivative
+            moved += 1
+            say(f"[adjoint FD] slot {b}: the perturbation moved a break, slot replaced")
+            continue
+        fd = (lp - lm) / (2.0 * h)
+        err = abs(gk[b] - fd) / abs(gk[b])
+        # rounding floor of the difference: each loss carries relative rounding near
+        # 1e-13 (sums over 200 sensors after 2,000 steps), divided by 2 h |g_b|
+        floor = 1e-13 * L0 / (2.0 * h * abs(gk[b]))
+        say(f"[adjoint FD] slot {b}: adjoint {gk[b]:.6e} FD {fd:.6e} rel {err:.2e} predicted floor {floor:.1e}")
+        worst = max(worst, err / max(1e-5, 10.0 * floor))
+        assert err <= max(1e-5, 10.0 * floor)
+        done += 1
+    say(f"[adjoint FD] {done} slots (replaced {moved}): worst error over its allowance {worst:.3f}")
+    assert done == 50
+
+
+@pytest.fixture(scope="module")
+def batch64():
+    from paper_2105_04150_amd import Simulation, apply_workload
+    ws = pi.batch_instances(count=64)  # 5,000 Euler-Cromer steps
+    g = Simulation()
+    g.set_mapping("staged", 1)
+    g.build_family_batch([w.coords for w in ws], [w.horizon for w in ws])
+    g.set_integrator("euler_cromer", ws[0].dt)
+    for b, w in enumerate(ws):
+        apply_workload(g, w, inst=b, stiffness="node")
+    say(f"[run] batch of 64 built: {g.info()['n_slots']} slots")
+    yield ws, g
+    g.close()
+
+
+def test_batch64_all_instances_prefix(batch64):
+    """All 64 instances against their own oracle runs after a 100-step prefix."""
+    ws, g = batch64
+    steps = 100
+    g.step(steps)
+    worst = 0.0
+    for b, w in enumerate(ws):
+        o = oracle_run(w, steps, nthreads=THREADS)
+        eu = rel_err(g.u(b), o.u)
+        mism = int((g.broken(b).astype(bool) != o.broken_mask).sum())
+        worst = max(worst, eu)
+        assert np.abs(o.u).max() > 0 and mism == 0 and eu <= TOL_FP64, (b, eu, mism)
+    say(f"[batch64] all 64 instances after {steps} steps: worst u rel {worst:.3e}")
+
+
+def test_batch64_end_to_end(batch64):
+    """Four instances from the smallest to the largest over the full 5,000 steps."""
+    ws, g = batch64
+    for b in range(len(ws)):  # back to rest at step 0
+        n, nnz = g.size(b)
+        g.load_state({"u": np.zeros((n, 3)), "v": np.zeros((n, 3)), "broken": np.zeros(nnz, np.uint8),
+                      "step": 0}, inst=b)
+    g.step(ws[0].steps)
+    for b in (0, 21, 42, 63):
+        o = oracle_run(ws[b], ws[b].steps, nthreads=THREADS)
+        eu, ev, mism, ephi = compare(g, o, TOL_FP64, f"batch64 inst {b} {ws[b].dims} {ws[b].steps} steps", inst=b)
+        assert np.abs(o.u).max() > 0 and mism == 0 and eu <= TOL_FP64

@@ -1,4 +1,4 @@
-"""Stiffness corrections on the GPU against the oracle (Secs. 2.2-2.3): conical
+"""Stiffness corrections on the GPU against the oracle (Secs. 2.2, 2.3 and 2.5): conical
 micromodulus, partial volumes, volume-method surface correction, alone and together, on
 top of uniform, per-slot and per-node stiffness.  The oracle forms its factors itself;
 the library folds them into the per-slot stiffness on the host.  Bars as everywhere:

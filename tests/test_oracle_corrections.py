@@ -1,4 +1,4 @@
-"""Pins of the oracle's stiffness corrections (Secs. 2.2-2.3): the conical micromodulus,
+"""Pins of the oracle's stiffness corrections (Secs. 2.2, 2.3 and 2.5): the conical micromodulus,
 partial volumes and the volume-method surface correction.
 
 Fixed by mathematics rather than by the oracle's own formulas: the continuum integral
