@@ -14,8 +14,8 @@
 // even in y.  With symmetric stiffness and schedule, (J_F^T nu)_i is the gather
 //   sum over the family of i of k_b K_b (V_i nu_j - V_j nu_i),
 // the same shape as the force, so the reverse pass walks the forward slot layout and
-// needs no reverse-slot index.  1/L - 1/r = (1/L)(1 - (1+q)^(-1/2)) and 1/r = (1/L)(1+q)^(-1/2)
-// use the cancellation-free q = |y|^2/|xi|^2 - 1 of the step kernel.
+// needs no reverse-slot index.  1/L - 1/r = (1/L)(1 - (1+q)^(-1/2)) uses the
+// cancellation-free q = |y|^2/|xi|^2 - 1 of the step kernel, and 1/r is 1/L less that.
 #include "pdmi_device.h"
 
 namespace pdmi {
@@ -38,7 +38,7 @@ __device__ __forceinline__ double adj_slot(bool active, const double2 p0, const 
     const double iL = rsq64<1>(L2);
     const double q = active ? tq * (iL * iL) : 0.0;
     const double sr = iL * one_minus_rsqrt1p(q);  // s/r = 1/L - 1/r
-    const double ir = iL * rsq64<2>(1.0 + q);     // 1/r
+    const double ir = iL - sr;                    // 1/r, no cancellation: sr is about |s| of iL
     const double ir3 = ir * ir * ir;
     const double w0 = Vi * nj[0] - Vj * ni[0], w1 = Vi * nj[1] - Vj * ni[1], w2 = Vi * nj[2] - Vj * ni[2];
     const double yw = __builtin_fma(y2, w2, __builtin_fma(y1, w1, y0 * w0));
