@@ -371,6 +371,16 @@ int pd_get_resultant(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes,
  * Errors: PD_EINVAL (node id out of range, m < 1). */
 int pd_get_mean_displacement(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes, double out[3]);
 
+/* pd_get_mean_displacement for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or measurement loops, harnesses that forbid hipMalloc):
+ * the same readout, bit for bit, calling no hipMalloc, hipFree or other allocating
+ * routine.  The node ids and the sums live in a fixed device array of this library on the
+ * context's GPU (262,144 node ids and three sums, about 2 MiB per GPU, held until the
+ * process ends); every call on that GPU shares it, so calls that overlap on one GPU (from
+ * several threads or contexts) race.  Synchronising.  Errors: PD_EINVAL (m < 1, m >
+ * 262144, node id out of range, NULL arguments), PD_ESTATE (no problem built). */
+int pd_get_mean_displacement_noalloc(pd_ctx *ctx, int32_t inst, int64_t m, const int64_t *nodes, double out[3]);
+
 /* Overwrite the state of instance `inst` (checkpoint / restart: Sec. 3.6 lets a run
  * start from an intermediate state).  Any of u, v, a (host n x 3) or broken
  * (host nnz; replaces the broken set exactly, un-breaking included) may be NULL to

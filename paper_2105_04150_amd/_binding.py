@@ -35,7 +35,7 @@ SYMBOLS = [
     "pd_step", "pd_prepare", "pd_sync", "pd_get_step", "pd_get_u", "pd_get_v", "pd_get_a", "pd_get_damage",
     "pd_get_broken", "pd_set_state", "pd_set_step", "pd_set_mapping", "pd_set_lanes_per_node", "pd_autotune",
     "pd_get_info", "pd_last_step_ms", "pd_adj_forward", "pd_adj_backward", "pd_get_break_steps",
-    "pd_get_state", "pd_load_state", "pd_stretch_exact",
+    "pd_get_state", "pd_load_state", "pd_stretch_exact", "pd_get_mean_displacement_noalloc",
 ]
 
 
@@ -94,6 +94,7 @@ def load() -> C.CDLL:
         "pd_get_force": [P, i32, P],
         "pd_get_resultant": [P, i32, i64, P, P],
         "pd_get_mean_displacement": [P, i32, i64, P, P],
+        "pd_get_mean_displacement_noalloc": [P, i32, i64, P, P],
         "pd_set_damage_law": [P, i32, i32, i32, P, P],
         "pd_set_bond_classes": [P, i32, P],
         "pd_clear_damage_laws": [P, i32],
@@ -266,6 +267,14 @@ def pd_get_mean_displacement(ctx, inst: int, nodes) -> np.ndarray:
     nd = np.ascontiguousarray(nodes, dtype=np.int64)
     out = np.zeros(3)
     _check(ctx, load().pd_get_mean_displacement(ctx, inst, nd.shape[0], _p(nd) if nd.shape[0] else None, _p(out)))
+    return out
+
+
+def pd_get_mean_displacement_noalloc(ctx, inst: int, nodes) -> np.ndarray:
+    nd = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros(3)
+    _check(ctx, load().pd_get_mean_displacement_noalloc(ctx, inst, nd.shape[0], _p(nd) if nd.shape[0] else None,
+                                                        _p(out)))
     return out
 
 

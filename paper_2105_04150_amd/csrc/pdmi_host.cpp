@@ -1711,6 +1711,8 @@ int pd_create(pd_ctx** out, int device, int precision, void* hip_stream)
         ctx->precision = precision;
         if (precision == PD_FP32) ctx->mapping = PD_MAP_STAGED;  // FP32 bond arithmetic lives in the staged kernel
         set_device(ctx.get());
+        int64_t* scr = nullptr;  // the allocation-free readout's scratch array on this GPU, looked up once
+        hip_check(scratch_address(device, &scr), "scratch address");
         if (hip_stream) {
             ctx->stream = static_cast<hipStream_t>(hip_stream);
         } else {
@@ -2365,6 +2367,38 @@ int pd_get_mean_displacement(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t
             set_sum(ctx, idx, ctx->um[ctx->cur].as<double>(), 1, ctx->nn, nullptr, w, out);
         else            // the node records: x then u, 6 doubles per node
             set_sum(ctx, idx, ctx->rec[ctx->cur].as<double>() + 3, 6, 1, nullptr, w, out);
+    });
+}
+
+int pd_get_mean_displacement_noalloc(pd_ctx* ctx, int32_t inst, int64_t m, const int64_t* nodes, double out[3])
+{
+    if (!ctx) return PD_EINVAL;
+    return guarded(ctx, [&] {
+        const Inst& I = instance(ctx, inst);
+        if (!out || !nodes) fail(PD_EINVAL, "out or nodes is NULL");
+        if (m < 1) fail(PD_EINVAL, "m must be >= 1");
+        if (m > kScratchNodes) fail(PD_EINVAL, "at most 262144 nodes (the size of the device scratch array)");
+        for (int64_t p = 0; p < m; ++p)
+            if (nodes[p] < 0 || nodes[p] >= I.n) fail(PD_EINVAL, "node id out of range");
+        require_built(ctx);
+        set_device(ctx);
+        int64_t* scr = nullptr;  // this GPU's scratch array: node ids, then the three sums
+        hip_check(scratch_address(ctx->device, &scr), "scratch address");
+        double* sums = reinterpret_cast<double*>(scr + kScratchNodes);
+        hip_check(hipMemcpyAsync(scr, nodes, static_cast<size_t>(m) * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream),
+                  "node ids to scratch");
+        const double w = 1.0 / static_cast<double>(m);
+        const int64_t* map = ctx->unode.as<int64_t>() + I.user_off;  // user node -> device node
+        if (fp32(ctx))
+            hip_check(launch_set_sum(ctx->um[ctx->cur].as<double>(), 1, ctx->nn, nullptr, w, scr, m, sums, ctx->stream,
+                                     map),
+                      "set-sum launch");
+        else
+            hip_check(launch_set_sum(ctx->rec[ctx->cur].as<double>() + 3, 6, 1, nullptr, w, scr, m, sums, ctx->stream,
+                                     map),
+                      "set-sum launch");
+        hip_check(hipMemcpyAsync(out, sums, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "sums to host");
+        sync(ctx);
     });
 }
 

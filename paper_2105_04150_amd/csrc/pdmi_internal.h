@@ -206,9 +206,16 @@ hipError_t launch_step_staged_f64(const StepArgs& a, int mode, int split, bool e
 hipError_t launch_step_staged_f32(const StepArgs& a, int mode, int split, bool ext, hipStream_t s);
 
 // out[d] = sum over the m device nodes idx[] of w_i field[i * snode + d * scomp], w_i = wv[i]
-// or w when wv is nullptr, summed in a fixed order (force resultants, set means)
+// or w when wv is nullptr, summed in a fixed order (force resultants, set means); with
+// map, idx holds user node ids and node i is map[idx[r]]
 hipError_t launch_set_sum(const double* field, int64_t snode, int64_t scomp, const double* wv, double w,
-                          const int64_t* idx, int64_t m, double* out, hipStream_t s);
+                          const int64_t* idx, int64_t m, double* out, hipStream_t s, const int64_t* map = nullptr);
+
+// Allocation-free readouts: a per-GPU device array of kScratchNodes int64 node ids
+// followed by 4 doubles, defined beside its kernels; its device address on `device`
+// (looked up once per device, then cached; calls on one GPU share the array).
+constexpr int64_t kScratchNodes = int64_t(1) << 18;
+hipError_t scratch_address(int device, int64_t** out);
 
 hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s);
 

@@ -3,6 +3,8 @@
 // dispatch to the step-kernel launcher files.
 #include "pdmi_device.h"
 
+#include <mutex>
+
 namespace pdmi {
 namespace {
 
@@ -120,12 +122,12 @@ __global__ void advance_kernel(int64_t* step_base, int64_t by)
 __global__ __launch_bounds__(kBlock) void set_sum_kernel(const double* __restrict__ field, int64_t snode,
                                                         int64_t scomp, const double* __restrict__ wv, double w,
                                                         const int64_t* __restrict__ idx, int64_t m,
-                                                        double* __restrict__ out)
+                                                        double* __restrict__ out, const int64_t* __restrict__ map)
 {
     __shared__ double red[3][kBlock];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int64_t r = threadIdx.x; r < m; r += kBlock) {
-        const int64_t i = idx[r];
+        const int64_t i = map ? map[idx[r]] : idx[r];
         const double wi = wv ? wv[i] : w;
         const double* f = field + i * snode;
         s0 += wi * f[0];
@@ -210,10 +212,39 @@ hipError_t launch_damage_staged(const DamageArgs& a, hipStream_t s)
 }
 
 hipError_t launch_set_sum(const double* field, int64_t snode, int64_t scomp, const double* wv, double w,
-                          const int64_t* idx, int64_t m, double* out, hipStream_t s)
+                          const int64_t* idx, int64_t m, double* out, hipStream_t s, const int64_t* map)
 {
-    hipLaunchKernelGGL(set_sum_kernel, dim3(1), dim3(kBlock), 0, s, field, snode, scomp, wv, w, idx, m, out);
+    hipLaunchKernelGGL(set_sum_kernel, dim3(1), dim3(kBlock), 0, s, field, snode, scomp, wv, w, idx, m, out, map);
     return hipGetLastError();
+}
+
+// Device scratch of the allocation-free set readout: kScratchNodes node ids, then the
+// three sums (as doubles).  One array per GPU, held until the process ends.  In host code
+// `scratch` names a host-side stand-in, never the device memory: kernels and copies take
+// the address scratch_address() looked up on the device.
+static __device__ __align__(256) int64_t scratch[kScratchNodes + 4];
+
+hipError_t scratch_address(int device, int64_t** out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static int64_t* addr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<int64_t*>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 // Exact stretch of m bonds (xi, y: m x 3 row-major), one work-item per bond.
