@@ -110,6 +110,27 @@ def cpu_baseline(w, steps: int, threads: int, single_steps: int):
             "family_build_s": family_s, "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
+SETTLE = True  # cleared by --no-settle (counter runs, which time nothing)
+
+
+def settle(sim, seconds: float = 0.4):
+    """Bring the GPU to its steady clock before a measurement: run steps for about
+    `seconds` of device time, then put the problem back exactly as it was (u, v, a,
+    broken flags and the step counter), so the timed steps start from the state the
+    warm-up steps leave, as without this.  Part of setup, outside every timed region."""
+    if not SETTLE:
+        return
+    u, v, a, br, k = sim.u(), sim.v(), sim.a(), sim.broken(), sim.step_count
+    sim.step(8)
+    sim.sync()
+    per = max(sim.last_step_ms() / 8, 1e-3)
+    sim.step(max(8, int(seconds * 1e3 / per)))
+    sim.sync()
+    sim.set_state(u=u, v=v, a=a, broken=br)
+    sim.set_step(k)
+    sim.prepare()
+
+
 def _timed(fn, sync):
     sync()
     t0 = time.perf_counter()
@@ -163,7 +184,7 @@ def adjoint_extra(P, pi, sync, steps: int, ckpt: int):
                                 "adjoint_vs_plain": (nnz * steps / (t_fwd1 + t_bwd1)) / plain}}
 
 
-def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
+def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int, tune: bool = True):
     """Many uneven uncertainty-quantification beams advanced together, against the same
     instances advanced one problem at a time (a sample of them) on the same GPU.  The
     mapping and node order come from the library's autotuner run on four of the beams
@@ -171,19 +192,21 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
     stiffness field is passed as its node values (bond stiffness sqrt(k_i k_j))."""
     ws = pi.batch_instances(count=count, steps=steps)
     t0 = time.perf_counter()
-    sub = [ws[b] for b in np.unique(np.linspace(0, count - 1, min(4, count)).round().astype(int))]
-    tun = P.Simulation()
-    tun.build_family_batch([w.coords for w in sub], [w.horizon for w in sub], order="auto")
-    tun.set_integrator("euler_cromer", ws[0].dt)
-    for b, w in enumerate(sub):
-        P.apply_workload(tun, w, inst=b, stiffness="node")
-    tun.autotune(trial_steps=5)
-    ti = tun.info()
-    tun.close()
-    mapping = "staged" if ti["mapping"] == P.PD_MAP_STAGED else "sliced"
-    lanes = ti["lanes_per_node"]
-    order = "morton" if ti["order"] == P.PD_ORDER_MORTON else "natural"
-    print(f"# batched: autotuned on {len(sub)} beams: {mapping}-{lanes}, {order}", file=sys.stderr, flush=True)
+    mapping, lanes, order = "staged", 1, "natural"
+    if tune:
+        sub = [ws[b] for b in np.unique(np.linspace(0, count - 1, min(4, count)).round().astype(int))]
+        tun = P.Simulation()
+        tun.build_family_batch([w.coords for w in sub], [w.horizon for w in sub], order="auto")
+        tun.set_integrator("euler_cromer", ws[0].dt)
+        for b, w in enumerate(sub):
+            P.apply_workload(tun, w, inst=b, stiffness="node")
+        tun.autotune(trial_steps=5)
+        ti = tun.info()
+        tun.close()
+        mapping = "staged" if ti["mapping"] == P.PD_MAP_STAGED else "sliced"
+        lanes = ti["lanes_per_node"]
+        order = "morton" if ti["order"] == P.PD_ORDER_MORTON else "natural"
+        print(f"# batched: autotuned on {len(sub)} beams: {mapping}-{lanes}, {order}", file=sys.stderr, flush=True)
     sim = P.Simulation()
     sim.set_mapping(mapping, lanes)
     sim.build_family_batch([w.coords for w in ws], [w.horizon for w in ws], order=order)
@@ -202,7 +225,7 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
     idx = np.unique(np.linspace(0, count - 1, min(seq_sample, count)).round().astype(int))
     seq_slots, seq_t = 0, 0.0
     print(f"# batched: {t_b * 1e3 / steps:.3f} ms/step; sequential sample next", file=sys.stderr, flush=True)
-    for b in idx:
+    for b in (idx if seq_sample > 0 else []):
         s1 = P.simulation_for(ws[b], lanes=lanes, mapping=mapping, order=order, stiffness="node")
         s1.prepare()
         s1.step(20)
@@ -211,7 +234,7 @@ def batched_extra(P, pi, sync, count: int, steps: int, seq_sample: int):
         seq_slots += s1.info()["n_slots"]
         s1.close()
     batched = nnz * steps / t_b
-    seq = seq_slots * steps / seq_t
+    seq = seq_slots * steps / seq_t if seq_t > 0 else float("nan")
     return {"config": f"{count} beams, dims {ws[0].dims}..{ws[-1].dims}, {steps} Euler-Cromer steps, f64",
             "instances": count, "nodes": info["n_nodes"], "bond_slots": nnz,
             "mapping": mapping if mapping == "staged" else f"sliced-{lanes}", "node_order": order,
@@ -323,6 +346,7 @@ def corrections_extra(P, pi, sync, workload: str, steps: int, plain_ms: float):
     w.corrections = dict(micro="conical", surface=True, delta=w.horizon, dx=w.dx)
     sim = P.simulation_for(w, mapping="staged")
     sim.prepare()
+    settle(sim)
     info = sim.info()
     sim.step(20)
     sim.sync()
@@ -345,6 +369,7 @@ def state_based_extra(P, pi, sync, workload: str, steps: int, plain_ms: float):
     w.order = "natural"
     sim = P.simulation_for(w, mapping="staged")
     sim.prepare()
+    settle(sim)
     info = sim.info()
     sim.step(20)
     sim.sync()
@@ -355,6 +380,7 @@ def state_based_extra(P, pi, sync, workload: str, steps: int, plain_ms: float):
     # the FP32 build of the same step
     sim = P.simulation_for(w, precision=P.PD_FP32, mapping="staged")
     sim.prepare()
+    settle(sim)
     sim.step(20)
     sim.sync()
     t32 = _timed(lambda: (sim.step(steps), sim.sync()), sync)
@@ -377,6 +403,7 @@ def wide_extra(P, pi, sync, steps: int):
     t0 = time.perf_counter()
     sim = P.simulation_for(w, mapping="staged")
     sim.prepare()
+    settle(sim)
     setup = time.perf_counter() - t0
     info = sim.info()
     sim.step(5)
@@ -399,6 +426,7 @@ def fp32_extra(P, pi, sync, workload: str, steps: int):
     w.order = "natural"
     sim = P.simulation_for(w, precision=P.PD_FP32, mapping="staged")
     sim.prepare()
+    settle(sim)
     info = sim.info()
     sim.step(20)
     sim.sync()
@@ -438,7 +466,14 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=300)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--extra", default="", choices=["", "adjoint", "batched", "corrections", "quasistatic"],
+                    help="profiling runs: only this extra measurement, in a process with one library "
+                         "context (batched: staged-1, natural order, no sequential sample); prints its line")
+    ap.add_argument("--no-settle", action="store_true",
+                    help="skip the clock warm-up before each measurement (counter-collection runs)")
     args = ap.parse_args()
+    global SETTLE
+    SETTLE = not args.no_settle
 
     if args.calib_copy_mib:
         import torch
@@ -460,6 +495,23 @@ def main():
     import pd_inputs as pi
     import paper_2105_04150_amd as P
 
+    if args.extra:
+        try:
+            import torch
+            sync = torch.cuda.synchronize if torch.cuda.is_available() else (lambda: None)
+        except Exception:
+            sync = lambda: None  # noqa: E731
+        if args.extra == "adjoint":
+            line = adjoint_extra(P, pi, sync, args.adjoint_steps, 100)
+        elif args.extra == "batched":
+            line = batched_extra(P, pi, sync, args.batch_count, args.batch_steps, 0, tune=False)
+        elif args.extra == "corrections":
+            line = corrections_extra(P, pi, sync, args.workload, args.steps, float("nan"))
+        else:
+            line = quasistatic_extra(P, pi, sync, args.steps, 50)
+        print(json.dumps({"extra": args.extra, **line}), flush=True)
+        return
+
     w = pi.workload(args.workload, model=args.model)
     if args.model == "state_based" and (args.mapping != "staged" or args.precision != "f64"):
         sys.exit("the state-based model runs with --mapping staged --precision f64")
@@ -472,6 +524,7 @@ def main():
     else:
         sim = P.simulation_for(w, precision=prec, lanes=args.lanes, mapping=args.mapping)
     sim.prepare()  # step graphs built before the warm-up, not inside the timed region
+    settle(sim)
     setup_s = time.perf_counter() - t0
     info = sim.info()
     mapping = "staged" if info["mapping"] == P.PD_MAP_STAGED else "sliced"
