@@ -742,6 +742,13 @@ int pdo_adjoint_ec(const pdo_problem *P, const int32_t *frozen, int64_t nsteps,
         for (int d = 0; d < 3; ++d) lu[3 * sensors[p] + d] += dLdu[3 * p + d];
     memset(grad_k, 0, (size_t)nnz * sizeof(double));
     double gA = 0.0;
+    double *gAi = calloc((size_t)(n > 0 ? n : 1), sizeof(double));  /* per-node load-gradient terms */
+    if (!gAi) {
+        free(traj); free(F); free(unew); free(lu); free(lv); free(nu); free(jt);
+        free(S.u); free(S.v);
+        return -1;
+    }
+    set_threads(P);
     const double h = dt / P->rho;
     const double damp = 1.0 - dt * P->eta / P->rho;
     for (int64_t s = nsteps - 1; s >= 0; --s) {
@@ -761,7 +768,9 @@ int pdo_adjoint_ec(const pdo_problem *P, const int32_t *frozen, int64_t nsteps,
                     if (kind == PDO_DISP) lu[q] = 0.0;
                 }
             }
-        /* parameter gradients: dF_i/dk_b = V_j s y / r, dF_i/dA = bhat_i */
+        /* parameter gradients: dF_i/dk_b = V_j s y / r, dF_i/dA = bhat_i (rows in parallel:
+         * each row updates only its own slots; the load terms are summed in node order below) */
+#pragma omp parallel for schedule(dynamic, 256)
         for (int64_t i = 0; i < n; ++i) {
             for (int64_t b = P->row_ptr[i]; b < P->row_ptr[i + 1]; ++b) {
                 if (!(k < (int64_t)frozen[b])) continue;
@@ -776,10 +785,12 @@ int pdo_adjoint_ec(const pdo_problem *P, const int32_t *frozen, int64_t nsteps,
                 double sv = ((r - L) / L) * P->vol[j] / r;
                 grad_k[b] += h * sv * (y[0] * nu[3 * i] + y[1] * nu[3 * i + 1] + y[2] * nu[3 * i + 2]);
             }
-            if (P->bhat)
-                gA += h * (P->bhat[3 * i] * nu[3 * i] + P->bhat[3 * i + 1] * nu[3 * i + 1] +
-                           P->bhat[3 * i + 2] * nu[3 * i + 2]);
+            gAi[i] = P->bhat ? h * (P->bhat[3 * i] * nu[3 * i] + P->bhat[3 * i + 1] * nu[3 * i + 1] +
+                                    P->bhat[3 * i + 2] * nu[3 * i + 2])
+                             : 0.0;
         }
+        if (P->bhat)
+            for (int64_t i = 0; i < n; ++i) gA += gAi[i];
         pdo_apply_jt(P, frozen, u, k, nu, jt);
         for (int64_t q = 0; q < n3; ++q) {
             lu[q] = lu[q] + h * jt[q];
@@ -787,6 +798,7 @@ int pdo_adjoint_ec(const pdo_problem *P, const int32_t *frozen, int64_t nsteps,
         }
     }
     *grad_A = gA;
+    free(gAi);
     free(traj); free(F); free(unew); free(lu); free(lv); free(nu); free(jt);
     free(S.u); free(S.v);
     return 0;
