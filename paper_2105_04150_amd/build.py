@@ -31,6 +31,8 @@ def _run(cmd):
 
 KERNEL_SOURCES = ("pdmi_step_sliced.hip", "pdmi_step_staged_f64.hip", "pdmi_step_staged_f32.hip",
                   "pdmi_kernels.hip", "pdmi_adjoint.hip", "pdmi_osb.hip")
+HOST_SOURCES = ("pdmi_layout.cpp", "pdmi_upload.cpp", "pdmi_run.cpp", "pdmi_api.cpp", "pdmi_api_state.cpp",
+                "pdmi_api_adjoint.cpp")
 
 
 def build(verbose: bool = False) -> str:
@@ -42,10 +44,11 @@ def build(verbose: bool = False) -> str:
         objs.append(o)
         cmds.append(["hipcc", "-c", "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *NO_PACKED_FP32,
                      "-munsafe-fp-atomics", os.path.join(CSRC, src), "-o", o])
-    host_o = os.path.join(BUILD_DIR, "pdmi_host.o")
-    objs.append(host_o)
-    cmds.append(["hipcc", "-c", "-x", "c++", *COMMON, "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__",
-                 "-I", os.path.join(ROCM, "include"), os.path.join(CSRC, "pdmi_host.cpp"), "-o", host_o])
+    for src in HOST_SOURCES:
+        o = os.path.join(BUILD_DIR, src.replace(".cpp", ".o"))
+        objs.append(o)
+        cmds.append(["hipcc", "-c", "-x", "c++", *COMMON, "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__",
+                     "-I", os.path.join(ROCM, "include"), os.path.join(CSRC, src), "-o", o])
     with ThreadPoolExecutor(len(cmds)) as ex:
         out = "".join(ex.map(_run, cmds))
     tmp = LIB + ".tmp"
