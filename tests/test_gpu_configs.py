@@ -8,7 +8,7 @@ them, their full lengths, in the launch configurations bench.py times.
 - the adjoint beam (100 x 25 x 20) for its full 2,000 steps with checkpoints every 100
   steps against the oracle's reverse pass, and central differences (h = 1e-6 k_b) on 50
   slots drawn from the top decile of |dL/dk_b|, each printed beside its predicted
-  rounding floor;
+  rounding floor (one ulp of the loss per side over 2 h |dL/dk_b|);
 - the 64-beam batch in one launch per step: four instances (smallest to largest)
   end to end for the full 5,000 steps, and all 64 over a 100-step prefix.
 
@@ -136,12 +136,13 @@ def test_adjoint_beam_full_length():
             continue
         fd = (lp - lm) / (2.0 * h)
         err = abs(gk[b] - fd) / abs(gk[b])
-        # rounding floor of the difference: each loss carries relative rounding near
-        # 1e-13 (sums over 200 sensors after 2,000 steps), divided by 2 h |g_b|
-        floor = 1e-13 * L0 / (2.0 * h * abs(gk[b]))
+        # rounding floor of the difference quotient: one unit in the last place of the loss
+        # on each side (the two runs round alike elsewhere), divided by 2 h |g_b|; the bar
+        # allows 32 such units, or 1e-5 where that is larger
+        floor = 2.0 * np.finfo(float).eps * L0 / (2.0 * h * abs(gk[b]))
         say(f"[adjoint FD] slot {b}: adjoint {gk[b]:.6e} FD {fd:.6e} rel {err:.2e} predicted floor {floor:.1e}")
-        worst = max(worst, err / max(1e-5, 10.0 * floor))
-        assert err <= max(1e-5, 10.0 * floor)
+        worst = max(worst, err / max(1e-5, 32.0 * floor))
+        assert err <= max(1e-5, 32.0 * floor)
         done += 1
     say(f"[adjoint FD] {done} slots (replaced {moved}): worst error over its allowance {worst:.3f}")
     assert done == 50
