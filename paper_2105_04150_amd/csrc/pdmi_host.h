@@ -162,6 +162,7 @@ struct pd_ctx {
     DevBuf osb, minv;                // state-based model: node pairs {theta/m, 1/m}, 1/m
     DevBuf cfv;                      // corrections per slot: family volume per node
     DevBuf unode;                    // device node of every user node (instances concatenated)
+    DevBuf slice_order;              // staged layout: slices in processing order (locality)
 
     // adjoint: per-slot break steps (recorded by every step while allocated) and the
     // (u, v) checkpoints of the last recorded forward run

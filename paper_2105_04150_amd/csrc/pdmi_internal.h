@@ -158,6 +158,7 @@ struct StepArgs {
     const int64_t* slice_ptr;
     const int32_t* slice_T;
     const int32_t* slice_inst;
+    const int32_t* slice_order; // staged step: slice of each workgroup in dispatch order (nullptr: its own)
     const InstParams* params;
     const int32_t* bc_id;
     const BCRec* bc;

@@ -152,6 +152,32 @@ static void node_order(Inst& I, int order, double h)
     I.perm = std::move(p);
 }
 
+// Processing order of the staged slices (context-wide indices).  xcd_remap hands each XCD
+// a contiguous share of the dispatch positions; within every share the slices keep their
+// device order but the longer ones (more slot rows, in buckets of 8) go first, so that the
+// last workgroups of a launch are the short ones and the tail of the launch is short.
+// Every slice writes only its own nodes, so results do not depend on the order.
+static std::vector<int32_t> slice_dispatch_order(const std::vector<int32_t>& slice_piece,
+                                                 const std::vector<int2>& pieces)
+{
+    const int64_t nsl = static_cast<int64_t>(slice_piece.size()) - 1;
+    std::vector<int32_t> order(static_cast<size_t>(nsl)), rows(static_cast<size_t>(nsl), 0);
+    for (int64_t s = 0; s < nsl; ++s) {
+        order[s] = static_cast<int32_t>(s);
+        for (int32_t q = slice_piece[s]; q < slice_piece[s + 1]; ++q) rows[s] += (pieces[q].y >> 8) & 0xff;
+    }
+    constexpr int64_t X = 8;  // XCDs, as xcd_remap splits the dispatch
+    const int64_t m = nsl / X, r = nsl % X;
+    int64_t b0 = 0;
+    for (int64_t x = 0; x < X; ++x) {
+        const int64_t len = m + (x < r ? 1 : 0);
+        std::stable_sort(order.begin() + b0, order.begin() + b0 + len,
+                         [&](int32_t a, int32_t b) { return rows[a] / 8 > rows[b] / 8; });
+        b0 += len;
+    }
+    return order;
+}
+
 // Order of each row's slots on the device: by the bond offset rounded to the lattice
 // spacing (z, then y, then x), so lanes of neighbouring nodes visit neighbours at the
 // same relative position together.  On a natural-order lattice this is ascending j.
@@ -384,6 +410,11 @@ void build_layout(pd_ctx* ctx, const HostState* S)
     if (ctx->mapping == PD_MAP_STAGED) {
         upload(ctx->pieces, pcs.data(), pcs.size() * sizeof(int2), 0, ctx->stream);
         upload(ctx->slice_piece, spc.data(), spc.size() * sizeof(int32_t), 0, ctx->stream);
+        const std::vector<int32_t> order = slice_dispatch_order(spc, pcs);
+        ctx->slice_order.alloc(order.size() * sizeof(int32_t));
+        upload(ctx->slice_order, order.data(), order.size() * sizeof(int32_t), 0, ctx->stream);
+    } else {
+        ctx->slice_order.release();
     }
     const int64_t st = ctx->step;
     upload(ctx->step_base, &st, sizeof st, 0, ctx->stream);

@@ -32,6 +32,7 @@ StepArgs step_args(pd_ctx* ctx, int in, int out, int64_t step_local)
     A.slice_ptr = ctx->slice_ptr.as<int64_t>();
     A.slice_T = ctx->slice_T.as<int32_t>();
     A.slice_inst = ctx->slice_inst.as<int32_t>();
+    A.slice_order = ctx->slice_order.p ? ctx->slice_order.as<int32_t>() : nullptr;
     A.params = ctx->params.as<InstParams>();
     A.bc_id = ctx->bc_id.as<int32_t>();
     A.bc = ctx->bc.as<BCRec>();

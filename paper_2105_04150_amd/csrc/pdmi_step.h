@@ -60,7 +60,7 @@ struct SlotTerm32 {
 __device__ __forceinline__ bool slot_force(bool live, bool breakable, const double2 p0, const double2 p1, const double2 p2,
                                            double X0, double X1, double X2, double U0, double U1, double U2,
                                            double kv, double q0, double& F0, double& F1, double& F2, SlotTerm& st,
-                                           const SeriesCoef& sk = SeriesCoef())
+                                           const SeriesCoef& sk = SeriesCoef(), uint64_t* cand_ballot = nullptr)
 {
     const double xi0 = p0.x - X0, xi1 = p0.y - X1, xi2 = p1.x - X2;
     const double e0 = p1.y - U0, e1 = p2.x - U1, e2 = p2.y - U2;
@@ -71,8 +71,13 @@ __device__ __forceinline__ bool slot_force(bool live, bool breakable, const doub
     const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
     const double iL = rsq64<1>(L2);
     const double q = tq * (iL * iL);
-    const bool cand = breakable && q >= q0;
+    // one comparison decides both ways (a NaN q, from a non-finite state, is a candidate:
+    // the rare branch adds it)
+    const bool below = q < q0;
+    const bool cand = breakable && !below;
     const bool alive = live && !cand;
+    // the lanes' candidates as a mask (each ballot of a comparison is its lane mask)
+    if (cand_ballot) *cand_ballot = __builtin_amdgcn_ballot_w64(breakable) & ~__builtin_amdgcn_ballot_w64(below);
     // broken and padding slots (and candidates) evaluate g(0) = 0 and add nothing
     const double coef = (kv * iL) * one_minus_rsqrt1p(alive ? q : 0.0, sk);
     st = SlotTerm{q, coef, y0, y1, y2};
@@ -490,8 +495,9 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     double* const lvol = reinterpret_cast<double*>(lrec + kRecChunks + kEntChunks);
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
+    int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
     if (slice >= A.nslices) return;
+    if (A.slice_order) slice = __builtin_amdgcn_readfirstlane(A.slice_order[slice]);
     const int32_t* __restrict__ slice_inst = A.slice_inst;
     const InstParams* __restrict__ params = A.params;
     const InstParams P = params[slice_inst[slice]];
@@ -504,6 +510,9 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     const float Uf0 = __uint_as_float(static_cast<uint32_t>(ub1)), Uf1 = __uint_as_float(static_cast<uint32_t>(ub1 >> 32)),
                 Uf2 = __uint_as_float(static_cast<uint32_t>(ub2));  // FP32 build
     const double cv = P.c * P.volume;
+    // plain FP64 kernels with uniform c and V accumulate sum (1/|xi|) g(q) y and apply c V
+    // once, after the sum
+    constexpr bool UNI = !FP32 && !STIFF && !VOLN && !KNODE && !CORR && !EXT;
     const float cvf = static_cast<float>(cv), q0f = static_cast<float>(P.q0);
     uint16_t* __restrict__ entw = A.ent;
     int32_t* __restrict__ bstep = A.bstep;
@@ -533,6 +542,10 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     for (int q = p0; q < pa && q < p1; ++q) ent += static_cast<int64_t>(rows_of(q)) * kWave;
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
     float Ff0 = 0.0f, Ff1 = 0.0f, Ff2 = 0.0f;
+    // FP64 plain kernels: the candidates of a row are kept as its lane mask (scalar), and the
+    // rare branch finds the lanes again
+    constexpr bool ROWMASK = !EXT && !FP32;
+    uint64_t cmask = 0;  // candidate lanes of the slot evaluated last
 
     // staging registers of the next piece (weights and stiffness; records and entries go
     // straight to LDS)
@@ -540,6 +553,13 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     int vlen = 0;
     constexpr int kKPre = 2;  // stiffness rows fetched a piece ahead; the rest when the piece starts
     double kcur[kPieceRows], knext[kKPre];
+    auto kcur_at = [&](int t) {  // kcur[t] for a row index only known at run time (no indexed registers)
+        double k = 0.0;
+#pragma unroll
+        for (int u = 0; u < kPieceRows; ++u)
+            if (u == t) k = kcur[u];
+        return k;
+    };
 
     // Loads of piece p (first entry e): a fixed 256-chunk window from the range start
     // (the record buffers end with kRecPad spare records) and the whole 8-row entry block
@@ -587,7 +607,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
         const double2 q0 = *reinterpret_cast<const double2*>(lrecb + off);
         const double2 q1 = *reinterpret_cast<const double2*>(lrecb + off + 16);
         const double2 q2 = *reinterpret_cast<const double2*>(lrecb + off + 32);
-        double kv = cv;
+        double kv = UNI ? 1.0 : cv;
         const uint32_t widx = (off * 0xAAABu) >> 21;  // off / 48
         if (KNODE) {
             kv = ai * lvol[widx];
@@ -614,7 +634,8 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             return slot_force32(live, breakable, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2,
                                 (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : kvf,
                                 q0f, Gf0, Gf1, Gf2, st32);
-        return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, G0, G1, G2, st, sk);
+        return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, G0, G1, G2, st, sk,
+                          ROWMASK ? &cmask : nullptr);
     };
     auto eval = [&](uint16_t e, double kst, bool live, bool breakable, SlotTerm& st, SlotTerm32& st32) {
         return eval_into(e, kst, live, breakable, st, st32, F0, F1, F2, Ff0, Ff1, Ff2);
@@ -711,7 +732,9 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                     kcur[t] = t < kKPre ? knext[t] : __builtin_nontemporal_load(A.kslot + ent + t * kWave + lane);
             if (p + S < p1) issue(p + S, ent_next);
             wave_sync();  // the piece's LDS copy is complete
-            uint32_t flags = 0;  // rows of this piece whose slot takes the rare branch
+            // rows of this piece whose slot takes the rare branch: per lane, or (FP64 plain
+            // kernels) rows in which some lane's slot does, wave-uniform
+            uint32_t flags = 0;
 #pragma unroll
             for (int t = 0; t < kPieceRows; t += 2) {
                 if (t >= T) break;
@@ -721,18 +744,44 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                     SlotTerm sa, sb;
                     SlotTerm32 sa32, sb32;
                     const bool ba = row(ea, STIFF ? kcur[t] : 0.0, sa, sa32);
+                    const uint64_t cm_a = cmask;
                     const bool bb = row(eb, STIFF ? kcur[t + 1] : 0.0, sb, sb32);
-                    flags |= (ba ? 1u << t : 0u) | (bb ? 2u << t : 0u);
+                    if constexpr (ROWMASK)
+                        flags |= (cm_a != 0 ? 1u << t : 0u) | (cmask != 0 ? 2u << t : 0u);
+                    else
+                        flags |= (ba ? 1u << t : 0u) | (bb ? 2u << t : 0u);
                 } else {
                     SlotTerm sa;
                     SlotTerm32 sa32;
-                    flags |= row(ea, STIFF ? kcur[t] : 0.0, sa, sa32) ? 1u << t : 0u;
+                    const bool ba = row(ea, STIFF ? kcur[t] : 0.0, sa, sa32);
+                    if constexpr (ROWMASK)
+                        flags |= cmask != 0 ? 1u << t : 0u;
+                    else
+                        flags |= ba ? 1u << t : 0u;
                 }
             }
-            if (__builtin_amdgcn_ballot_w64(flags != 0) != 0) {
+            if constexpr (!ROWMASK) {
+                if (__builtin_amdgcn_ballot_w64(flags != 0) != 0) {
 #pragma unroll
-                for (int t = 0; t < kPieceRows; ++t)
-                    if (flags & (1u << t)) flagged(ent + t * kWave + lane, lent[t * kWave + lane], STIFF ? kcur[t] : 0.0);
+                    for (int t = 0; t < kPieceRows; ++t)
+                        if (flags & (1u << t)) flagged(ent + t * kWave + lane, lent[t * kWave + lane], STIFF ? kcur[t] : 0.0);
+                }
+            } else if (__builtin_amdgcn_readfirstlane(flags) != 0) {
+                // the lanes of a marked row whose slot the common path left out, found again
+                // (the same arithmetic on the same staged record decides the same way)
+#pragma unroll 1
+                for (int t = 0; t < T; ++t) {
+                    if (!(__builtin_amdgcn_readfirstlane(flags) & (1u << t))) continue;
+                    const uint16_t e = lent[t * kWave + lane];
+                    const double kst = STIFF ? kcur_at(t) : 0.0;
+                    SlotTerm st;
+                    SlotTerm32 st32;
+                    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+                    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+                    const bool live = !(e & kEntBroken);
+                    if (eval_into(e, kst, live, MODE != kModeForce && live, st, st32, d0, d1, d2, f0, f1, f2))
+                        flagged(ent + t * kWave + lane, e, kst);
+                }
             }
             ent = ent_next;
         }
@@ -758,6 +807,11 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             F1 += r[kWave];
             F2 += r[2 * kWave];
         }
+    }
+    if (UNI) {
+        F0 *= cv;
+        F1 *= cv;
+        F2 *= cv;
     }
     node_update<MODE, FP32>(A, P, node, U0, U1, U2, F0, F1, F2);
 }
