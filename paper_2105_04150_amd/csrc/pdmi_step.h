@@ -510,9 +510,9 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     const float Uf0 = __uint_as_float(static_cast<uint32_t>(ub1)), Uf1 = __uint_as_float(static_cast<uint32_t>(ub1 >> 32)),
                 Uf2 = __uint_as_float(static_cast<uint32_t>(ub2));  // FP32 build
     const double cv = P.c * P.volume;
-    // plain FP64 kernels with uniform c and V accumulate sum (1/|xi|) g(q) y and apply c V
-    // once, after the sum
-    constexpr bool UNI = !FP32 && !STIFF && !VOLN && !KNODE && !CORR && !EXT;
+    // plain kernels with uniform c and V accumulate sum (1/|xi|) g(q) y and apply c V once,
+    // after the sum (in f64)
+    constexpr bool UNI = !STIFF && !VOLN && !KNODE && !CORR && !EXT;
     const float cvf = static_cast<float>(cv), q0f = static_cast<float>(P.q0);
     uint16_t* __restrict__ entw = A.ent;
     int32_t* __restrict__ bstep = A.bstep;
@@ -618,7 +618,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
             const double L2 = __builtin_fma(xc, xc, __builtin_fma(xb, xb, xa * xa));
             kv = cv * corr_factor(P, L2 * rsq64<1>(L2), fvi, lvol[widx]);
         }
-        float kvf = cvf;
+        float kvf = UNI ? 1.0f : cvf;
         if (CORR && FP32) {  // the same factors in single precision, from slot_force32's bond vector
             const float xa = static_cast<float>(q0.x - X0), xb = static_cast<float>(q0.y - X1),
                         xc = static_cast<float>(q1.x - X2);
