@@ -510,9 +510,9 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     const float Uf0 = __uint_as_float(static_cast<uint32_t>(ub1)), Uf1 = __uint_as_float(static_cast<uint32_t>(ub1 >> 32)),
                 Uf2 = __uint_as_float(static_cast<uint32_t>(ub2));  // FP32 build
     const double cv = P.c * P.volume;
-    // plain kernels with uniform c and V accumulate sum (1/|xi|) g(q) y and apply c V once,
-    // after the sum (in f64)
-    constexpr bool UNI = !STIFF && !VOLN && !KNODE && !CORR && !EXT;
+    // kernels with uniform c and V accumulate sum (1/|xi|) g(q) y (and the bond-model
+    // branch's corrections in the same units) and apply c V once, after the sum (in f64)
+    constexpr bool UNI = !STIFF && !VOLN && !KNODE && !CORR;
     const float cvf = static_cast<float>(cv), q0f = static_cast<float>(P.q0);
     uint16_t* __restrict__ entw = A.ent;
     int32_t* __restrict__ bstep = A.bstep;
@@ -542,9 +542,9 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     for (int q = p0; q < pa && q < p1; ++q) ent += static_cast<int64_t>(rows_of(q)) * kWave;
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
     float Ff0 = 0.0f, Ff1 = 0.0f, Ff2 = 0.0f;
-    // FP64 plain kernels: the candidates of a row are kept as its lane mask (scalar), and the
-    // rare branch finds the lanes again
-    constexpr bool ROWMASK = !EXT && !FP32;
+    // FP64 kernels: the slots of a row that take the rare branch are kept as its lane mask
+    // (scalar), and the rare branch finds the lanes again
+    constexpr bool ROWMASK = !FP32;
     uint64_t cmask = 0;  // candidate lanes of the slot evaluated last
 
     // staging registers of the next piece (weights and stiffness; records and entries go
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                                 (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : kvf,
                                 q0f, Gf0, Gf1, Gf2, st32);
         return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, G0, G1, G2, st, sk,
-                          ROWMASK ? &cmask : nullptr);
+                          ROWMASK && !EXT ? &cmask : nullptr);
     };
     auto eval = [&](uint16_t e, double kst, bool live, bool breakable, SlotTerm& st, SlotTerm32& st32) {
         return eval_into(e, kst, live, breakable, st, st32, F0, F1, F2, Ff0, Ff1, Ff2);
@@ -645,9 +645,15 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     auto row = [&](uint16_t e, double kst, SlotTerm& st, SlotTerm32& st32) {
         const bool live = !(e & kEntBroken);
         if constexpr (EXT) {
-            eval(e, kst, live, false, st, st32);
             const bool soft = (e & kEntSoft) != 0;
+            // the condition as lane masks (each ballot of a comparison is one), the entry's
+            // taken before the evaluation's branch
+            const uint64_t lm = ROWMASK ? __builtin_amdgcn_ballot_w64(live) : 0;
+            const uint64_t sm = ROWMASK ? __builtin_amdgcn_ballot_w64(soft) : 0;
+            eval(e, kst, live, false, st, st32);
             const bool over = FP32 ? static_cast<float>(st32.q) >= q0f : st.q >= P.q0;
+            if constexpr (ROWMASK)
+                cmask = lm & (MODE == kModeForce ? sm : (__builtin_amdgcn_ballot_w64(over) | sm));
             return live && (MODE == kModeForce ? soft : (over || soft));
         } else {
             return eval(e, kst, live, MODE != kModeForce && live, st, st32);
@@ -732,8 +738,8 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                     kcur[t] = t < kKPre ? knext[t] : __builtin_nontemporal_load(A.kslot + ent + t * kWave + lane);
             if (p + S < p1) issue(p + S, ent_next);
             wave_sync();  // the piece's LDS copy is complete
-            // rows of this piece whose slot takes the rare branch: per lane, or (FP64 plain
-            // kernels) rows in which some lane's slot does, wave-uniform
+            // rows of this piece whose slot takes the rare branch: per lane (FP32), or rows in
+            // which some lane's slot does, wave-uniform (FP64)
             uint32_t flags = 0;
 #pragma unroll
             for (int t = 0; t < kPieceRows; t += 2) {
@@ -767,8 +773,8 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                         if (flags & (1u << t)) flagged(ent + t * kWave + lane, lent[t * kWave + lane], STIFF ? kcur[t] : 0.0);
                 }
             } else if (__builtin_amdgcn_readfirstlane(flags) != 0) {
-                // the lanes of a marked row whose slot the common path left out, found again
-                // (the same arithmetic on the same staged record decides the same way)
+                // the lanes of a marked row that take the rare branch, found again (the same
+                // arithmetic on the same staged record decides the same way)
 #pragma unroll 1
                 for (int t = 0; t < T; ++t) {
                     if (!(__builtin_amdgcn_readfirstlane(flags) & (1u << t))) continue;
@@ -779,8 +785,16 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                     double d0 = 0.0, d1 = 0.0, d2 = 0.0;
                     float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
                     const bool live = !(e & kEntBroken);
-                    if (eval_into(e, kst, live, MODE != kModeForce && live, st, st32, d0, d1, d2, f0, f1, f2))
+                    if constexpr (EXT) {
+                        // the slot's terms as the common path formed them, then (for the lanes
+                        // that take the branch) its damage state's weight
+                        eval_into(e, kst, live, false, st, st32, d0, d1, d2, f0, f1, f2);
+                        const bool soft = (e & kEntSoft) != 0;
+                        if (live && (MODE == kModeForce ? soft : (st.q >= P.q0 || soft)))
+                            model(ent + t * kWave + lane, e, st, st32);
+                    } else if (eval_into(e, kst, live, MODE != kModeForce && live, st, st32, d0, d1, d2, f0, f1, f2)) {
                         flagged(ent + t * kWave + lane, e, kst);
+                    }
                 }
             }
             ent = ent_next;
