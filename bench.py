@@ -139,13 +139,18 @@ def _timed(fn, sync):
     return time.perf_counter() - t0
 
 
-def adjoint_extra(P, pi, sync, steps: int, ckpt: int):
+def adjoint_extra(P, pi, sync, steps: int, ckpt: int, mapping: str = "auto"):
     """Adjoint on the 100 x 25 x 20 beam (Euler-Cromer, stiffness field, tip load, 200
     sensors): plain steps, the recording forward run and the reverse pass, timed on the
-    same problem.  Rates are bond-updates per second of simulated forward steps."""
+    same problem.  Rates are bond-updates per second of simulated forward steps.
+    mapping "staged" fixes four wavefronts per slice instead of asking the autotuner (the
+    counter runs do, since counter collection serialises the trial launches)."""
     w = pi.workload("adjoint_beam", steps=steps)
     sim = P.simulation_for(w, lanes=4)
-    sim.autotune(trial_steps=10)
+    if mapping == "staged":
+        sim.set_mapping("staged", 4)
+    else:
+        sim.autotune(trial_steps=10)
     sim.prepare()
     info = sim.info()
     nnz = info["n_slots"]
@@ -462,6 +467,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32, adjoint, batched and quasi-static measurements")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-mapping", default="auto", choices=["auto", "staged"],
+                    help="adjoint line: the autotuner's mapping, or staged with four wavefronts per slice")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=300)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -502,7 +509,7 @@ def main():
         except Exception:
             sync = lambda: None  # noqa: E731
         if args.extra == "adjoint":
-            line = adjoint_extra(P, pi, sync, args.adjoint_steps, 100)
+            line = adjoint_extra(P, pi, sync, args.adjoint_steps, 100, args.adjoint_mapping)
         elif args.extra == "batched":
             line = batched_extra(P, pi, sync, args.batch_count, args.batch_steps, 0, tune=False)
         elif args.extra == "corrections":

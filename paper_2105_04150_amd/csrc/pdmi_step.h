@@ -92,7 +92,8 @@ __device__ __forceinline__ bool slot_force(bool live, bool breakable, const doub
 // 1 - (1+q)^(-1/2) uses four series terms (below 1.3e-10 relative for |q| < 4e-3).
 __device__ __forceinline__ bool slot_force32(bool live, bool breakable, const double2 p0, const double2 p1, const double2 p2,
                                              double X0, double X1, double X2, float U0, float U1, float U2,
-                                             float kv, float q0, float& F0, float& F1, float& F2, SlotTerm32& st)
+                                             float kv, float q0, float& F0, float& F1, float& F2, SlotTerm32& st,
+                                             uint64_t* brk_ballot = nullptr)
 {
     const float xi0 = static_cast<float>(p0.x - X0), xi1 = static_cast<float>(p0.y - X1),
                 xi2 = static_cast<float>(p1.x - X2);
@@ -108,6 +109,8 @@ __device__ __forceinline__ bool slot_force32(bool live, bool breakable, const do
     const float q = tq * (iL * iL);
     const bool brk = breakable && q >= q0;
     const bool alive = live && !brk;
+    // the lanes that break as a mask (each ballot of a comparison is its lane mask)
+    if (brk_ballot) *brk_ballot = __builtin_amdgcn_ballot_w64(breakable) & __builtin_amdgcn_ballot_w64(q >= q0);
     const float qa = alive ? q : 0.0f;
     float g;
     if (fabsf(qa) < 4.0e-3f) {
@@ -542,9 +545,9 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     for (int q = p0; q < pa && q < p1; ++q) ent += static_cast<int64_t>(rows_of(q)) * kWave;
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
     float Ff0 = 0.0f, Ff1 = 0.0f, Ff2 = 0.0f;
-    // FP64 kernels: the slots of a row that take the rare branch are kept as its lane mask
-    // (scalar), and the rare branch finds the lanes again
-    constexpr bool ROWMASK = !FP32;
+    // the slots of a row that take the rare branch are kept as its lane mask (scalar), and
+    // the rare branch finds the lanes again (the FP32 bond-model kernels keep per-lane bits)
+    constexpr bool ROWMASK = !FP32 || !EXT;
     uint64_t cmask = 0;  // candidate lanes of the slot evaluated last
 
     // staging registers of the next piece (weights and stiffness; records and entries go
@@ -633,7 +636,7 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
         if (FP32)
             return slot_force32(live, breakable, q0, q1, q2, X0, X1, X2, Uf0, Uf1, Uf2,
                                 (STIFF || VOLN || KNODE) ? static_cast<float>(kv) : kvf,
-                                q0f, Gf0, Gf1, Gf2, st32);
+                                q0f, Gf0, Gf1, Gf2, st32, ROWMASK && !EXT ? &cmask : nullptr);
         return slot_force(live, breakable, q0, q1, q2, X0, X1, X2, U0, U1, U2, kv, P.q0, G0, G1, G2, st, sk,
                           ROWMASK && !EXT ? &cmask : nullptr);
     };
@@ -738,8 +741,8 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
                     kcur[t] = t < kKPre ? knext[t] : __builtin_nontemporal_load(A.kslot + ent + t * kWave + lane);
             if (p + S < p1) issue(p + S, ent_next);
             wave_sync();  // the piece's LDS copy is complete
-            // rows of this piece whose slot takes the rare branch: per lane (FP32), or rows in
-            // which some lane's slot does, wave-uniform (FP64)
+            // rows of this piece whose slot takes the rare branch: rows in which some lane's
+            // slot does, wave-uniform, or per lane (FP32 bond-model kernels)
             uint32_t flags = 0;
 #pragma unroll
             for (int t = 0; t < kPieceRows; t += 2) {
