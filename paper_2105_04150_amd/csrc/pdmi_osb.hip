@@ -133,15 +133,17 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
     auto dma = [&](int p, int64_t e) {
         const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
         const double2* rs = rin + 3 * static_cast<int64_t>(m.x) + lane;
+        // one address and one LDS base for the four 1 KB chunks: the instruction's immediate
+        // offset advances the global and the LDS address alike
         __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(rs + kWave, (lds_ptr)(lrec + kWave), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(rs + 2 * kWave, (lds_ptr)(lrec + 2 * kWave), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(rs + 3 * kWave, (lds_ptr)(lrec + 3 * kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 16 * kWave, 0);
+        __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 2 * 16 * kWave, 0);
+        __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 3 * 16 * kWave, 0);
         __builtin_amdgcn_global_load_lds(ent2 + e / 8 + lane, (lds_ptr)(lent), 16, 0, 0);
         if (PASS == 1) {  // the pair buffer ends with 2 x 64 spare pairs
             const double2* ps = A.osb + m.x + lane;
             __builtin_amdgcn_global_load_lds(ps, (lds_ptr)(lpair), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds(ps + kWave, (lds_ptr)(lpair + kWave), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(ps, (lds_ptr)(lpair), 16, 16 * kWave, 0);
         }
         if (VOLN) {  // per-node volumes: the volume buffer ends with spare entries
             const float* ws = reinterpret_cast<const float*>(A.vol + m.x) + lane;

@@ -583,10 +583,12 @@ __global__ __launch_bounds__(kWave * S) void step_staged(StepArgs A, const int2*
     auto dma = [&](int p, int64_t e) {
         const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
         const double2* rs = rin + 3 * static_cast<int64_t>(m.x) + lane;
+        // one address and one LDS base for the four 1 KB chunks: the instruction's immediate
+        // offset advances the global and the LDS address alike
         __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(rs + kWave, (lds_ptr)(lrec + kWave), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(rs + 2 * kWave, (lds_ptr)(lrec + 2 * kWave), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(rs + 3 * kWave, (lds_ptr)(lrec + 3 * kWave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 16 * kWave, 0);
+        __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 2 * 16 * kWave, 0);
+        __builtin_amdgcn_global_load_lds(rs, (lds_ptr)(lrec), 16, 3 * 16 * kWave, 0);
         __builtin_amdgcn_global_load_lds(ent2 + e / 8 + lane, (lds_ptr)(lent), 16, 0, 0);
         if (CORR) {
             const float* ws = reinterpret_cast<const float*>(A.cfv + m.x) + lane;
