@@ -164,8 +164,12 @@ __device__ __forceinline__ void adj_wave_sync()
 // entries, so the fixed windows need no clamping); per-slot break steps, stiffness and
 // the gradient stream by row.  Padding entries point at an LDS sentinel (far record,
 // zero adjoint velocity and weights).  Partial sums of J meet in LDS in a fixed order.
+// The layout tables come as restrict parameters: their loads are then scalar, and a
+// piece's descriptor does not wait behind the vector loads in flight.
 template <int KM, bool VOLN, int S>
-__global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
+__global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A, const int2* __restrict__ pieces,
+                                                         const int32_t* __restrict__ slice_piece,
+                                                         const int64_t* __restrict__ slice_ptr)
 {
     constexpr bool KNODE = KM == kKNode;
     constexpr int kW = (kEntPad / 48 + 2) / 2 * 2;  // staged weights per array (sentinel at kEntPad / 48)
@@ -204,10 +208,10 @@ __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
     if (VOLN && lane == 0) lvol[kEntPad / 48] = 0.0;
     if (KNODE && lane == 0) lna[kEntPad / 48] = 0.0;
 
-    const int p0 = __builtin_amdgcn_readfirstlane(A.slice_piece[slice]);
-    const int p1 = __builtin_amdgcn_readfirstlane(A.slice_piece[slice + 1]);
-    auto rows_of = [&](int p) { return (A.pieces[__builtin_amdgcn_readfirstlane(p)].y >> 8) & 0xff; };
-    int64_t ent = wave_uniform(A.slice_ptr[slice]);
+    const int p0 = __builtin_amdgcn_readfirstlane(slice_piece[slice]);
+    const int p1 = __builtin_amdgcn_readfirstlane(slice_piece[slice + 1]);
+    auto rows_of = [&](int p) { return (pieces[__builtin_amdgcn_readfirstlane(p)].y >> 8) & 0xff; };
+    int64_t ent = wave_uniform(slice_ptr[slice]);
     const int pa = p0 + wv;
     for (int q = p0; q < pa && q < p1; ++q) ent += static_cast<int64_t>(rows_of(q)) * kWave;
 
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
     double n0, n1, n2, n3, vs0 = 0.0, vs1 = 0.0, as0 = 0.0, as1 = 0.0;
     int vlen = 0;
     auto issue = [&](int p, int64_t e) {
-        const int2 m = A.pieces[__builtin_amdgcn_readfirstlane(p)];
+        const int2 m = pieces[__builtin_amdgcn_readfirstlane(p)];
         const double2* rs = rec + 3 * static_cast<int64_t>(m.x) + lane;
         r0 = rs[0];
         r1 = rs[kWave];
@@ -287,9 +291,10 @@ __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
             for (int q = p + 1; q < p + S && q < p1; ++q) ent_next += static_cast<int64_t>(rows_of(q)) * kWave;
             adj_wave_sync();  // the previous piece is no longer read
             commit();
-            if (p + S < p1) issue(p + S, ent_next);
             // the piece's per-slot streams, all eight rows of its block at once (rows past T
-            // belong to the next piece or the spare rows and are not used)
+            // belong to the next piece or the spare rows and are not used), issued before
+            // the next piece's prefetch: vector-memory loads complete in order, so the rows
+            // wait for these only and the prefetch stays in flight behind them
 #pragma unroll
             for (int t = 0; t < kPieceRows; ++t) {
                 const int64_t ds = ent + t * kWave + lane;
@@ -297,6 +302,7 @@ __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A)
                 gr[t] = A.grad[ds];
                 if (KM == kKSlot) kr[t] = A.kslot[ds];
             }
+            if (p + S < p1) issue(p + S, ent_next);
             adj_wave_sync();  // the piece's LDS copy is complete
 #pragma unroll
             for (int t = 0; t < kPieceRows; ++t) {
@@ -403,9 +409,9 @@ hipError_t adj_launch_kv(const AdjArgs& a, bool staged, int lanes, hipStream_t s
     const dim3 grid(static_cast<unsigned>(a.nslices));
     if (staged) {
         switch (lanes) {  // wavefronts per slice
-        case 1: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 1>), grid, dim3(kWave), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 2>), grid, dim3(2 * kWave), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 4>), grid, dim3(4 * kWave), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 1>), grid, dim3(kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+        case 2: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 2>), grid, dim3(2 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+        case 4: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 4>), grid, dim3(4 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
