@@ -14,8 +14,9 @@
 // even in y.  With symmetric stiffness and schedule, (J_F^T nu)_i is the gather
 //   sum over the family of i of k_b K_b (V_i nu_j - V_j nu_i),
 // the same shape as the force, so the reverse pass walks the forward slot layout and
-// needs no reverse-slot index.  1/L - 1/r = (1/L)(1 - (1+q)^(-1/2)) uses the
-// cancellation-free q = |y|^2/|xi|^2 - 1 of the step kernel, and 1/r is 1/L less that.
+// needs no reverse-slot index.  1/L - 1/r = (1/L)(1 - (1+q)^(-1/2)) uses
+// q = |y|^2/|xi|^2 - 1 with the numerator formed without cancellation, eta.(xi + y), and
+// 1/r is 1/L less that.
 #include "pdmi_device.h"
 
 namespace pdmi {

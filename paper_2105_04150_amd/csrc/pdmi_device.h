@@ -47,7 +47,7 @@ __device__ __forceinline__ double one_minus_rsqrt1p(double q, const SeriesCoef& 
 // kernel keeps a bond only while s < s0): s = (|y| - |xi|)/|xi| with the squares summed
 // as (a^2 + b^2) + c^2, every product and sum rounded once (no fused multiply-add), and
 // the square roots and the division correctly rounded (the device's IEEE sequences).  The
-// step kernels decide on the cancellation-free q almost always; a slot whose q lies
+// step kernels decide on their fast q almost always; a slot whose q lies
 // within the instance's margin of the threshold (or a law's breakpoint) is decided here,
 // so that two implementations reading the same x and u break the same bonds.
 __device__ __forceinline__ double stretch_exact(double xi0, double xi1, double xi2, double y0, double y1, double y2)

@@ -1,7 +1,7 @@
 """Break decisions equal to the oracle's by construction (FP64 build).
 
 The paper's rule (Eq. mu, Algorithm 2) keeps a bond only while s < s0, with
-s = (|y| - |xi|)/|xi|.  The kernels decide on a cancellation-free q almost always, and on
+s = (|y| - |xi|)/|xi|.  The kernels decide on a fast q-form almost always, and on
 the oracle's exact sequence of operations inside a narrow margin around every
 threshold.  These tests read the same x and u on both sides and require the same
 decision slot for slot, with thresholds placed -2, -1, 0, +1 and +2 ulp from the
