@@ -14,14 +14,15 @@
 //
 // Bond arithmetic (per slot b = (i, j), Eqs. microelastic and simpleBond):
 //   xi = x_j - x_i,  eta = u_j - u_i,  y = xi + eta
-//   q  = |y|^2/|xi|^2 - 1, the numerator as one fused chain |y|^2 - |xi|^2
+//   q  = |y|^2/|xi|^2 - 1, the numerator as |y|^2 - |xi|^2, both sums in the same order
 //   break when s >= s0, i.e. q >= (1 + s0)^2 - 1
 //   f  = c s V_j y/|y| = c V_j (1/|xi|) (1 - (1+q)^(-1/2)) y
-// The FP64 numerator cancels: q carries an absolute error of about four units of 2^-53
-// (plus 1e-14 relative from 1/|xi|), the same order as the rounding of the oracle's own
-// (|y| - |xi|)/|xi|.  1 - (1+q)^(-1/2) is summed as its binomial series for |q| < 4e-3,
-// so the force adds no second cancellation.  The FP32 kernels keep the cancellation-free
-// numerator eta.(xi + y): in single precision the fused chain would lose most digits of
+// The FP64 numerator cancels: q carries an absolute error of a few units of 2^-53 (plus
+// 1e-14 relative from 1/|xi|), the same order as the rounding of the oracle's own
+// (|y| - |xi|)/|xi|, and is exactly zero for an unstretched bond (y = xi).
+// 1 - (1+q)^(-1/2) is summed as its binomial series for |q| < 4e-3, so the force adds no
+// second cancellation.  The FP32 kernels keep the cancellation-free numerator
+// eta.(xi + y): in single precision the difference of squares would lose most digits of
 // a small stretch.
 // The break decision is made on q except within a narrow margin around the threshold,
 // where a rare branch recomputes s = (|y| - |xi|)/|xi| in the oracle's exact order of
@@ -70,9 +71,12 @@ __device__ __forceinline__ bool slot_force(bool live, bool breakable, const doub
     const double e0 = p1.y - U0, e1 = p2.x - U1, e2 = p2.y - U2;
     const double y0 = xi0 + e0, y1 = xi1 + e1, y2 = xi2 + e2;
     const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
-    // |y|^2 - |xi|^2: three fewer operations than eta.(xi + y), for an absolute error in q
-    // near 4.4e-16, six orders of magnitude inside the decision margin
-    const double tq = __builtin_fma(y2, y2, __builtin_fma(y1, y1, __builtin_fma(y0, y0, -L2)));
+    // |y|^2 - |xi|^2 with both squares summed in the same order: two fewer operations than
+    // eta.(xi + y), an absolute error in q below 7e-16 (six orders of magnitude inside the
+    // decision margin), and exactly zero when y = xi (a body at rest or rigidly translated
+    // feels no bond force)
+    const double Y2 = __builtin_fma(y2, y2, __builtin_fma(y1, y1, y0 * y0));
+    const double tq = Y2 - L2;
     const double iL = rsq64<1>(L2);
     const double q = tq * (iL * iL);
     // one comparison decides both ways (a NaN q, from a non-finite state, is a candidate:

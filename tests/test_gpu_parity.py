@@ -277,6 +277,36 @@ def test_all_bonds_broken_free_flight(oracle_lib, mapping, lanes):
         assert np.all(g.damage() == 1.0) and np.all(g.broken())
 
 
+@pytest.mark.parametrize("mapping,lanes,precision,model", [
+    ("sliced", 4, "f64", "pmb"), ("staged", 1, "f64", "pmb"), ("staged", 4, "f64", "pmb"),
+    ("staged", 1, "f32", "pmb"), ("staged", 1, "f64", "state_based")])
+@pytest.mark.parametrize("scheme", ["euler_cromer", "velocity_verlet"])
+def test_rest_and_rigid_translation_exact(mapping, lanes, precision, model, scheme):
+    """A body at rest under no load stays at rest, and a rigid translation is force-free:
+    the stretch depends on the relative displacement only (Eq. simpleBond and the
+    state-based dilation), so every bond is unstretched and every node keeps its
+    displacement and a zero velocity, bit for bit, in both precisions and models."""
+    from paper_2105_04150_amd import PD_FP32, PD_FP64, Simulation
+    w = pi.workload("block10", dims=(7, 6, 5), steps=60, model=model)
+    # a shift of a fraction of the spacing, exactly representable in single precision
+    shift = (np.array([0.37, -0.21, 0.13]) * w.dx).astype(np.float32).astype(np.float64)
+    z = np.zeros((w.n, 3))
+    with Simulation(precision=PD_FP32 if precision == "f32" else PD_FP64) as g:
+        g.set_mapping(mapping, lanes)
+        g.build_family(w.coords, w.horizon)
+        g.set_integrator(scheme, w.dt)
+        g.set_material(w.rho, w.c, w.s0, 0.0, w.volume)
+        if model == "state_based":
+            g.set_model("state_based", *w.state_based)
+        g.step(w.steps)
+        assert not g.u().any() and not g.v().any()
+        uc = np.tile(shift, (w.n, 1))
+        g.set_state(u=uc, v=z, a=z)
+        g.step(w.steps)
+        assert np.array_equal(g.u(), uc) and not g.v().any()
+        assert not g.broken().any()
+
+
 def test_coincident_nodes_rejected():
     from paper_2105_04150_amd import PdmiError, Simulation
     x = pi.lattice((4, 4, 4), 1.0e-3)[0]
