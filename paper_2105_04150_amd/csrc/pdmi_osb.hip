@@ -213,9 +213,10 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
         const double xi0 = r0.x - X0, xi1 = r0.y - X1, xi2 = r1.x - X2;
         const double e0 = r1.y - U0, e1 = r2.x - U1, e2 = r2.y - U2;
         const double y0 = xi0 + e0, y1 = xi1 + e1, y2 = xi2 + e2;
-        const double z0 = xi0 + y0, z1 = xi1 + y1, z2 = xi2 + y2;
-        const double tq = __builtin_fma(e2, z2, __builtin_fma(e1, z1, e0 * z0));
+        // |y|^2 - |xi|^2 from two sums in the same order (exactly zero for an unstretched
+        // bond), as the bond-based kernels form it
         const double L2 = __builtin_fma(xi2, xi2, __builtin_fma(xi1, xi1, xi0 * xi0));
+        const double tq = __builtin_fma(y2, y2, __builtin_fma(y1, y1, y0 * y0)) - L2;
         const double q = tq * rcp64_1(L2);  // neither pass needs 1/|xi| itself
         // a break candidate: q at or above the lower edge of the decision (the rare branch
         // below decides, on the exact stretch within the margin)
