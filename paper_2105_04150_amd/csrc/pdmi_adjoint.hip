@@ -170,7 +170,8 @@ __device__ __forceinline__ void adj_wave_sync()
 template <int KM, bool VOLN, int S>
 __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A, const int2* __restrict__ pieces,
                                                          const int32_t* __restrict__ slice_piece,
-                                                         const int64_t* __restrict__ slice_ptr)
+                                                         const int64_t* __restrict__ slice_ptr,
+                                                         const int32_t* __restrict__ slice_order)
 {
     constexpr bool KNODE = KM == kKNode;
     constexpr int kW = (kEntPad / 48 + 2) / 2 * 2;  // staged weights per array (sentinel at kEntPad / 48)
@@ -191,8 +192,11 @@ __global__ __launch_bounds__(kWave * S) void adjoint_lds(AdjArgs A, const int2* 
     double* const lvol = reinterpret_cast<double*>(lrec + kRecChunks + kNuChunks + kEntChunks);
     double* const lna = lvol + (VOLN ? kW : 0);
 
-    const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
+    int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
     if (slice >= A.nslices) return;
+    // the step kernels' processing order (each XCD's share longest first): the grid
+    // ends on short slices when it does not fit the chip in one round
+    if (slice_order) slice = __builtin_amdgcn_readfirstlane(slice_order[slice]);
     const InstParams P = A.params[A.slice_inst[slice]];
     const int64_t node = slice * kWave + lane;
     const double2* __restrict__ rec = reinterpret_cast<const double2*>(A.rec);
@@ -405,14 +409,14 @@ void adj_launch_sliced(const AdjArgs& a, hipStream_t s)
 }
 
 template <int KM, bool VOLN>
-hipError_t adj_launch_kv(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
+hipError_t adj_launch_kv(const AdjArgs& a, const int32_t* order, bool staged, int lanes, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>(a.nslices));
     if (staged) {
         switch (lanes) {  // wavefronts per slice
-        case 1: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 1>), grid, dim3(kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
-        case 2: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 2>), grid, dim3(2 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
-        case 4: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 4>), grid, dim3(4 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr); break;
+        case 1: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 1>), grid, dim3(kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr, order); break;
+        case 2: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 2>), grid, dim3(2 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr, order); break;
+        case 4: hipLaunchKernelGGL((adjoint_lds<KM, VOLN, 4>), grid, dim3(4 * kWave), 0, s, a, a.pieces, a.slice_piece, a.slice_ptr, order); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -428,21 +432,28 @@ hipError_t adj_launch_kv(const AdjArgs& a, bool staged, int lanes, hipStream_t s
 }
 
 template <int KM>
-hipError_t adj_launch_k(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
+hipError_t adj_launch_k(const AdjArgs& a, const int32_t* order, bool staged, int lanes, hipStream_t s)
 {
-    return a.vol ? adj_launch_kv<KM, true>(a, staged, lanes, s) : adj_launch_kv<KM, false>(a, staged, lanes, s);
+    return a.vol ? adj_launch_kv<KM, true>(a, order, staged, lanes, s)
+                 : adj_launch_kv<KM, false>(a, order, staged, lanes, s);
 }
 
 unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
-hipError_t launch_adjoint(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
+hipError_t launch_adjoint_ordered(const AdjArgs& a, const int32_t* slice_order, bool staged, int lanes,
+                                  hipStream_t s)
 {
     if (a.nslices <= 0) return hipSuccess;
-    if (a.kslot) return adj_launch_k<kKSlot>(a, staged, lanes, s);
-    if (a.na) return adj_launch_k<kKNode>(a, staged, lanes, s);
-    return adj_launch_k<kKUniform>(a, staged, lanes, s);
+    if (a.kslot) return adj_launch_k<kKSlot>(a, slice_order, staged, lanes, s);
+    if (a.na) return adj_launch_k<kKNode>(a, slice_order, staged, lanes, s);
+    return adj_launch_k<kKUniform>(a, slice_order, staged, lanes, s);
+}
+
+hipError_t launch_adjoint(const AdjArgs& a, bool staged, int lanes, hipStream_t s)
+{
+    return launch_adjoint_ordered(a, nullptr, staged, lanes, s);
 }
 
 hipError_t launch_bstep_init(int32_t* bstep, const int32_t* col, const uint16_t* ent, int64_t ns, hipStream_t s)

@@ -187,7 +187,9 @@ int pd_adj_backward(pd_ctx* ctx, int64_t recording, int64_t m, const int64_t* se
                 a.nu_in = nu[nin].as<double>();
                 a.nu_out = nu[1 - nin].as<double>();
                 a.k = s0 + s;
-                hip_check(launch_adjoint(a, staged, ctx->lanes, st), "adjoint launch");
+                hip_check(launch_adjoint_ordered(a, staged ? ctx->slice_order.as<int32_t>() : nullptr, staged,
+                                                 ctx->lanes, st),
+                          "adjoint launch");
                 nin ^= 1;
             }
         }

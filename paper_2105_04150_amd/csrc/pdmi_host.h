@@ -362,4 +362,9 @@ void set_sum(pd_ctx* ctx, const std::vector<int64_t>& idx, const double* field, 
              const double* wv, double w, double out[3]);
 
 }  // namespace host
+
+// the reverse pass with the staged layout's slices in the order given (nullptr: dispatch
+// order; defined beside the reverse kernels)
+hipError_t launch_adjoint_ordered(const AdjArgs& a, const int32_t* slice_order, bool staged, int lanes,
+                                  hipStream_t s);
 }  // namespace pdmi
