@@ -98,8 +98,9 @@ __global__ __launch_bounds__(kWave * S) void osb_staged(StepArgs A, const int2* 
     double* const lvol = reinterpret_cast<double*>(lrec + kRecChunks + kEntChunks + kPairChunks);
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
+    int64_t slice = wave_uniform(xcd_remap(blockIdx.x, gridDim.x));
     if (slice >= A.nslices) return;
+    if (A.slice_order) slice = __builtin_amdgcn_readfirstlane(A.slice_order[slice]);  // long slices first
     const InstParams P = A.params[A.slice_inst[slice]];
     const int64_t node = slice * kWave + lane;
     const double2* __restrict__ rin = reinterpret_cast<const double2*>(A.rec_in);
