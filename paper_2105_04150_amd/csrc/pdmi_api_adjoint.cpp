@@ -187,8 +187,9 @@ int pd_adj_backward(pd_ctx* ctx, int64_t recording, int64_t m, const int64_t* se
                 a.nu_in = nu[nin].as<double>();
                 a.nu_out = nu[1 - nin].as<double>();
                 a.k = s0 + s;
-                hip_check(launch_adjoint_ordered(a, staged ? ctx->slice_order.as<int32_t>() : nullptr, staged,
-                                                 ctx->lanes, st),
+                // staged: the step kernels' slice order (each XCD's share longest first)
+                hip_check(staged ? launch_adjoint_ordered(a, ctx->slice_order.as<int32_t>(), true, ctx->lanes, st)
+                                 : launch_adjoint(a, false, ctx->lanes, st),
                           "adjoint launch");
                 nin ^= 1;
             }
